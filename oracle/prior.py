@@ -1,0 +1,33 @@
+"""One GLR prior step (oracle): detect keys, match globally, group top-K,
+shrink each group by WNNM, aggregate (Method section, eq. 1, eq. 8 sizes,
+the low-rank objective and WNNM)."""
+import numpy as np
+
+from .detector import detect_keys
+from .matching import topk_exact
+from .lowrank import shrink_groups
+from .aggregate import aggregate
+
+
+def prior_step(x, patch, n_keys, K, sigma, c, eps, is_complex=False, keys=None):
+    """Apply the prior to iterate ``x`` (planar real ``[C'][H][W]``; complex
+    data as ``[2][H][W]`` = (Re, Im)).  ``keys`` may be supplied to bypass the
+    detector.  Returns a dict with keys, idx, dist, Xhat, sv, x_out."""
+    x = np.asarray(x, dtype=np.float64)
+    if keys is None:
+        keys = detect_keys(x, patch, n_keys, is_complex=is_complex)
+    idx, dist = topk_exact(x, patch, keys, K)
+    Xhat, sv = shrink_groups(x, patch, idx, sigma, c, eps)
+    x_out, cnt = aggregate(x, patch, idx, Xhat)
+    return {"keys": keys, "idx": idx, "dist": dist, "Xhat": Xhat, "sv": sv,
+            "x_out": x_out, "count": cnt}
+
+
+def to_planar(z):
+    """complex ``[H][W]`` -> planar ``[2][H][W]`` (Re, Im)."""
+    return np.stack([np.real(z), np.imag(z)]).astype(np.float64)
+
+
+def from_planar(p):
+    """planar ``[2][H][W]`` -> complex ``[H][W]``."""
+    return p[0] + 1j * p[1]

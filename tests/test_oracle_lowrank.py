@@ -1,0 +1,114 @@
+"""Pins for the oracle's WNNM group shrinkage and aggregation."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import lowrank as lr
+from oracle import aggregate as ag
+from oracle import prior as pr
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rank1_group(D, K, s1, seed):
+    rng = np.random.default_rng(seed)
+    u = rng.standard_normal(D)
+    u /= np.linalg.norm(u)
+    v = rng.standard_normal(K)
+    v -= v.mean()               # v orthogonal to the ones vector: centring keeps it
+    v /= np.linalg.norm(v)
+    mu = rng.uniform(size=D)
+    return mu[:, None] + s1 * np.outer(u, v), mu, u, v
+
+
+def test_rank1_golden_value():
+    g = json.load(open(os.path.join(GOLD, "wnnm_rank1.json")))
+    Y, mu, u, v = _rank1_group(9, g["K"], g["s1"], 0)
+    X, s = lr.wnnm_group(Y, g["sigma"], g["c"], g["eps"])
+    assert abs(s[0] - g["s1"]) < 1e-12 and np.all(s[1:] < 1e-12)
+    expect = mu[:, None] + g["s1_shrunk"] * np.outer(u, v)
+    np.testing.assert_allclose(X, expect, rtol=0, atol=1e-12)
+
+
+def test_sigma_zero_is_identity():
+    Y = np.random.default_rng(1).uniform(size=(20, 7))
+    X, _ = lr.wnnm_group(Y, 0.0, 2.8, 1e-16)
+    np.testing.assert_array_equal(X, Y)
+
+
+def test_huge_sigma_gives_row_mean():
+    Y = np.random.default_rng(2).uniform(size=(12, 6))
+    X, _ = lr.wnnm_group(Y, 1e3, 2.8, 1e-16)
+    np.testing.assert_allclose(X, np.repeat(Y.mean(1, keepdims=True), 6, axis=1), atol=1e-12)
+
+
+def test_exact_low_rank_recovery_keeps_rank():
+    rng = np.random.default_rng(3)
+    D, K, r = 30, 16, 3
+    Y = rng.standard_normal((D, r)) @ rng.standard_normal((r, K)) * 2 + 0.5
+    X, s = lr.wnnm_group(Y, 0.05, 2 * np.sqrt(2), 1e-16)
+    Xc = X - X.mean(1, keepdims=True)
+    sx = np.linalg.svd(Xc, compute_uv=False)
+    assert np.all(sx[r:] < 1e-10 * sx[0])
+    # only the threshold moves the retained singular values
+    s_new = lr.wnnm_weights(s[:r], K, 0.05, 2 * np.sqrt(2), 1e-16)
+    np.testing.assert_allclose(sx[:r], s_new, rtol=1e-10)
+
+
+def test_shrinkage_bounds_and_denoising():
+    rng = np.random.default_rng(4)
+    D, K, r, sig = 64, 32, 2, 0.1
+    clean = rng.standard_normal((D, r)) @ rng.standard_normal((r, K)) + 0.3
+    errs = []
+    for t in range(5):
+        noisy = clean + sig * rng.standard_normal((D, K))
+        X, s = lr.wnnm_group(noisy, sig, 2 * np.sqrt(2), 1e-16)
+        sn = lr.wnnm_weights(s, K, sig, 2 * np.sqrt(2), 1e-16)
+        assert np.all(sn >= 0) and np.all(sn <= s)
+        errs.append((np.linalg.norm(X - clean), np.linalg.norm(noisy - clean)))
+    assert all(a < b for a, b in errs)
+
+
+def test_lapack_svd_invariants():
+    Y = np.random.default_rng(5).standard_normal((40, 12))
+    U, s, Vt = np.linalg.svd(Y, full_matrices=False)
+    assert np.abs(U.T @ U - np.eye(12)).max() < 1e-12
+    assert np.abs(Vt @ Vt.T - np.eye(12)).max() < 1e-12
+    assert np.linalg.norm(U * s @ Vt - Y) / np.linalg.norm(Y) < 1e-12
+
+
+def test_aggregate_identity_shrink_dyadic():
+    # sigma = 0 -> every estimate equals its patch; dyadic values make the
+    # per-pixel mean exact, so the prior step returns its input bit for bit
+    rng = np.random.default_rng(6)
+    x = rng.integers(0, 256, size=(2, 20, 22)).astype(np.float64) / 256.0
+    out = pr.prior_step(x, 4, 12, 9, 0.0, 2.8, 1e-16)
+    np.testing.assert_array_equal(out["x_out"], x)
+
+
+def test_aggregate_constant_image_and_counts():
+    x = np.full((3, 16, 17), 0.375)
+    out = pr.prior_step(x, 5, 6, 7, 0.05, 2.8, 1e-16)
+    np.testing.assert_allclose(out["x_out"], x, atol=1e-15)
+    cnt = ag.coverage_count(16, 17, 5, out["idx"])
+    np.testing.assert_array_equal(out["count"], cnt)
+
+
+def test_aggregate_single_member_by_hand():
+    xbar = np.zeros((1, 6, 7))
+    P, Wc = 2, 6
+    idx = np.array([[1 * Wc + 3]])
+    est = np.full((1, 1, 4), 7.0)
+    out, cnt = ag.aggregate(xbar, P, idx, est)
+    expect = np.zeros((1, 6, 7))
+    expect[0, 1:3, 3:5] = 7.0
+    np.testing.assert_array_equal(out, expect)
+    # two members overlapping one pixel: the mean
+    idx = np.array([[0, 1 * Wc + 1]])
+    est = np.stack([np.full(4, 2.0), np.full(4, 4.0)])[None]
+    out, cnt = ag.aggregate(xbar, P, idx, est)
+    assert out[0, 1, 1] == 3.0 and out[0, 0, 0] == 2.0 and out[0, 2, 2] == 4.0
+    assert cnt[1, 1] == 2 and cnt[3, 3] == 0
