@@ -1,0 +1,196 @@
+/*
+ * glr.h - C ABI of libglr, the MI355X (gfx950) implementation of the global
+ * low-rank (GLR) prior step and of its data-fidelity loop, after
+ * "Large-scale Global Low-rank Optimization for Computational Compressed
+ * Imaging" (Li, Xu, Cao, Yuan, Brady, Bian; arXiv 2301.03047).
+ *
+ * The calls follow the paper's problem statement: a measurement y of an
+ * image x through a sensing matrix Phi (the low-rank objective of the Method
+ * section: minimise sum_i rank(R_i x) subject to y = Phi x), a patch size P
+ * and a number N of exemplar (key) patches (the heat-map sizes given with
+ * eq. 8), a group size K (the KNN grouping of block matching), and an
+ * iterative solver (GAP or ADMM, named with the objective).
+ *
+ * Conventions for every call
+ * - Array arguments are DEVICE pointers unless marked "host".  The caller
+ *   owns all device memory (inputs, outputs, workspace); the library never
+ *   allocates device memory.  A plan holds host metadata only.
+ * - Every compute call is asynchronous on the given HIP stream; results are
+ *   valid once the stream has completed.  Calls on one plan must not overlap
+ *   (plans are not thread-safe); separate plans may run on separate streams.
+ * - Arguments are validated on the host before anything is enqueued.  On an
+ *   error nothing is launched, inputs are untouched and outputs are
+ *   unspecified; the status is returned and a detail string is available from
+ *   glr_last_error_message().  No C++ exception crosses this interface.
+ * - Device pointers must be 16-byte aligned; the workspace 256-byte aligned.
+ * - Image layouts: real data is planar float32 [C][H][W] (C = frames for
+ *   CACTI, bands for MSFA); MRI data is complex64 interleaved [H][W]
+ *   (re, im pairs).  "Real channels" C' is C for real data and 2 for MRI.
+ * - Patch vectors are ordered d = (c*P + dy)*P + dx (channel slowest); a
+ *   complex patch is stacked [Re; Im].  Candidate patches are all stride-1
+ *   top-left positions of the (H-P+1) x (W-P+1) grid (the heat-map size of
+ *   eq. 8); a position is the linear index t = r*(W-P+1) + c.
+ */
+#ifndef GLR_H
+#define GLR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GLR_API __attribute__((visibility("default")))
+
+typedef int32_t glr_status;
+enum {
+  GLR_OK = 0,
+  GLR_ERR_INVALID_ARG = 1,        /* null pointer, bad enum, bad scalar      */
+  GLR_ERR_SHAPE = 2,              /* sizes inconsistent (K > N_cand, P > H)  */
+  GLR_ERR_ALIGNMENT = 3,          /* pointer not aligned as required         */
+  GLR_ERR_UNSUPPORTED = 4,        /* valid but outside this build's limits   */
+  GLR_ERR_WORKSPACE_TOO_SMALL = 5,
+  GLR_ERR_HIP = 6                 /* a HIP runtime call or launch failed     */
+};
+
+enum { GLR_CACTI = 0, GLR_MRI = 1, GLR_MSFA = 2 };   /* eq. 2, eq. 3, eq. 4-5 */
+enum { GLR_SOLVER_GAP = 0, GLR_SOLVER_ADMM = 1 };
+enum { GLR_PREC_FP32 = 0, GLR_PREC_BF16_RESCORE = 1 };
+
+/* Sensing problem (eq. 2-5). */
+typedef struct glr_problem {
+  int32_t modality;      /* GLR_CACTI | GLR_MRI | GLR_MSFA                      */
+  int32_t H, W;          /* image size                                          */
+  int32_t C;             /* CACTI: frames per snapshot; MSFA: bands (16); MRI: 1 */
+  const uint8_t* mask;   /* device. CACTI: [C][H][W] in {0,1} (the coded
+                            apertures A_t of eq. 2). MRI: [H] k_y-line mask in
+                            {0,1}, expanded along k_x (M of eq. 3). MSFA: NULL
+                            (4x4 periodic array, band 4*(r%4)+(c%4), eq. 4-5). */
+} glr_problem;
+
+/* Method parameters.  Fields the paper leaves open are readings; their
+ * defaults are those of glr_params_default(). */
+typedef struct glr_params {
+  int32_t patch;         /* P, patch side (heat-map sizes with eq. 8)           */
+  int32_t n_keys;        /* N, exemplar (key) patches per prior step            */
+  int32_t k;             /* K, group size (K nearest patches), 1..64            */
+  int32_t iters;         /* T, outer iterations of glr_reconstruct              */
+  int32_t solver;        /* GAP for CACTI/MSFA, ADMM for MRI                    */
+  float rho;             /* ADMM penalty                                        */
+  const float* sigma;    /* host [iters]: noise level per iteration (copied)    */
+  float wnnm_c;          /* WNNM weight constant c (default 2*sqrt(2))          */
+  float wnnm_eps;        /* WNNM weight regulariser (default 1e-16)             */
+  int32_t precision;     /* GLR_PREC_FP32 | GLR_PREC_BF16_RESCORE               */
+  int32_t dist_chunk_mb; /* max size of one distance-matrix chunk (MiB)         */
+  int32_t timing;        /* nonzero: record per-stage HIP event pairs on the
+                            stream (no host sync); glr_read_stats() sums them */
+} glr_params;
+
+/* Counters of the last prior steps, read by glr_read_stats(). */
+typedef struct glr_stats {
+  int64_t prior_steps;        /* prior steps since the plan was created/reset   */
+  int64_t margin_sum;         /* sum over keys of the certified margin-set size  */
+  int32_t margin_max;         /* largest margin set                              */
+  int32_t overflow_keys;      /* keys that took the exact full-row path          */
+  int32_t jacobi_sweeps_max;  /* most Jacobi sweeps any group needed             */
+  int32_t keys_selected;      /* corner keys in the last step (before any fill)  */
+  /* with params.timing: milliseconds summed over all prior steps, per stage */
+  float ms_detect, ms_match, ms_topk, ms_select, ms_lowrank, ms_aggregate, ms_data;
+  float ms_norms;             /* key gather and candidate norms                  */
+  int64_t match_launches;     /* matcher kernel launches timed in ms_match       */
+} glr_stats;
+
+typedef struct glr_plan glr_plan;
+
+/* --------------------------------------------------------------- basics */
+GLR_API int32_t glr_version(void);                    /* 100*major + minor          */
+GLR_API const char* glr_status_string(glr_status s);
+/* Thread-local detail of the last failed call on this thread ("" if none). */
+GLR_API const char* glr_last_error_message(void);
+/* Fill *p with the defaults (c = 2*sqrt(2), eps = 1e-16, rho = 1, FP32,
+ * 2048 MiB chunks, GAP, no timing); patch/n_keys/k/iters are set to 0. */
+GLR_API void glr_params_default(glr_params* p);
+
+/* Create a plan for one problem shape.  Validates everything that does not
+ * depend on data pointers and reports the workspace size every later call
+ * needs (*workspace_bytes, 256-byte aligned buffer owned by the caller).
+ * problem->mask is recorded (the caller keeps it alive).  Limits: K <= 64,
+ * 1 <= N <= N_cand, K <= N_cand, P <= min(H, W), D = C'*P*P <= 4096;
+ * MRI needs H, W powers of two in [4, 2048]; MSFA needs C == 16 and H, W
+ * multiples of 4. */
+GLR_API glr_status glr_plan_create(glr_plan** out, const glr_problem* problem,
+                           const glr_params* params, size_t* workspace_bytes);
+GLR_API glr_status glr_plan_destroy(glr_plan* plan);
+GLR_API glr_status glr_workspace_size(const glr_plan* plan, size_t* bytes);
+
+/* --------------------------------------------------------------- operators
+ * y = Phi x (eq. 2, eq. 3, eq. 4).  x in the image layout; y: CACTI/MSFA
+ * float32 [H][W], MRI complex64 [H][W] (k-space, orthonormal DFT, unshifted,
+ * zero outside the sampled lines). */
+GLR_API glr_status glr_forward(glr_plan* plan, const void* x, void* y, void* ws, void* stream);
+/* x = Phi^T y (Phi^H for MRI).  Same layouts. */
+GLR_API glr_status glr_adjoint(glr_plan* plan, const void* y, void* x, void* ws, void* stream);
+/* Orthonormal 2-D DFT of a complex64 [H][W] array (MRI plans only);
+ * inverse != 0 gives the inverse transform.  In-place allowed. */
+GLR_API glr_status glr_fft2d(glr_plan* plan, const void* in, void* out, int32_t inverse,
+                     void* ws, void* stream);
+/* Data step.  GAP (CACTI, MSFA): x_out = x + Phi^T((y - Phi x) / R~) with
+ * R = diag(Phi Phi^T) and zeros of R replaced by 1.  ADMM (MRI): x_out =
+ * F^H((M y + rho F(z - u)) / (M + rho)); z and u are complex64 [H][W] and
+ * ignored for GAP (may be NULL).  In-place (x_out == x) allowed. */
+GLR_API glr_status glr_data_step(glr_plan* plan, const void* y, const void* x, const void* z,
+                         const void* u, void* x_out, void* ws, void* stream);
+
+/* --------------------------------------------------------------- prior step
+ * Key detection (corner exemplars, Method section / Fig. 1a): keys[N] int32,
+ * ascending top-left positions.  Reading: integer Harris on a u8 detection
+ * image, 3x3 non-maximum suppression, best N by score, uniform raster fill
+ * when fewer corners exist. */
+GLR_API glr_status glr_detect_keys(glr_plan* plan, const void* x, int32_t* keys, void* ws,
+                           void* stream);
+/* Global matching and grouping (eq. 1 made global; eq. 8 candidate grid):
+ * for each key g, idx[g][0..K) are the K candidates with the smallest
+ * squared L2 patch distance, ordered by (distance, position) ascending, and
+ * dist[g][q] those distances (float32).  keys: device int32 [N] (any order,
+ * each < N_cand).  The distance contraction runs on MFMA; candidates within a
+ * certified error margin of the K-th distance are rescored with compensated
+ * (double-float32) arithmetic so that the selection equals the exact one. */
+GLR_API glr_status glr_match_topk(glr_plan* plan, const void* x, const int32_t* keys,
+                          int32_t* idx, float* dist, void* ws, void* stream);
+/* Low-rank step and aggregation (WNNM on each group, the low-rank objective
+ * of the Method section): each group Y (D x K, column q = patch idx[g][q]) is
+ * mean-centred, decomposed by a one-sided Jacobi SVD (QR-preconditioned),
+ * its singular values shrunk by the WNNM weights for noise level sigma, and
+ * the member estimates averaged back per pixel; pixels no member covers keep
+ * x_in.  sv: optional device float32 [N][K], singular values descending
+ * (NULL to skip).  x_out must not alias x_in. */
+GLR_API glr_status glr_lowrank_aggregate(glr_plan* plan, const void* x_in, const int32_t* idx,
+                                 float sigma, void* x_out, float* sv, void* ws,
+                                 void* stream);
+/* The whole prior step: detect, match, group, shrink, aggregate. x_out must
+ * not alias x_in. */
+GLR_API glr_status glr_prior_step(glr_plan* plan, const void* x_in, float sigma, void* x_out,
+                          void* ws, void* stream);
+
+/* --------------------------------------------------------------- loop
+ * Run outer iterations t_begin .. t_end-1 of the GAP/ADMM loop with the GLR
+ * prior (sigma[t] per iteration).  state: device buffer of
+ * glr_state_bytes() holding the loop state (iterate; MRI: x, z, u); when
+ * t_begin == 0 it is initialised from y (CACTI: Phi^T(y / R~); MSFA: 4x4
+ * cell replication; MRI: x = z = F^H(M y), u = 0), otherwise it must hold
+ * the state left by a previous call, so a run may be split and resumed.
+ * x_out receives the current estimate (CACTI/MSFA: the last prior output;
+ * MRI: z). */
+GLR_API glr_status glr_state_bytes(const glr_plan* plan, size_t* bytes);
+GLR_API glr_status glr_reconstruct(glr_plan* plan, const void* y, void* state, int32_t t_begin,
+                           int32_t t_end, void* x_out, void* ws, void* stream);
+
+/* Synchronise the plan's last stream and copy the counters; reset != 0 zeroes
+ * them afterwards. */
+GLR_API glr_status glr_read_stats(glr_plan* plan, glr_stats* host_out, int32_t reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GLR_H */

@@ -1,0 +1,637 @@
+// libglr host layer: plans, validation, workspace layout and the stream-ordered
+// launch sequences behind the C ABI declared in include/glr.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+glr_status fail(glr_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+glr_status fail(glr_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+glr_status check_hip(const char* where) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(GLR_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+  return GLR_OK;
+}
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+size_t up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Carver {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    size_t o = off;
+    off = up(off + (bytes ? bytes : 1), 256);
+    return o;
+  }
+};
+
+#define REQUIRE_PTR(p)                                                         \
+  do {                                                                         \
+    if (!(p)) return fail(GLR_ERR_INVALID_ARG, "%s: %s is NULL", __func__, #p); \
+    if (!aligned((p), 16))                                                     \
+      return fail(GLR_ERR_ALIGNMENT, "%s: %s not 16-byte aligned", __func__, #p); \
+  } while (0)
+
+glr_status check_plan_ws(const glr_plan* pl, const void* ws, const char* fn) {
+  if (!pl) return fail(GLR_ERR_INVALID_ARG, "%s: plan is NULL", fn);
+  if (!ws) return fail(GLR_ERR_INVALID_ARG, "%s: workspace is NULL", fn);
+  if (!aligned(ws, 256)) return fail(GLR_ERR_ALIGNMENT, "%s: workspace not 256-byte aligned", fn);
+  return GLR_OK;
+}
+
+// Stats live in the workspace: clear them the first time a workspace is seen.
+void ensure_stats(glr_plan* pl, char* ws, hipStream_t s) {
+  if (pl->stats_ws != ws) {
+    launch_fill_u32((uint32_t*)(ws + pl->ws.stats), 0u, sizeof(DevStats) / 4, s);
+    pl->stats_ws = ws;
+  }
+  pl->last_stream = s;
+}
+
+// Optional per-stage timing: an event pair is recorded around each stage on
+// the caller's stream (no host synchronisation); glr_read_stats() waits for
+// the stream and folds the elapsed times into per-stage totals.
+struct StageTimer {
+  glr_plan* pl;
+  hipStream_t s;
+  int stage;
+  size_t slot;
+  StageTimer(glr_plan* p, hipStream_t st, int stg) : pl(p), s(st), stage(stg), slot(0) {
+    if (!pl->timing) return;
+    slot = pl->ev_used;
+    if (slot == pl->ev_pool.size()) {
+      hipEvent_t a = nullptr, b = nullptr;
+      hipEventCreate(&a);
+      hipEventCreate(&b);
+      pl->ev_pool.push_back({a, b});
+      pl->ev_stage.push_back(0);
+    }
+    pl->ev_stage[slot] = stage;
+    pl->ev_used++;
+    hipEventRecord(pl->ev_pool[slot].first, s);
+  }
+  ~StageTimer() {
+    if (pl->timing) hipEventRecord(pl->ev_pool[slot].second, s);
+  }
+};
+
+void fold_timers(glr_plan* pl) {
+  for (size_t i = 0; i < pl->ev_used; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, pl->ev_pool[i].first, pl->ev_pool[i].second) == hipSuccess)
+      pl->ms[pl->ev_stage[i]] += ms;
+  }
+  pl->ev_used = 0;
+}
+enum { T_DETECT = 0, T_MATCH, T_TOPK, T_SELECT, T_LOWRANK, T_AGG, T_DATA, T_NORMS, T_COUNT };
+
+// ---------------------------------------------------------------- prior step
+// xp: planar [Cp][H][W]; xo: planar output; keys_in: optional caller keys.
+// idx_out/dd_out: where groups go (may be the workspace buffers).
+glr_status match_stage(glr_plan* pl, const float* xp, const int32_t* keys, int32_t* idx_out,
+                       float* dd_out, char* ws, hipStream_t s) {
+  float* A = (float*)(ws + pl->ws.A);
+  float* kmeta = (float*)(ws + pl->ws.kmeta);
+  float* pnorm = (float*)(ws + pl->ws.pnorm);
+  float* prt = (float*)(ws + pl->ws.prt);
+  float* dist = (float*)(ws + pl->ws.dist);
+  int32_t* lj = (int32_t*)(ws + pl->ws.lj);
+  float* lu = (float*)(ws + pl->ws.lu);
+  float* ll = (float*)(ws + pl->ws.ll);
+  int32_t* lcnt = (int32_t*)(ws + pl->ws.lcnt);
+  DevStats* st = (DevStats*)(ws + pl->ws.stats);
+  {
+    StageTimer t(pl, s, T_NORMS);
+    launch_gather_keys(pl, xp, keys, A, kmeta, s);
+    launch_cand_norms(pl, xp, pnorm, prt, s);
+  }
+  for (int g0 = 0; g0 < pl->N; g0 += pl->n_chunk) {
+    const int nk = std::min(pl->n_chunk, pl->N - g0);
+    {
+      StageTimer t(pl, s, T_MATCH);
+      launch_match_f32(pl, xp, A, kmeta, pnorm, g0, nk, dist, s);
+      if (pl->timing) pl->match_launches++;
+    }
+    {
+      StageTimer t(pl, s, T_TOPK);
+      launch_topk_partial(pl, dist, kmeta, prt, g0, nk, lj, lu, ll, lcnt, s);
+    }
+    {
+      StageTimer t(pl, s, T_SELECT);
+      launch_select_rescore(pl, xp, A, g0, nk, lj, lu, ll, lcnt, idx_out, dd_out, st, s);
+    }
+  }
+  return check_hip("glr_match_topk");
+}
+
+glr_status lowrank_stage(glr_plan* pl, const float* xp, const int32_t* idx, float sigma, float* xo,
+                         float* sv, char* ws, hipStream_t s) {
+  float* xhat = (float*)(ws + pl->ws.xhat);
+  DevStats* st = (DevStats*)(ws + pl->ws.stats);
+  {
+    StageTimer t(pl, s, T_LOWRANK);
+    launch_wnnm(pl, xp, idx, sigma, xhat, sv, st, s);
+  }
+  {
+    StageTimer t(pl, s, T_AGG);
+    launch_aggregate(pl, xp, idx, xhat, (unsigned long long*)(ws + pl->ws.pairs),
+                     (int32_t*)(ws + pl->ws.offs), xo, s);
+  }
+  return check_hip("glr_lowrank_aggregate");
+}
+
+glr_status prior_planar(glr_plan* pl, const float* xp, float sigma, float* xo, char* ws,
+                        hipStream_t s) {
+  int32_t* keys = (int32_t*)(ws + pl->ws.keys);
+  int32_t* idx = (int32_t*)(ws + pl->ws.idx);
+  float* dd = (float*)(ws + pl->ws.dd);
+  {
+    StageTimer t(pl, s, T_DETECT);
+    launch_detect(pl, xp, ws, keys, s);
+  }
+  glr_status e = check_hip("detect");
+  if (e) return e;
+  e = match_stage(pl, xp, keys, idx, dd, ws, s);
+  if (e) return e;
+  e = lowrank_stage(pl, xp, idx, sigma, xo, (float*)(ws + pl->ws.sv), ws, s);
+  if (e) return e;
+  launch_count_step((DevStats*)(ws + pl->ws.stats), s);
+  return check_hip("prior step");
+}
+
+// input image (modality layout) -> planar pointer (complex data is split into ws.xp)
+const float* planar_in(glr_plan* pl, const void* x, char* ws, hipStream_t s) {
+  if (!pl->is_complex) return (const float*)x;
+  float* xp = (float*)(ws + pl->ws.xp);
+  launch_to_planar((const float2*)x, xp, pl->H * pl->W, s);
+  return xp;
+}
+
+glr_status data_step_impl(glr_plan* pl, const void* y, const void* x, const void* z,
+                          const void* u, void* x_out, char* ws, hipStream_t s) {
+  StageTimer t(pl, s, T_DATA);
+  const int H = pl->H, W = pl->W, HW = H * W;
+  if (pl->modality == GLR_CACTI) {
+    launch_cacti_gap((const float*)x, (const float*)y, pl->mask, (float*)x_out, pl->C, HW, s);
+  } else if (pl->modality == GLR_MSFA) {
+    launch_msfa_gap((const float*)x, (const float*)y, (float*)x_out, H, W, s);
+  } else {
+    float2* a = (float2*)(ws + pl->ws.cplx_a);
+    launch_cplx_axpby((const float2*)z, (const float2*)u, a, 1.0f, -1.0f, HW, s);
+    launch_fft2d(a, a, H, W, 0, s);
+    launch_admm_kspace((const float2*)y, pl->mask, a, a, pl->rho, H, W, s);
+    launch_fft2d(a, (float2*)x_out, H, W, 1, s);
+  }
+  return check_hip("glr_data_step");
+}
+
+}  // namespace
+
+// ================================================================== ABI
+extern "C" {
+
+int32_t glr_version(void) { return 100; }
+
+const char* glr_status_string(glr_status s) {
+  switch (s) {
+    case GLR_OK: return "GLR_OK";
+    case GLR_ERR_INVALID_ARG: return "GLR_ERR_INVALID_ARG";
+    case GLR_ERR_SHAPE: return "GLR_ERR_SHAPE";
+    case GLR_ERR_ALIGNMENT: return "GLR_ERR_ALIGNMENT";
+    case GLR_ERR_UNSUPPORTED: return "GLR_ERR_UNSUPPORTED";
+    case GLR_ERR_WORKSPACE_TOO_SMALL: return "GLR_ERR_WORKSPACE_TOO_SMALL";
+    case GLR_ERR_HIP: return "GLR_ERR_HIP";
+    default: return "GLR_ERR_UNKNOWN";
+  }
+}
+
+const char* glr_last_error_message(void) { return g_err.c_str(); }
+
+void glr_params_default(glr_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof *p);
+  p->solver = GLR_SOLVER_GAP;
+  p->rho = 1.0f;
+  p->wnnm_c = 2.0f * std::sqrt(2.0f);
+  p->wnnm_eps = 1e-16f;
+  p->precision = GLR_PREC_FP32;
+  p->dist_chunk_mb = 2048;
+  p->timing = 0;
+}
+
+glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_params* pr,
+                           size_t* workspace_bytes) {
+  g_err.clear();
+  if (!out || !pb || !pr) return fail(GLR_ERR_INVALID_ARG, "glr_plan_create: NULL argument");
+  *out = nullptr;
+  if (pb->modality < GLR_CACTI || pb->modality > GLR_MSFA)
+    return fail(GLR_ERR_INVALID_ARG, "unknown modality %d", pb->modality);
+  if (pb->H <= 0 || pb->W <= 0 || pb->C <= 0)
+    return fail(GLR_ERR_SHAPE, "image size must be positive (H=%d W=%d C=%d)", pb->H, pb->W, pb->C);
+  if ((long long)pb->H * pb->W > (1LL << 26))
+    return fail(GLR_ERR_UNSUPPORTED, "image larger than 2^26 pixels");
+  const int P = pr->patch;
+  if (P < 1 || P > std::min(pb->H, pb->W))
+    return fail(GLR_ERR_SHAPE, "patch %d must be in [1, min(H, W)]", P);
+  if (P > 16) return fail(GLR_ERR_UNSUPPORTED, "patch %d > 16", P);
+  const int Cp = pb->modality == GLR_MRI ? 2 : pb->C;
+  const int D = Cp * P * P;
+  if (D > 4096) return fail(GLR_ERR_UNSUPPORTED, "patch dimension %d > 4096", D);
+  const int Hc = pb->H - P + 1, Wc = pb->W - P + 1;
+  const long long Ncand = (long long)Hc * Wc;
+  if (pr->k < 1 || pr->k > Ncand) return fail(GLR_ERR_SHAPE, "K=%d must be in [1, N_cand=%lld]", pr->k, Ncand);
+  if (pr->k > 64) return fail(GLR_ERR_UNSUPPORTED, "K=%d > 64", pr->k);
+  if (pr->n_keys < 1 || pr->n_keys > Ncand)
+    return fail(GLR_ERR_SHAPE, "n_keys=%d must be in [1, N_cand=%lld]", pr->n_keys, Ncand);
+  if ((long long)pr->n_keys * pr->k > (1LL << 30))
+    return fail(GLR_ERR_UNSUPPORTED, "n_keys*K too large");
+  if (pr->iters < 0) return fail(GLR_ERR_INVALID_ARG, "iters < 0");
+  if (pr->iters > 0 && !pr->sigma) return fail(GLR_ERR_INVALID_ARG, "sigma is NULL");
+  if (pr->precision != GLR_PREC_FP32 && pr->precision != GLR_PREC_BF16_RESCORE)
+    return fail(GLR_ERR_INVALID_ARG, "unknown precision %d", pr->precision);
+  if (pr->precision == GLR_PREC_BF16_RESCORE)
+    return fail(GLR_ERR_UNSUPPORTED, "BF16 matching is not available in this build");
+  if (!(pr->wnnm_c >= 0.f) || !(pr->wnnm_eps > 0.f) || !(pr->rho > 0.f))
+    return fail(GLR_ERR_INVALID_ARG, "wnnm_c >= 0, wnnm_eps > 0 and rho > 0 required");
+  if (pb->modality == GLR_MRI) {
+    if (pb->C != 1) return fail(GLR_ERR_SHAPE, "MRI plans take C = 1 (complex image)");
+    if (!pow2(pb->H) || !pow2(pb->W) || pb->H < 4 || pb->W < 4 || pb->H > 2048 || pb->W > 2048)
+      return fail(GLR_ERR_UNSUPPORTED, "MRI needs H, W powers of two in [4, 2048]");
+    if (pr->solver != GLR_SOLVER_ADMM) return fail(GLR_ERR_INVALID_ARG, "MRI uses the ADMM solver");
+  } else if (pr->solver != GLR_SOLVER_GAP) {
+    return fail(GLR_ERR_INVALID_ARG, "CACTI/MSFA use the GAP solver");
+  }
+  if (pb->modality == GLR_MSFA) {
+    if (pb->C != 16) return fail(GLR_ERR_UNSUPPORTED, "MSFA needs 16 bands");
+    if (pb->H % 4 || pb->W % 4) return fail(GLR_ERR_SHAPE, "MSFA needs H, W multiples of 4");
+  } else if (!pb->mask) {
+    return fail(GLR_ERR_INVALID_ARG, "mask is NULL");
+  }
+  if (pb->mask && !aligned(pb->mask, 16)) return fail(GLR_ERR_ALIGNMENT, "mask not 16-byte aligned");
+
+  glr_plan* pl = new (std::nothrow) glr_plan();
+  if (!pl) return fail(GLR_ERR_INVALID_ARG, "out of host memory");
+  pl->modality = pb->modality;
+  pl->H = pb->H;
+  pl->W = pb->W;
+  pl->C = pb->C;
+  pl->Cp = Cp;
+  pl->is_complex = pb->modality == GLR_MRI;
+  pl->mask = pb->mask;
+  pl->P = P;
+  pl->N = pr->n_keys;
+  pl->K = pr->k;
+  pl->T = pr->iters;
+  pl->solver = pr->solver;
+  pl->precision = pr->precision;
+  pl->timing = pr->timing;
+  pl->rho = pr->rho;
+  pl->wnnm_c = pr->wnnm_c;
+  pl->wnnm_eps = pr->wnnm_eps;
+  if (pr->iters > 0) pl->sigma.assign(pr->sigma, pr->sigma + pr->iters);
+  pl->Hc = Hc;
+  pl->Wc = Wc;
+  pl->Ncand = (int)Ncand;
+  pl->D = D;
+  pl->ldd = (int)up((size_t)Ncand, 64);
+  size_t chunk_bytes = (size_t)(pr->dist_chunk_mb > 0 ? pr->dist_chunk_mb : 2048) << 20;
+  long long nch = (long long)(chunk_bytes / ((size_t)pl->ldd * 4));
+  if (nch < 1) nch = 1;
+  if (nch >= 128) nch = nch / 128 * 128;
+  pl->n_chunk = (int)std::min<long long>(nch, pl->N);
+  int ns = (8192 + pl->n_chunk - 1) / pl->n_chunk;
+  ns = std::min(ns, 64);
+  ns = std::min<long long>(ns, (Ncand + 1023) / 1024);
+  if (ns < 1) ns = 1;
+  pl->split_len = (int)up((size_t)((Ncand + ns - 1) / ns), 256);
+  pl->n_split = (int)((Ncand + pl->split_len - 1) / pl->split_len);
+  pl->M = pl->N * pl->K;
+  pl->M2 = 2048;
+  while (pl->M2 < pl->M) pl->M2 <<= 1;
+
+  const size_t HW = (size_t)pl->H * pl->W;
+  Carver c;
+  WsLayout& L = pl->ws;
+  L.xp = c.take(HW * Cp * 4);
+  L.xo = c.take(HW * Cp * 4);
+  L.q = c.take(HW);
+  L.gxx = c.take(HW * 4);
+  L.gyy = c.take(HW * 4);
+  L.gxy = c.take(HW * 4);
+  L.r25 = c.take(HW * 8);
+  L.cflag = c.take((size_t)Ncand);
+  L.slist = c.take((size_t)Ncand * 4);
+  L.keys = c.take((size_t)pl->N * 4);
+  L.A = c.take((size_t)pl->N * D * 4);
+  L.kmeta = c.take((size_t)pl->N * 8);
+  L.pnorm = c.take((size_t)Ncand * 4);
+  L.prt = c.take((size_t)Ncand * 4);
+  L.dist = c.take((size_t)pl->n_chunk * pl->ldd * 4);
+  const size_t nlist = (size_t)pl->n_chunk * pl->n_split;
+  L.lj = c.take(nlist * GLR_SPLIT_CAP * 4);
+  L.lu = c.take(nlist * GLR_SPLIT_CAP * 4);
+  L.ll = c.take(nlist * GLR_SPLIT_CAP * 4);
+  L.lcnt = c.take(nlist * 4);
+  L.idx = c.take((size_t)pl->M * 4);
+  L.dd = c.take((size_t)pl->M * 4);
+  L.xhat = c.take((size_t)pl->M * D * 4);
+  L.sv = c.take((size_t)pl->M * 4);
+  L.pairs = c.take((size_t)pl->M2 * 8);
+  L.offs = c.take(((size_t)Ncand + 1) * 4);
+  L.cplx_a = c.take(pl->is_complex ? HW * 8 : 0);
+  L.cplx_b = c.take(pl->is_complex ? HW * 8 : 0);
+  L.red = c.take(256);
+  L.stats = c.take(sizeof(DevStats));
+  L.total = c.off;
+
+  pl->ev_used = 0;
+  pl->stats_ws = nullptr;
+  pl->last_stream = nullptr;
+  for (double& m : pl->ms) m = 0.0;
+  pl->match_launches = 0;
+  if (workspace_bytes) *workspace_bytes = L.total;
+  *out = pl;
+  return GLR_OK;
+}
+
+glr_status glr_plan_destroy(glr_plan* pl) {
+  if (!pl) return fail(GLR_ERR_INVALID_ARG, "glr_plan_destroy: NULL plan");
+  for (auto& e : pl->ev_pool) {
+    hipEventDestroy(e.first);
+    hipEventDestroy(e.second);
+  }
+  delete pl;
+  return GLR_OK;
+}
+
+glr_status glr_workspace_size(const glr_plan* pl, size_t* bytes) {
+  if (!pl || !bytes) return fail(GLR_ERR_INVALID_ARG, "glr_workspace_size: NULL argument");
+  *bytes = pl->ws.total;
+  return GLR_OK;
+}
+
+glr_status glr_forward(glr_plan* pl, const void* x, void* y, void* ws, void* stream) {
+  glr_status e = check_plan_ws(pl, ws, __func__);
+  if (e) return e;
+  REQUIRE_PTR(x);
+  REQUIRE_PTR(y);
+  hipStream_t s = (hipStream_t)stream;
+  ensure_stats(pl, (char*)ws, s);
+  const int H = pl->H, W = pl->W;
+  if (pl->modality == GLR_CACTI)
+    launch_cacti_forward((const float*)x, pl->mask, (float*)y, pl->C, H * W, s);
+  else if (pl->modality == GLR_MSFA)
+    launch_msfa_forward((const float*)x, (float*)y, H, W, s);
+  else {
+    float2* a = (float2*)((char*)ws + pl->ws.cplx_a);
+    launch_fft2d((const float2*)x, a, H, W, 0, s);
+    launch_kspace_mask(a, pl->mask, (float2*)y, H, W, s);
+  }
+  return check_hip(__func__);
+}
+
+glr_status glr_adjoint(glr_plan* pl, const void* y, void* x, void* ws, void* stream) {
+  glr_status e = check_plan_ws(pl, ws, __func__);
+  if (e) return e;
+  REQUIRE_PTR(x);
+  REQUIRE_PTR(y);
+  hipStream_t s = (hipStream_t)stream;
+  ensure_stats(pl, (char*)ws, s);
+  const int H = pl->H, W = pl->W;
+  if (pl->modality == GLR_CACTI)
+    launch_cacti_adjoint((const float*)y, pl->mask, (float*)x, pl->C, H * W, s);
+  else if (pl->modality == GLR_MSFA)
+    launch_msfa_adjoint((const float*)y, (float*)x, H, W, s);
+  else {
+    float2* a = (float2*)((char*)ws + pl->ws.cplx_a);
+    launch_kspace_mask((const float2*)y, pl->mask, a, H, W, s);
+    launch_fft2d(a, (float2*)x, H, W, 1, s);
+  }
+  return check_hip(__func__);
+}
+
+glr_status glr_fft2d(glr_plan* pl, const void* in, void* out, int32_t inverse, void* ws,
+                     void* stream) {
+  glr_status e = check_plan_ws(pl, ws, __func__);
+  if (e) return e;
+  REQUIRE_PTR(in);
+  REQUIRE_PTR(out);
+  if (!pl->is_complex) return fail(GLR_ERR_UNSUPPORTED, "glr_fft2d needs an MRI plan");
+  hipStream_t s = (hipStream_t)stream;
+  launch_fft2d((const float2*)in, (float2*)out, pl->H, pl->W, inverse ? 1 : 0, s);
+  return check_hip(__func__);
+}
+
+glr_status glr_data_step(glr_plan* pl, const void* y, const void* x, const void* z, const void* u,
+                         void* x_out, void* ws, void* stream) {
+  glr_status e = check_plan_ws(pl, ws, __func__);
+  if (e) return e;
+  REQUIRE_PTR(y);
+  REQUIRE_PTR(x_out);
+  if (pl->is_complex) {
+    REQUIRE_PTR(z);
+    REQUIRE_PTR(u);
+  } else {
+    REQUIRE_PTR(x);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  ensure_stats(pl, (char*)ws, s);
+  return data_step_impl(pl, y, x, z, u, x_out, (char*)ws, s);
+}
+
+glr_status glr_detect_keys(glr_plan* pl, const void* x, int32_t* keys, void* ws, void* stream) {
+  glr_status e = check_plan_ws(pl, ws, __func__);
+  if (e) return e;
+  REQUIRE_PTR(x);
+  REQUIRE_PTR(keys);
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  ensure_stats(pl, w, s);
+  const float* xp = planar_in(pl, x, w, s);
+  {
+    StageTimer t(pl, s, T_DETECT);
+    launch_detect(pl, xp, w, keys, s);
+  }
+  return check_hip(__func__);
+}
+
+glr_status glr_match_topk(glr_plan* pl, const void* x, const int32_t* keys, int32_t* idx,
+                          float* dist, void* ws, void* stream) {
+  glr_status e = check_plan_ws(pl, ws, __func__);
+  if (e) return e;
+  REQUIRE_PTR(x);
+  REQUIRE_PTR(keys);
+  REQUIRE_PTR(idx);
+  REQUIRE_PTR(dist);
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  ensure_stats(pl, w, s);
+  const float* xp = planar_in(pl, x, w, s);
+  return match_stage(pl, xp, keys, idx, dist, w, s);
+}
+
+glr_status glr_lowrank_aggregate(glr_plan* pl, const void* x_in, const int32_t* idx, float sigma,
+                                 void* x_out, float* sv, void* ws, void* stream) {
+  glr_status e = check_plan_ws(pl, ws, __func__);
+  if (e) return e;
+  REQUIRE_PTR(x_in);
+  REQUIRE_PTR(idx);
+  REQUIRE_PTR(x_out);
+  if (sv && !aligned(sv, 16)) return fail(GLR_ERR_ALIGNMENT, "sv not 16-byte aligned");
+  if (!(sigma >= 0.f) || !std::isfinite(sigma)) return fail(GLR_ERR_INVALID_ARG, "sigma must be finite and >= 0");
+  if (x_in == x_out) return fail(GLR_ERR_INVALID_ARG, "x_out must not alias x_in");
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  ensure_stats(pl, w, s);
+  const float* xp = planar_in(pl, x_in, w, s);
+  float* xo = pl->is_complex ? (float*)(w + pl->ws.xo) : (float*)x_out;
+  e = lowrank_stage(pl, xp, idx, sigma, xo, sv, w, s);
+  if (e) return e;
+  if (pl->is_complex) launch_from_planar(xo, (float2*)x_out, pl->H * pl->W, s);
+  return check_hip(__func__);
+}
+
+glr_status glr_prior_step(glr_plan* pl, const void* x_in, float sigma, void* x_out, void* ws,
+                          void* stream) {
+  glr_status e = check_plan_ws(pl, ws, __func__);
+  if (e) return e;
+  REQUIRE_PTR(x_in);
+  REQUIRE_PTR(x_out);
+  if (!(sigma >= 0.f) || !std::isfinite(sigma)) return fail(GLR_ERR_INVALID_ARG, "sigma must be finite and >= 0");
+  if (x_in == x_out) return fail(GLR_ERR_INVALID_ARG, "x_out must not alias x_in");
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  ensure_stats(pl, w, s);
+  const float* xp = planar_in(pl, x_in, w, s);
+  float* xo = pl->is_complex ? (float*)(w + pl->ws.xo) : (float*)x_out;
+  e = prior_planar(pl, xp, sigma, xo, w, s);
+  if (e) return e;
+  if (pl->is_complex) launch_from_planar(xo, (float2*)x_out, pl->H * pl->W, s);
+  return check_hip(__func__);
+}
+
+glr_status glr_state_bytes(const glr_plan* pl, size_t* bytes) {
+  if (!pl || !bytes) return fail(GLR_ERR_INVALID_ARG, "glr_state_bytes: NULL argument");
+  const size_t HW = (size_t)pl->H * pl->W;
+  *bytes = pl->is_complex ? 3 * HW * 8 : (size_t)pl->C * HW * 4;
+  return GLR_OK;
+}
+
+glr_status glr_reconstruct(glr_plan* pl, const void* y, void* state, int32_t t_begin,
+                           int32_t t_end, void* x_out, void* ws, void* stream) {
+  glr_status e = check_plan_ws(pl, ws, __func__);
+  if (e) return e;
+  REQUIRE_PTR(y);
+  REQUIRE_PTR(state);
+  REQUIRE_PTR(x_out);
+  if (t_begin < 0 || t_end < t_begin || t_end > pl->T)
+    return fail(GLR_ERR_INVALID_ARG, "need 0 <= t_begin <= t_end <= iters (%d)", pl->T);
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  ensure_stats(pl, w, s);
+  const int H = pl->H, W = pl->W, HW = H * W;
+  if (!pl->is_complex) {
+    float* x = (float*)state;
+    float* xb = (float*)(w + pl->ws.xp);
+    if (t_begin == 0) {
+      if (pl->modality == GLR_CACTI) launch_cacti_init((const float*)y, pl->mask, x, pl->C, HW, s);
+      else launch_msfa_init((const float*)y, x, H, W, s);
+    }
+    for (int t = t_begin; t < t_end; ++t) {
+      e = data_step_impl(pl, y, x, nullptr, nullptr, xb, w, s);
+      if (e) return e;
+      e = prior_planar(pl, xb, pl->sigma[t], x, w, s);
+      if (e) return e;
+    }
+    hipMemcpyAsync(x_out, x, (size_t)pl->C * HW * 4, hipMemcpyDeviceToDevice, s);
+  } else {
+    float2* x = (float2*)state;
+    float2* z = x + HW;
+    float2* u = z + HW;
+    float2* v = (float2*)(w + pl->ws.cplx_b);
+    float* vp = (float*)(w + pl->ws.xp);
+    float* zp = (float*)(w + pl->ws.xo);
+    if (t_begin == 0) {
+      float2* a = (float2*)(w + pl->ws.cplx_a);
+      launch_kspace_mask((const float2*)y, pl->mask, a, H, W, s);
+      launch_fft2d(a, z, H, W, 1, s);
+      launch_cplx_axpby(z, z, x, 1.0f, 0.0f, HW, s);
+      launch_cplx_axpby(z, z, u, 0.0f, 0.0f, HW, s);
+    }
+    for (int t = t_begin; t < t_end; ++t) {
+      e = data_step_impl(pl, y, nullptr, z, u, x, w, s);
+      if (e) return e;
+      launch_cplx_axpby(x, u, v, 1.0f, 1.0f, HW, s);
+      launch_to_planar(v, vp, HW, s);
+      e = prior_planar(pl, vp, pl->sigma[t], zp, w, s);
+      if (e) return e;
+      launch_from_planar(zp, z, HW, s);
+      launch_admm_dual(u, x, z, HW, s);
+    }
+    hipMemcpyAsync(x_out, z, (size_t)HW * 8, hipMemcpyDeviceToDevice, s);
+  }
+  return check_hip(__func__);
+}
+
+glr_status glr_read_stats(glr_plan* pl, glr_stats* out, int32_t reset) {
+  if (!pl || !out) return fail(GLR_ERR_INVALID_ARG, "glr_read_stats: NULL argument");
+  std::memset(out, 0, sizeof *out);
+  if (pl->stats_ws) {
+    if (hipStreamSynchronize(pl->last_stream) != hipSuccess)
+      return fail(GLR_ERR_HIP, "hipStreamSynchronize failed");
+    fold_timers(pl);
+    DevStats d;
+    if (hipMemcpy(&d, (const char*)pl->stats_ws + pl->ws.stats, sizeof d, hipMemcpyDeviceToHost) !=
+        hipSuccess)
+      return fail(GLR_ERR_HIP, "stats copy failed");
+    out->prior_steps = (int64_t)d.steps;
+    out->margin_sum = (int64_t)d.margin_sum;
+    out->margin_max = d.margin_max;
+    out->overflow_keys = d.overflow;
+    out->jacobi_sweeps_max = d.sweeps_max;
+    out->keys_selected = d.keys_selected;
+    if (reset) {
+      launch_fill_u32((uint32_t*)((char*)pl->stats_ws + pl->ws.stats), 0u, sizeof(DevStats) / 4,
+                      pl->last_stream);
+      hipStreamSynchronize(pl->last_stream);
+    }
+  }
+  out->ms_detect = (float)pl->ms[T_DETECT];
+  out->ms_match = (float)pl->ms[T_MATCH];
+  out->ms_topk = (float)pl->ms[T_TOPK];
+  out->ms_select = (float)pl->ms[T_SELECT];
+  out->ms_lowrank = (float)pl->ms[T_LOWRANK];
+  out->ms_aggregate = (float)pl->ms[T_AGG];
+  out->ms_data = (float)pl->ms[T_DATA];
+  out->ms_norms = (float)pl->ms[T_NORMS];
+  out->match_launches = pl->match_launches;
+  if (reset) {
+    for (double& m : pl->ms) m = 0.0;
+    pl->match_launches = 0;
+  }
+  return GLR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,270 @@
+// Key (exemplar) patch detection: corner points instead of a uniform grid
+// (Method section, Fig. 1a).  Reading: an integer Harris detector on a u8
+// detection image.  Only the quantiser uses floating point (IEEE FP32 with no
+// contraction: the file is built with -ffp-contract=off); everything after it
+// is exact integer arithmetic, so the keys are reproducible bit for bit.
+#include "common.h"
+#include "internal.h"
+
+namespace {
+
+constexpr int TPB = 256;
+inline int nblk(size_t n) { return (int)((n + TPB - 1) / TPB); }
+
+// q = floor((sum_c clamp(rint(255 x_c), 0, 255) + C/2) / C)
+__global__ void k_quant_real(const float* __restrict__ x, int C, int HW, uint8_t* __restrict__ q) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= HW) return;
+  int s = 0;
+  for (int c = 0; c < C; ++c) {
+    float v = rintf(255.0f * x[(size_t)c * HW + p]);
+    v = fminf(fmaxf(v, 0.0f), 255.0f);
+    s += (int)v;
+  }
+  q[p] = (uint8_t)((s + C / 2) / C);
+}
+
+// largest squared magnitude (non-negative floats order like their bit patterns)
+__global__ void k_mag2_max(const float* __restrict__ xp, int HW, uint32_t* __restrict__ out) {
+  __shared__ uint32_t red[TPB / 64];
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t b = 0;
+  if (p < HW) {
+    float re = xp[p], im = xp[HW + p];
+    b = __float_as_uint(re * re + im * im);
+  }
+  for (int o = 32; o > 0; o >>= 1) b = max(b, (uint32_t)__shfl_xor((int)b, o, 64));
+  if (lane_id() == 0) red[threadIdx.x >> 6] = b;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t m = red[0];
+    for (int i = 1; i < TPB / 64; ++i) m = max(m, red[i]);
+    atomicMax(out, m);
+  }
+}
+
+// q = clamp(rint(255 * (m * (1/max m))), 0, 255); all zero if max m == 0
+__global__ void k_quant_cplx(const float* __restrict__ xp, int HW, const uint32_t* __restrict__ mx,
+                             uint8_t* __restrict__ q) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= HW) return;
+  float m_max = __uint_as_float(*mx);
+  if (!(m_max > 0.0f)) {
+    q[p] = 0;
+    return;
+  }
+  float s = __fdiv_rn(1.0f, m_max);
+  float re = xp[p], im = xp[HW + p];
+  float m = re * re + im * im;
+  float v = rintf(255.0f * (m * s));
+  v = fminf(fmaxf(v, 0.0f), 255.0f);
+  q[p] = (uint8_t)v;
+}
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// Sobel with replicate borders; products gx^2, gy^2, gx*gy.
+__global__ void k_sobel(const uint8_t* __restrict__ q, int H, int W, int* __restrict__ gxx,
+                        int* __restrict__ gyy, int* __restrict__ gxy) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= H * W) return;
+  int r = p / W, c = p - r * W;
+  int rm = clampi(r - 1, 0, H - 1), rp = clampi(r + 1, 0, H - 1);
+  int cm = clampi(c - 1, 0, W - 1), cp = clampi(c + 1, 0, W - 1);
+  auto Q = [&](int rr, int cc) { return (int)q[rr * W + cc]; };
+  int gx = (Q(rm, cp) + 2 * Q(r, cp) + Q(rp, cp)) - (Q(rm, cm) + 2 * Q(r, cm) + Q(rp, cm));
+  int gy = (Q(rp, cm) + 2 * Q(rp, c) + Q(rp, cp)) - (Q(rm, cm) + 2 * Q(rm, c) + Q(rm, cp));
+  gxx[p] = gx * gx;
+  gyy[p] = gy * gy;
+  gxy[p] = gx * gy;
+}
+
+// 5x5 binomial structure tensor (replicate borders) and R25 = 25 det - tr^2.
+__global__ void k_harris(const int* __restrict__ gxx, const int* __restrict__ gyy,
+                         const int* __restrict__ gxy, int H, int W, long long* __restrict__ r25) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= H * W) return;
+  int r = p / W, c = p - r * W;
+  const int w5[5] = {1, 4, 6, 4, 1};
+  int sxx = 0, syy = 0, sxy = 0;
+  for (int a = 0; a < 5; ++a) {
+    int rr = clampi(r + a - 2, 0, H - 1);
+    for (int b = 0; b < 5; ++b) {
+      int cc = clampi(c + b - 2, 0, W - 1);
+      int w = w5[a] * w5[b];
+      int i = rr * W + cc;
+      sxx += w * gxx[i];
+      syy += w * gyy[i];
+      sxy += w * gxy[i];
+    }
+  }
+  long long A = sxx, B = syy, X = sxy;
+  r25[p] = 25 * (A * B - X * X) - (A + B) * (A + B);
+}
+
+// 3x3 non-maximum suppression under (R25 desc, pixel index asc), neighbours
+// inside the image; flag per top-left grid position of a domain centre.
+__global__ void k_nms(const long long* __restrict__ R, int H, int W, int P, uint8_t* __restrict__ flag) {
+  const int o = (P - 1) / 2;
+  const int Hc = H - P + 1, Wc = W - P + 1;
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= Hc * Wc) return;
+  int gr = t / Wc, gc = t - gr * Wc;
+  int r = gr + o, c = gc + o;
+  long long v = R[(size_t)r * W + c];
+  bool keep = v > 0;
+  for (int dr = -1; dr <= 1; ++dr)
+    for (int dc = -1; dc <= 1; ++dc) {
+      if (dr == 0 && dc == 0) continue;
+      int rr = r + dr, cc = c + dc;
+      if (rr < 0 || rr >= H || cc < 0 || cc >= W) continue;
+      long long nb = R[(size_t)rr * W + cc];
+      bool earlier = dr < 0 || (dr == 0 && dc < 0);
+      keep = keep && (earlier ? (v > nb) : (v >= nb));
+    }
+  flag[t] = keep ? 1 : 0;
+}
+
+constexpr int SEL_T = 1024;
+
+__device__ long long block_sum_ll(long long v, long long* sh) {
+  v = wave_sum_i64(v);
+  if (lane_id() == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  long long s = 0;
+  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += sh[i];
+  __syncthreads();
+  return s;
+}
+
+// Single workgroup: ordered selection of the best N survivors by
+// (R25 desc, position asc), uniform raster fill, ascending key list.
+// `flag` holds the NMS survivors on entry and the chosen set on exit.
+__global__ void __launch_bounds__(SEL_T) k_select(uint8_t* __restrict__ flag,
+                                                  const long long* __restrict__ R, int H, int W,
+                                                  int P, int N, int32_t* __restrict__ slist,
+                                                  int32_t* __restrict__ keys, DevStats* st) {
+  __shared__ int scan_sh[SEL_T / 64 + 1];
+  __shared__ long long red_sh[SEL_T / 64];
+  const int o = (P - 1) / 2;
+  const int Hc = H - P + 1, Wc = W - P + 1;
+  const int Ncand = Hc * Wc;
+  const int tid = threadIdx.x;
+  auto score = [&](int t) {
+    int gr = t / Wc, gc = t - gr * Wc;
+    return R[(size_t)(gr + o) * W + gc + o];
+  };
+  // A. ordered list of survivors
+  int S = 0;
+  for (int base = 0; base < Ncand; base += SEL_T) {
+    int t = base + tid;
+    int f = (t < Ncand) ? flag[t] : 0;
+    int tot;
+    int pre = block_excl_scan(f, scan_sh, &tot);
+    if (f) slist[S + pre] = t;
+    S += tot;
+  }
+  __syncthreads();
+  // B. threshold: largest v with #(R >= v) >= N
+  long long vstar = 1;
+  int need_eq = 0;
+  if (S > N) {
+    long long mx = 0;
+    for (int i = tid; i < S; i += SEL_T) mx = max(mx, score(slist[i]));
+    for (int o2 = 32; o2 > 0; o2 >>= 1) mx = max(mx, (long long)__shfl_xor(mx, o2, 64));
+    if (lane_id() == 0) red_sh[tid >> 6] = mx;
+    __syncthreads();
+    long long mxa = 0;
+    for (int i = 0; i < SEL_T / 64; ++i) mxa = max(mxa, red_sh[i]);
+    __syncthreads();
+    long long lo = 1, hi = mxa;
+    while (lo < hi) {
+      long long mid = lo + (hi - lo + 1) / 2;
+      long long c = 0;
+      for (int i = tid; i < S; i += SEL_T) c += (score(slist[i]) >= mid) ? 1 : 0;
+      c = block_sum_ll(c, red_sh);
+      if (c >= N) lo = mid; else hi = mid - 1;
+    }
+    vstar = lo;
+    long long gt = 0;
+    for (int i = tid; i < S; i += SEL_T) gt += (score(slist[i]) > vstar) ? 1 : 0;
+    gt = block_sum_ll(gt, red_sh);
+    need_eq = N - (int)gt;
+    // C. drop survivors below the threshold and the surplus ties (highest positions)
+    int eq_seen = 0;
+    for (int base = 0; base < S; base += SEL_T) {
+      int i = base + tid;
+      long long v = (i < S) ? score(slist[i]) : 0;
+      int is_eq = (i < S && v == vstar) ? 1 : 0;
+      int tot;
+      int pre = block_excl_scan(is_eq, scan_sh, &tot);
+      if (i < S) {
+        bool sel = v > vstar || (is_eq && eq_seen + pre < need_eq);
+        if (!sel) flag[slist[i]] = 0;
+      }
+      eq_seen += tot;
+    }
+  }
+  const int n_sel = S < N ? S : N;
+  if (tid == 0 && st) st->keys_selected = n_sel;
+  __syncthreads();
+  // D. uniform raster fill (step s, then step 1) of positions not chosen
+  int need = N - n_sel;
+  if (need > 0) {
+    int s = 1;
+    while ((long long)s * s * N < (long long)Ncand) ++s;
+    for (int pass = 0; pass < 2 && need > 0; ++pass) {
+      int step = pass == 0 ? s : 1;
+      int nr = (Hc + step - 1) / step, nc = (Wc + step - 1) / step;
+      int tot_pos = nr * nc;
+      for (int base = 0; base < tot_pos && need > 0; base += SEL_T) {
+        int i = base + tid;
+        int t = -1;
+        if (i < tot_pos) t = (i / nc) * step * Wc + (i % nc) * step;
+        int cand = (t >= 0 && !flag[t]) ? 1 : 0;
+        int tot;
+        int pre = block_excl_scan(cand, scan_sh, &tot);
+        if (cand && pre < need) flag[t] = 1;
+        need -= tot < need ? tot : need;
+      }
+    }
+  }
+  __syncthreads();
+  // E. ascending key list
+  int n_out = 0;
+  for (int base = 0; base < Ncand; base += SEL_T) {
+    int t = base + tid;
+    int f = (t < Ncand) ? flag[t] : 0;
+    int tot;
+    int pre = block_excl_scan(f, scan_sh, &tot);
+    if (f && n_out + pre < N) keys[n_out + pre] = t;
+    n_out += tot;
+  }
+}
+
+}  // namespace
+
+void launch_detect(const glr_plan* pl, const float* xp, char* ws, int32_t* keys, hipStream_t s) {
+  const int H = pl->H, W = pl->W, HW = H * W;
+  uint8_t* q = (uint8_t*)(ws + pl->ws.q);
+  int* gxx = (int*)(ws + pl->ws.gxx);
+  int* gyy = (int*)(ws + pl->ws.gyy);
+  int* gxy = (int*)(ws + pl->ws.gxy);
+  long long* r25 = (long long*)(ws + pl->ws.r25);
+  uint8_t* flag = (uint8_t*)(ws + pl->ws.cflag);
+  int32_t* slist = (int32_t*)(ws + pl->ws.slist);
+  DevStats* st = (DevStats*)(ws + pl->ws.stats);
+  if (pl->is_complex) {
+    uint32_t* mx = (uint32_t*)(ws + pl->ws.red);
+    launch_fill_u32(mx, 0u, 1, s);
+    hipLaunchKernelGGL(k_mag2_max, dim3(nblk(HW)), dim3(TPB), 0, s, xp, HW, mx);
+    hipLaunchKernelGGL(k_quant_cplx, dim3(nblk(HW)), dim3(TPB), 0, s, xp, HW, mx, q);
+  } else {
+    hipLaunchKernelGGL(k_quant_real, dim3(nblk(HW)), dim3(TPB), 0, s, xp, pl->Cp, HW, q);
+  }
+  hipLaunchKernelGGL(k_sobel, dim3(nblk(HW)), dim3(TPB), 0, s, q, H, W, gxx, gyy, gxy);
+  hipLaunchKernelGGL(k_harris, dim3(nblk(HW)), dim3(TPB), 0, s, gxx, gyy, gxy, H, W, r25);
+  hipLaunchKernelGGL(k_nms, dim3(nblk((size_t)pl->Ncand)), dim3(TPB), 0, s, r25, H, W, pl->P, flag);
+  hipLaunchKernelGGL(k_select, dim3(1), dim3(SEL_T), 0, s, flag, r25, H, W, pl->P, pl->N, slist,
+                     keys, st);
+}

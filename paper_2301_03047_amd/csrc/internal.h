@@ -1,0 +1,116 @@
+// Host-side plan and the kernel launchers of libglr (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+#include <utility>
+#include <vector>
+
+#include "../../include/glr.h"
+
+// Device-side counters kept in the workspace.
+struct DevStats {
+  unsigned long long margin_sum;
+  unsigned long long steps;
+  int margin_max;
+  int overflow;
+  int sweeps_max;
+  int keys_selected;
+};
+
+// Byte offsets of the workspace buffers (all 256-aligned).
+struct WsLayout {
+  size_t xp, xo;                 // planar copies of input / output (complex data)
+  size_t q, gxx, gyy, gxy, r25;  // detector
+  size_t cflag, slist;           // detector candidate flags / survivor list
+  size_t keys;                   // detected keys [N]
+  size_t A, kmeta;               // key matrix [N][D] f32; key norms
+  size_t pnorm, prt;             // candidate norms, sqrt
+  size_t dist;                   // distance chunk [n_chunk][ldd]
+  size_t lj, lu, ll, lcnt;       // partial top-K lists
+  size_t idx, dd;                // groups [N][K], distances [N][K]
+  size_t xhat, sv;               // group estimates [N][K][D]; singular values
+  size_t pairs, offs;            // aggregation sort keys, CSR offsets
+  size_t cplx_a, cplx_b;         // complex scratch (FFT / ADMM)
+  size_t red;                    // small reduction scratch
+  size_t stats;                  // DevStats
+  size_t total;
+};
+
+struct glr_plan {
+  int modality, H, W, C, Cp, is_complex;
+  const uint8_t* mask;
+  int P, N, K, T, solver, precision, timing;
+  float rho, wnnm_c, wnnm_eps;
+  std::vector<float> sigma;
+  // derived sizes
+  int Hc, Wc, Ncand, D, ldd;
+  int n_chunk, n_split, split_len;
+  int M, M2;                      // aggregation entries (N*K) and power of two
+  WsLayout ws;
+  hipStream_t last_stream;
+  const void* stats_ws;           // workspace whose stats region is initialised
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;   // timing event pairs
+  std::vector<int> ev_stage;      // stage of each recorded pair
+  size_t ev_used;                 // pairs recorded since the last read
+  // host-side timing accumulators (ms)
+  double ms[8];
+  long long match_launches;
+};
+
+// list capacity of one top-K split (entries) and of the union per key
+#define GLR_SPLIT_CAP 1024
+#define GLR_UNION_CAP 4096
+
+// ------------------------------------------------------------------ launchers
+// ops.hip
+void launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
+void launch_count_step(DevStats* st, hipStream_t s);
+void launch_cacti_forward(const float* x, const uint8_t* m, float* y, int F, int HW, hipStream_t s);
+void launch_cacti_adjoint(const float* y, const uint8_t* m, float* x, int F, int HW, hipStream_t s);
+void launch_cacti_init(const float* y, const uint8_t* m, float* x, int F, int HW, hipStream_t s);
+void launch_cacti_gap(const float* x, const float* y, const uint8_t* m, float* xo, int F, int HW,
+                      hipStream_t s);
+void launch_msfa_forward(const float* x, float* y, int H, int W, hipStream_t s);
+void launch_msfa_adjoint(const float* y, float* x, int H, int W, hipStream_t s);
+void launch_msfa_init(const float* y, float* x, int H, int W, hipStream_t s);
+void launch_msfa_gap(const float* x, const float* y, float* xo, int H, int W, hipStream_t s);
+void launch_fft2d(const float2* in, float2* out, int H, int W, int inverse, hipStream_t s);
+void launch_kspace_mask(const float2* in, const uint8_t* lines, float2* out, int H, int W,
+                        hipStream_t s);
+void launch_cplx_axpby(const float2* a, const float2* b, float2* out, float alpha, float beta,
+                       int n, hipStream_t s);
+void launch_admm_kspace(const float2* y, const uint8_t* lines, const float2* fz, float2* out,
+                        float rho, int H, int W, hipStream_t s);
+void launch_admm_dual(float2* u, const float2* x, const float2* z, int n, hipStream_t s);
+void launch_to_planar(const float2* z, float* p, int n, hipStream_t s);
+void launch_from_planar(const float* p, float2* z, int n, hipStream_t s);
+
+// detect.hip
+void launch_detect(const glr_plan* pl, const float* xp, char* ws, int32_t* keys, hipStream_t s);
+
+// match.hip
+void launch_gather_keys(const glr_plan* pl, const float* xp, const int32_t* keys, float* A,
+                        float* kmeta, hipStream_t s);
+void launch_cand_norms(const glr_plan* pl, const float* xp, float* pnorm, float* prt,
+                       hipStream_t s);
+void launch_match_f32(const glr_plan* pl, const float* xp, const float* A, const float* kmeta,
+                      const float* pnorm, int g0, int nk, float* dist, hipStream_t s);
+
+// topk.hip
+void launch_topk_partial(const glr_plan* pl, const float* dist, const float* kmeta,
+                         const float* prt, int g0, int nk, int32_t* lj, float* lu, float* ll,
+                         int32_t* lcnt, hipStream_t s);
+void launch_select_rescore(const glr_plan* pl, const float* xp, const float* A, int g0, int nk,
+                           const int32_t* lj, const float* lu, const float* ll,
+                           const int32_t* lcnt, int32_t* idx, float* dd, DevStats* st,
+                           hipStream_t s);
+
+// lowrank.hip
+void launch_wnnm(const glr_plan* pl, const float* xp, const int32_t* idx, float sigma,
+                 float* xhat, float* sv, DevStats* st, hipStream_t s);
+
+// aggregate.hip
+void launch_aggregate(const glr_plan* pl, const float* xbar, const int32_t* idx,
+                      const float* xhat, unsigned long long* pairs, int32_t* offs, float* out,
+                      hipStream_t s);

@@ -1,0 +1,310 @@
+// Sensing operators and data-fidelity updates (eq. 2-5; GAP / ADMM).
+// All kernels are elementwise or per-row/per-column and bound by HBM traffic.
+#include "common.h"
+#include "internal.h"
+
+namespace {
+
+constexpr int TPB = 256;
+
+inline int nblk(size_t n, int tpb = TPB) { return (int)((n + tpb - 1) / tpb); }
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_count_step(DevStats* st) { st->steps += 1; }
+
+// ---------------------------------------------------------------- CACTI (eq. 2)
+// y = sum_t A_t x_t, summed in frame order.
+__global__ void k_cacti_forward(const float* __restrict__ x, const uint8_t* __restrict__ m,
+                                float* __restrict__ y, int F, int HW) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= HW) return;
+  float acc = 0.f;
+  for (int t = 0; t < F; ++t)
+    if (m[(size_t)t * HW + p]) acc += x[(size_t)t * HW + p];
+  y[p] = acc;
+}
+
+__global__ void k_cacti_adjoint(const float* __restrict__ y, const uint8_t* __restrict__ m,
+                                float* __restrict__ x, int F, int HW) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= HW) return;
+  float v = y[p];
+  for (int t = 0; t < F; ++t) x[(size_t)t * HW + p] = m[(size_t)t * HW + p] ? v : 0.f;
+}
+
+// x0 = Phi^T (y / R~), R = sum_t A_t, zeros of R replaced by 1.
+__global__ void k_cacti_init(const float* __restrict__ y, const uint8_t* __restrict__ m,
+                             float* __restrict__ x, int F, int HW) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= HW) return;
+  int R = 0;
+  for (int t = 0; t < F; ++t) R += m[(size_t)t * HW + p] ? 1 : 0;
+  float v = y[p] / (float)(R ? R : 1);
+  for (int t = 0; t < F; ++t) x[(size_t)t * HW + p] = m[(size_t)t * HW + p] ? v : 0.f;
+}
+
+// GAP: x_bar = x + Phi^T((y - Phi x) / R~).  In-place safe.
+__global__ void k_cacti_gap(const float* x, const float* __restrict__ y,
+                            const uint8_t* __restrict__ m, float* xo, int F, int HW) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= HW) return;
+  float phi = 0.f;
+  int R = 0;
+  for (int t = 0; t < F; ++t)
+    if (m[(size_t)t * HW + p]) {
+      phi += x[(size_t)t * HW + p];
+      ++R;
+    }
+  float upd = (y[p] - phi) / (float)(R ? R : 1);
+  for (int t = 0; t < F; ++t) {
+    size_t i = (size_t)t * HW + p;
+    xo[i] = x[i] + (m[i] ? upd : 0.f);
+  }
+}
+
+// ---------------------------------------------------------------- MSFA (eq. 4-5)
+__device__ __forceinline__ int msfa_band(int r, int c) { return 4 * (r & 3) + (c & 3); }
+
+__global__ void k_msfa_forward(const float* __restrict__ x, float* __restrict__ y, int H, int W) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= H * W) return;
+  int r = p / W, c = p - r * W;
+  y[p] = x[(size_t)msfa_band(r, c) * H * W + p];
+}
+
+__global__ void k_msfa_adjoint(const float* __restrict__ y, float* __restrict__ x, int H, int W) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= H * W) return;
+  int r = p / W, c = p - r * W;
+  int b = msfa_band(r, c);
+  float v = y[p];
+  for (int k = 0; k < 16; ++k) x[(size_t)k * H * W + p] = (k == b) ? v : 0.f;
+}
+
+// Replication start: band b = 4*rb + cb takes the sample at (rb, cb) of each 4x4 cell.
+__global__ void k_msfa_init(const float* __restrict__ y, float* __restrict__ x, int H, int W) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= H * W) return;
+  int r = p / W, c = p - r * W;
+  int r0 = r & ~3, c0 = c & ~3;
+  for (int b = 0; b < 16; ++b) x[(size_t)b * H * W + p] = y[(r0 + (b >> 2)) * W + c0 + (b & 3)];
+}
+
+// GAP with Phi Phi^T = I: only the measured band of each pixel moves.
+__global__ void k_msfa_gap(const float* x, const float* __restrict__ y, float* xo, int H, int W) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= H * W) return;
+  int r = p / W, c = p - r * W;
+  int b = msfa_band(r, c);
+  for (int k = 0; k < 16; ++k) {
+    size_t i = (size_t)k * H * W + p;
+    float v = x[i];
+    xo[i] = (k == b) ? v + (y[p] - v) : v;
+  }
+}
+
+// ---------------------------------------------------------------- FFT (eq. 3)
+// Radix-2 Stockham autosort FFT in LDS.  Twiddles exp(-+2 pi i k / n) from
+// sincospif on exact dyadic arguments.
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// One workgroup per row of length n (power of two).
+__global__ void k_fft_rows(const float2* in, float2* out, int n,
+                           int inverse, float scale) {
+  extern __shared__ float2 sm[];
+  float2* a = sm;
+  float2* b = sm + n;
+  float2* tw = sm + 2 * n;
+  const size_t row = blockIdx.x;
+  const int half = n >> 1;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) a[i] = in[row * n + i];
+  for (int i = threadIdx.x; i < half; i += blockDim.x) {
+    float s, c;
+    sincospif(-2.0f * (float)i / (float)n, &s, &c);
+    tw[i] = make_float2(c, inverse ? -s : s);
+  }
+  __syncthreads();
+  for (int ns = 1; ns < n; ns <<= 1) {
+    const int tstride = n / (2 * ns);
+    for (int j = threadIdx.x; j < half; j += blockDim.x) {
+      int k = j & (ns - 1);
+      float2 x0 = a[j];
+      float2 x1 = cmul(a[j + half], tw[k * tstride]);
+      int o = ((j - k) << 1) + k;
+      b[o] = make_float2(x0.x + x1.x, x0.y + x1.y);
+      b[o + ns] = make_float2(x0.x - x1.x, x0.y - x1.y);
+    }
+    __syncthreads();
+    float2* t = a;
+    a = b;
+    b = t;
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    out[row * n + i] = make_float2(a[i].x * scale, a[i].y * scale);
+}
+
+// One workgroup per `cb` adjacent columns of an n-row array with row stride W.
+__global__ void k_fft_cols(float2* data, int n, int W, int cb, int inverse, float scale) {
+  extern __shared__ float2 sm[];
+  float2* a = sm;
+  float2* b = sm + (size_t)n * cb;
+  float2* tw = sm + (size_t)2 * n * cb;
+  const int c0 = blockIdx.x * cb;
+  const int half = n >> 1;
+  for (int t = threadIdx.x; t < n * cb; t += blockDim.x) {
+    int r = t / cb, cc = t - r * cb;
+    a[t] = data[(size_t)r * W + c0 + cc];
+  }
+  for (int i = threadIdx.x; i < half; i += blockDim.x) {
+    float s, c;
+    sincospif(-2.0f * (float)i / (float)n, &s, &c);
+    tw[i] = make_float2(c, inverse ? -s : s);
+  }
+  __syncthreads();
+  for (int ns = 1; ns < n; ns <<= 1) {
+    const int tstride = n / (2 * ns);
+    for (int t = threadIdx.x; t < half * cb; t += blockDim.x) {
+      int j = t / cb, cc = t - j * cb;
+      int k = j & (ns - 1);
+      float2 x0 = a[j * cb + cc];
+      float2 x1 = cmul(a[(j + half) * cb + cc], tw[k * tstride]);
+      int o = ((j - k) << 1) + k;
+      b[o * cb + cc] = make_float2(x0.x + x1.x, x0.y + x1.y);
+      b[(o + ns) * cb + cc] = make_float2(x0.x - x1.x, x0.y - x1.y);
+    }
+    __syncthreads();
+    float2* t = a;
+    a = b;
+    b = t;
+  }
+  for (int t = threadIdx.x; t < n * cb; t += blockDim.x) {
+    int r = t / cb, cc = t - r * cb;
+    data[(size_t)r * W + c0 + cc] = make_float2(a[t].x * scale, a[t].y * scale);
+  }
+}
+
+__global__ void k_kspace_mask(const float2* __restrict__ in, const uint8_t* __restrict__ lines,
+                              float2* __restrict__ out, int H, int W) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= H * W) return;
+  out[p] = lines[p / W] ? in[p] : make_float2(0.f, 0.f);
+}
+
+__global__ void k_cplx_axpby(const float2* a, const float2* b, float2* out, float alpha,
+                             float beta, int n) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  float2 u = a[p], v = b[p];
+  out[p] = make_float2(alpha * u.x + beta * v.x, alpha * u.y + beta * v.y);
+}
+
+// k-space part of the ADMM x-update: (M y + rho F(z - u)) / (M + rho).
+__global__ void k_admm_kspace(const float2* __restrict__ y, const uint8_t* __restrict__ lines,
+                              const float2* fz, float2* out, float rho, int H, int W) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= H * W) return;
+  const bool m = lines[p / W] != 0;
+  float2 f = fz[p];
+  float2 yy = m ? y[p] : make_float2(0.f, 0.f);
+  float den = (m ? 1.f : 0.f) + rho;
+  out[p] = make_float2((yy.x + rho * f.x) / den, (yy.y + rho * f.y) / den);
+}
+
+// u <- u + x - z
+__global__ void k_admm_dual(float2* u, const float2* __restrict__ x, const float2* __restrict__ z,
+                            int n) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  float2 a = u[p], b = x[p], c = z[p];
+  u[p] = make_float2((a.x + b.x) - c.x, (a.y + b.y) - c.y);
+}
+
+__global__ void k_to_planar(const float2* __restrict__ z, float* __restrict__ p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float2 v = z[i];
+  p[i] = v.x;
+  p[n + i] = v.y;
+}
+
+__global__ void k_from_planar(const float* __restrict__ p, float2* __restrict__ z, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  z[i] = make_float2(p[i], p[n + i]);
+}
+
+}  // namespace
+
+void launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_fill_u32, dim3(nblk(n)), dim3(TPB), 0, s, p, v, n);
+}
+void launch_count_step(DevStats* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_count_step, dim3(1), dim3(1), 0, s, st);
+}
+void launch_cacti_forward(const float* x, const uint8_t* m, float* y, int F, int HW, hipStream_t s) {
+  hipLaunchKernelGGL(k_cacti_forward, dim3(nblk(HW)), dim3(TPB), 0, s, x, m, y, F, HW);
+}
+void launch_cacti_adjoint(const float* y, const uint8_t* m, float* x, int F, int HW, hipStream_t s) {
+  hipLaunchKernelGGL(k_cacti_adjoint, dim3(nblk(HW)), dim3(TPB), 0, s, y, m, x, F, HW);
+}
+void launch_cacti_init(const float* y, const uint8_t* m, float* x, int F, int HW, hipStream_t s) {
+  hipLaunchKernelGGL(k_cacti_init, dim3(nblk(HW)), dim3(TPB), 0, s, y, m, x, F, HW);
+}
+void launch_cacti_gap(const float* x, const float* y, const uint8_t* m, float* xo, int F, int HW,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_cacti_gap, dim3(nblk(HW)), dim3(TPB), 0, s, x, y, m, xo, F, HW);
+}
+void launch_msfa_forward(const float* x, float* y, int H, int W, hipStream_t s) {
+  hipLaunchKernelGGL(k_msfa_forward, dim3(nblk((size_t)H * W)), dim3(TPB), 0, s, x, y, H, W);
+}
+void launch_msfa_adjoint(const float* y, float* x, int H, int W, hipStream_t s) {
+  hipLaunchKernelGGL(k_msfa_adjoint, dim3(nblk((size_t)H * W)), dim3(TPB), 0, s, y, x, H, W);
+}
+void launch_msfa_init(const float* y, float* x, int H, int W, hipStream_t s) {
+  hipLaunchKernelGGL(k_msfa_init, dim3(nblk((size_t)H * W)), dim3(TPB), 0, s, y, x, H, W);
+}
+void launch_msfa_gap(const float* x, const float* y, float* xo, int H, int W, hipStream_t s) {
+  hipLaunchKernelGGL(k_msfa_gap, dim3(nblk((size_t)H * W)), dim3(TPB), 0, s, x, y, xo, H, W);
+}
+
+// Orthonormal 2-D DFT: rows then columns, each scaled by 1/sqrt(length).
+void launch_fft2d(const float2* in, float2* out, int H, int W, int inverse, hipStream_t s) {
+  size_t lds_r = (size_t)(2 * W + W / 2) * sizeof(float2);
+  hipLaunchKernelGGL(k_fft_rows, dim3(H), dim3(TPB), lds_r, s, in, out, W, inverse,
+                     1.0f / sqrtf((float)W));
+  int cb = 1;
+  while (cb * 2 <= 16 && (size_t)(cb * 2) * H * 2 * sizeof(float2) + (size_t)H / 2 * sizeof(float2) <= 48 * 1024 &&
+         W % (cb * 2) == 0)
+    cb *= 2;
+  size_t lds_c = ((size_t)2 * H * cb + H / 2) * sizeof(float2);
+  hipLaunchKernelGGL(k_fft_cols, dim3(W / cb), dim3(TPB), lds_c, s, out, H, W, cb, inverse,
+                     1.0f / sqrtf((float)H));
+}
+void launch_kspace_mask(const float2* in, const uint8_t* lines, float2* out, int H, int W,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_kspace_mask, dim3(nblk((size_t)H * W)), dim3(TPB), 0, s, in, lines, out, H, W);
+}
+void launch_cplx_axpby(const float2* a, const float2* b, float2* out, float alpha, float beta,
+                       int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_cplx_axpby, dim3(nblk(n)), dim3(TPB), 0, s, a, b, out, alpha, beta, n);
+}
+void launch_admm_kspace(const float2* y, const uint8_t* lines, const float2* fz, float2* out,
+                        float rho, int H, int W, hipStream_t s) {
+  hipLaunchKernelGGL(k_admm_kspace, dim3(nblk((size_t)H * W)), dim3(TPB), 0, s, y, lines, fz, out,
+                     rho, H, W);
+}
+void launch_admm_dual(float2* u, const float2* x, const float2* z, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_admm_dual, dim3(nblk(n)), dim3(TPB), 0, s, u, x, z, n);
+}
+void launch_to_planar(const float2* z, float* p, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_planar, dim3(nblk(n)), dim3(TPB), 0, s, z, p, n);
+}
+void launch_from_planar(const float* p, float2* z, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_from_planar, dim3(nblk(n)), dim3(TPB), 0, s, p, z, n);
+}

@@ -1,0 +1,192 @@
+"""GPU parity of every step of the GLR prior step against the CPU oracle,
+through the C ABI.  Same FP32 inputs on both sides (the oracle upcasts
+exactly).  Bar: keys and groups bit-exact (up to certified numerical ties,
+see gpu_util.check_groups), images and singular values within 1e-5 relative."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2301_03047_amd as glr
+import synth
+from synth.workloads import random_image
+from oracle import detector as odet, matching as om, lowrank as olr, aggregate as oag
+from oracle import prior as opr, metrics
+from gpu_util import require_gpu, gpu, host, planar, ones_mask, check_groups, WNNM_C, WNNM_EPS
+
+pytestmark = pytest.mark.gpu
+
+
+def _plan(C, H, W, P, N, K, **kw):
+    return glr.Plan("cacti", H, W, C, P, N, K, mask=ones_mask(C, H, W), **kw)
+
+
+MATCH_CASES = [
+    # C, H, W, P, N, K, kind          (ragged key tiles / candidate tiles / odd P)
+    (2, 12, 12, 3, 5, 5, "uniform"),
+    (2, 21, 150, 3, 17, 5, "smooth"),
+    (8, 40, 41, 6, 130, 32, "smooth"),
+    (3, 37, 29, 7, 50, 64, "uniform"),
+    (1, 64, 300, 5, 257, 45, "smooth"),
+    (2, 30, 30, 1, 40, 9, "uniform"),
+    (1, 40, 40, 16, 20, 8, "smooth"),
+    (4, 24, 24, 4, 30, 11, "dup"),
+]
+
+
+@pytest.mark.parametrize("case", MATCH_CASES, ids=lambda c: "x".join(map(str, c[:6])) + c[6])
+def test_match_topk_vs_oracle(case):
+    require_gpu()
+    C, H, W, P, N, K, kind = case
+    print("case", case, flush=True)
+    x = random_image(C, H, W, seed=H * W + P, kind=kind)
+    n_cand = (H - P + 1) * (W - P + 1)
+    keys = np.sort(np.random.default_rng(7).choice(n_cand, size=N, replace=False))
+    plan = _plan(C, H, W, P, N, K)
+    idx, dist = plan.match_topk(gpu(x), gpu(keys.astype(np.int32)))
+    idx, dist = host(idx), host(dist)
+    ref_idx, ref_dist = om.topk_exact(x.astype(np.float64), P, keys, K)
+    ties = check_groups(x.astype(np.float64), P, keys, idx, ref_idx)
+    assert ties == 0, f"{ties} numerical-tie rows"
+    np.testing.assert_allclose(dist, ref_dist, rtol=1e-6, atol=1e-30)
+
+
+def test_match_topk_small_chunks_and_splits():
+    # force several distance chunks (1 MiB) and many splits
+    require_gpu()
+    C, H, W, P, N, K = 3, 64, 200, 5, 300, 20
+    x = random_image(C, H, W, seed=3, kind="smooth")
+    keys = np.arange(0, N * 37, 37)
+    plan = _plan(C, H, W, P, N, K, dist_chunk_mb=1)
+    idx, _ = plan.match_topk(gpu(x), gpu(keys.astype(np.int32)))
+    ref, _ = om.topk_exact(x.astype(np.float64), P, keys, K)
+    assert check_groups(x.astype(np.float64), P, keys, host(idx), ref) == 0
+
+
+def test_match_topk_constant_image_exact_path():
+    # every distance is exactly 0: the certified margin holds every candidate,
+    # the exact full-row path runs and ties resolve to the lowest positions
+    require_gpu()
+    C, H, W, P, N, K = 2, 40, 50, 4, 6, 10
+    x = np.full((C, H, W), 0.3, dtype=np.float32)
+    keys = np.array([0, 5, 100, 500, 900, 1300])
+    plan = _plan(C, H, W, P, N, K)
+    idx, dist = plan.match_topk(gpu(x), gpu(keys.astype(np.int32)))
+    st = plan.read_stats()
+    np.testing.assert_array_equal(host(idx), np.tile(np.arange(K), (N, 1)))
+    assert np.all(host(dist) == 0)
+    assert st["overflow_keys"] == N
+
+
+def test_detect_keys_real_vs_oracle():
+    require_gpu()
+    for (C, H, W, P, N, kind, seed) in [(1, 20, 23, 4, 9, "uniform", 1), (8, 128, 128, 6, 128, "scene", 0),
+                                         (3, 50, 61, 5, 400, "smooth", 2), (2, 16, 16, 3, 50, "const", 0)]:
+        print("detect", C, H, W, P, N, kind, flush=True)
+        if kind == "scene":
+            x = synth.make_instance(synth.WORKLOADS["cacti_128"])["x_true"]
+        elif kind == "const":
+            x = np.full((C, H, W), 0.25, np.float32)
+        else:
+            x = random_image(C, H, W, seed=seed, kind=kind)
+        plan = _plan(C, H, W, P, N, 4)
+        keys = host(plan.detect_keys(gpu(x)))
+        ref = odet.detect_keys(x, P, N)
+        np.testing.assert_array_equal(keys, ref)
+
+
+def test_detect_keys_complex_vs_oracle():
+    require_gpu()
+    wl = synth.WORKLOADS["mri_256"]
+    inst = synth.make_instance(wl)
+    z = inst["x_true"]
+    plan = glr.Plan("mri", wl.H, wl.W, 1, wl.patch, wl.n_keys, wl.k, mask=gpu(inst["mask"]))
+    keys = host(plan.detect_keys(gpu(z)))
+    ref = odet.detect_keys(planar(z), wl.patch, wl.n_keys, is_complex=True)
+    np.testing.assert_array_equal(keys, ref)
+
+
+@pytest.mark.parametrize("shape", [(8, 40, 40, 6, 60, 32), (2, 30, 33, 5, 40, 45),
+                                   (16, 32, 32, 6, 20, 64), (1, 20, 20, 3, 10, 1)])
+def test_lowrank_aggregate_vs_oracle(shape):
+    require_gpu()
+    C, H, W, P, N, K = shape
+    print("lowrank", shape, flush=True)
+    x = random_image(C, H, W, seed=C + H, kind="smooth")
+    x64 = x.astype(np.float64)
+    keys = odet.detect_keys(x, P, N)
+    idx, _ = om.topk_exact(x64, P, keys, K)
+    sigma = 0.05
+    plan = _plan(C, H, W, P, N, K)
+    out, sv = plan.lowrank_aggregate(gpu(x), gpu(idx.astype(np.int32)), sigma, want_sv=True)
+    Xhat, sv_ref = olr.shrink_groups(x64, P, idx, sigma, WNNM_C, WNNM_EPS)
+    ref, _ = oag.aggregate(x64, P, idx, Xhat)
+    err = metrics.rel_l2(host(out), ref)
+    assert err <= 1e-5, err
+    svg = host(sv)[:, :sv_ref.shape[1]]
+    assert np.abs(svg - sv_ref).max() <= 1e-5 * sv_ref.max()
+
+
+def test_identity_shrink_returns_input_exactly():
+    require_gpu()
+    C, H, W, P, N, K = 3, 30, 30, 4, 40, 12
+    x = (np.random.default_rng(3).integers(0, 256, size=(C, H, W)) / 256.0).astype(np.float32)
+    plan = _plan(C, H, W, P, N, K)
+    out = plan.prior_step(gpu(x), 0.0)
+    np.testing.assert_array_equal(host(out), x)
+
+
+def test_prior_step_cacti_iterate_vs_oracle():
+    require_gpu()
+    wl = synth.WORKLOADS["cacti_128"]
+    inst = synth.make_instance(wl)
+    m = inst["mask"]
+    from oracle import operators as ops
+    y = ops.cacti_forward(inst["x_true"].astype(np.float64), m)
+    R = ops.cacti_mask_sum(m)
+    x0 = ops.cacti_adjoint(y / np.where(R == 0, 1, R), m)
+    xb = ops.gap_update(x0, y, lambda v: ops.cacti_forward(v, m), lambda r: ops.cacti_adjoint(r, m), R)
+    x = xb.astype(np.float32)
+    sigma = float(synth.sigma_schedule(wl)[0])
+    plan = glr.Plan("cacti", wl.H, wl.W, wl.C, wl.patch, wl.n_keys, wl.k, mask=gpu(m))
+    xg = gpu(x)
+    keys = host(plan.detect_keys(xg))
+    idx, _ = plan.match_topk(xg, gpu(keys))
+    out = host(plan.prior_step(xg, sigma))
+    ref = opr.prior_step(x.astype(np.float64), wl.patch, wl.n_keys, wl.k, sigma, WNNM_C, WNNM_EPS)
+    np.testing.assert_array_equal(keys, ref["keys"])
+    assert check_groups(x.astype(np.float64), wl.patch, keys, host(idx), ref["idx"]) == 0
+    err = metrics.rel_l2(out, ref["x_out"])
+    assert err <= 1e-5, err
+    st = plan.read_stats()
+    print("stats", st)
+
+
+def test_prior_step_mri_full_size_vs_oracle():
+    require_gpu()
+    wl = synth.WORKLOADS["mri_256"]
+    inst = synth.make_instance(wl)
+    rng = np.random.default_rng(5)
+    z = (inst["x_true"] + 0.03 * (rng.standard_normal((wl.H, wl.W)) + 1j * rng.standard_normal((wl.H, wl.W)))).astype(np.complex64)
+    sigma = 0.03
+    plan = glr.Plan("mri", wl.H, wl.W, 1, wl.patch, wl.n_keys, wl.k, mask=gpu(inst["mask"]))
+    zg = gpu(z)
+    keys = host(plan.detect_keys(zg))
+    idx, dist = plan.match_topk(zg, gpu(keys))
+    out = host(plan.prior_step(zg, sigma))
+    ref = opr.prior_step(planar(z), wl.patch, wl.n_keys, wl.k, sigma, WNNM_C, WNNM_EPS, is_complex=True)
+    np.testing.assert_array_equal(keys, ref["keys"])
+    ties = check_groups(planar(z), wl.patch, keys, host(idx), ref["idx"])
+    assert ties == 0, ties
+    err = metrics.rel_l2(out, opr.from_planar(ref["x_out"]))
+    assert err <= 1e-5, err
+    print("stats", plan.read_stats())
+
+
+def test_prior_step_deterministic():
+    require_gpu()
+    C, H, W, P, N, K = 8, 64, 64, 6, 100, 32
+    x = random_image(C, H, W, seed=9, kind="smooth")
+    plan = _plan(C, H, W, P, N, K)
+    a = host(plan.prior_step(gpu(x), 0.04))
+    b = host(plan.prior_step(gpu(x), 0.04))
+    np.testing.assert_array_equal(a, b)
