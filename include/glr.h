@@ -99,6 +99,7 @@ typedef struct glr_stats {
   float ms_detect, ms_match, ms_topk, ms_select, ms_lowrank, ms_aggregate, ms_data;
   float ms_norms;             /* key gather and candidate norms                  */
   int64_t match_launches;     /* matcher kernel launches timed in ms_match       */
+  int64_t jacobi_sweeps_sum;  /* Jacobi sweeps summed over all groups            */
 } glr_stats;
 
 typedef struct glr_plan glr_plan;

@@ -97,27 +97,30 @@ __global__ void k_offsets(const unsigned long long* __restrict__ keys, int M, in
   offs[t] = lo;
 }
 
-constexpr int CB = 8;             // channels per gather thread
+constexpr int CB = 8;             // channels per gather block
+constexpr int GX = 64;            // pixels per gather block (one image row segment)
 
+// One thread per (pixel, dy): sums the estimates of the patches whose top
+// row covers the pixel at offset dy, over dx and the CSR bucket; the P
+// partial sums of a pixel are then added in dy order (fixed order).
 __global__ void k_gather(const float* __restrict__ xbar, const float* __restrict__ xhat,
                          const unsigned long long* __restrict__ keys,
                          const int32_t* __restrict__ offs, int Cp, int H, int W, int P, int D,
-                         float* __restrict__ out) {
-  const int HW = H * W;
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  const int cb = blockIdx.y;
-  if (p >= HW) return;
-  const int r = p / W, c = p - r * W;
+                         int K, float* __restrict__ out) {
+  extern __shared__ float part[];          // [P][GX][CB + 1]
+  const int tx = threadIdx.x, dy = threadIdx.y;
+  const int r = blockIdx.y;
+  const int c = blockIdx.x * GX + tx;
+  const int cb = blockIdx.z;
   const int Hc = H - P + 1, Wc = W - P + 1;
   const int PP = P * P;
+  const int nch = min(CB, Cp - cb * CB);
   float acc[CB];
 #pragma unroll
   for (int u = 0; u < CB; ++u) acc[u] = 0.f;
   int cnt = 0;
-  const int nch = min(CB, Cp - cb * CB);
-  for (int dy = 0; dy < P; ++dy) {
-    const int gr = r - dy;
-    if (gr < 0 || gr >= Hc) continue;
+  const int gr = r - dy;
+  if (c < W && gr >= 0 && gr < Hc) {
     for (int dx = 0; dx < P; ++dx) {
       const int gc = c - dx;
       if (gc < 0 || gc >= Wc) continue;
@@ -125,17 +128,37 @@ __global__ void k_gather(const float* __restrict__ xbar, const float* __restrict
       const int a = offs[t], b = offs[t + 1];
       cnt += b - a;
       for (int i = a; i < b; ++i) {
-        const size_t e = (size_t)(uint32_t)(keys[i] & 0xffffffffull);
-        const float* src = xhat + e * D + (size_t)(cb * CB) * PP + dy * P + dx;
+        // entry e = g*K + j; estimates are d-major per group: xhat[(g*D + d)*K + j]
+        const uint32_t e = (uint32_t)(keys[i] & 0xffffffffull);
+        const uint32_t g = e / (uint32_t)K, j = e - g * (uint32_t)K;
+        const float* src = xhat + ((size_t)g * D + (size_t)(cb * CB) * PP + dy * P + dx) * K + j;
 #pragma unroll
         for (int u = 0; u < CB; ++u)
-          if (u < nch) acc[u] += src[(size_t)u * PP];
+          if (u < nch) acc[u] += src[(size_t)u * PP * K];
       }
     }
   }
-  for (int u = 0; u < nch; ++u) {
-    const size_t o = (size_t)(cb * CB + u) * HW + p;
-    out[o] = cnt ? acc[u] / (float)cnt : xbar[o];
+  float* mine = part + ((size_t)dy * GX + tx) * (CB + 1);
+#pragma unroll
+  for (int u = 0; u < CB; ++u) mine[u] = acc[u];
+  mine[CB] = __int_as_float(cnt);
+  __syncthreads();
+  if (dy == 0 && c < W) {
+    float sum[CB];
+#pragma unroll
+    for (int u = 0; u < CB; ++u) sum[u] = 0.f;
+    int n = 0;
+    for (int y = 0; y < P; ++y) {
+      const float* pp = part + ((size_t)y * GX + tx) * (CB + 1);
+#pragma unroll
+      for (int u = 0; u < CB; ++u) sum[u] += pp[u];
+      n += __float_as_int(pp[CB]);
+    }
+    const size_t HW = (size_t)H * W;
+    for (int u = 0; u < nch; ++u) {
+      const size_t o = (size_t)(cb * CB + u) * HW + (size_t)r * W + c;
+      out[o] = n ? sum[u] / (float)n : xbar[o];
+    }
   }
 }
 
@@ -155,8 +178,8 @@ void launch_aggregate(const glr_plan* pl, const float* xbar, const int32_t* idx,
   }
   hipLaunchKernelGGL(k_offsets, dim3((pl->Ncand + 1 + 255) / 256), dim3(256), 0, s, pairs, M,
                      pl->Ncand, offs);
-  const int HW = pl->H * pl->W;
-  dim3 grid((HW + 255) / 256, (pl->Cp + CB - 1) / CB);
-  hipLaunchKernelGGL(k_gather, grid, dim3(256), 0, s, xbar, xhat, pairs, offs, pl->Cp, pl->H,
-                     pl->W, pl->P, pl->D, out);
+  dim3 grid((pl->W + GX - 1) / GX, pl->H, (pl->Cp + CB - 1) / CB);
+  const size_t lds = (size_t)pl->P * GX * (CB + 1) * sizeof(float);
+  hipLaunchKernelGGL(k_gather, grid, dim3(GX, pl->P), lds, s, xbar, xhat, pairs, offs, pl->Cp,
+                     pl->H, pl->W, pl->P, pl->D, pl->K, out);
 }

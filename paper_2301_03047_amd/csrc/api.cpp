@@ -121,6 +121,7 @@ glr_status match_stage(glr_plan* pl, const float* xp, const int32_t* keys, int32
   float* lu = (float*)(ws + pl->ws.lu);
   float* ll = (float*)(ws + pl->ws.ll);
   int32_t* lcnt = (int32_t*)(ws + pl->ws.lcnt);
+  int32_t* oflag = (int32_t*)(ws + pl->ws.oflag);
   DevStats* st = (DevStats*)(ws + pl->ws.stats);
   {
     StageTimer t(pl, s, T_NORMS);
@@ -140,7 +141,7 @@ glr_status match_stage(glr_plan* pl, const float* xp, const int32_t* keys, int32
     }
     {
       StageTimer t(pl, s, T_SELECT);
-      launch_select_rescore(pl, xp, A, g0, nk, lj, lu, ll, lcnt, idx_out, dd_out, st, s);
+      launch_select_rescore(pl, xp, A, g0, nk, lj, lu, ll, lcnt, idx_out, dd_out, oflag, st, s);
     }
   }
   return check_hip("glr_match_topk");
@@ -250,8 +251,8 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
     return fail(GLR_ERR_INVALID_ARG, "unknown modality %d", pb->modality);
   if (pb->H <= 0 || pb->W <= 0 || pb->C <= 0)
     return fail(GLR_ERR_SHAPE, "image size must be positive (H=%d W=%d C=%d)", pb->H, pb->W, pb->C);
-  if ((long long)pb->H * pb->W > (1LL << 26))
-    return fail(GLR_ERR_UNSUPPORTED, "image larger than 2^26 pixels");
+  if (pb->H > 65535 || pb->W > 65535 || (long long)pb->H * pb->W > (1LL << 26))
+    return fail(GLR_ERR_UNSUPPORTED, "image side > 65535 or more than 2^26 pixels");
   const int P = pr->patch;
   if (P < 1 || P > std::min(pb->H, pb->W))
     return fail(GLR_ERR_SHAPE, "patch %d must be in [1, min(H, W)]", P);
@@ -343,6 +344,7 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
   L.r25 = c.take(HW * 8);
   L.cflag = c.take((size_t)Ncand);
   L.slist = c.take((size_t)Ncand * 4);
+  L.sval = c.take((size_t)Ncand * 8);
   L.keys = c.take((size_t)pl->N * 4);
   L.A = c.take((size_t)pl->N * D * 4);
   L.kmeta = c.take((size_t)pl->N * 8);
@@ -354,6 +356,7 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
   L.lu = c.take(nlist * GLR_SPLIT_CAP * 4);
   L.ll = c.take(nlist * GLR_SPLIT_CAP * 4);
   L.lcnt = c.take(nlist * 4);
+  L.oflag = c.take((size_t)pl->n_chunk * 4);
   L.idx = c.take((size_t)pl->M * 4);
   L.dd = c.take((size_t)pl->M * 4);
   L.xhat = c.take((size_t)pl->M * D * 4);
@@ -611,6 +614,7 @@ glr_status glr_read_stats(glr_plan* pl, glr_stats* out, int32_t reset) {
     out->margin_max = d.margin_max;
     out->overflow_keys = d.overflow;
     out->jacobi_sweeps_max = d.sweeps_max;
+    out->jacobi_sweeps_sum = (int64_t)d.sweeps_sum;
     out->keys_selected = d.keys_selected;
     if (reset) {
       launch_fill_u32((uint32_t*)((char*)pl->stats_ws + pl->ws.stats), 0u, sizeof(DevStats) / 4,

@@ -126,15 +126,39 @@ __global__ void k_nms(const long long* __restrict__ R, int H, int W, int P, uint
 }
 
 constexpr int SEL_T = 1024;
+constexpr int RUN = 16;           // consecutive positions per thread per scan step
 
-__device__ long long block_sum_ll(long long v, long long* sh) {
-  v = wave_sum_i64(v);
-  if (lane_id() == 0) sh[threadIdx.x >> 6] = v;
-  __syncthreads();
-  long long s = 0;
-  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += sh[i];
-  __syncthreads();
-  return s;
+// Ordered compaction of the positions t < n with flag[t] != 0 into list[];
+// optionally records their scores.  Returns the count (block-uniform).
+__device__ int ordered_compact(const uint8_t* __restrict__ flag, int n, int32_t* __restrict__ list,
+                               int cap, long long* __restrict__ vals,
+                               const long long* __restrict__ R, int W, int Wc, int o,
+                               int* scan_sh) {
+  int S = 0;
+  for (int base = 0; base < n; base += SEL_T * RUN) {
+    const int t0 = base + threadIdx.x * RUN;
+    int c = 0;
+    for (int u = 0; u < RUN; ++u) {
+      const int t = t0 + u;
+      c += (t < n && flag[t]) ? 1 : 0;
+    }
+    int tot;
+    const int pre = block_excl_scan(c, scan_sh, &tot);
+    int w = S + pre;
+    for (int u = 0; u < RUN; ++u) {
+      const int t = t0 + u;
+      if (t < n && flag[t] && w < cap) {
+        list[w] = t;
+        if (vals) {
+          const int gr = t / Wc, gc = t - gr * Wc;
+          vals[w] = R[(size_t)(gr + o) * W + gc + o];
+        }
+        ++w;
+      }
+    }
+    S += tot;
+  }
+  return S;
 }
 
 // Single workgroup: ordered selection of the best N survivors by
@@ -143,63 +167,62 @@ __device__ long long block_sum_ll(long long v, long long* sh) {
 __global__ void __launch_bounds__(SEL_T) k_select(uint8_t* __restrict__ flag,
                                                   const long long* __restrict__ R, int H, int W,
                                                   int P, int N, int32_t* __restrict__ slist,
+                                                  long long* __restrict__ sval,
                                                   int32_t* __restrict__ keys, DevStats* st) {
   __shared__ int scan_sh[SEL_T / 64 + 1];
-  __shared__ long long red_sh[SEL_T / 64];
+  __shared__ int hist[256];
+  __shared__ unsigned long long s_prefix;
+  __shared__ int s_remaining;
   const int o = (P - 1) / 2;
   const int Hc = H - P + 1, Wc = W - P + 1;
   const int Ncand = Hc * Wc;
   const int tid = threadIdx.x;
-  auto score = [&](int t) {
-    int gr = t / Wc, gc = t - gr * Wc;
-    return R[(size_t)(gr + o) * W + gc + o];
-  };
-  // A. ordered list of survivors
-  int S = 0;
-  for (int base = 0; base < Ncand; base += SEL_T) {
-    int t = base + tid;
-    int f = (t < Ncand) ? flag[t] : 0;
-    int tot;
-    int pre = block_excl_scan(f, scan_sh, &tot);
-    if (f) slist[S + pre] = t;
-    S += tot;
-  }
+  // A. ordered list of survivors and their scores
+  const int S = ordered_compact(flag, Ncand, slist, Ncand, sval, R, W, Wc, o, scan_sh);
   __syncthreads();
-  // B. threshold: largest v with #(R >= v) >= N
-  long long vstar = 1;
-  int need_eq = 0;
+  // B. radix select (8 bits per pass, most significant first) of the N-th
+  //    largest score v*; need_eq = how many survivors equal to v* are taken
   if (S > N) {
-    long long mx = 0;
-    for (int i = tid; i < S; i += SEL_T) mx = max(mx, score(slist[i]));
-    for (int o2 = 32; o2 > 0; o2 >>= 1) mx = max(mx, (long long)__shfl_xor(mx, o2, 64));
-    if (lane_id() == 0) red_sh[tid >> 6] = mx;
-    __syncthreads();
-    long long mxa = 0;
-    for (int i = 0; i < SEL_T / 64; ++i) mxa = max(mxa, red_sh[i]);
-    __syncthreads();
-    long long lo = 1, hi = mxa;
-    while (lo < hi) {
-      long long mid = lo + (hi - lo + 1) / 2;
-      long long c = 0;
-      for (int i = tid; i < S; i += SEL_T) c += (score(slist[i]) >= mid) ? 1 : 0;
-      c = block_sum_ll(c, red_sh);
-      if (c >= N) lo = mid; else hi = mid - 1;
+    if (tid == 0) {
+      s_prefix = 0ull;
+      s_remaining = N;
     }
-    vstar = lo;
-    long long gt = 0;
-    for (int i = tid; i < S; i += SEL_T) gt += (score(slist[i]) > vstar) ? 1 : 0;
-    gt = block_sum_ll(gt, red_sh);
-    need_eq = N - (int)gt;
-    // C. drop survivors below the threshold and the surplus ties (highest positions)
+    for (int shift = 56; shift >= 0; shift -= 8) {
+      if (tid < 256) hist[tid] = 0;
+      __syncthreads();
+      const unsigned long long prefix = s_prefix;
+      for (int i = tid; i < S; i += SEL_T) {
+        const unsigned long long v = (unsigned long long)sval[i];
+        const bool match = shift == 56 || ((v >> (shift + 8)) == (prefix >> (shift + 8)));
+        if (match) atomicAdd(&hist[(v >> shift) & 255u], 1);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        int cum = 0, rem = s_remaining, digit = 0;
+        for (int b = 255; b >= 0; --b) {
+          if (cum + hist[b] >= rem) {
+            digit = b;
+            break;
+          }
+          cum += hist[b];
+        }
+        s_prefix = prefix | ((unsigned long long)digit << shift);
+        s_remaining = rem - cum;
+      }
+      __syncthreads();
+    }
+    const long long vstar = (long long)s_prefix;
+    const int need_eq = s_remaining;
+    // C. drop survivors below v* and the surplus ties (highest positions)
     int eq_seen = 0;
     for (int base = 0; base < S; base += SEL_T) {
-      int i = base + tid;
-      long long v = (i < S) ? score(slist[i]) : 0;
-      int is_eq = (i < S && v == vstar) ? 1 : 0;
+      const int i = base + tid;
+      const long long v = (i < S) ? sval[i] : 0;
+      const int is_eq = (i < S && v == vstar) ? 1 : 0;
       int tot;
-      int pre = block_excl_scan(is_eq, scan_sh, &tot);
+      const int pre = block_excl_scan(is_eq, scan_sh, &tot);
       if (i < S) {
-        bool sel = v > vstar || (is_eq && eq_seen + pre < need_eq);
+        const bool sel = v > vstar || (is_eq && eq_seen + pre < need_eq);
         if (!sel) flag[slist[i]] = 0;
       }
       eq_seen += tot;
@@ -214,32 +237,24 @@ __global__ void __launch_bounds__(SEL_T) k_select(uint8_t* __restrict__ flag,
     int s = 1;
     while ((long long)s * s * N < (long long)Ncand) ++s;
     for (int pass = 0; pass < 2 && need > 0; ++pass) {
-      int step = pass == 0 ? s : 1;
-      int nr = (Hc + step - 1) / step, nc = (Wc + step - 1) / step;
-      int tot_pos = nr * nc;
+      const int step = pass == 0 ? s : 1;
+      const int nr = (Hc + step - 1) / step, nc = (Wc + step - 1) / step;
+      const int tot_pos = nr * nc;
       for (int base = 0; base < tot_pos && need > 0; base += SEL_T) {
-        int i = base + tid;
+        const int i = base + tid;
         int t = -1;
         if (i < tot_pos) t = (i / nc) * step * Wc + (i % nc) * step;
-        int cand = (t >= 0 && !flag[t]) ? 1 : 0;
+        const int cand = (t >= 0 && !flag[t]) ? 1 : 0;
         int tot;
-        int pre = block_excl_scan(cand, scan_sh, &tot);
+        const int pre = block_excl_scan(cand, scan_sh, &tot);
         if (cand && pre < need) flag[t] = 1;
         need -= tot < need ? tot : need;
       }
     }
   }
   __syncthreads();
-  // E. ascending key list
-  int n_out = 0;
-  for (int base = 0; base < Ncand; base += SEL_T) {
-    int t = base + tid;
-    int f = (t < Ncand) ? flag[t] : 0;
-    int tot;
-    int pre = block_excl_scan(f, scan_sh, &tot);
-    if (f && n_out + pre < N) keys[n_out + pre] = t;
-    n_out += tot;
-  }
+  // E. ascending key list (exactly N chosen positions)
+  ordered_compact(flag, Ncand, keys, N, nullptr, R, W, Wc, o, scan_sh);
 }
 
 }  // namespace
@@ -253,6 +268,7 @@ void launch_detect(const glr_plan* pl, const float* xp, char* ws, int32_t* keys,
   long long* r25 = (long long*)(ws + pl->ws.r25);
   uint8_t* flag = (uint8_t*)(ws + pl->ws.cflag);
   int32_t* slist = (int32_t*)(ws + pl->ws.slist);
+  long long* sval = (long long*)(ws + pl->ws.sval);
   DevStats* st = (DevStats*)(ws + pl->ws.stats);
   if (pl->is_complex) {
     uint32_t* mx = (uint32_t*)(ws + pl->ws.red);
@@ -266,5 +282,5 @@ void launch_detect(const glr_plan* pl, const float* xp, char* ws, int32_t* keys,
   hipLaunchKernelGGL(k_harris, dim3(nblk(HW)), dim3(TPB), 0, s, gxx, gyy, gxy, H, W, r25);
   hipLaunchKernelGGL(k_nms, dim3(nblk((size_t)pl->Ncand)), dim3(TPB), 0, s, r25, H, W, pl->P, flag);
   hipLaunchKernelGGL(k_select, dim3(1), dim3(SEL_T), 0, s, flag, r25, H, W, pl->P, pl->N, slist,
-                     keys, st);
+                     sval, keys, st);
 }

@@ -12,6 +12,7 @@
 struct DevStats {
   unsigned long long margin_sum;
   unsigned long long steps;
+  unsigned long long sweeps_sum;
   int margin_max;
   int overflow;
   int sweeps_max;
@@ -22,14 +23,14 @@ struct DevStats {
 struct WsLayout {
   size_t xp, xo;                 // planar copies of input / output (complex data)
   size_t q, gxx, gyy, gxy, r25;  // detector
-  size_t cflag, slist;           // detector candidate flags / survivor list
+  size_t cflag, slist, sval;     // detector candidate flags / survivor list, scores
   size_t keys;                   // detected keys [N]
   size_t A, kmeta;               // key matrix [N][D] f32; key norms
   size_t pnorm, prt;             // candidate norms, sqrt
   size_t dist;                   // distance chunk [n_chunk][ldd]
-  size_t lj, lu, ll, lcnt;       // partial top-K lists
+  size_t lj, lu, ll, lcnt, oflag; // partial top-K lists, per-key overflow flags
   size_t idx, dd;                // groups [N][K], distances [N][K]
-  size_t xhat, sv;               // group estimates [N][K][D]; singular values
+  size_t xhat, sv;               // group estimates [N][D][K]; singular values
   size_t pairs, offs;            // aggregation sort keys, CSR offsets
   size_t cplx_a, cplx_b;         // complex scratch (FFT / ADMM)
   size_t red;                    // small reduction scratch
@@ -103,8 +104,8 @@ void launch_topk_partial(const glr_plan* pl, const float* dist, const float* kme
                          int32_t* lcnt, hipStream_t s);
 void launch_select_rescore(const glr_plan* pl, const float* xp, const float* A, int g0, int nk,
                            const int32_t* lj, const float* lu, const float* ll,
-                           const int32_t* lcnt, int32_t* idx, float* dd, DevStats* st,
-                           hipStream_t s);
+                           const int32_t* lcnt, int32_t* idx, float* dd, int32_t* oflag,
+                           DevStats* st, hipStream_t s);
 
 // lowrank.hip
 void launch_wnnm(const glr_plan* pl, const float* xp, const int32_t* idx, float sigma,

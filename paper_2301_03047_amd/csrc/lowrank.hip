@@ -2,230 +2,318 @@
 // objective of the Method section, solved by weighted nuclear-norm
 // minimisation [Gu et al. 2014]).
 //
-// One workgroup per group Y (D x K, column q = member patch q):
-//  1. row means mu and Yc = Y - mu 1^T, streamed in chunks of 64 rows;
-//  2. R = triangular factor of Yc by a streaming (TSQR-style) Householder QR:
-//     each chunk B is folded into the running R by eliminating [R; B];
-//  3. one-sided Jacobi SVD of R (columns orthogonalised in a round-robin
-//     order, rotation angles computed in FP64), accumulating V;  R and Yc
-//     share singular values and right singular vectors;
-//  4. WNNM: sigma_hat = sqrt(max(s^2 - K sigma^2, 0)),
-//     tau = c sqrt(K) sigma^2 / (sigma_hat + eps), s' = max(s - tau, 0);
-//  5. X = Y - Yc W with W = V diag((s - s')/s) V^T, i.e. the residual
-//     sum_i (s_i - s'_i) u_i v_i^T, accumulated in FP64 (sigma = 0 gives
-//     W = 0 and X = Y exactly).
+// One wave per group Y (D x K, column j = member patch j); lane j owns
+// column j and keeps it in registers; columns move between lanes through LDS
+// with 16-byte accesses (many in flight per wave):
+//  1. rows are streamed in chunks of 64 (each lane loads one row and removes
+//     its mean, Yc = Y - mu 1^T); the chunk is folded into the running
+//     triangular factor R by Householder reflections on [R; chunk]; the
+//     reflector column is broadcast through LDS;
+//  2. one-sided Jacobi on the columns of R^T (round-robin pairs, partner
+//     columns exchanged through LDS, rotation angles computed in FP64); the
+//     converged columns are sigma_i v_i with v_i the right singular vectors
+//     of R, hence of Yc, so V is read off them without accumulating
+//     rotations;
+//  3. WNNM: sigma_hat = sqrt(max(s^2 - K sigma^2, 0)),
+//     tau = c sqrt(K) sigma^2 / (sigma_hat + eps), s' = max(s - tau, 0),
+//     w = (s - s') / s;
+//  4. X = Y - Yc W, W = V diag(w) V^T: the residual sum_i (s_i - s'_i) u_i v_i^T
+//     accumulated in FP64 (sigma = 0 gives w = 0, W = 0, X = Y exactly).
 // Data and the SVD are FP32; only the angles and the residual use FP64.
+// Estimates are written d-major per group: xhat[(g*D + d)*K + j].
 #include "common.h"
 #include "internal.h"
 
 namespace {
 
-constexpr int WT = 256;
-constexpr int KMAX = 64;
+constexpr int LS = 65;           // LDS stride (conflict-free column/row access)
 constexpr int BR = 64;           // rows per streamed chunk
-constexpr int RS = KMAX + 1;     // LDS row stride
 
-struct GroupGeom {
-  int H, W, P, Cp, D, K;
-  size_t HW;
-};
-
-// image offset of row d of member patch with top-left pixel offset `base`
-__device__ __forceinline__ size_t elem_off(const GroupGeom& G, int base, int d) {
-  const int PP = G.P * G.P;
-  int ch = d / PP;
-  int rem = d - ch * PP;
-  int dy = rem / G.P, dx = rem - dy * G.P;
-  return (size_t)ch * G.HW + base + dy * G.W + dx;
+__device__ __forceinline__ size_t elem_off(int d, int P, int W, size_t HW) {
+  const int PP = P * P;
+  const int ch = d / PP;
+  const int rem = d - ch * PP;
+  const int dy = rem / P, dx = rem - dy * P;
+  return (size_t)ch * HW + (size_t)dy * W + dx;
 }
 
-// Load rows [d0, d0+nb) of Y into B (raw values) and their means into smu.
-__device__ void load_chunk(const GroupGeom& G, const float* __restrict__ xp, const int* spos, int d0,
-                           int nb, float* B, float* smu) {
-  const int K = G.K;
-  for (int e = threadIdx.x; e < nb * K; e += WT) {
-    int i = e % nb, j = e / nb;
-    B[i * RS + j] = xp[elem_off(G, spos[j], d0 + i)];
-  }
-  __syncthreads();
-  if (threadIdx.x < nb) {
-    const int i = threadIdx.x;
+__device__ __forceinline__ float bcast(float v, int lane) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+
+// Lane i < nb loads row d0+i of Y into B[i][0..K) (raw values) and its mean.
+__device__ __forceinline__ void load_rows(const float* __restrict__ xp, const int* spos, int d0,
+                                          int nb, int K, int P, int W, size_t HW, float* B,
+                                          float* smu) {
+  const int i = threadIdx.x;
+  if (i < nb) {
+    const size_t o = elem_off(d0 + i, P, W, HW);
     float s = 0.f;
-    for (int j = 0; j < K; ++j) s += B[i * RS + j];
+#pragma unroll 8
+    for (int j = 0; j < K; ++j) {
+      const float v = xp[o + spos[j]];
+      B[i * LS + j] = v;
+      s += v;
+    }
     smu[i] = s / (float)K;
   }
   __syncthreads();
 }
 
-__global__ void __launch_bounds__(WT)
-k_wnnm(const float* __restrict__ xp, int H, int W, int P, int Cp, int D,
-       const int32_t* __restrict__ idx, int K, float sigma, float wc, float weps, int max_sweeps,
-       float* __restrict__ xhat, float* __restrict__ sv, DevStats* st) {
-  __shared__ float Rm[KMAX * RS];
-  __shared__ float Vm[KMAX * RS];
-  __shared__ float Bm[BR * RS];
-  __shared__ float red[4][KMAX];
-  __shared__ float smu[BR];
-  __shared__ float swt[KMAX];
-  __shared__ float ssig[KMAX];
-  __shared__ int spos[KMAX];
-  __shared__ int sflag[3];
+// FP64 Jacobi rotation annihilating gamma for column norms a1 (first) and a2:
+// t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), zeta = (a2 - a1) / (2 gamma),
+// written with one division; c = 1/sqrt(1 + t^2), s = c t.
+__device__ __forceinline__ void jacobi_angle(float a1, float a2, float ga, float& c, float& s) {
+  const double d = (double)a2 - (double)a1;
+  const double g2 = 2.0 * (double)ga;
+  const double sg = ((d >= 0.0) == (g2 >= 0.0)) ? 1.0 : -1.0;     // sign(zeta), zeta = 0 -> +1
+  const double t = sg * fabs(g2) / (fabs(d) + sqrt(d * d + g2 * g2));
+  const double cs = 1.0 / sqrt(1.0 + t * t);
+  c = (float)cs;
+  s = (float)(cs * t);
+}
+
+// LDS ordering between lanes of the one wave that runs a group.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int N>
+__device__ __forceinline__ void store_vec(float* dst, const float (&v)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; i += 4)
+    *reinterpret_cast<float4*>(dst + i) = make_float4(v[i], v[i + 1], v[i + 2], v[i + 3]);
+}
+template <int N>
+__device__ __forceinline__ void load_vec(float (&v)[N], const float* src) {
+#pragma unroll
+  for (int i = 0; i < N; i += 4) {
+    const float4 t = *reinterpret_cast<const float4*>(src + i);
+    v[i] = t.x; v[i + 1] = t.y; v[i + 2] = t.z; v[i + 3] = t.w;
+  }
+}
+
+template <int KP>
+__global__ void __launch_bounds__(64)
+k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* __restrict__ idx,
+       int K, float sigma, float wc, float weps, int max_sweeps, float* __restrict__ xhat,
+       float* __restrict__ sv, DevStats* st) {
+  constexpr int XS = KP + 4;       // row stride of the column-exchange buffer (16-byte rows)
+  __shared__ float Rl[64 * LS];    // R columns (Rl[j*LS + i]); later W columns
+  // chunk rows Bl[i*LS + j]; then exchange rows and V rows with stride XS
+  constexpr int BLN = 64 * (XS > LS ? XS : LS);
+  __shared__ __align__(16) float Bl[BLN];
+  __shared__ __align__(16) float Cb[BR + 4];    // broadcast column, its squared norm at [BR]
+  __shared__ float smu[64];
+  __shared__ int spos[64];
+  __shared__ float sw[64];
+  __shared__ float ssig[64];
 
   const int g = blockIdx.x;
-  const int tid = threadIdx.x;
+  const int lane = threadIdx.x;
   const int Wc = W - P + 1;
-  GroupGeom G{H, W, P, Cp, D, K, (size_t)H * W};
+  const size_t HW = (size_t)H * W;
 
-  if (tid < K) {
-    int t = idx[(size_t)g * K + tid];
-    int r = t / Wc, c = t - r * Wc;
-    spos[tid] = r * W + c;
+  if (lane < K) {
+    const int t = idx[(size_t)g * K + lane];
+    const int r = t / Wc, c = t - r * Wc;
+    spos[lane] = r * W + c;
   }
-  for (int e = tid; e < KMAX * RS; e += WT) {
-    Rm[e] = 0.f;
-    Vm[e] = 0.f;
-  }
-  if (tid < 3) sflag[tid] = 0;
+  for (int i = 0; i < 64; ++i) Rl[lane * LS + i] = 0.f;
   __syncthreads();
 
-  // ---- 1-2: streamed Householder QR of Yc
-  const int jc = tid & 63, part = tid >> 6;
+  // ---- 1. streamed Householder QR of Yc
   for (int d0 = 0; d0 < D; d0 += BR) {
     const int nb = min(BR, D - d0);
-    load_chunk(G, xp, spos, d0, nb, Bm, smu);
-    for (int e = tid; e < nb * K; e += WT) {
-      int i = e % nb, j = e / nb;
-      Bm[i * RS + j] -= smu[i];
+    load_rows(xp, spos, d0, nb, K, P, W, HW, Bl, smu);
+    float b[BR];
+#pragma unroll
+    for (int i = 0; i < BR; ++i) b[i] = (i < nb && lane < K) ? Bl[i * LS + lane] - smu[i] : 0.f;
+    for (int k = 0; k < K; ++k) {
+      if (lane == k) {
+        float q0 = 0.f, q1 = 0.f;
+#pragma unroll
+        for (int i = 0; i < BR; i += 2) {
+          q0 = fmaf(b[i], b[i], q0);
+          q1 = fmaf(b[i + 1], b[i + 1], q1);
+        }
+        store_vec(Cb, b);
+        Cb[BR] = q0 + q1;
+      }
+      wave_sync();
+      const float sig2 = Cb[BR];
+      if (sig2 > 0.f) {
+        const float x0 = Rl[k * LS + k];
+        const float nrm = sqrtf(x0 * x0 + sig2);
+        const float alpha = x0 >= 0.f ? -nrm : nrm;
+        const float v0 = x0 - alpha;
+        const float beta = 2.0f / (v0 * v0 + sig2);
+        if (lane > k && lane < K) {
+          float v[BR];
+          load_vec(v, Cb);
+          float w0 = 0.f, w1 = 0.f, w2 = 0.f, w3 = 0.f;
+#pragma unroll
+          for (int i = 0; i < BR; i += 4) {
+            w0 = fmaf(v[i], b[i], w0);
+            w1 = fmaf(v[i + 1], b[i + 1], w1);
+            w2 = fmaf(v[i + 2], b[i + 2], w2);
+            w3 = fmaf(v[i + 3], b[i + 3], w3);
+          }
+          const float rk = Rl[lane * LS + k];
+          const float bw = beta * fmaf(v0, rk, (w0 + w1) + (w2 + w3));
+#pragma unroll
+          for (int i = 0; i < BR; ++i) b[i] = fmaf(-bw, v[i], b[i]);
+          Rl[lane * LS + k] = fmaf(-bw, v0, rk);
+        }
+        if (lane == k) Rl[k * LS + k] = alpha;
+      }
+      wave_sync();
     }
     __syncthreads();
-    const int q = (nb + 3) / 4;
-    const int i0 = part * q, i1 = min(nb, i0 + q);
-    for (int k = 0; k < K; ++k) {
-      if (jc >= k && jc < K) {
-        float p = 0.f;
-        for (int i = i0; i < i1; ++i) p += Bm[i * RS + k] * Bm[i * RS + jc];
-        red[part][jc] = p;
-      }
-      __syncthreads();
-      const float sig2 = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
-      float beta = 0.f, v0 = 0.f, alpha = 0.f, w = 0.f;
-      const bool active = sig2 > 0.f;
-      if (active) {
-        const float x0 = Rm[k * RS + k];
-        const float nrm = sqrtf(x0 * x0 + sig2);
-        alpha = x0 >= 0.f ? -nrm : nrm;
-        v0 = x0 - alpha;
-        beta = 2.0f / (v0 * v0 + sig2);
-        if (jc > k && jc < K)
-          w = v0 * Rm[k * RS + jc] + (((red[0][jc] + red[1][jc]) + red[2][jc]) + red[3][jc]);
-      }
-      __syncthreads();
-      if (active) {
-        if (jc > k && jc < K) {
-          const float bw = beta * w;
-          for (int i = i0; i < i1; ++i) Bm[i * RS + jc] -= bw * Bm[i * RS + k];
-          if (part == 0) Rm[k * RS + jc] -= bw * v0;
-        }
-        if (jc == k && part == 0) Rm[k * RS + k] = alpha;
-      }
-      __syncthreads();
-    }
   }
 
-  // ---- 3: one-sided Jacobi on the columns of R, V accumulated
-  for (int e = tid; e < K; e += WT) Vm[e * RS + e] = 1.0f;
-  __syncthreads();
+  // ---- 2. one-sided Jacobi on the columns of M = R^T: lane i holds row i of R
+  float m[KP];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) m[k] = (lane < K && k < K) ? Rl[k * LS + lane] : 0.f;
   const int Kp = K + (K & 1);
-  const int npairs = Kp / 2;
-  const int pr = tid >> 3, sub = tid & 7;
   const float tol = (float)K * 5.9604644775390625e-08f;
+  float* xrow = Bl + lane * XS;              // this lane's exchange row
   int sweeps = 0;
-  for (int sw = 0; sw < max_sweeps; ++sw) {
-    // three flag slots: this sweep writes sw%3, the next one is cleared now,
-    // and the slot read at the end of the previous sweep is left alone
-    if (tid == 0) sflag[(sw + 1) % 3] = 0;
-    for (int round = 0; round < Kp - 1; ++round) {
-      int a = -1, b = -1;
-      if (pr < npairs) {
-        a = pr == 0 ? 0 : 1 + ((pr - 1 + round) % (Kp - 1));
-        int m2 = Kp - 1 - pr;
-        b = m2 == 0 ? 0 : 1 + ((m2 - 1 + round) % (Kp - 1));
+  for (int swp = 0; swp < max_sweeps; ++swp) {
+    bool rotated = false;
+    for (int r = 0; r < Kp - 1; ++r) {
+      // round-robin partner: position 0 fixed, the others rotate by one per round
+      int q = -1;
+      if (lane < Kp) {
+        const int mpos = lane == 0 ? 0 : 1 + ((lane - 1 - r) % (Kp - 1) + (Kp - 1)) % (Kp - 1);
+        const int ppos = Kp - 1 - mpos;
+        q = ppos == 0 ? 0 : 1 + ((ppos - 1 + r) % (Kp - 1));
       }
-      const bool valid = pr < npairs && a < K && b < K;
-      float al = 0.f, be = 0.f, ga = 0.f;
-      if (valid)
-        for (int i = sub; i < K; i += 8) {
-          float x = Rm[i * RS + a], y = Rm[i * RS + b];
-          al += x * x;
-          be += y * y;
-          ga += x * y;
+      float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+#pragma unroll
+      for (int k = 0; k < KP; k += 4) {
+        a0 = fmaf(m[k], m[k], a0);
+        a1 = fmaf(m[k + 1], m[k + 1], a1);
+        a2 = fmaf(m[k + 2], m[k + 2], a2);
+        a3 = fmaf(m[k + 3], m[k + 3], a3);
+      }
+      const float al = (a0 + a1) + (a2 + a3);
+      store_vec(xrow, m);
+      xrow[KP] = al;
+      wave_sync();
+      float o[KP];
+      const float* prow = Bl + (q < 0 ? lane : q) * XS;
+      load_vec(o, prow);
+      const float be = prow[KP];
+      float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f;
+#pragma unroll
+      for (int k = 0; k < KP; k += 4) {
+        g0 = fmaf(m[k], o[k], g0);
+        g1 = fmaf(m[k + 1], o[k + 1], g1);
+        g2 = fmaf(m[k + 2], o[k + 2], g2);
+        g3 = fmaf(m[k + 3], o[k + 3], g3);
+      }
+      const float ga = (g0 + g1) + (g2 + g3);    // same products and order in both lanes
+      wave_sync();                               // exchange rows are rewritten next round
+      const bool first = lane < q;
+      const float n1 = first ? al : be;          // norm^2 of the lower-index column
+      const float n2 = first ? be : al;
+      const bool act = q >= 0 && lane < K && q < K && ga != 0.f &&
+                       fabsf(ga) > tol * sqrtf(n1) * sqrtf(n2);
+      if (act) {
+        float c, s;
+        jacobi_angle(n1, n2, ga, c, s);
+        if (first) {
+#pragma unroll
+          for (int k = 0; k < KP; ++k) m[k] = fmaf(c, m[k], -s * o[k]);
+        } else {
+#pragma unroll
+          for (int k = 0; k < KP; ++k) m[k] = fmaf(s, o[k], c * m[k]);
         }
-      // butterfly over the 8 lanes of the pair: identical sums in every lane
-      for (int o = 1; o < 8; o <<= 1) {
-        al += __shfl_xor(al, o, 64);
-        be += __shfl_xor(be, o, 64);
-        ga += __shfl_xor(ga, o, 64);
       }
-      if (valid && ga != 0.f && fabsf(ga) > tol * sqrtf(al) * sqrtf(be)) {
-        const double zeta = ((double)be - (double)al) / (2.0 * (double)ga);
-        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double cs = 1.0 / sqrt(1.0 + t * t);
-        const float c = (float)cs, s = (float)(cs * t);
-        for (int i = sub; i < K; i += 8) {
-          float x = Rm[i * RS + a], y = Rm[i * RS + b];
-          Rm[i * RS + a] = c * x - s * y;
-          Rm[i * RS + b] = s * x + c * y;
-          float vx = Vm[i * RS + a], vy = Vm[i * RS + b];
-          Vm[i * RS + a] = c * vx - s * vy;
-          Vm[i * RS + b] = s * vx + c * vy;
-        }
-        if (sub == 0) sflag[sw % 3] = 1;
-      }
-      __syncthreads();
+      rotated = rotated || act;
     }
-    sweeps = sw + 1;
-    if (sflag[sw % 3] == 0) break;
+    sweeps = swp + 1;
+    if (__ballot(rotated) == 0) break;
   }
   __syncthreads();
 
-  // ---- 4: singular values and WNNM factors
-  if (tid < K) {
-    float s2 = 0.f;
-    for (int i = 0; i < K; ++i) s2 += Rm[i * RS + tid] * Rm[i * RS + tid];
-    const float s = sqrtf(s2);
+  // ---- 3. singular values, WNNM factors, V into LDS (V[k][i] = column i / sigma_i)
+  float s2a = 0.f, s2b = 0.f;
+#pragma unroll
+  for (int k = 0; k < KP; k += 2) {
+    s2a = fmaf(m[k], m[k], s2a);
+    s2b = fmaf(m[k + 1], m[k + 1], s2b);
+  }
+  const float s = sqrtf(s2a + s2b);
+  if (lane < K) {
     const float shat = sqrtf(fmaxf(s * s - (float)K * sigma * sigma, 0.f));
     const float tau = wc * sqrtf((float)K) * sigma * sigma / (shat + weps);
     const float sn = fmaxf(s - tau, 0.f);
-    ssig[tid] = s;
-    swt[tid] = s > 0.f ? (s - sn) / s : 0.f;
+    ssig[lane] = s;
+    sw[lane] = s > 0.f ? (s - sn) / s : 0.f;
+    const float inv = s > 0.f ? 1.0f / s : 0.f;
+#pragma unroll
+    for (int k = 0; k < KP; ++k)
+      if (k < K) Bl[k * XS + lane] = m[k] * inv;
   }
   __syncthreads();
-  if (sv && tid < K) {
-    const float s = ssig[tid];
+  if (sv && lane < K) {
     int rank = 0;
-    for (int i = 0; i < K; ++i) rank += (ssig[i] > s || (ssig[i] == s && i < tid)) ? 1 : 0;
+    for (int i = 0; i < K; ++i) rank += (ssig[i] > s || (ssig[i] == s && i < lane)) ? 1 : 0;
     sv[(size_t)g * K + rank] = s;
   }
-  if (tid == 0 && st) atomicMax(&st->sweeps_max, sweeps);
-  // W = V diag(w) V^T into Rm
-  for (int e = tid; e < K * K; e += WT) {
-    const int a = e / K, b = e - a * K;
-    float acc = 0.f;
-    for (int i = 0; i < K; ++i) acc += Vm[a * RS + i] * swt[i] * Vm[b * RS + i];
-    Rm[a * RS + b] = acc;
+  if (lane == 0 && st) {
+    atomicMax(&st->sweeps_max, sweeps);
+    atomicAdd(&st->sweeps_sum, (unsigned long long)sweeps);
+  }
+  // W[a][b] = sum_i w_i V[a][i] V[b][i]; lane b holds w_i V[b][i] and builds
+  // column b of W into Rl[b*LS + a]
+  {
+    float vb[KP];
+    load_vec(vb, Bl + lane * XS);
+#pragma unroll
+    for (int i = 0; i < KP; ++i) vb[i] = (lane < K && i < K) ? vb[i] * sw[i] : 0.f;
+    if (lane < K)
+      for (int a = 0; a < K; ++a) {
+        float va[KP];
+        load_vec(va, Bl + a * XS);
+        float c0 = 0.f, c1 = 0.f, c2 = 0.f, c3 = 0.f;
+#pragma unroll
+        for (int i = 0; i < KP; i += 4) {
+          c0 = fmaf(va[i], vb[i], c0);
+          c1 = fmaf(va[i + 1], vb[i + 1], c1);
+          c2 = fmaf(va[i + 2], vb[i + 2], c2);
+          c3 = fmaf(va[i + 3], vb[i + 3], c3);
+        }
+        Rl[lane * LS + a] = (c0 + c1) + (c2 + c3);
+      }
   }
   __syncthreads();
+  double wcol[KP];
+#pragma unroll
+  for (int a = 0; a < KP; ++a) wcol[a] = (lane < K && a < K) ? (double)Rl[lane * LS + a] : 0.0;
 
-  // ---- 5: X = Y - Yc W, residual accumulated in FP64
+  // ---- 4. X = Y - Yc W (residual in FP64), d-major output
   for (int d0 = 0; d0 < D; d0 += BR) {
     const int nb = min(BR, D - d0);
-    load_chunk(G, xp, spos, d0, nb, Bm, smu);
-    for (int e = tid; e < nb * K; e += WT) {
-      const int i = e % nb, j = e / nb;
-      const float mu = smu[i];
-      double res = 0.0;
-      for (int k = 0; k < K; ++k) res += (double)(Bm[i * RS + k] - mu) * (double)Rm[k * RS + j];
-      xhat[((size_t)g * K + j) * D + d0 + i] = (float)((double)Bm[i * RS + j] - res);
+    load_rows(xp, spos, d0, nb, K, P, W, HW, Bl, smu);
+    if (lane < K) {
+      float* outp = xhat + ((size_t)g * D + d0) * K + lane;
+      for (int i = 0; i < nb; ++i) {
+        const float mu = smu[i];
+        const float* row = Bl + i * LS;
+        double r0 = 0.0, r1 = 0.0;
+#pragma unroll
+        for (int a = 0; a < KP; a += 2) {
+          if (a < K) r0 = fma((double)(row[a] - mu), wcol[a], r0);
+          if (a + 1 < K) r1 = fma((double)(row[a + 1] - mu), wcol[a + 1], r1);
+        }
+        outp[(size_t)i * K] = (float)((double)row[lane] - (r0 + r1));
+      }
     }
     __syncthreads();
   }
@@ -235,6 +323,14 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int Cp, int D,
 
 void launch_wnnm(const glr_plan* pl, const float* xp, const int32_t* idx, float sigma,
                  float* xhat, float* sv, DevStats* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_wnnm, dim3(pl->N), dim3(WT), 0, s, xp, pl->H, pl->W, pl->P, pl->Cp, pl->D,
-                     idx, pl->K, sigma, pl->wnnm_c, pl->wnnm_eps, 30, xhat, sv, st);
+  const int K = pl->K;
+  if (K <= 32)
+    hipLaunchKernelGGL(k_wnnm<32>, dim3(pl->N), dim3(64), 0, s, xp, pl->H, pl->W, pl->P, pl->D,
+                       idx, K, sigma, pl->wnnm_c, pl->wnnm_eps, 30, xhat, sv, st);
+  else if (K <= 48)
+    hipLaunchKernelGGL(k_wnnm<48>, dim3(pl->N), dim3(64), 0, s, xp, pl->H, pl->W, pl->P, pl->D,
+                       idx, K, sigma, pl->wnnm_c, pl->wnnm_eps, 30, xhat, sv, st);
+  else
+    hipLaunchKernelGGL(k_wnnm<64>, dim3(pl->N), dim3(64), 0, s, xp, pl->H, pl->W, pl->P, pl->D,
+                       idx, K, sigma, pl->wnnm_c, pl->wnnm_eps, 30, xhat, sv, st);
 }

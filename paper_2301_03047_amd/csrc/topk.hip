@@ -19,19 +19,49 @@ namespace {
 constexpr int CAP = GLR_SPLIT_CAP;        // entries per wave buffer
 constexpr int UCAP = GLR_UNION_CAP;       // entries per key in stage 2
 
-// K-th smallest of vals[0..n) (as ordered uint32) by bisection over the
-// value range; one wave.  Requires n >= K >= 1.
-__device__ float wave_kth_smallest(const float* vals, int n, int K) {
-  uint32_t lo = 0u, hi = 0xffffffffu;
+// K-th smallest of vals[0..n) by radix selection on the ordered uint32 keys:
+// four passes of an 8-bit digit histogram in LDS (integer adds), most
+// significant digit first.  One wave; requires n >= K >= 1.
+__device__ float wave_kth_smallest(const float* vals, int n, int K, int* hist) {
   const int l = lane_id();
-  while (lo < hi) {
-    uint32_t mid = lo + ((hi - lo) >> 1);
-    int c = 0;
-    for (int i = l; i < n; i += 64) c += (f2ord(vals[i]) <= mid) ? 1 : 0;
-    c = wave_sum_i32(c);
-    if (c >= K) hi = mid; else lo = mid + 1;
+  uint32_t prefix = 0u;
+  int remaining = K;
+  for (int shift = 24; shift >= 0; shift -= 8) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) hist[4 * l + b] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const uint32_t hmask = shift == 24 ? 0u : (0xffffffffu << (shift + 8));
+    for (int i = l; i < n; i += 64) {
+      const uint32_t key = f2ord(vals[i]);
+      if ((key & hmask) == (prefix & hmask)) atomicAdd(&hist[(key >> shift) & 255u], 1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // lane l owns bins 4l..4l+3; find the bin holding the remaining-th key
+    const int c0 = hist[4 * l], c1 = hist[4 * l + 1], c2 = hist[4 * l + 2], c3 = hist[4 * l + 3];
+    const int tot = c0 + c1 + c2 + c3;
+    const int incl = wave_incl_scan(tot);
+    const int excl = incl - tot;
+    const bool mine = excl < remaining && remaining <= incl;
+    int digit = 0, below = 0;
+    if (mine) {
+      int r = remaining - excl;
+      if (r <= c0) { digit = 4 * l; below = excl; }
+      else if (r <= c0 + c1) { digit = 4 * l + 1; below = excl + c0; }
+      else if (r <= c0 + c1 + c2) { digit = 4 * l + 2; below = excl + c0 + c1; }
+      else { digit = 4 * l + 3; below = excl + c0 + c1 + c2; }
+    }
+    const uint64_t who = __ballot(mine);
+    const int src = who ? (int)__builtin_ctzll(who) : 0;
+    digit = __shfl(digit, src, 64);
+    below = __shfl(below, src, 64);
+    prefix |= (uint32_t)digit << shift;
+    remaining -= below;
   }
-  return ord2f(lo);
+  return ord2f(prefix);
 }
 
 // keep entries with L <= T (ordered, in place); returns the new count
@@ -66,6 +96,7 @@ k_topk_partial(const float* __restrict__ dist, size_t ldd, const float2* __restr
   __shared__ int sbj[4][CAP];
   __shared__ float sbu[4][CAP];
   __shared__ float sbl[4][CAP];
+  __shared__ int shist[4][256];
   const int wave = threadIdx.x >> 6;
   const int l = lane_id();
   const int item = blockIdx.x * 4 + wave;
@@ -73,6 +104,7 @@ k_topk_partial(const float* __restrict__ dist, size_t ldd, const float2* __restr
   int* bj = sbj[wave];
   float* bu = sbu[wave];
   float* bl = sbl[wave];
+  int* hist = shist[wave];
   const int g = item / S, sp = item - g * S;
   const int j0 = sp * split_len;
   const int j1 = min(Ncand, j0 + split_len);
@@ -81,50 +113,103 @@ k_topk_partial(const float* __restrict__ dist, size_t ldd, const float2* __restr
   float T = __int_as_float(0x7f800000);     // +inf
   int cnt = 0;
   bool ovf = false;
-  for (int base = j0; base < j1; base += 256) {
-    const int j = base + 4 * l;
-    float dv[4], pv[4];
-    if (j + 3 < j1) {
-      float4 a = *reinterpret_cast<const float4*>(drow + j);
-      float4 b = *reinterpret_cast<const float4*>(prt + j);
-      dv[0] = a.x; dv[1] = a.y; dv[2] = a.z; dv[3] = a.w;
-      pv[0] = b.x; pv[1] = b.y; pv[2] = b.z; pv[3] = b.w;
-    } else {
+  // 1024 candidates per chunk (four float4 loads of d~ and of ||p|| per
+  // lane); the next chunk's loads are issued before the current chunk is
+  // processed.  One ballot rejects a chunk in the common case where no
+  // element can enter the margin set.
+  constexpr int U4 = 4;
+  constexpr int CH = 256 * U4;
+  float dv[U4][4], pv[U4][4], dn[U4][4], pn[U4][4];
+  auto load = [&](int base, float (&d)[U4][4], float (&p)[U4][4]) {
+#pragma unroll
+    for (int u = 0; u < U4; ++u) {
+      const int j = base + u * 256 + 4 * l;
+      if (j + 3 < j1) {
+        const float4 a = *reinterpret_cast<const float4*>(drow + j);
+        const float4 b = *reinterpret_cast<const float4*>(prt + j);
+        d[u][0] = a.x; d[u][1] = a.y; d[u][2] = a.z; d[u][3] = a.w;
+        p[u][0] = b.x; p[u][1] = b.y; p[u][2] = b.z; p[u][3] = b.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const bool ok = j + e < j1;
+          d[u][e] = ok ? drow[j + e] : 0.f;
+          p[u][e] = ok ? prt[j + e] : 0.f;
+        }
+      }
+    }
+  };
+  load(j0, dv, pv);
+  for (int base = j0; base < j1; base += CH) {
+    if (base + CH < j1) load(base + CH, dn, pn);
+    // positions past the end of the range are never admitted (explicit
+    // validity: an infinite L would still pass L <= T while T is +inf)
+    float Lv[U4][4], Uv[U4][4];
+    bool ok[U4][4];
+#pragma unroll
+    for (int u = 0; u < U4; ++u)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        bool ok = j + e < j1;
-        dv[e] = ok ? drow[j + e] : 0.f;
-        pv[e] = ok ? prt[j + e] : 0.f;
+        const int j = base + u * 256 + 4 * l + e;
+        const float sm = kr + pv[u][e];
+        const float eps = coef * (sm * sm);
+        ok[u][e] = j < j1;
+        Uv[u][e] = dv[u][e] + eps;
+        Lv[u][e] = dv[u][e] - eps;
       }
-    }
+    if (base == j0) {
+      // seed T with the K-th smallest U of the first chunk (an upper bound of
+      // the range's K-th smallest U)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const float s = kr + pv[e];
-      const float eps = coef * (s * s);
-      const float U = dv[e] + eps;
-      const float L = dv[e] - eps;
-      const bool adm = (j + e < j1) && (L <= T);
-      uint64_t m = __ballot(adm);
-      if (adm) {
-        int pos = cnt + lanes_below(m);
-        bj[pos] = j + e;
-        bu[pos] = U;
-        bl[pos] = L;
-      }
-      cnt += __popcll(m);
+      for (int u = 0; u < U4; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          bu[(u * 64 + l) * 4 + e] = ok[u][e] ? Uv[u][e] : __int_as_float(0x7f800000);
+      T = wave_kth_smallest(bu, CH, K, hist);
     }
-    if (cnt > CAP - 256) {
-      float Tn = wave_kth_smallest(bu, cnt, K);
-      T = fminf(T, Tn);
-      cnt = wave_compact(bj, bu, bl, cnt, T);
-      if (cnt > CAP - 256) {
-        ovf = true;
-        break;
+    bool any = false;
+#pragma unroll
+    for (int u = 0; u < U4; ++u)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) any = any || (ok[u][e] && Lv[u][e] <= T);
+    if (__ballot(any) != 0) {
+#pragma unroll
+      for (int u = 0; u < U4; ++u) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const bool adm = ok[u][e] && Lv[u][e] <= T;
+          const uint64_t m = __ballot(adm);
+          if (adm) {
+            const int pos = cnt + lanes_below(m);
+            bj[pos] = base + u * 256 + 4 * l + e;
+            bu[pos] = Uv[u][e];
+            bl[pos] = Lv[u][e];
+          }
+          cnt += __popcll(m);
+        }
+        // room for the next 256 entries, else tighten T and compact
+        if (cnt > CAP - 256) {
+          const float Tn = wave_kth_smallest(bu, cnt, K, hist);
+          T = fminf(T, Tn);
+          cnt = wave_compact(bj, bu, bl, cnt, T);
+          if (cnt > CAP - 256) {
+            ovf = true;
+            break;
+          }
+        }
       }
     }
+    if (ovf) break;
+#pragma unroll
+    for (int u = 0; u < U4; ++u)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        dv[u][e] = dn[u][e];
+        pv[u][e] = pn[u][e];
+      }
   }
   if (!ovf && cnt >= K) {
-    float Tn = wave_kth_smallest(bu, cnt, K);
+    const float Tn = wave_kth_smallest(bu, cnt, K, hist);
     T = fminf(T, Tn);
     cnt = wave_compact(bj, bu, bl, cnt, T);
   }
@@ -186,39 +271,164 @@ __device__ void block_bitonic(float* h, float* lo, int* j, int n) {
     }
 }
 
-__global__ void __launch_bounds__(ST)
+// Wave-level bitonic sort of n (power of two, <= UW) entries by (hi, lo, j).
+__device__ void wave_bitonic(float* h, float* lo, int* j, int n) {
+  const int l = lane_id();
+  for (int k = 2; k <= n; k <<= 1)
+    for (int s = k >> 1; s > 0; s >>= 1) {
+      for (int i = l; i < n; i += 64) {
+        const int p = i ^ s;
+        if (p > i) {
+          const bool up = (i & k) == 0;
+          const bool gt = df_less(h[p], lo[p], j[p], h[i], lo[i], j[i]);   // a[i] > a[p]
+          if (gt == up) {
+            const float th = h[i], tl = lo[i];
+            const int tj = j[i];
+            h[i] = h[p]; lo[i] = lo[p]; j[i] = j[p];
+            h[p] = th; lo[p] = tl; j[p] = tj;
+          }
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+constexpr int UW = 1024;          // union capacity per key (wave path)
+
+// One wave per key: merge the per-range lists, apply the key's threshold,
+// rescore the margin set with compensated arithmetic, sort by
+// (distance, position) and keep the first K.  Keys whose lists overflowed
+// are flagged for the exact full-row kernel below.
+__global__ void __launch_bounds__(256)
 k_select_rescore(const float* __restrict__ xp, int H, int W, int P, int Cp, int D,
-                 const float* __restrict__ A, int g0, int S, int Ncand, int K,
+                 const float* __restrict__ A, int g0, int nk, int S, int Ncand, int K,
                  const int32_t* __restrict__ lj, const float* __restrict__ lu,
                  const float* __restrict__ ll, const int32_t* __restrict__ lcnt,
-                 int32_t* __restrict__ idx, float* __restrict__ dd, DevStats* st) {
+                 int32_t* __restrict__ idx, float* __restrict__ dd, int32_t* __restrict__ oflag,
+                 DevStats* st) {
+  __shared__ float su[4][UW];
+  __shared__ float sl[4][UW];
+  __shared__ int sj[4][UW];
+  __shared__ int shist[4][256];
+  const int wave = threadIdx.x >> 6;
+  const int l = lane_id();
+  const int g = blockIdx.x * 4 + wave;
+  if (g >= nk) return;                      // wave-uniform
+  float* u = su[wave];
+  float* lo = sl[wave];
+  int* jj = sj[wave];
+  const int gg = g0 + g;
+  const int Wc = W - P + 1;
+  // split counts (S <= 64: one lane per split)
+  const int c = l < S ? lcnt[g * S + l] : 0;
+  const bool bad = __ballot(c < 0) != 0;
+  const int incl = wave_incl_scan(c < 0 ? 0 : c);
+  const int tot = __shfl(incl, 63, 64);
+  if (bad || tot > UW) {
+    if (l == 0) oflag[g] = bad ? 2 : 1;     // 1: merge in the block kernel; 2: full row
+    return;
+  }
+  if (l == 0) oflag[g] = 0;
+  const int off = incl - (c < 0 ? 0 : c);
+  for (int sp = 0; sp < S; ++sp) {
+    const int csp = __shfl(c, sp, 64);
+    const int osp = __shfl(off, sp, 64);
+    const size_t o = ((size_t)g * S + sp) * CAP;
+    for (int i = l; i < csp; i += 64) {
+      u[osp + i] = lu[o + i];
+      lo[osp + i] = ll[o + i];
+      jj[osp + i] = lj[o + i];
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const float T = wave_kth_smallest(u, tot, K, shist[wave]);
+  // margin set: ordered compaction of the positions with L <= T
+  int m = 0;
+  for (int base = 0; base < tot; base += 64) {
+    const int i = base + l;
+    const int jv = i < tot ? jj[i] : -1;
+    const bool keep = i < tot && lo[i] <= T && jv >= 0 && jv < Ncand;
+    const uint64_t msk = __ballot(keep);
+    if (keep) jj[m + lanes_below(msk)] = jv;
+    m += __popcll(msk);
+  }
+  if (m < K) {                               // cannot happen with valid lists; stay safe
+    if (l == 0) oflag[g] = 2;
+    return;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // compensated rescoring, one entry per lane
+  const float* kvec = A + (size_t)gg * D;
+  for (int i = l; i < m; i += 64) {
+    const df32 v = exact_dist(xp, H, W, P, Cp, kvec, jj[i], Wc);
+    u[i] = v.hi;
+    lo[i] = v.lo;
+  }
+  int n2 = 1;
+  while (n2 < m) n2 <<= 1;
+  for (int i = m + l; i < n2; i += 64) {
+    u[i] = __int_as_float(0x7f800000);
+    lo[i] = 0.f;
+    jj[i] = 0x7fffffff;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  wave_bitonic(u, lo, jj, n2);
+  for (int q = l; q < K; q += 64) {
+    idx[(size_t)gg * K + q] = jj[q];
+    dd[(size_t)gg * K + q] = u[q];
+  }
+  if (l == 0 && st) {
+    atomicAdd(&st->margin_sum, (unsigned long long)m);
+    atomicMax(&st->margin_max, m);
+  }
+}
+
+// Flagged keys, one block per key (unflagged keys exit at once):
+//  flag 1: the merged lists exceed the wave buffer; merge them here (LDS for
+//          up to UCAP entries), same threshold / rescore / sort as the wave path;
+//  flag 2 (a range list overflowed) or a merge above UCAP: exact full-row
+//          path, every candidate rescored with compensated arithmetic and a
+//          running best list kept in LDS (flat images, where most distances
+//          lie within the error bound of each other).
+__global__ void __launch_bounds__(ST)
+k_rescore_overflow(const float* __restrict__ xp, int H, int W, int P, int Cp, int D,
+                   const float* __restrict__ A, int g0, int S, int Ncand, int K,
+                   const int32_t* __restrict__ lj, const float* __restrict__ lu,
+                   const float* __restrict__ ll, const int32_t* __restrict__ lcnt,
+                   const int32_t* __restrict__ oflag, int32_t* __restrict__ idx,
+                   float* __restrict__ dd, DevStats* st) {
   __shared__ float su[UCAP];
   __shared__ float sl[UCAP];
   __shared__ int sj[UCAP];
-  __shared__ int soff[65];
   __shared__ int ssh[ST / 64 + 1];
-  __shared__ int sflag;
+  __shared__ int soff[65];
   const int g = blockIdx.x;
+  const int flag = oflag[g];
+  if (flag == 0) return;                     // block-uniform
   const int gg = g0 + g;
   const int tid = threadIdx.x;
   const int Wc = W - P + 1;
   const float* kvec = A + (size_t)gg * D;
-
   if (tid == 0) {
-    int tot = 0, ovf = 0;
+    int tot = 0;
     for (int sp = 0; sp < S; ++sp) {
-      int c = lcnt[g * S + sp];
       soff[sp] = tot;
-      if (c < 0) ovf = 1; else tot += c;
+      const int c = lcnt[g * S + sp];
+      tot += c < 0 ? 0 : c;
     }
     soff[S] = tot;
-    sflag = (ovf || tot > UCAP) ? 1 : 0;
   }
   __syncthreads();
-  const bool overflow = sflag != 0;
-  int m = 0;
-  if (!overflow) {
-    const int tot = soff[S];
+  const int tot = soff[S];
+  if (flag == 1 && tot <= UCAP && tot >= K) {
     for (int sp = 0; sp < S; ++sp) {
       const int c = soff[sp + 1] - soff[sp];
       const size_t o = ((size_t)g * S + sp) * CAP;
@@ -229,30 +439,29 @@ k_select_rescore(const float* __restrict__ xp, int H, int W, int P, int Cp, int 
       }
     }
     __syncthreads();
-    // key threshold T = K-th smallest U of the union
     uint32_t lo = 0u, hi = 0xffffffffu;
     while (lo < hi) {
-      uint32_t mid = lo + ((hi - lo) >> 1);
+      const uint32_t mid = lo + ((hi - lo) >> 1);
       int c = 0;
       for (int i = tid; i < tot; i += ST) c += (f2ord(su[i]) <= mid) ? 1 : 0;
       c = block_sum_i(c, ssh);
       if (c >= K) hi = mid; else lo = mid + 1;
     }
     const float T = ord2f(lo);
-    // margin set, ordered compaction into the front of the arrays
+    int m = 0;
     for (int base = 0; base < tot; base += ST) {
-      int i = base + tid;
-      bool keep = i < tot && sl[i] <= T;
-      int jj = keep ? sj[i] : 0;
+      const int i = base + tid;
+      const int jv = i < tot ? sj[i] : -1;
+      const bool keep = i < tot && sl[i] <= T && jv >= 0 && jv < Ncand;
       int tc;
-      int pre = block_excl_scan(keep ? 1 : 0, ssh, &tc);
-      if (keep) sj[m + pre] = jj;            // pre + m <= i: never ahead of unread entries
+      const int pre = block_excl_scan(keep ? 1 : 0, ssh, &tc);
+      if (keep) sj[m + pre] = jv;
       m += tc;
     }
     __syncthreads();
-    // compensated rescoring of the margin set
+    if (m < K) goto full_row;                 // cannot happen with valid lists; stay safe
     for (int i = tid; i < m; i += ST) {
-      df32 v = exact_dist(xp, H, W, P, Cp, kvec, sj[i], Wc);
+      const df32 v = exact_dist(xp, H, W, P, Cp, kvec, sj[i], Wc);
       su[i] = v.hi;
       sl[i] = v.lo;
     }
@@ -269,62 +478,58 @@ k_select_rescore(const float* __restrict__ xp, int H, int W, int P, int Cp, int 
       idx[(size_t)gg * K + q] = sj[q];
       dd[(size_t)gg * K + q] = su[q];
     }
-  } else {
-    // exact scan of the whole row: keep a running best list
-    const int BEST = UCAP;
-    int cur = 0;
-    float th = __int_as_float(0x7f800000), tl = 0.f;
-    int tj = 0x7fffffff;
-    for (int base = 0; base < Ncand; base += ST) {
-      int j = base + tid;
-      df32 v = {0.f, 0.f};
-      bool adm = false;
-      if (j < Ncand) {
-        v = exact_dist(xp, H, W, P, Cp, kvec, j, Wc);
-        adm = df_less(v.hi, v.lo, j, th, tl, tj) || cur < K;
-      }
-      int tc;
-      int pre = block_excl_scan(adm ? 1 : 0, ssh, &tc);
-      if (adm) {
-        su[cur + pre] = v.hi;
-        sl[cur + pre] = v.lo;
-        sj[cur + pre] = j;
-      }
-      cur += tc;
-      __syncthreads();
-      if (cur > BEST - ST || base + ST >= Ncand) {
-        int n2 = 1;
-        while (n2 < cur) n2 <<= 1;
-        for (int i = cur + tid; i < n2; i += ST) {
-          su[i] = __int_as_float(0x7f800000);
-          sl[i] = 0.f;
-          sj[i] = 0x7fffffff;
-        }
-        __syncthreads();
-        block_bitonic(su, sl, sj, n2);
-        cur = cur < K ? cur : K;
-        if (cur >= K) {
-          th = su[K - 1];
-          tl = sl[K - 1];
-          tj = sj[K - 1];
-        }
-        __syncthreads();
-      }
-    }
-    for (int q = tid; q < K; q += ST) {
-      idx[(size_t)gg * K + q] = sj[q];
-      dd[(size_t)gg * K + q] = su[q];
-    }
-    m = -1;
-  }
-  if (tid == 0 && st) {
-    if (m >= 0) {
+    if (tid == 0 && st) {
       atomicAdd(&st->margin_sum, (unsigned long long)m);
       atomicMax(&st->margin_max, m);
-    } else {
-      atomicAdd(&st->overflow, 1);
+    }
+    return;
+  }
+full_row:
+  const int BEST = UCAP;
+  int cur = 0;
+  float th = __int_as_float(0x7f800000), tl = 0.f;
+  int tj = 0x7fffffff;
+  for (int base = 0; base < Ncand; base += ST) {
+    const int j = base + tid;
+    df32 v = {0.f, 0.f};
+    bool adm = false;
+    if (j < Ncand) {
+      v = exact_dist(xp, H, W, P, Cp, kvec, j, Wc);
+      adm = cur < K || df_less(v.hi, v.lo, j, th, tl, tj);
+    }
+    int tc;
+    const int pre = block_excl_scan(adm ? 1 : 0, ssh, &tc);
+    if (adm) {
+      su[cur + pre] = v.hi;
+      sl[cur + pre] = v.lo;
+      sj[cur + pre] = j;
+    }
+    cur += tc;
+    __syncthreads();
+    if (cur > BEST - ST || base + ST >= Ncand) {
+      int n2 = 1;
+      while (n2 < cur) n2 <<= 1;
+      for (int i = cur + tid; i < n2; i += ST) {
+        su[i] = __int_as_float(0x7f800000);
+        sl[i] = 0.f;
+        sj[i] = 0x7fffffff;
+      }
+      __syncthreads();
+      block_bitonic(su, sl, sj, n2);
+      cur = cur < K ? cur : K;
+      if (cur >= K) {
+        th = su[K - 1];
+        tl = sl[K - 1];
+        tj = sj[K - 1];
+      }
+      __syncthreads();
     }
   }
+  for (int q = tid; q < K; q += ST) {
+    idx[(size_t)gg * K + q] = sj[q];
+    dd[(size_t)gg * K + q] = su[q];
+  }
+  if (tid == 0 && st) atomicAdd(&st->overflow, 1);
 }
 
 }  // namespace
@@ -341,9 +546,12 @@ void launch_topk_partial(const glr_plan* pl, const float* dist, const float* kme
 
 void launch_select_rescore(const glr_plan* pl, const float* xp, const float* A, int g0, int nk,
                            const int32_t* lj, const float* lu, const float* ll,
-                           const int32_t* lcnt, int32_t* idx, float* dd, DevStats* st,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_select_rescore, dim3(nk), dim3(ST), 0, s, xp, pl->H, pl->W, pl->P, pl->Cp,
-                     pl->D, A, g0, pl->n_split, pl->Ncand, pl->K, lj, lu, ll,
-                     lcnt, idx, dd, st);
+                           const int32_t* lcnt, int32_t* idx, float* dd, int32_t* oflag,
+                           DevStats* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_select_rescore, dim3((nk + 3) / 4), dim3(256), 0, s, xp, pl->H, pl->W, pl->P,
+                     pl->Cp, pl->D, A, g0, nk, pl->n_split, pl->Ncand, pl->K, lj, lu, ll, lcnt, idx,
+                     dd, oflag, st);
+  hipLaunchKernelGGL(k_rescore_overflow, dim3(nk), dim3(ST), 0, s, xp, pl->H, pl->W, pl->P, pl->Cp,
+                     pl->D, A, g0, pl->n_split, pl->Ncand, pl->K, lj, lu, ll, lcnt, oflag, idx, dd,
+                     st);
 }

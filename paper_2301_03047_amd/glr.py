@@ -44,7 +44,7 @@ class Stats(ctypes.Structure):
                 ("ms_topk", ctypes.c_float), ("ms_select", ctypes.c_float),
                 ("ms_lowrank", ctypes.c_float), ("ms_aggregate", ctypes.c_float),
                 ("ms_data", ctypes.c_float), ("ms_norms", ctypes.c_float),
-                ("match_launches", ctypes.c_int64)]
+                ("match_launches", ctypes.c_int64), ("jacobi_sweeps_sum", ctypes.c_int64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

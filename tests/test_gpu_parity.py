@@ -106,7 +106,8 @@ def test_detect_keys_complex_vs_oracle():
 
 
 @pytest.mark.parametrize("shape", [(8, 40, 40, 6, 60, 32), (2, 30, 33, 5, 40, 45),
-                                   (16, 32, 32, 6, 20, 64), (1, 20, 20, 3, 10, 1)])
+                                   (16, 32, 32, 6, 20, 64), (1, 20, 20, 3, 10, 1),
+                                   (1, 24, 24, 3, 12, 16)])
 def test_lowrank_aggregate_vs_oracle(shape):
     require_gpu()
     C, H, W, P, N, K = shape
