@@ -38,18 +38,33 @@ def parse():
     ap.add_argument("--warmup", type=int, default=30, help="untimed GLR iterations first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=5, help="oracle iterations in the CPU sample")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one plain 1 GiB device-to-device copy (a known-size "
+                         "kernel that scales the HBM byte counters of a profiler run)")
     return ap.parse_args()
 
 
-def algorithmic_work(wl, stats, n_iter):
-    """Per-launch algorithmic work of the main kernels."""
-    N, K, D, Ncand = wl.n_keys, wl.k, wl.dim, wl.n_cand
-    return {
-        # matcher: 2 N N_cand D flop per launch (one launch per distance chunk)
-        "match_flop_per_iter": 2.0 * N * Ncand * D,
-        # top-K scan: reads the FP32 distance chunk once
-        "topk_bytes_per_iter": 4.0 * N * Ncand,
-    }
+KERNEL_SOURCES = {
+    "k_wnnm": "paper_2301_03047_amd/csrc/lowrank.hip",
+    "k_match_f32": "paper_2301_03047_amd/csrc/match.hip",
+    "k_topk_partial": "paper_2301_03047_amd/csrc/topk.hip",
+}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mri_256_traffic.json")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of ``kernel`` from the committed profiler counters
+    (FETCH_SIZE + WRITE_SIZE, scaled by a known-size copy), or None when the
+    kernel's source has changed since the counters were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_FILE))["kernels"][kernel]
+        src = os.path.join(ROOT, KERNEL_SOURCES[kernel])
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["sha256"]:
+            return None
+        return int(rec["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def main():
@@ -64,6 +79,12 @@ def main():
     import synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate_copy:
+        src = torch.ones(256 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     wl = synth.WORKLOADS[WORKLOAD]
     inst = synth.make_instance(wl)
     sig = synth.sigma_schedule(wl)
@@ -108,7 +129,8 @@ def main():
     if dominant == "match":
         roof = {"kernel": "k_match_f32", "bound": "mfma", "achieved": round(match_tflops, 3),
                 "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(match_tflops / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None}
+                "frac": round(match_tflops / PEAK_FP32_MFMA_TFLOPS, 4),
+                "traffic": measured_traffic("k_match_f32")}
     elif dominant == "lowrank":
         # WNNM per group: streamed Householder QR (2 D K^2), Jacobi sweeps on the
         # K x K factor (6 K flop per pair per sweep for the three dots plus 12 K
@@ -120,13 +142,14 @@ def main():
         ach = flop / (stages["lowrank"] * 1e-3) / 1e12
         roof = {"kernel": "k_wnnm", "bound": "alu", "achieved": round(ach, 4),
                 "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(ach / PEAK_FP32_VALU_TFLOPS, 5), "traffic": None,
+                "frac": round(ach / PEAK_FP32_VALU_TFLOPS, 5),
+                "traffic": measured_traffic("k_wnnm"),
                 "note": "upper-bound flop count at the worst group's sweep count"}
     elif dominant == "topk":
         gbs = 4.0 * wl.n_keys * wl.n_cand / (stages["topk"] * 1e-3) / 1e9
         roof = {"kernel": "k_topk_partial", "bound": "hbm", "achieved": round(gbs, 1),
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
-                "traffic": None}
+                "traffic": measured_traffic("k_topk_partial")}
     else:
         roof = {"kernel": dominant, "bound": "latency", "achieved": None, "peak": None,
                 "unit": None, "frac": None, "traffic": None}

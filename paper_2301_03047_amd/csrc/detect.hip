@@ -197,17 +197,25 @@ __global__ void __launch_bounds__(SEL_T) k_select(uint8_t* __restrict__ flag,
         if (match) atomicAdd(&hist[(v >> shift) & 255u], 1);
       }
       __syncthreads();
-      if (tid == 0) {
-        int cum = 0, rem = s_remaining, digit = 0;
-        for (int b = 255; b >= 0; --b) {
-          if (cum + hist[b] >= rem) {
-            digit = b;
-            break;
-          }
-          cum += hist[b];
+      if (tid < 64) {
+        // wave 0: lane l owns bins 255-4l .. 252-4l (descending), so a prefix
+        // sum over lanes counts the scores above each bin
+        const int rem = s_remaining;
+        const int b0 = 255 - 4 * tid;
+        const int c0 = hist[b0], c1 = hist[b0 - 1], c2 = hist[b0 - 2], c3 = hist[b0 - 3];
+        const int tot = c0 + c1 + c2 + c3;
+        const int incl = wave_incl_scan(tot);
+        const int excl = incl - tot;
+        if (excl < rem && rem <= incl) {
+          int digit, above;
+          const int r = rem - excl;
+          if (r <= c0) { digit = b0; above = excl; }
+          else if (r <= c0 + c1) { digit = b0 - 1; above = excl + c0; }
+          else if (r <= c0 + c1 + c2) { digit = b0 - 2; above = excl + c0 + c1; }
+          else { digit = b0 - 3; above = excl + c0 + c1 + c2; }
+          s_prefix = prefix | ((unsigned long long)digit << shift);
+          s_remaining = rem - above;
         }
-        s_prefix = prefix | ((unsigned long long)digit << shift);
-        s_remaining = rem - cum;
       }
       __syncthreads();
     }
