@@ -81,7 +81,12 @@ typedef struct glr_params {
   const float* sigma;    /* host [iters]: noise level per iteration (copied)    */
   float wnnm_c;          /* WNNM weight constant c (default 2*sqrt(2))          */
   float wnnm_eps;        /* WNNM weight regulariser (default 1e-16)             */
-  int32_t precision;     /* GLR_PREC_FP32 | GLR_PREC_BF16_RESCORE               */
+  int32_t precision;     /* matcher contraction: GLR_PREC_FP32 (FP32 MFMA) or
+                            GLR_PREC_BF16_RESCORE (BF16 MFMA on mean-centred
+                            key and candidate patches, FP32 accumulation, with
+                            its own certified error bound); the groups are the
+                            same exact top-K with either, only the margin set
+                            that is rescored differs in size                  */
   int32_t dist_chunk_mb; /* max size of one distance-matrix chunk (MiB)         */
   int32_t timing;        /* nonzero: record per-stage HIP event pairs on the
                             stream (no host sync); glr_read_stats() sums them */

@@ -84,6 +84,34 @@ def topk_exact(x, patch, keys, K, chunk=256, return_boundary=False):
     return idx, dist
 
 
+def distance_map(x, patch, key):
+    """d(key, j) for every candidate j (FP64, ``[Hc*Wc]``) by the direct sum,
+    accumulated one patch offset (c, dy, dx) at a time over shifted copies of
+    the image: no patch matrix, no GEMM form, memory O(H*W).  Used to check
+    single keys of full-size images."""
+    x = np.asarray(x, dtype=np.float64)
+    C, H, W = x.shape
+    P = patch
+    Hc, Wc = H - P + 1, W - P + 1
+    r, c = divmod(int(key), Wc)
+    d = np.zeros((Hc, Wc))
+    for ch in range(C):
+        for dy in range(P):
+            for dx in range(P):
+                diff = x[ch, dy:dy + Hc, dx:dx + Wc] - x[ch, r + dy, c + dx]
+                d += diff * diff
+    return d.reshape(-1)
+
+
+def topk_one(x, patch, key, K):
+    """Exact group of one key from ``distance_map``: (idx [K], dist [K], the
+    (K+1)-th distance or inf)."""
+    d = distance_map(x, patch, key)
+    order = np.lexsort((np.arange(d.size), d))[:K + 1]
+    nxt = d[order[K]] if order.size > K else np.inf
+    return order[:K], d[order[:K]], nxt
+
+
 def topk_bruteforce(x, patch, keys, K):
     """Direct-sum reference over every candidate (no shortlist), FP64."""
     pm = patch_matrix(x, patch)

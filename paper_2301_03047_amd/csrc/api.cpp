@@ -123,21 +123,32 @@ glr_status match_stage(glr_plan* pl, const float* xp, const int32_t* keys, int32
   int32_t* lcnt = (int32_t*)(ws + pl->ws.lcnt);
   int32_t* oflag = (int32_t*)(ws + pl->ws.oflag);
   DevStats* st = (DevStats*)(ws + pl->ws.stats);
+  const bool bf = pl->precision == GLR_PREC_BF16_RESCORE;
+  uint16_t* Ab = (uint16_t*)(ws + pl->ws.Ab);
+  float* kmb = (float*)(ws + pl->ws.kmb);
+  float* cmeta = (float*)(ws + pl->ws.cmeta);
+  float* cm2 = (float*)(ws + pl->ws.cm2);
   {
     StageTimer t(pl, s, T_NORMS);
     launch_gather_keys(pl, xp, keys, A, kmeta, s);
-    launch_cand_norms(pl, xp, pnorm, prt, s);
+    if (bf) {
+      launch_keys_bf16(pl, A, Ab, kmb, s);
+      launch_cand_meta(pl, xp, cmeta, cm2, s);
+    } else {
+      launch_cand_norms(pl, xp, pnorm, prt, s);
+    }
   }
   for (int g0 = 0; g0 < pl->N; g0 += pl->n_chunk) {
     const int nk = std::min(pl->n_chunk, pl->N - g0);
     {
       StageTimer t(pl, s, T_MATCH);
-      launch_match_f32(pl, xp, A, kmeta, pnorm, g0, nk, dist, s);
+      if (bf) launch_match_bf16(pl, xp, Ab, kmb, cmeta, g0, nk, dist, s);
+      else launch_match_f32(pl, xp, A, kmeta, pnorm, g0, nk, dist, s);
       if (pl->timing) pl->match_launches++;
     }
     {
       StageTimer t(pl, s, T_TOPK);
-      launch_topk_partial(pl, dist, kmeta, prt, g0, nk, lj, lu, ll, lcnt, s);
+      launch_topk_partial(pl, dist, bf ? kmb : kmeta, bf ? cm2 : prt, g0, nk, lj, lu, ll, lcnt, s);
     }
     {
       StageTimer t(pl, s, T_SELECT);
@@ -272,8 +283,6 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
   if (pr->iters > 0 && !pr->sigma) return fail(GLR_ERR_INVALID_ARG, "sigma is NULL");
   if (pr->precision != GLR_PREC_FP32 && pr->precision != GLR_PREC_BF16_RESCORE)
     return fail(GLR_ERR_INVALID_ARG, "unknown precision %d", pr->precision);
-  if (pr->precision == GLR_PREC_BF16_RESCORE)
-    return fail(GLR_ERR_UNSUPPORTED, "BF16 matching is not available in this build");
   if (!(pr->wnnm_c >= 0.f) || !(pr->wnnm_eps > 0.f) || !(pr->rho > 0.f))
     return fail(GLR_ERR_INVALID_ARG, "wnnm_c >= 0, wnnm_eps > 0 and rho > 0 required");
   if (pb->modality == GLR_MRI) {
@@ -350,6 +359,11 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
   L.kmeta = c.take((size_t)pl->N * 8);
   L.pnorm = c.take((size_t)Ncand * 4);
   L.prt = c.take((size_t)Ncand * 4);
+  const bool bf = pr->precision == GLR_PREC_BF16_RESCORE;
+  L.Ab = c.take(bf ? (size_t)pl->N * Cp * bf16_key_row(P) * 2 : 0);
+  L.kmb = c.take(bf ? (size_t)pl->N * 16 : 0);
+  L.cmeta = c.take(bf ? (size_t)Ncand * 16 : 0);
+  L.cm2 = c.take(bf ? (size_t)Ncand * 8 : 0);
   L.dist = c.take((size_t)pl->n_chunk * pl->ldd * 4);
   const size_t nlist = (size_t)pl->n_chunk * pl->n_split;
   L.lj = c.take(nlist * GLR_SPLIT_CAP * 4);

@@ -27,6 +27,7 @@ struct WsLayout {
   size_t keys;                   // detected keys [N]
   size_t A, kmeta;               // key matrix [N][D] f32; key norms
   size_t pnorm, prt;             // candidate norms, sqrt
+  size_t Ab, kmb, cmeta, cm2;    // BF16 form: centred keys, key / candidate metadata
   size_t dist;                   // distance chunk [n_chunk][ldd]
   size_t lj, lu, ll, lcnt, oflag; // partial top-K lists, per-key overflow flags
   size_t idx, dd;                // groups [N][K], distances [N][K]
@@ -97,10 +98,16 @@ void launch_cand_norms(const glr_plan* pl, const float* xp, float* pnorm, float*
                        hipStream_t s);
 void launch_match_f32(const glr_plan* pl, const float* xp, const float* A, const float* kmeta,
                       const float* pnorm, int g0, int nk, float* dist, hipStream_t s);
+int bf16_key_row(int P);     // bf16 values per key and channel in the BF16 key layout
+void launch_keys_bf16(const glr_plan* pl, const float* A, uint16_t* Ab, float* kmb, hipStream_t s);
+void launch_cand_meta(const glr_plan* pl, const float* xp, float* cmeta, float* cm2,
+                      hipStream_t s);
+void launch_match_bf16(const glr_plan* pl, const float* xp, const uint16_t* Ab, const float* kmb,
+                       const float* cmeta, int g0, int nk, float* dist, hipStream_t s);
 
 // topk.hip
-void launch_topk_partial(const glr_plan* pl, const float* dist, const float* kmeta,
-                         const float* prt, int g0, int nk, int32_t* lj, float* lu, float* ll,
+void launch_topk_partial(const glr_plan* pl, const float* dist, const float* km,
+                         const float* cm, int g0, int nk, int32_t* lj, float* lu, float* ll,
                          int32_t* lcnt, hipStream_t s);
 void launch_select_rescore(const glr_plan* pl, const float* xp, const float* A, int g0, int nk,
                            const int32_t* lj, const float* lu, const float* ll,

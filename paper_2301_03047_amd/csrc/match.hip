@@ -188,6 +188,251 @@ void launch_match_t(const glr_plan* pl, const float* xp, const float* A, const f
                      (size_t)pl->ldd);
 }
 
+
+// ---------------------------------------------------------------- BF16 form
+// Centred form of the same distance (exact identity):
+//   a = k - mu_k 1, pbar = p - mu_p 1 (FP32),  dmu = mu_k - mu_p,
+//   ||k - p||^2 = ||a||^2 + ||pbar||^2 - 2<a, pbar> + D dmu^2 + 2 dmu (sum a - sum pbar)
+// (plus rounding residues of the two subtractions, covered by the error
+// bound).  <a, pbar> runs on BF16 MFMA with FP32 accumulation; centring both
+// operands shrinks the BF16 rounding error, which scales with ||a|| ||pbar||.
+
+__device__ __forceinline__ uint32_t bf16_rne(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;        // round to nearest even (finite input)
+}
+
+// BF16 operand layout.  A channel's P x P patch block is padded to R rows of
+// X = 8 (P <= 8) or 16 (P <= 16) columns and cut into NS = R*X/8 slices of 8
+// consecutive columns; slice t = y*(X/8) + dx/8.  One MFMA (K = 16) takes two
+// slices, lanes 0-31 the even one and lanes 32-63 the odd one, for the key
+// and the candidate alike.  R is P rounded up to even for X = 8, and 12 or
+// 16 for X = 16 (padding is zero).
+__host__ __device__ constexpr int bf16_slices(int P) {
+  return P <= 8 ? P + (P & 1) : (P <= 12 ? 24 : 32);
+}
+
+// Per key: Ab[g][c][t][0..8) = bf16(k - mu_k) (padding zero),
+// kmb[g] = (||a||^2, mu_k, sum a, ||a||).  One wave per key.
+__global__ void k_keys_bf16(const float* __restrict__ A, int D, int P, int Cp, int NS, int XS,
+                            int N, uint16_t* __restrict__ Ab, float4* __restrict__ kmb) {
+  const int g = blockIdx.x;
+  if (g >= N) return;
+  const float* k = A + (size_t)g * D;
+  const int l = threadIdx.x;
+  float s = 0.f;
+  for (int d = l; d < D; d += 64) s += k[d];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  const float mu = s / (float)D;
+  float an = 0.f, sa = 0.f;
+  const int row = NS * 8;
+  for (int e = l; e < Cp * row; e += 64) {
+    const int c = e / row, rem = e - c * row, t = rem >> 3;
+    const int y = t / XS, dx = (t - y * XS) * 8 + (rem & 7);
+    float a = 0.f;
+    if (y < P && dx < P) {
+      a = k[(c * P + y) * P + dx] - mu;
+      an = fmaf(a, a, an);
+      sa += a;
+    }
+    Ab[(size_t)g * Cp * row + e] = (uint16_t)bf16_rne(a);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    an += __shfl_xor(an, o, 64);
+    sa += __shfl_xor(sa, o, 64);
+  }
+  if (l == 0) kmb[g] = make_float4(an, mu, sa, sqrtf(an));
+}
+
+// Per candidate: cmeta[j] = (mu_p, ||pbar||^2, ||pbar||, sum pbar) with
+// pbar = p - mu_p computed in FP32 exactly as the matcher forms its operand;
+// cm2[j] = (mu_p, ||pbar||) for the error bound of the top-K pass.
+__global__ void k_cand_meta(const float* __restrict__ xp, int Cp, int H, int W, int P,
+                            float4* __restrict__ cmeta, float2* __restrict__ cm2) {
+  const int Wc = W - P + 1, Hc = H - P + 1;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= Hc * Wc) return;
+  const int r = j / Wc, c = j - r * Wc;
+  const int D = Cp * P * P;
+  float s = 0.f;
+  for (int ch = 0; ch < Cp; ++ch)
+    for (int dy = 0; dy < P; ++dy) {
+      const float* row = xp + ((size_t)ch * H + r + dy) * W + c;
+      for (int dx = 0; dx < P; ++dx) s += row[dx];
+    }
+  const float mu = s / (float)D;
+  float pn = 0.f, sp = 0.f;
+  for (int ch = 0; ch < Cp; ++ch)
+    for (int dy = 0; dy < P; ++dy) {
+      const float* row = xp + ((size_t)ch * H + r + dy) * W + c;
+      for (int dx = 0; dx < P; ++dx) {
+        const float v = row[dx] - mu;
+        pn = fmaf(v, v, pn);
+        sp += v;
+      }
+    }
+  const float pr = sqrtf(pn);
+  cmeta[j] = make_float4(mu, pn, pr, sp);
+  cm2[j] = make_float2(mu, pr);
+}
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// BF16 MFMA matcher: 128 keys x 128 candidates per block (one grid-row
+// segment), one channel (NS slices of the padded patch block) per step.
+// The candidate operand is built in LDS per step from the staged image rows:
+// Bs[t][j][0..8) = bf16(x[c][r+y][c0+j+dx] - mu_p(j)) for slice t = (y, dx/8).
+template <int NS>
+__global__ void __launch_bounds__(256)
+k_match_bf16(const float* __restrict__ xp, int H, int W, int P, int Cp,
+             const uint16_t* __restrict__ Ab, const float4* __restrict__ kmb,
+             const float4* __restrict__ cmeta, int g0, int nk, float* __restrict__ dist,
+             size_t ldd) {
+  constexpr int XS = NS > 8 ? 2 : 1;      // slices per patch row
+  constexpr int RP = NS / XS;             // padded rows
+  constexpr int ROWB = NS * 8;            // bf16 per key and channel
+  constexpr int AST = ROWB + 8;           // LDS row stride of the key slab (bf16)
+  constexpr int SEGW = BN + 8 * XS;       // staged image row length
+  constexpr int NAU = ROWB / 16;          // uint4 per thread for the key slab (2 threads/key)
+  constexpr int NSEG = (RP * SEGW + 255) / 256;
+  __shared__ __align__(16) uint16_t As[BM * AST];
+  __shared__ __align__(16) uint16_t Bs[NS * BN * 8];
+  __shared__ float seg[RP * SEGW];
+  __shared__ float mup[BN];
+
+  const int Hc = H - P + 1, Wc = W - P + 1;
+  const int ntc = (Wc + BN - 1) / BN;
+  int b = blockIdx.x;
+  const int ct = b % ntc;
+  b /= ntc;
+  const int r = b % Hc;
+  const int kt = b / Hc;
+  const int c0 = ct * BN;
+  const int kbase = kt * BM;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int l32 = lane & 31, lhi = lane >> 5;
+  const int D = Cp * P * P;
+
+  if (tid < BN) {
+    const int col = c0 + tid;
+    mup[tid] = col < Wc ? cmeta[(size_t)r * Wc + col].x : 0.f;
+  }
+  uint4 ra[NAU];
+  float rs[NSEG];
+  const int akey = tid >> 1, ahalf = tid & 1;
+  auto load_stage = [&](int ch) {
+    const int g = kbase + akey;
+#pragma unroll
+    for (int u = 0; u < NAU; ++u) {
+      ra[u] = make_uint4(0, 0, 0, 0);
+      if (g < nk)
+        ra[u] = *reinterpret_cast<const uint4*>(Ab + ((size_t)(g0 + g) * Cp + ch) * ROWB +
+                                                ahalf * (ROWB / 2) + u * 8);
+    }
+#pragma unroll
+    for (int u = 0; u < NSEG; ++u) {
+      const int e = tid + u * 256;
+      float v = 0.f;
+      if (e < RP * SEGW) {
+        const int y = e / SEGW, cc = c0 + (e - y * SEGW);
+        if (y < P && cc < W) v = xp[((size_t)ch * H + r + y) * W + cc];
+      }
+      rs[u] = v;
+    }
+  };
+
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[i][j][q] = 0.f;
+
+  load_stage(0);
+  for (int ch = 0; ch < Cp; ++ch) {
+#pragma unroll
+    for (int u = 0; u < NAU; ++u)
+      *reinterpret_cast<uint4*>(As + akey * AST + ahalf * (ROWB / 2) + u * 8) = ra[u];
+#pragma unroll
+    for (int u = 0; u < NSEG; ++u) {
+      const int e = tid + u * 256;
+      if (e < RP * SEGW) seg[e] = rs[u];
+    }
+    __syncthreads();
+    for (int e = tid; e < NS * BN; e += 256) {
+      const int t = e / BN, j = e - t * BN;
+      const int y = t / XS, xb = (t - y * XS) * 8;
+      const float m = mup[j];
+      uint32_t w[4];
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const int dx0 = xb + 2 * h, dx1 = xb + 2 * h + 1;
+        const float v0 = (dx0 < P && y < P) ? seg[y * SEGW + j + dx0] - m : 0.f;
+        const float v1 = (dx1 < P && y < P) ? seg[y * SEGW + j + dx1] - m : 0.f;
+        w[h] = bf16_rne(v0) | (bf16_rne(v1) << 16);
+      }
+      *reinterpret_cast<uint4*>(Bs + (size_t)e * 8) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+    __syncthreads();
+    if (ch + 1 < Cp) load_stage(ch + 1);
+#pragma unroll
+    for (int kk = 0; kk < NS / 2; ++kk) {
+      const int t = 2 * kk + lhi;
+      bf16x8 a[2], bb[2];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+        a[mt] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(
+                    As + (wm * 64 + mt * 32 + l32) * AST + t * 8));
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt)
+        bb[nt] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(
+                     Bs + ((size_t)t * BN + wn * 64 + nt * 32 + l32) * 8));
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+          acc[mt][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mt], bb[nt], acc[mt][nt], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+  // epilogue: d~ = ||a||^2 + ||pbar||^2 - 2 S + D dmu^2 + 2 dmu (sum a - sum pbar)
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+      const int col = c0 + wn * 64 + nt * 32 + l32;
+      const bool cok = col < Wc;
+      const size_t t = (size_t)r * Wc + col;
+      const float4 cm = cok ? cmeta[t] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int i = wm * 64 + mt * 32 + 8 * (q >> 2) + 4 * lhi + (q & 3);
+        const int g = kbase + i;
+        if (cok && g < nk) {
+          const float4 km = kmb[g0 + g];
+          const float dmu = km.y - cm.x;
+          const float base = (km.x + cm.y) - 2.0f * acc[mt][nt][q];
+          dist[(size_t)g * ldd + t] = (base + ((float)D * dmu) * dmu) + 2.0f * dmu * (km.z - cm.w);
+        }
+      }
+    }
+}
+
+template <int NS>
+void launch_match_bf16_t(const glr_plan* pl, const float* xp, const uint16_t* Ab,
+                         const float* kmb, const float* cmeta, int g0, int nk, float* dist,
+                         hipStream_t s) {
+  const int ntc = (pl->Wc + BN - 1) / BN;
+  const int nkt = (nk + BM - 1) / BM;
+  const size_t blocks = (size_t)nkt * pl->Hc * ntc;
+  hipLaunchKernelGGL(k_match_bf16<NS>, dim3((unsigned)blocks), dim3(256), 0, s, xp, pl->H, pl->W,
+                     pl->P, pl->Cp, Ab, (const float4*)kmb, (const float4*)cmeta, g0, nk, dist,
+                     (size_t)pl->ldd);
+}
 }  // namespace
 
 void launch_gather_keys(const glr_plan* pl, const float* xp, const int32_t* keys, float* A,
@@ -214,5 +459,32 @@ void launch_match_f32(const glr_plan* pl, const float* xp, const float* A, const
     case 6: launch_match_t<12>(pl, xp, A, kmeta, pnorm, g0, nk, dist, s); break;
     case 7: launch_match_t<14>(pl, xp, A, kmeta, pnorm, g0, nk, dist, s); break;
     default: launch_match_t<16>(pl, xp, A, kmeta, pnorm, g0, nk, dist, s); break;
+  }
+}
+
+int bf16_key_row(int P) { return bf16_slices(P) * 8; }
+
+void launch_keys_bf16(const glr_plan* pl, const float* A, uint16_t* Ab, float* kmb, hipStream_t s) {
+  const int NS = bf16_slices(pl->P);
+  hipLaunchKernelGGL(k_keys_bf16, dim3(pl->N), dim3(64), 0, s, A, pl->D, pl->P, pl->Cp, NS,
+                     NS > 8 ? 2 : 1, pl->N, Ab, (float4*)kmb);
+}
+
+void launch_cand_meta(const glr_plan* pl, const float* xp, float* cmeta, float* cm2,
+                      hipStream_t s) {
+  const int n = pl->Ncand;
+  hipLaunchKernelGGL(k_cand_meta, dim3((n + 255) / 256), dim3(256), 0, s, xp, pl->Cp, pl->H,
+                     pl->W, pl->P, (float4*)cmeta, (float2*)cm2);
+}
+
+void launch_match_bf16(const glr_plan* pl, const float* xp, const uint16_t* Ab, const float* kmb,
+                       const float* cmeta, int g0, int nk, float* dist, hipStream_t s) {
+  switch (bf16_slices(pl->P)) {
+    case 2: launch_match_bf16_t<2>(pl, xp, Ab, kmb, cmeta, g0, nk, dist, s); break;
+    case 4: launch_match_bf16_t<4>(pl, xp, Ab, kmb, cmeta, g0, nk, dist, s); break;
+    case 6: launch_match_bf16_t<6>(pl, xp, Ab, kmb, cmeta, g0, nk, dist, s); break;
+    case 8: launch_match_bf16_t<8>(pl, xp, Ab, kmb, cmeta, g0, nk, dist, s); break;
+    case 24: launch_match_bf16_t<24>(pl, xp, Ab, kmb, cmeta, g0, nk, dist, s); break;
+    default: launch_match_bf16_t<32>(pl, xp, Ab, kmb, cmeta, g0, nk, dist, s); break;
   }
 }

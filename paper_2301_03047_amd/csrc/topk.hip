@@ -1,9 +1,13 @@
 // Top-K grouping (eq. 1 with KNN grouping, searched over the whole image).
 //
-// The matcher's d~ carries a rounding error bounded by
-//     eps_j = coef * (||k|| + ||p_j||)^2,   coef = 2 (D + 8) 2^-24
-// (dot product and norms in FP32, plus the epilogue roundings, with a safety
-// factor of two).  With U_j = d~_j + eps_j and L_j = d~_j - eps_j, let T be
+// The matcher's d~ carries a rounding error bounded by eps_j:
+//  FP32 form:  eps_j = 2 (D + 8) u (||k|| + ||p_j||)^2
+//    (dot product and norms in FP32, plus the epilogue roundings);
+//  BF16 form:  eps_j = 4 (2 b + b^2) ||a|| ||pbar_j|| + (3 D + 26) u R_j^2,
+//              R_j = ||a|| + ||pbar_j|| + sqrt(D) |mu_k - mu_j|
+//    (a, pbar_j the centred key and candidate, b = 2^-9 the BF16 operand
+//    rounding, FP32 accumulation and epilogue in the second term),
+// u = 2^-24, each with a safety factor of two.  With U_j = d~_j + eps_j and L_j = d~_j - eps_j, let T be
 // the K-th smallest U_j of a key: every member of the exact top-K has
 // L_j <= d_j <= T, so the margin set {j : L_j <= T} contains the exact
 // answer.  Stage 1 finds, per (key, candidate range), the range's margin set
@@ -11,6 +15,8 @@
 // pass; stage 2 merges the ranges, applies the key's T, recomputes the
 // distance of each margin member with compensated (double-float32)
 // arithmetic and sorts by (distance, position), lowest position winning ties.
+#include <cmath>
+
 #include "common.h"
 #include "internal.h"
 
@@ -18,6 +24,40 @@ namespace {
 
 constexpr int CAP = GLR_SPLIT_CAP;        // entries per wave buffer
 constexpr int UCAP = GLR_UNION_CAP;       // entries per key in stage 2
+
+// One digit of a radix selection: hist[256] holds the counts of the keys
+// that match the prefix so far, by digit; find the digit of the
+// remaining-th smallest of them and fold it into prefix / remaining.
+// Lane l owns bins 4l..4l+3.
+__device__ __forceinline__ void wave_radix_digit(const int* hist, int shift, uint32_t& prefix,
+                                                 int& remaining) {
+  const int l = lane_id();
+  const int c0 = hist[4 * l], c1 = hist[4 * l + 1], c2 = hist[4 * l + 2], c3 = hist[4 * l + 3];
+  const int tot = c0 + c1 + c2 + c3;
+  const int incl = wave_incl_scan(tot);
+  const int excl = incl - tot;
+  const bool mine = excl < remaining && remaining <= incl;
+  int digit = 0, below = 0;
+  if (mine) {
+    int r = remaining - excl;
+    if (r <= c0) { digit = 4 * l; below = excl; }
+    else if (r <= c0 + c1) { digit = 4 * l + 1; below = excl + c0; }
+    else if (r <= c0 + c1 + c2) { digit = 4 * l + 2; below = excl + c0 + c1; }
+    else { digit = 4 * l + 3; below = excl + c0 + c1 + c2; }
+  }
+  const uint64_t who = __ballot(mine);
+  const int src = who ? (int)__builtin_ctzll(who) : 0;
+  digit = __shfl(digit, src, 64);
+  below = __shfl(below, src, 64);
+  prefix |= (uint32_t)digit << shift;
+  remaining -= below;
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // K-th smallest of vals[0..n) by radix selection on the ordered uint32 keys:
 // four passes of an 8-bit digit histogram in LDS (integer adds), most
@@ -29,37 +69,40 @@ __device__ float wave_kth_smallest(const float* vals, int n, int K, int* hist) {
   for (int shift = 24; shift >= 0; shift -= 8) {
 #pragma unroll
     for (int b = 0; b < 4; ++b) hist[4 * l + b] = 0;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_sync_lds();
     const uint32_t hmask = shift == 24 ? 0u : (0xffffffffu << (shift + 8));
     for (int i = l; i < n; i += 64) {
       const uint32_t key = f2ord(vals[i]);
       if ((key & hmask) == (prefix & hmask)) atomicAdd(&hist[(key >> shift) & 255u], 1);
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // lane l owns bins 4l..4l+3; find the bin holding the remaining-th key
-    const int c0 = hist[4 * l], c1 = hist[4 * l + 1], c2 = hist[4 * l + 2], c3 = hist[4 * l + 3];
-    const int tot = c0 + c1 + c2 + c3;
-    const int incl = wave_incl_scan(tot);
-    const int excl = incl - tot;
-    const bool mine = excl < remaining && remaining <= incl;
-    int digit = 0, below = 0;
-    if (mine) {
-      int r = remaining - excl;
-      if (r <= c0) { digit = 4 * l; below = excl; }
-      else if (r <= c0 + c1) { digit = 4 * l + 1; below = excl + c0; }
-      else if (r <= c0 + c1 + c2) { digit = 4 * l + 2; below = excl + c0 + c1; }
-      else { digit = 4 * l + 3; below = excl + c0 + c1 + c2; }
+    wave_sync_lds();
+    wave_radix_digit(hist, shift, prefix, remaining);
+  }
+  return ord2f(prefix);
+}
+
+// Same selection over S lists in global memory: list sp holds
+// __shfl(c, sp) values at lists + sp * CAP (c: lane sp's count).  Requires
+// the total count >= K >= 1.
+__device__ float wave_kth_lists(const float* __restrict__ lists, int c, int S, int K, int* hist) {
+  const int l = lane_id();
+  uint32_t prefix = 0u;
+  int remaining = K;
+  for (int shift = 24; shift >= 0; shift -= 8) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) hist[4 * l + b] = 0;
+    wave_sync_lds();
+    const uint32_t hmask = shift == 24 ? 0u : (0xffffffffu << (shift + 8));
+    for (int sp = 0; sp < S; ++sp) {
+      const int csp = __shfl(c, sp, 64);
+      const float* src = lists + (size_t)sp * CAP;
+      for (int i = l; i < csp; i += 64) {
+        const uint32_t key = f2ord(src[i]);
+        if ((key & hmask) == (prefix & hmask)) atomicAdd(&hist[(key >> shift) & 255u], 1);
+      }
     }
-    const uint64_t who = __ballot(mine);
-    const int src = who ? (int)__builtin_ctzll(who) : 0;
-    digit = __shfl(digit, src, 64);
-    below = __shfl(below, src, 64);
-    prefix |= (uint32_t)digit << shift;
-    remaining -= below;
+    wave_sync_lds();
+    wave_radix_digit(hist, shift, prefix, remaining);
   }
   return ord2f(prefix);
 }
@@ -88,11 +131,15 @@ __device__ int wave_compact(int* bj, float* bu, float* bl, int n, float T) {
   return w;
 }
 
+// BF = false: km = (||k||^2, ||k||) per key, cm = ||p_j|| per candidate.
+// BF = true:  km = (||a||^2, mu_k, sum a, ||a||) per key, cm = (mu_j, ||pbar_j||)
+//             per candidate.
+template <bool BF>
 __global__ void __launch_bounds__(256)
-k_topk_partial(const float* __restrict__ dist, size_t ldd, const float2* __restrict__ kmeta, int g0,
-               const float* __restrict__ prt, int Ncand, int split_len, int S, int nk, int K,
-               float coef, int32_t* __restrict__ lj, float* __restrict__ lu, float* __restrict__ ll,
-               int32_t* __restrict__ lcnt) {
+k_topk_partial(const float* __restrict__ dist, size_t ldd, const float* __restrict__ km, int g0,
+               const float* __restrict__ cm, int Ncand, int split_len, int S, int nk, int K,
+               float coef, float coef2, float sqrtD, int32_t* __restrict__ lj,
+               float* __restrict__ lu, float* __restrict__ ll, int32_t* __restrict__ lcnt) {
   __shared__ int sbj[4][CAP];
   __shared__ float sbu[4][CAP];
   __shared__ float sbl[4][CAP];
@@ -108,7 +155,8 @@ k_topk_partial(const float* __restrict__ dist, size_t ldd, const float2* __restr
   const int g = item / S, sp = item - g * S;
   const int j0 = sp * split_len;
   const int j1 = min(Ncand, j0 + split_len);
-  const float kr = kmeta[g0 + g].y;
+  const float kr = BF ? km[4 * (size_t)(g0 + g) + 3] : km[2 * (size_t)(g0 + g) + 1];
+  const float kmu = BF ? km[4 * (size_t)(g0 + g) + 1] : 0.f;
   const float* drow = dist + (size_t)g * ldd;
   float T = __int_as_float(0x7f800000);     // +inf
   int cnt = 0;
@@ -119,29 +167,42 @@ k_topk_partial(const float* __restrict__ dist, size_t ldd, const float2* __restr
   // element can enter the margin set.
   constexpr int U4 = 4;
   constexpr int CH = 256 * U4;
-  float dv[U4][4], pv[U4][4], dn[U4][4], pn[U4][4];
-  auto load = [&](int base, float (&d)[U4][4], float (&p)[U4][4]) {
+  // pv: ||p_j|| (FP32 form) or ||pbar_j|| (BF16 form); mv: mu_j (BF16 form)
+  float dv[U4][4], pv[U4][4], mv[U4][4], dn[U4][4], pn[U4][4], mn[U4][4];
+  auto load = [&](int base, float (&d)[U4][4], float (&p)[U4][4], float (&m)[U4][4]) {
 #pragma unroll
     for (int u = 0; u < U4; ++u) {
       const int j = base + u * 256 + 4 * l;
       if (j + 3 < j1) {
         const float4 a = *reinterpret_cast<const float4*>(drow + j);
-        const float4 b = *reinterpret_cast<const float4*>(prt + j);
         d[u][0] = a.x; d[u][1] = a.y; d[u][2] = a.z; d[u][3] = a.w;
-        p[u][0] = b.x; p[u][1] = b.y; p[u][2] = b.z; p[u][3] = b.w;
+        if constexpr (BF) {
+          const float4 b0 = *reinterpret_cast<const float4*>(cm + 2 * (size_t)j);
+          const float4 b1 = *reinterpret_cast<const float4*>(cm + 2 * (size_t)j + 4);
+          m[u][0] = b0.x; p[u][0] = b0.y; m[u][1] = b0.z; p[u][1] = b0.w;
+          m[u][2] = b1.x; p[u][2] = b1.y; m[u][3] = b1.z; p[u][3] = b1.w;
+        } else {
+          const float4 b = *reinterpret_cast<const float4*>(cm + j);
+          p[u][0] = b.x; p[u][1] = b.y; p[u][2] = b.z; p[u][3] = b.w;
+        }
       } else {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const bool ok = j + e < j1;
           d[u][e] = ok ? drow[j + e] : 0.f;
-          p[u][e] = ok ? prt[j + e] : 0.f;
+          if constexpr (BF) {
+            m[u][e] = ok ? cm[2 * (size_t)(j + e)] : 0.f;
+            p[u][e] = ok ? cm[2 * (size_t)(j + e) + 1] : 0.f;
+          } else {
+            p[u][e] = ok ? cm[j + e] : 0.f;
+          }
         }
       }
     }
   };
-  load(j0, dv, pv);
+  load(j0, dv, pv, mv);
   for (int base = j0; base < j1; base += CH) {
-    if (base + CH < j1) load(base + CH, dn, pn);
+    if (base + CH < j1) load(base + CH, dn, pn, mn);
     // positions past the end of the range are never admitted (explicit
     // validity: an infinite L would still pass L <= T while T is +inf)
     float Lv[U4][4], Uv[U4][4];
@@ -151,8 +212,14 @@ k_topk_partial(const float* __restrict__ dist, size_t ldd, const float2* __restr
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int j = base + u * 256 + 4 * l + e;
-        const float sm = kr + pv[u][e];
-        const float eps = coef * (sm * sm);
+        float eps;
+        if constexpr (BF) {
+          const float R = (kr + pv[u][e]) + sqrtD * fabsf(kmu - mv[u][e]);
+          eps = coef * (kr * pv[u][e]) + coef2 * (R * R);
+        } else {
+          const float sm = kr + pv[u][e];
+          eps = coef * (sm * sm);
+        }
         ok[u][e] = j < j1;
         Uv[u][e] = dv[u][e] + eps;
         Lv[u][e] = dv[u][e] - eps;
@@ -206,6 +273,7 @@ k_topk_partial(const float* __restrict__ dist, size_t ldd, const float2* __restr
       for (int e = 0; e < 4; ++e) {
         dv[u][e] = dn[u][e];
         pv[u][e] = pn[u][e];
+        if constexpr (BF) mv[u][e] = mn[u][e];
       }
   }
   if (!ovf && cnt >= K) {
@@ -295,12 +363,15 @@ __device__ void wave_bitonic(float* h, float* lo, int* j, int n) {
     }
 }
 
-constexpr int UW = 1024;          // union capacity per key (wave path)
+constexpr int UW = 1024;          // margin-set capacity per key (wave path)
 
-// One wave per key: merge the per-range lists, apply the key's threshold,
-// rescore the margin set with compensated arithmetic, sort by
-// (distance, position) and keep the first K.  Keys whose lists overflowed
-// are flagged for the exact full-row kernel below.
+// One wave per key: the key's threshold T (K-th smallest U over all range
+// lists) by a radix selection streamed over the lists, the margin set
+// {L <= T} gathered in list order, rescored with compensated arithmetic,
+// sorted by (distance, position); the first K are kept.  Only the margin set
+// is held in LDS, so the lists' union may be far larger than UW.  Keys
+// whose margin set exceeds UW, or whose range lists overflowed, are flagged
+// for the kernel below.
 __global__ void __launch_bounds__(256)
 k_select_rescore(const float* __restrict__ xp, int H, int W, int P, int Cp, int D,
                  const float* __restrict__ A, int g0, int nk, int S, int Ncand, int K,
@@ -324,45 +395,34 @@ k_select_rescore(const float* __restrict__ xp, int H, int W, int P, int Cp, int 
   // split counts (S <= 64: one lane per split)
   const int c = l < S ? lcnt[g * S + l] : 0;
   const bool bad = __ballot(c < 0) != 0;
-  const int incl = wave_incl_scan(c < 0 ? 0 : c);
-  const int tot = __shfl(incl, 63, 64);
-  if (bad || tot > UW) {
-    if (l == 0) oflag[g] = bad ? 2 : 1;     // 1: merge in the block kernel; 2: full row
+  const int tot = wave_sum_i32(c < 0 ? 0 : c);
+  if (bad || tot < K) {
+    if (l == 0) oflag[g] = 2;               // exact full-row path
+    return;
+  }
+  const size_t o0 = (size_t)g * S * CAP;
+  const float T = wave_kth_lists(lu + o0, c, S, K, shist[wave]);
+  // margin set: ordered compaction of the entries with L <= T
+  int m = 0;
+  for (int sp = 0; sp < S; ++sp) {
+    const int csp = __shfl(c, sp, 64);
+    const size_t o = o0 + (size_t)sp * CAP;
+    for (int base = 0; base < csp; base += 64) {
+      const int i = base + l;
+      const int jv = i < csp ? lj[o + i] : -1;
+      const bool keep = i < csp && ll[o + i] <= T && jv >= 0 && jv < Ncand;
+      const uint64_t msk = __ballot(keep);
+      const int pos = m + lanes_below(msk);
+      if (keep && pos < UW) jj[pos] = jv;
+      m += __popcll(msk);
+    }
+  }
+  if (m > UW || m < K) {                     // m < K cannot happen with valid lists
+    if (l == 0) oflag[g] = m > UW ? 1 : 2;
     return;
   }
   if (l == 0) oflag[g] = 0;
-  const int off = incl - (c < 0 ? 0 : c);
-  for (int sp = 0; sp < S; ++sp) {
-    const int csp = __shfl(c, sp, 64);
-    const int osp = __shfl(off, sp, 64);
-    const size_t o = ((size_t)g * S + sp) * CAP;
-    for (int i = l; i < csp; i += 64) {
-      u[osp + i] = lu[o + i];
-      lo[osp + i] = ll[o + i];
-      jj[osp + i] = lj[o + i];
-    }
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  const float T = wave_kth_smallest(u, tot, K, shist[wave]);
-  // margin set: ordered compaction of the positions with L <= T
-  int m = 0;
-  for (int base = 0; base < tot; base += 64) {
-    const int i = base + l;
-    const int jv = i < tot ? jj[i] : -1;
-    const bool keep = i < tot && lo[i] <= T && jv >= 0 && jv < Ncand;
-    const uint64_t msk = __ballot(keep);
-    if (keep) jj[m + lanes_below(msk)] = jv;
-    m += __popcll(msk);
-  }
-  if (m < K) {                               // cannot happen with valid lists; stay safe
-    if (l == 0) oflag[g] = 2;
-    return;
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  wave_sync_lds();
   // compensated rescoring, one entry per lane
   const float* kvec = A + (size_t)gg * D;
   for (int i = l; i < m; i += 64) {
@@ -377,9 +437,7 @@ k_select_rescore(const float* __restrict__ xp, int H, int W, int P, int Cp, int 
     lo[i] = 0.f;
     jj[i] = 0x7fffffff;
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  wave_sync_lds();
   wave_bitonic(u, lo, jj, n2);
   for (int q = l; q < K; q += 64) {
     idx[(size_t)gg * K + q] = jj[q];
@@ -392,12 +450,12 @@ k_select_rescore(const float* __restrict__ xp, int H, int W, int P, int Cp, int 
 }
 
 // Flagged keys, one block per key (unflagged keys exit at once):
-//  flag 1: the merged lists exceed the wave buffer; merge them here (LDS for
-//          up to UCAP entries), same threshold / rescore / sort as the wave path;
-//  flag 2 (a range list overflowed) or a merge above UCAP: exact full-row
-//          path, every candidate rescored with compensated arithmetic and a
-//          running best list kept in LDS (flat images, where most distances
-//          lie within the error bound of each other).
+//  flag 1: the margin set exceeds the wave buffer; same threshold / rescore /
+//          sort as the wave path with up to UCAP margin entries in LDS;
+//  flag 2 (a range list overflowed) or a margin set above UCAP: exact
+//          full-row path, every candidate rescored with compensated
+//          arithmetic and a running best list kept in LDS (flat images, where
+//          most distances lie within the error bound of each other).
 __global__ void __launch_bounds__(ST)
 k_rescore_overflow(const float* __restrict__ xp, int H, int W, int P, int Cp, int D,
                    const float* __restrict__ A, int g0, int S, int Ncand, int K,
@@ -409,7 +467,7 @@ k_rescore_overflow(const float* __restrict__ xp, int H, int W, int P, int Cp, in
   __shared__ float sl[UCAP];
   __shared__ int sj[UCAP];
   __shared__ int ssh[ST / 64 + 1];
-  __shared__ int soff[65];
+  __shared__ int scnt[64];
   const int g = blockIdx.x;
   const int flag = oflag[g];
   if (flag == 0) return;                     // block-uniform
@@ -417,48 +475,39 @@ k_rescore_overflow(const float* __restrict__ xp, int H, int W, int P, int Cp, in
   const int tid = threadIdx.x;
   const int Wc = W - P + 1;
   const float* kvec = A + (size_t)gg * D;
-  if (tid == 0) {
-    int tot = 0;
-    for (int sp = 0; sp < S; ++sp) {
-      soff[sp] = tot;
-      const int c = lcnt[g * S + sp];
-      tot += c < 0 ? 0 : c;
-    }
-    soff[S] = tot;
-  }
+  if (tid < S) scnt[tid] = lcnt[g * S + tid];
   __syncthreads();
-  const int tot = soff[S];
-  if (flag == 1 && tot <= UCAP && tot >= K) {
-    for (int sp = 0; sp < S; ++sp) {
-      const int c = soff[sp + 1] - soff[sp];
-      const size_t o = ((size_t)g * S + sp) * CAP;
-      for (int i = tid; i < c; i += ST) {
-        su[soff[sp] + i] = lu[o + i];
-        sl[soff[sp] + i] = ll[o + i];
-        sj[soff[sp] + i] = lj[o + i];
-      }
-    }
-    __syncthreads();
+  if (flag == 1) {
+    const size_t o0 = (size_t)g * S * CAP;
+    // T: smallest U value (as ordered bits) with at least K list values <= it
     uint32_t lo = 0u, hi = 0xffffffffu;
     while (lo < hi) {
       const uint32_t mid = lo + ((hi - lo) >> 1);
       int c = 0;
-      for (int i = tid; i < tot; i += ST) c += (f2ord(su[i]) <= mid) ? 1 : 0;
+      for (int sp = 0; sp < S; ++sp) {
+        const int csp = scnt[sp];
+        for (int i = tid; i < csp; i += ST) c += (f2ord(lu[o0 + (size_t)sp * CAP + i]) <= mid) ? 1 : 0;
+      }
       c = block_sum_i(c, ssh);
       if (c >= K) hi = mid; else lo = mid + 1;
     }
     const float T = ord2f(lo);
     int m = 0;
-    for (int base = 0; base < tot; base += ST) {
-      const int i = base + tid;
-      const int jv = i < tot ? sj[i] : -1;
-      const bool keep = i < tot && sl[i] <= T && jv >= 0 && jv < Ncand;
-      int tc;
-      const int pre = block_excl_scan(keep ? 1 : 0, ssh, &tc);
-      if (keep) sj[m + pre] = jv;
-      m += tc;
+    for (int sp = 0; sp < S; ++sp) {
+      const int csp = scnt[sp];
+      const size_t o = o0 + (size_t)sp * CAP;
+      for (int base = 0; base < csp; base += ST) {
+        const int i = base + tid;
+        const int jv = i < csp ? lj[o + i] : -1;
+        const bool keep = i < csp && ll[o + i] <= T && jv >= 0 && jv < Ncand;
+        int tc;
+        const int pre = block_excl_scan(keep ? 1 : 0, ssh, &tc);
+        if (keep && m + pre < UCAP) sj[m + pre] = jv;
+        m += tc;
+      }
     }
     __syncthreads();
+    if (m > UCAP) goto full_row;
     if (m < K) goto full_row;                 // cannot happen with valid lists; stay safe
     for (int i = tid; i < m; i += ST) {
       const df32 v = exact_dist(xp, H, W, P, Cp, kvec, sj[i], Wc);
@@ -534,14 +583,27 @@ full_row:
 
 }  // namespace
 
-void launch_topk_partial(const glr_plan* pl, const float* dist, const float* kmeta,
-                         const float* prt, int g0, int nk, int32_t* lj, float* lu, float* ll,
+void launch_topk_partial(const glr_plan* pl, const float* dist, const float* km,
+                         const float* cm, int g0, int nk, int32_t* lj, float* lu, float* ll,
                          int32_t* lcnt, hipStream_t s) {
-  const float coef = 2.0f * (float)(pl->D + 8) * 5.9604644775390625e-08f;   // 2^-24
+  const double u = 5.9604644775390625e-08;      // 2^-24
+  const double b = 0.001953125;                 // 2^-9
   const int items = nk * pl->n_split;
-  hipLaunchKernelGGL(k_topk_partial, dim3((items + 3) / 4), dim3(256), 0, s, dist, (size_t)pl->ldd,
-                     (const float2*)kmeta, g0, prt, pl->Ncand, pl->split_len, pl->n_split, nk,
-                     pl->K, coef, lj, lu, ll, lcnt);
+  const dim3 grid((items + 3) / 4);
+  if (pl->precision == GLR_PREC_BF16_RESCORE) {
+    // coefficients rounded up so that the float values are not below the bound
+    const float coef = std::nextafter((float)(4.0 * (2.0 * b + b * b)), 1.f);
+    const float coef2 = std::nextafter((float)((3.0 * pl->D + 26.0) * u), 1.f);
+    const float sqrtD = std::nextafter((float)std::sqrt((double)pl->D), 1e9f);
+    hipLaunchKernelGGL(k_topk_partial<true>, grid, dim3(256), 0, s, dist, (size_t)pl->ldd, km, g0,
+                       cm, pl->Ncand, pl->split_len, pl->n_split, nk, pl->K, coef, coef2, sqrtD,
+                       lj, lu, ll, lcnt);
+  } else {
+    const float coef = std::nextafter((float)(2.0 * (pl->D + 8) * u), 1.f);
+    hipLaunchKernelGGL(k_topk_partial<false>, grid, dim3(256), 0, s, dist, (size_t)pl->ldd, km, g0,
+                       cm, pl->Ncand, pl->split_len, pl->n_split, nk, pl->K, coef, 0.f, 0.f, lj,
+                       lu, ll, lcnt);
+  }
 }
 
 void launch_select_rescore(const glr_plan* pl, const float* xp, const float* A, int g0, int nk,

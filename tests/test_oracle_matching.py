@@ -97,3 +97,20 @@ def test_patch_vector_order():
     row = pm[1 * Wc + 2]
     assert row.tolist() == [x[0, 1, 2], x[0, 1, 3], x[0, 2, 2], x[0, 2, 3],
                             x[1, 1, 2], x[1, 1, 3], x[1, 2, 2], x[1, 2, 3]]
+
+
+@pytest.mark.parametrize("kind", ["uniform", "dup", "smooth"])
+def test_single_key_distance_map_equals_exact_rational_bruteforce(kind):
+    # the shifted-image form used for full-size single keys gives the same
+    # groups as exact rational arithmetic, and its distances are the direct sums
+    x = synth.workloads.random_image(2, 12, 12, seed=11, kind=kind)
+    P, K = 3, 6
+    keys = [0, 23, 50, 99]
+    ref = _bf_exact(x, P, keys, K)
+    for a, g in enumerate(keys):
+        idx, dist, nxt = mt.topk_one(x, P, g, K)
+        assert idx.tolist() == ref[a]
+        full = mt.distance_map(x, P, g)
+        np.testing.assert_allclose(full, mt.direct_distances(x, P, g, np.arange(full.size)),
+                                   rtol=1e-13, atol=1e-300)
+        assert nxt >= dist[-1]
