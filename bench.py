@@ -3,9 +3,12 @@
 
 A step is one outer iteration of the data-fidelity loop: the data step plus
 the whole GLR prior step (key detection, global matching, top-K grouping,
-WNNM shrinkage, aggregation) over the synthetic single-coil MRI workload
-(256 x 256 complex64, 6 x 6 patches, 1024 keys, K = 45, 30 ADMM iterations).
-Inputs are resident in HBM before the timed region starts.
+WNNM shrinkage, aggregation).  The default workload is the synthetic
+single-coil MRI problem (256 x 256 complex64, 6 x 6 patches, 1024 keys,
+K = 45, 30 ADMM iterations); ``--workload`` selects another one (the
+1024 x 1024 x 24-frame CACTI problem with ``--precision bf16`` is the
+precision form at scale).  Inputs are resident in HBM before the timed
+region starts.
 
 Prints one JSON line.  ``roofline`` covers the dominant kernel (largest share
 of the timed region), with its average launch duration taken from HIP events
@@ -27,6 +30,7 @@ WORKLOAD = "mri_256"
 
 # MI355X published peaks
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_FP32_VALU_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
@@ -38,6 +42,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=30, help="untimed GLR iterations first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=5, help="oracle iterations in the CPU sample")
+    ap.add_argument("--workload", default=WORKLOAD, choices=["mri_256", "cacti_1024", "msfa_512",
+                                                              "cacti_128"])
+    ap.add_argument("--precision", default=None, choices=["fp32", "bf16"],
+                    help="matcher precision (default: the workload's own)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 1 GiB device-to-device copy (a known-size "
                          "kernel that scales the HBM byte counters of a profiler run)")
@@ -47,18 +55,31 @@ def parse():
 KERNEL_SOURCES = {
     "k_wnnm": "paper_2301_03047_amd/csrc/lowrank.hip",
     "k_match_f32": "paper_2301_03047_amd/csrc/match.hip",
+    "k_match_bf16": "paper_2301_03047_amd/csrc/match.hip",
     "k_topk_partial": "paper_2301_03047_amd/csrc/topk.hip",
 }
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mri_256_traffic.json")
+CONFIG_TEXT = {
+    "mri_256": {"image": "256x256 complex64", "solver": "ADMM",
+                "mask": "25% random Cartesian lines, 16 centre lines kept"},
+    "cacti_1024": {"image": "1024x1024, 24 frames per snapshot", "solver": "GAP",
+                   "mask": "Bernoulli(0.5) binary coded apertures"},
+    "msfa_512": {"image": "512x512x16 bands", "solver": "GAP", "mask": "4x4 periodic MSFA"},
+    "cacti_128": {"image": "128x128, 8 frames per snapshot", "solver": "GAP",
+                  "mask": "Bernoulli(0.5) binary coded apertures"},
+}
 
 
-def measured_traffic(kernel):
+def traffic_file(workload):
+    return os.path.join(ROOT, "profiles", f"{workload}_traffic.json")
+
+
+def measured_traffic(kernel, workload):
     """HBM bytes per launch of ``kernel`` from the committed profiler counters
     (FETCH_SIZE + WRITE_SIZE, scaled by a known-size copy), or None when the
     kernel's source has changed since the counters were taken."""
     import hashlib
     try:
-        rec = json.load(open(TRAFFIC_FILE))["kernels"][kernel]
+        rec = json.load(open(traffic_file(workload)))["kernels"][kernel]
         src = os.path.join(ROOT, KERNEL_SOURCES[kernel])
         if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["sha256"]:
             return None
@@ -85,14 +106,16 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    wl = synth.WORKLOADS[WORKLOAD]
+    wname = args.workload
+    wl = synth.WORKLOADS[wname]
+    prec = args.precision or wl.precision
     inst = synth.make_instance(wl)
     sig = synth.sigma_schedule(wl)
     T = wl.iters
-    mask = torch.from_numpy(inst["mask"]).cuda()
+    mask = torch.from_numpy(inst["mask"]).cuda() if inst["mask"] is not None else None
     x_true = torch.from_numpy(inst["x_true"]).cuda()
     plan = glr.Plan(wl.modality, wl.H, wl.W, wl.C, wl.patch, wl.n_keys, wl.k, iters=T,
-                    sigma=sig, mask=mask, timing=True)
+                    sigma=sig, mask=mask, timing=True, precision=prec)
     y = plan.forward(x_true)                       # measurement synthesised on the GPU
     state = plan.new_state()
     out = torch.empty_like(x_true)
@@ -126,11 +149,13 @@ def main():
     dominant = max(stages, key=stages.get)
 
     # roofline of the dominant kernel
+    match_kernel = "k_match_bf16" if prec == "bf16" else "k_match_f32"
+    match_peak = PEAK_BF16_MFMA_TFLOPS if prec == "bf16" else PEAK_FP32_MFMA_TFLOPS
     if dominant == "match":
-        roof = {"kernel": "k_match_f32", "bound": "mfma", "achieved": round(match_tflops, 3),
-                "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(match_tflops / PEAK_FP32_MFMA_TFLOPS, 4),
-                "traffic": measured_traffic("k_match_f32")}
+        roof = {"kernel": match_kernel, "bound": "mfma", "achieved": round(match_tflops, 3),
+                "peak": match_peak, "unit": "TFLOP/s",
+                "frac": round(match_tflops / match_peak, 4),
+                "traffic": measured_traffic(match_kernel, wname)}
     elif dominant == "lowrank":
         # WNNM per group: streamed Householder QR (2 D K^2), Jacobi sweeps on the
         # K x K factor (6 K flop per pair per sweep for the three dots plus 12 K
@@ -143,13 +168,13 @@ def main():
         roof = {"kernel": "k_wnnm", "bound": "alu", "achieved": round(ach, 4),
                 "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(ach / PEAK_FP32_VALU_TFLOPS, 5),
-                "traffic": measured_traffic("k_wnnm"),
+                "traffic": measured_traffic("k_wnnm", wname),
                 "note": "upper-bound flop count at the worst group's sweep count"}
     elif dominant == "topk":
         gbs = 4.0 * wl.n_keys * wl.n_cand / (stages["topk"] * 1e-3) / 1e9
         roof = {"kernel": "k_topk_partial", "bound": "hbm", "achieved": round(gbs, 1),
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
-                "traffic": measured_traffic("k_topk_partial")}
+                "traffic": measured_traffic("k_topk_partial", wname)}
     else:
         roof = {"kernel": dominant, "bound": "latency", "achieved": None, "peak": None,
                 "unit": None, "frac": None, "traffic": None}
@@ -162,7 +187,7 @@ def main():
 
     cpu = None
     psnr_cmp = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and wname == "mri_256":
         from threadpoolctl import threadpool_info
         from oracle import reconstruct as orc
         n_it = args.cpu_iters
@@ -174,7 +199,7 @@ def main():
         threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
         cpu = {"value": round(n_it / dt, 4), "unit": "iterations/s", "cores": threads,
                "kind": "oracle",
-               "sample": f"first {n_it} of {T} ADMM iterations of {WORKLOAD} (same input), "
+               "sample": f"first {n_it} of {T} ADMM iterations of {wname} (same input), "
                          f"{dt:.1f} s on {os.cpu_count()} host CPUs"}
         g5, _ = plan.reconstruct(y, 0, n_it)
         pg = om_metrics.psnr(g5.cpu().numpy(), xt)
@@ -186,15 +211,15 @@ def main():
     rec = {
         "metric": METRIC, "value": round(value, 3), "unit": "iterations/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16+f32" if prec == "bf16" else "f32",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "image": "256x256 complex64", "patch": 6,
-                   "keys": wl.n_keys, "K": wl.k, "iters": T, "solver": "ADMM",
-                   "mask": "25% random Cartesian lines, 16 centre lines kept"},
+        "config": dict({"workload": wname, "patch": wl.patch, "keys": wl.n_keys, "K": wl.k,
+                        "iters": T, "matcher": prec}, **CONFIG_TEXT[wname]),
         "roofline": roof,
         "cpu_baseline": cpu,
         "matching_tflops": round(match_tflops, 3),
-        "matching_frac_fp32_mfma_peak": round(match_tflops / PEAK_FP32_MFMA_TFLOPS, 4),
+        "matching_frac_mfma_peak": round(match_tflops / match_peak, 4),
         "stages_ms_per_step": {k: round(v, 4) for k, v in stages.items()},
         "psnr_full_db": round(psnr_full, 4),
         "psnr_vs_oracle": psnr_cmp,

@@ -81,12 +81,13 @@ typedef struct glr_params {
   const float* sigma;    /* host [iters]: noise level per iteration (copied)    */
   float wnnm_c;          /* WNNM weight constant c (default 2*sqrt(2))          */
   float wnnm_eps;        /* WNNM weight regulariser (default 1e-16)             */
-  int32_t precision;     /* matcher contraction: GLR_PREC_FP32 (FP32 MFMA) or
-                            GLR_PREC_BF16_RESCORE (BF16 MFMA on mean-centred
-                            key and candidate patches, FP32 accumulation, with
-                            its own certified error bound); the groups are the
-                            same exact top-K with either, only the margin set
-                            that is rescored differs in size                  */
+  int32_t precision;     /* matcher contraction on mean-centred key and
+                            candidate patches: GLR_PREC_FP32 (FP32 MFMA) or
+                            GLR_PREC_BF16_RESCORE (BF16 MFMA, FP32 sums, with
+                            its own certified error bound; keys whose margin
+                            set would not fit are re-matched in FP32).  The
+                            groups are the same exact top-K with either; only
+                            the work spent on the margin sets differs        */
   int32_t dist_chunk_mb; /* max size of one distance-matrix chunk (MiB)         */
   int32_t timing;        /* nonzero: record per-stage HIP event pairs on the
                             stream (no host sync); glr_read_stats() sums them */
@@ -105,6 +106,7 @@ typedef struct glr_stats {
   float ms_norms;             /* key gather and candidate norms                  */
   int64_t match_launches;     /* matcher kernel launches timed in ms_match       */
   int64_t jacobi_sweeps_sum;  /* Jacobi sweeps summed over all groups            */
+  int64_t rematch_keys;       /* BF16 form: keys re-matched with the FP32 form   */
 } glr_stats;
 
 typedef struct glr_plan glr_plan;
@@ -115,7 +117,7 @@ GLR_API const char* glr_status_string(glr_status s);
 /* Thread-local detail of the last failed call on this thread ("" if none). */
 GLR_API const char* glr_last_error_message(void);
 /* Fill *p with the defaults (c = 2*sqrt(2), eps = 1e-16, rho = 1, FP32,
- * 2048 MiB chunks, GAP, no timing); patch/n_keys/k/iters are set to 0. */
+ * 8192 MiB chunks, GAP, no timing); patch/n_keys/k/iters are set to 0. */
 GLR_API void glr_params_default(glr_params* p);
 
 /* Create a plan for one problem shape.  Validates everything that does not

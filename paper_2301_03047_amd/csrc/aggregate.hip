@@ -128,13 +128,12 @@ __global__ void k_gather(const float* __restrict__ xbar, const float* __restrict
       const int a = offs[t], b = offs[t + 1];
       cnt += b - a;
       for (int i = a; i < b; ++i) {
-        // entry e = g*K + j; estimates are d-major per group: xhat[(g*D + d)*K + j]
+        // entry e = g*K + j; estimates are entry-major: xhat[e*D + d]
         const uint32_t e = (uint32_t)(keys[i] & 0xffffffffull);
-        const uint32_t g = e / (uint32_t)K, j = e - g * (uint32_t)K;
-        const float* src = xhat + ((size_t)g * D + (size_t)(cb * CB) * PP + dy * P + dx) * K + j;
+        const float* src = xhat + (size_t)e * D + (size_t)(cb * CB) * PP + dy * P + dx;
 #pragma unroll
         for (int u = 0; u < CB; ++u)
-          if (u < nch) acc[u] += src[(size_t)u * PP * K];
+          if (u < nch) acc[u] += src[(size_t)u * PP];
       }
     }
   }

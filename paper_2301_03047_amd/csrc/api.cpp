@@ -113,48 +113,80 @@ enum { T_DETECT = 0, T_MATCH, T_TOPK, T_SELECT, T_LOWRANK, T_AGG, T_DATA, T_NORM
 glr_status match_stage(glr_plan* pl, const float* xp, const int32_t* keys, int32_t* idx_out,
                        float* dd_out, char* ws, hipStream_t s) {
   float* A = (float*)(ws + pl->ws.A);
-  float* kmeta = (float*)(ws + pl->ws.kmeta);
-  float* pnorm = (float*)(ws + pl->ws.pnorm);
-  float* prt = (float*)(ws + pl->ws.prt);
+  float* kmb = (float*)(ws + pl->ws.kmb);
+  float* cmeta = (float*)(ws + pl->ws.cmeta);
+  float* cm2 = (float*)(ws + pl->ws.cm2);
+  uint16_t* Ab = (uint16_t*)(ws + pl->ws.Ab);
+  uint32_t* tsh = (uint32_t*)(ws + pl->ws.tsh);
   float* dist = (float*)(ws + pl->ws.dist);
   int32_t* lj = (int32_t*)(ws + pl->ws.lj);
   float* lu = (float*)(ws + pl->ws.lu);
   float* ll = (float*)(ws + pl->ws.ll);
   int32_t* lcnt = (int32_t*)(ws + pl->ws.lcnt);
   int32_t* oflag = (int32_t*)(ws + pl->ws.oflag);
+  int32_t* klist = (int32_t*)(ws + pl->ws.klist);
+  int32_t* kcount = (int32_t*)(ws + pl->ws.kcount);
   DevStats* st = (DevStats*)(ws + pl->ws.stats);
   const bool bf = pl->precision == GLR_PREC_BF16_RESCORE;
-  uint16_t* Ab = (uint16_t*)(ws + pl->ws.Ab);
-  float* kmb = (float*)(ws + pl->ws.kmb);
-  float* cmeta = (float*)(ws + pl->ws.cmeta);
-  float* cm2 = (float*)(ws + pl->ws.cm2);
+  const BigMargin bm = {(int32_t*)(ws + pl->ws.bpos), (float*)(ws + pl->ws.bhi),
+                        (float*)(ws + pl->ws.blo), pl->mcap};
   {
     StageTimer t(pl, s, T_NORMS);
-    launch_gather_keys(pl, xp, keys, A, kmeta, s);
-    if (bf) {
-      launch_keys_bf16(pl, A, Ab, kmb, s);
-      launch_cand_meta(pl, xp, cmeta, cm2, s);
-    } else {
-      launch_cand_norms(pl, xp, pnorm, prt, s);
-    }
+    launch_gather_keys(pl, xp, keys, A, s);
+    launch_key_meta(pl, A, bf ? Ab : nullptr, kmb, s);
+    launch_cand_meta(pl, xp, cmeta, cm2, s);
   }
+  // FP32 pass over keys (kmap == null: rows 0..n) or over a key list
+  auto fp32_pass = [&](const int32_t* kmap, int n) {
+    for (int g0 = 0; g0 < n; g0 += pl->n_chunk) {
+      const int nk = std::min(pl->n_chunk, n - g0);
+      {
+        StageTimer t(pl, s, T_MATCH);
+        launch_match_f32(pl, xp, A, kmb, cmeta, kmap, g0, nk, dist, s);
+        if (pl->timing) pl->match_launches++;
+      }
+      {
+        StageTimer t(pl, s, T_TOPK);
+        launch_topk_partial(pl, dist, kmb, kmap, g0, cm2, nk, 0, tsh, lj, lu, ll, lcnt, s);
+      }
+      {
+        StageTimer t(pl, s, T_SELECT);
+        launch_select_rescore(pl, xp, A, kmap, g0, nk, lj, lu, ll, lcnt, idx_out, dd_out, oflag,
+                              0, bm, st, s);
+      }
+    }
+  };
+  if (!bf) {
+    fp32_pass(nullptr, pl->N);
+    return check_hip("glr_match_topk");
+  }
+  // BF16 pass; keys whose margin set or range lists overflow are re-matched
+  // with the FP32 form (a bound about 15x tighter) instead of being rescored
+  // against every candidate.
+  launch_fill_u32((uint32_t*)kcount, 0u, 1, s);
   for (int g0 = 0; g0 < pl->N; g0 += pl->n_chunk) {
     const int nk = std::min(pl->n_chunk, pl->N - g0);
     {
       StageTimer t(pl, s, T_MATCH);
-      if (bf) launch_match_bf16(pl, xp, Ab, kmb, cmeta, g0, nk, dist, s);
-      else launch_match_f32(pl, xp, A, kmeta, pnorm, g0, nk, dist, s);
+      launch_match_bf16(pl, xp, Ab, kmb, cmeta, g0, nk, dist, s);
       if (pl->timing) pl->match_launches++;
     }
     {
       StageTimer t(pl, s, T_TOPK);
-      launch_topk_partial(pl, dist, bf ? kmb : kmeta, bf ? cm2 : prt, g0, nk, lj, lu, ll, lcnt, s);
+      launch_topk_partial(pl, dist, kmb, nullptr, g0, cm2, nk, 1, tsh, lj, lu, ll, lcnt, s);
     }
     {
       StageTimer t(pl, s, T_SELECT);
-      launch_select_rescore(pl, xp, A, g0, nk, lj, lu, ll, lcnt, idx_out, dd_out, oflag, st, s);
+      launch_select_rescore(pl, xp, A, nullptr, g0, nk, lj, lu, ll, lcnt, idx_out, dd_out, oflag,
+                            1, bm, st, s);
+      launch_collect_flags(oflag, g0, nk, klist, kcount, st, s);
     }
   }
+  int32_t n_re = 0;
+  if (hipMemcpyAsync(&n_re, kcount, sizeof(n_re), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return check_hip("glr_match_topk");
+  if (n_re > 0) fp32_pass(klist, n_re);
   return check_hip("glr_match_topk");
 }
 
@@ -249,7 +281,7 @@ void glr_params_default(glr_params* p) {
   p->wnnm_c = 2.0f * std::sqrt(2.0f);
   p->wnnm_eps = 1e-16f;
   p->precision = GLR_PREC_FP32;
-  p->dist_chunk_mb = 2048;
+  p->dist_chunk_mb = 8192;
   p->timing = 0;
 }
 
@@ -326,12 +358,15 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
   pl->Ncand = (int)Ncand;
   pl->D = D;
   pl->ldd = (int)up((size_t)Ncand, 64);
-  size_t chunk_bytes = (size_t)(pr->dist_chunk_mb > 0 ? pr->dist_chunk_mb : 2048) << 20;
+  size_t chunk_bytes = (size_t)(pr->dist_chunk_mb > 0 ? pr->dist_chunk_mb : 8192) << 20;
   long long nch = (long long)(chunk_bytes / ((size_t)pl->ldd * 4));
   if (nch < 1) nch = 1;
   if (nch >= 128) nch = nch / 128 * 128;
   pl->n_chunk = (int)std::min<long long>(nch, pl->N);
-  int ns = (8192 + pl->n_chunk - 1) / pl->n_chunk;
+  // ranges per key: enough waves to fill the chip; more for the BF16 form,
+  // whose larger margin sets need the combined capacity of more range lists
+  const int target = pr->precision == GLR_PREC_BF16_RESCORE ? 32768 : 8192;
+  int ns = (target + pl->n_chunk - 1) / pl->n_chunk;
   ns = std::min(ns, 64);
   ns = std::min<long long>(ns, (Ncand + 1023) / 1024);
   if (ns < 1) ns = 1;
@@ -356,14 +391,18 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
   L.sval = c.take((size_t)Ncand * 8);
   L.keys = c.take((size_t)pl->N * 4);
   L.A = c.take((size_t)pl->N * D * 4);
-  L.kmeta = c.take((size_t)pl->N * 8);
-  L.pnorm = c.take((size_t)Ncand * 4);
-  L.prt = c.take((size_t)Ncand * 4);
   const bool bf = pr->precision == GLR_PREC_BF16_RESCORE;
+  L.kmb = c.take((size_t)pl->N * 16);
+  L.cmeta = c.take((size_t)Ncand * 16);
+  L.cm2 = c.take((size_t)Ncand * 8);
   L.Ab = c.take(bf ? (size_t)pl->N * Cp * bf16_key_row(P) * 2 : 0);
-  L.kmb = c.take(bf ? (size_t)pl->N * 16 : 0);
-  L.cmeta = c.take(bf ? (size_t)Ncand * 16 : 0);
-  L.cm2 = c.take(bf ? (size_t)Ncand * 8 : 0);
+  L.tsh = c.take((size_t)pl->n_chunk * 4);
+  L.klist = c.take(bf ? (size_t)pl->N * 4 : 0);
+  L.kcount = c.take(bf ? 4 : 0);
+  pl->mcap = (int)std::min<long long>(Ncand, 32768);
+  L.bpos = c.take((size_t)pl->n_chunk * pl->mcap * 4);
+  L.bhi = c.take((size_t)pl->n_chunk * pl->mcap * 4);
+  L.blo = c.take((size_t)pl->n_chunk * pl->mcap * 4);
   L.dist = c.take((size_t)pl->n_chunk * pl->ldd * 4);
   const size_t nlist = (size_t)pl->n_chunk * pl->n_split;
   L.lj = c.take(nlist * GLR_SPLIT_CAP * 4);
@@ -630,6 +669,7 @@ glr_status glr_read_stats(glr_plan* pl, glr_stats* out, int32_t reset) {
     out->jacobi_sweeps_max = d.sweeps_max;
     out->jacobi_sweeps_sum = (int64_t)d.sweeps_sum;
     out->keys_selected = d.keys_selected;
+    out->rematch_keys = (int64_t)d.rematch;
     if (reset) {
       launch_fill_u32((uint32_t*)((char*)pl->stats_ws + pl->ws.stats), 0u, sizeof(DevStats) / 4,
                       pl->last_stream);

@@ -17,6 +17,7 @@ struct DevStats {
   int overflow;
   int sweeps_max;
   int keys_selected;
+  int rematch;
 };
 
 // Byte offsets of the workspace buffers (all 256-aligned).
@@ -25,9 +26,12 @@ struct WsLayout {
   size_t q, gxx, gyy, gxy, r25;  // detector
   size_t cflag, slist, sval;     // detector candidate flags / survivor list, scores
   size_t keys;                   // detected keys [N]
-  size_t A, kmeta;               // key matrix [N][D] f32; key norms
-  size_t pnorm, prt;             // candidate norms, sqrt
-  size_t Ab, kmb, cmeta, cm2;    // BF16 form: centred keys, key / candidate metadata
+  size_t A;                      // key matrix [N][D] f32
+  size_t kmb, cmeta, cm2;        // centred key / candidate metadata
+  size_t Ab;                     // BF16 form: centred keys in the BF16 slice layout
+  size_t tsh;                    // per-key shared threshold bound [n_chunk]
+  size_t klist, kcount;          // BF16 form: keys re-matched in FP32 [N], their count
+  size_t bpos, bhi, blo;         // large-margin scratch [n_chunk][mcap]
   size_t dist;                   // distance chunk [n_chunk][ldd]
   size_t lj, lu, ll, lcnt, oflag; // partial top-K lists, per-key overflow flags
   size_t idx, dd;                // groups [N][K], distances [N][K]
@@ -48,6 +52,7 @@ struct glr_plan {
   // derived sizes
   int Hc, Wc, Ncand, D, ldd;
   int n_chunk, n_split, split_len;
+  int mcap;                       // large-margin capacity per key
   int M, M2;                      // aggregation entries (N*K) and power of two
   WsLayout ws;
   hipStream_t last_stream;
@@ -93,26 +98,40 @@ void launch_detect(const glr_plan* pl, const float* xp, char* ws, int32_t* keys,
 
 // match.hip
 void launch_gather_keys(const glr_plan* pl, const float* xp, const int32_t* keys, float* A,
-                        float* kmeta, hipStream_t s);
-void launch_cand_norms(const glr_plan* pl, const float* xp, float* pnorm, float* prt,
-                       hipStream_t s);
-void launch_match_f32(const glr_plan* pl, const float* xp, const float* A, const float* kmeta,
-                      const float* pnorm, int g0, int nk, float* dist, hipStream_t s);
+                        hipStream_t s);
 int bf16_key_row(int P);     // bf16 values per key and channel in the BF16 key layout
-void launch_keys_bf16(const glr_plan* pl, const float* A, uint16_t* Ab, float* kmb, hipStream_t s);
+// kmb[N] float4 (||a||^2, mu_k, sum a, ||a||); Ab (BF16 key slices) may be null
+void launch_key_meta(const glr_plan* pl, const float* A, uint16_t* Ab, float* kmb, hipStream_t s);
+// cmeta[Ncand] float4 (mu, ||pbar||^2, ||pbar||, sum pbar); cm2[Ncand] float2 (mu, ||pbar||)
 void launch_cand_meta(const glr_plan* pl, const float* xp, float* cmeta, float* cm2,
+                      hipStream_t s);
+// keys: rows g0..g0+nk of A, or rows kmap[g0..g0+nk) when kmap is not null
+void launch_match_f32(const glr_plan* pl, const float* xp, const float* A, const float* kmb,
+                      const float* cmeta, const int32_t* kmap, int g0, int nk, float* dist,
                       hipStream_t s);
 void launch_match_bf16(const glr_plan* pl, const float* xp, const uint16_t* Ab, const float* kmb,
                        const float* cmeta, int g0, int nk, float* dist, hipStream_t s);
 
 // topk.hip
-void launch_topk_partial(const glr_plan* pl, const float* dist, const float* km,
-                         const float* cm, int g0, int nk, int32_t* lj, float* lu, float* ll,
-                         int32_t* lcnt, hipStream_t s);
-void launch_select_rescore(const glr_plan* pl, const float* xp, const float* A, int g0, int nk,
-                           const int32_t* lj, const float* lu, const float* ll,
-                           const int32_t* lcnt, int32_t* idx, float* dd, int32_t* oflag,
+void launch_topk_partial(const glr_plan* pl, const float* dist, const float* kmb,
+                         const int32_t* kmap, int g0, const float* cm2, int nk, int bf16,
+                         uint32_t* tsh, int32_t* lj, float* lu, float* ll, int32_t* lcnt,
+                         hipStream_t s);
+// Global scratch of the large-margin path: per chunk key, cap entries of
+// position, rescored hi and lo.
+struct BigMargin {
+  int32_t* pos;
+  float* hi;
+  float* lo;
+  int cap;
+};
+void launch_select_rescore(const glr_plan* pl, const float* xp, const float* A,
+                           const int32_t* kmap, int g0, int nk, const int32_t* lj,
+                           const float* lu, const float* ll, const int32_t* lcnt, int32_t* idx,
+                           float* dd, int32_t* oflag, int defer, const BigMargin& bm,
                            DevStats* st, hipStream_t s);
+void launch_collect_flags(const int32_t* oflag, int g0, int nk, int32_t* klist, int32_t* kcount,
+                          DevStats* st, hipStream_t s);
 
 // lowrank.hip
 void launch_wnnm(const glr_plan* pl, const float* xp, const int32_t* idx, float sigma,

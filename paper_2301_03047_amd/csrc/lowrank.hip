@@ -20,7 +20,8 @@
 //  4. X = Y - Yc W, W = V diag(w) V^T: the residual sum_i (s_i - s'_i) u_i v_i^T
 //     accumulated in FP64 (sigma = 0 gives w = 0, W = 0, X = Y exactly).
 // Data and the SVD are FP32; only the angles and the residual use FP64.
-// Estimates are written d-major per group: xhat[(g*D + d)*K + j].
+// Estimates are written entry-major: xhat[(g*K + j)*D + d] (one member
+// patch's D values contiguous), staged through LDS so the stores coalesce.
 #include "common.h"
 #include "internal.h"
 
@@ -297,12 +298,12 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
 #pragma unroll
   for (int a = 0; a < KP; ++a) wcol[a] = (lane < K && a < K) ? (double)Rl[lane * LS + a] : 0.0;
 
-  // ---- 4. X = Y - Yc W (residual in FP64), d-major output
+  // ---- 4. X = Y - Yc W (residual in FP64); the chunk's results go to Rl
+  // (free once W is in registers) as [j][i], then out as contiguous rows
   for (int d0 = 0; d0 < D; d0 += BR) {
     const int nb = min(BR, D - d0);
     load_rows(xp, spos, d0, nb, K, P, W, HW, Bl, smu);
     if (lane < K) {
-      float* outp = xhat + ((size_t)g * D + d0) * K + lane;
       for (int i = 0; i < nb; ++i) {
         const float mu = smu[i];
         const float* row = Bl + i * LS;
@@ -312,8 +313,13 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
           if (a < K) r0 = fma((double)(row[a] - mu), wcol[a], r0);
           if (a + 1 < K) r1 = fma((double)(row[a + 1] - mu), wcol[a + 1], r1);
         }
-        outp[(size_t)i * K] = (float)((double)row[lane] - (r0 + r1));
+        Rl[lane * LS + i] = (float)((double)row[lane] - (r0 + r1));
       }
+    }
+    __syncthreads();
+    if (lane < nb) {
+      float* outp = xhat + (size_t)g * K * D + d0 + lane;
+      for (int j = 0; j < K; ++j) outp[(size_t)j * D] = Rl[j * LS + lane];
     }
     __syncthreads();
   }

@@ -1,11 +1,19 @@
 // Global patch matching (eq. 8 candidate grid; Im2Col + matrix product as the
 // acceleration of the paper's matching convolution): every key patch against
-// every stride-1 image patch, as one contraction
-//     d~[g][j] = ||k_g||^2 - 2 <k_g, p_j> + ||p_j||^2
-// on MFMA.  The candidate operand is never materialised: a 128-candidate
-// tile lies on one row of the top-left grid, so for each (channel, dy) the
-// tile's patch rows are one image row segment of 128 + P - 1 values staged in
-// LDS, and the MFMA B fragment for (candidate j, dx) is segment[j + dx].
+// every stride-1 image patch, as one contraction on MFMA.
+//
+// Both forms work on mean-centred patches: with a = k - mu_k 1 and
+// pbar = p - mu_p 1 (FP32) and dmu = mu_k - mu_p, the exact identity
+//     ||k - p||^2 = ||a||^2 + ||pbar||^2 - 2 <a, pbar> + D dmu^2
+//                   + 2 dmu (sum a - sum pbar)
+// gives the distance from one centred dot product; its rounding error scales
+// with the centred norms (||a|| ||pbar||) instead of the raw ones, which is
+// what keeps the certified margin of the top-K pass small on smooth images.
+//   FP32 form: <a, pbar> on v_mfma_f32_32x32x2f32;
+//   BF16 form: <bf16(a), bf16(pbar)> on v_mfma_f32_32x32x16_bf16 (FP32 sums).
+// The candidate operand is never materialised: a 128-candidate tile lies on
+// one row of the top-left grid, so for each (channel, dy) the tile's patch
+// rows are one image row segment of 128 + P - 1 values staged in LDS.
 #include "common.h"
 #include "internal.h"
 
@@ -14,63 +22,51 @@ namespace {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // ---------------------------------------------------------------- key matrix
-// A[g][d] = x[c][r_g + dy][c_g + dx], d = (c*P + dy)*P + dx;
-// kmeta[g] = (||k_g||^2, ||k_g||).  One wave per key; the norm is a per-lane
-// strided sum followed by a fixed butterfly (deterministic).
+// A[g][d] = x[c][r_g + dy][c_g + dx], d = (c*P + dy)*P + dx.  One wave per key.
 __global__ void k_gather_keys(const float* __restrict__ xp, int H, int W, int P, int D,
-                              const int32_t* __restrict__ keys, int N, float* __restrict__ A,
-                              float2* __restrict__ kmeta) {
+                              const int32_t* __restrict__ keys, int N, float* __restrict__ A) {
   const int g = blockIdx.x;
   if (g >= N) return;
   const int Wc = W - P + 1;
   const int t = keys[g];
   const int gr = t / Wc, gc = t - gr * Wc;
-  float acc = 0.f;
   for (int d = threadIdx.x; d < D; d += 64) {
     int c = d / (P * P);
     int rem = d - c * P * P;
     int dy = rem / P, dx = rem - dy * P;
-    float v = xp[((size_t)c * H + gr + dy) * W + gc + dx];
-    A[(size_t)g * D + d] = v;
-    acc += v * v;
+    A[(size_t)g * D + d] = xp[((size_t)c * H + gr + dy) * W + gc + dx];
   }
-  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-  if (threadIdx.x == 0) kmeta[g] = make_float2(acc, sqrtf(acc));
-}
-
-// ---------------------------------------------------------------- candidate norms
-// pnorm[j] = ||p_j||^2 summed in d order; prt[j] = sqrt(pnorm[j]).
-__global__ void k_cand_norms(const float* __restrict__ xp, int Cp, int H, int W, int P,
-                             float* __restrict__ pnorm, float* __restrict__ prt) {
-  const int Wc = W - P + 1, Hc = H - P + 1;
-  int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= Hc * Wc) return;
-  int r = j / Wc, c = j - r * Wc;
-  float acc = 0.f;
-  for (int ch = 0; ch < Cp; ++ch)
-    for (int dy = 0; dy < P; ++dy) {
-      const float* row = xp + ((size_t)ch * H + r + dy) * W + c;
-      for (int dx = 0; dx < P; ++dx) acc += row[dx] * row[dx];
-    }
-  pnorm[j] = acc;
-  prt[j] = sqrtf(acc);
 }
 
 // ---------------------------------------------------------------- FP32 MFMA matcher
 constexpr int BM = 128;   // keys per block
 constexpr int BN = 128;   // candidates per block (one grid-row segment)
 
-// P2 = P rounded up to even (the K=2 step of v_mfma_f32_32x32x2f32).
+// d~ from the centred dot product S (both forms)
+__device__ __forceinline__ float centred_dist(float4 km, float4 cm, float S, int D) {
+  // km = (||a||^2, mu_k, sum a, ||a||), cm = (mu_p, ||pbar||^2, ||pbar||, sum pbar)
+  const float dmu = km.y - cm.x;
+  const float base = (km.x + cm.y) - 2.0f * S;
+  return (base + ((float)D * dmu) * dmu) + 2.0f * dmu * (km.z - cm.w);
+}
+
+// P2 = P rounded up to even (the K=2 step of v_mfma_f32_32x32x2f32).  Keys
+// are rows g0 + g of A, or rows kmap[g0 + g] when kmap is given; output row
+// g of dist.  A is centred while staged (padding stays zero); the candidate
+// operand is centred in registers (seg[j + dx] - mu_j).
 template <int P2>
 __global__ void __launch_bounds__(256)
 k_match_f32(const float* __restrict__ xp, int H, int W, int P, int Cp,
-            const float* __restrict__ A, int D, const float2* __restrict__ kmeta,
-            const float* __restrict__ pnorm, int g0, int nk, float* __restrict__ dist,
-            size_t ldd) {
+            const float* __restrict__ A, int D, const float4* __restrict__ kmb,
+            const float4* __restrict__ cmeta, const int32_t* __restrict__ kmap, int g0, int nk,
+            float* __restrict__ dist, size_t ldd) {
   constexpr int SEG = BN + P2;
   constexpr int AST = P2 + 1;   // odd LDS stride for the key slab
   __shared__ float seg[2][SEG];
   __shared__ float As[2][BM * AST];
+  __shared__ float muk[BM];
+  __shared__ int krow[BM];
+  __shared__ float mub[BN];
 
   const int Hc = H - P + 1, Wc = W - P + 1;
   const int ntc = (Wc + BN - 1) / BN;
@@ -87,6 +83,17 @@ k_match_f32(const float* __restrict__ xp, int H, int W, int P, int Cp,
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int S = Cp * P;                      // (channel, dy) stages
+  if (tid < BM) {
+    const int g = kbase + tid;
+    const int gg = g < nk ? (kmap ? kmap[g0 + g] : g0 + g) : -1;
+    krow[tid] = gg;
+    muk[tid] = gg >= 0 ? kmb[gg].y : 0.f;
+  }
+  if (tid < BN) {
+    const int col = c0 + tid;
+    mub[tid] = col < Wc ? cmeta[(size_t)r * Wc + col].x : 0.f;
+  }
+  __syncthreads();
 
   // register staging of the next stage
   float rseg = 0.f;
@@ -106,8 +113,8 @@ k_match_f32(const float* __restrict__ xp, int H, int W, int P, int Cp,
       float v = 0.f;
       if (e < BM * P2) {
         int m = e / P2, dx = e - m * P2;
-        int g = kbase + m;
-        if (dx < P && g < nk) v = A[(size_t)(g0 + g) * D + (size_t)s * P + dx];
+        const int gg = krow[m];
+        if (dx < P && gg >= 0) v = A[(size_t)gg * D + (size_t)s * P + dx] - muk[m];
       }
       ra[u] = v;
     }
@@ -132,10 +139,11 @@ k_match_f32(const float* __restrict__ xp, int H, int W, int P, int Cp,
 #pragma unroll
       for (int q = 0; q < 16; ++q) acc[i][j][q] = 0.f;
 
+  const int l32 = lane & 31, lhi = lane >> 5;
+  const float mb0 = mub[wn * 64 + l32], mb1 = mub[wn * 64 + 32 + l32];
   load_stage(0);
   store_stage(0);
   __syncthreads();
-  const int l32 = lane & 31, lhi = lane >> 5;
   for (int s = 0; s < S; ++s) {
     const int cur = s & 1;
     if (s + 1 < S) load_stage(s + 1);
@@ -144,8 +152,8 @@ k_match_f32(const float* __restrict__ xp, int H, int W, int P, int Cp,
       const int dx = 2 * kk + lhi;
       float a0 = As[cur][(wm * 64 + l32) * AST + dx];
       float a1 = As[cur][(wm * 64 + 32 + l32) * AST + dx];
-      float b0 = seg[cur][wn * 64 + l32 + dx];
-      float b1 = seg[cur][wn * 64 + 32 + l32 + dx];
+      float b0 = seg[cur][wn * 64 + l32 + dx] - mb0;
+      float b1 = seg[cur][wn * 64 + 32 + l32 + dx] - mb1;
       acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
       acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
       acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
@@ -155,7 +163,6 @@ k_match_f32(const float* __restrict__ xp, int H, int W, int P, int Cp,
     __syncthreads();
   }
 
-  // epilogue: d~ = (||k||^2 - 2 S) + ||p||^2
 #pragma unroll
   for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
@@ -163,31 +170,29 @@ k_match_f32(const float* __restrict__ xp, int H, int W, int P, int Cp,
       const int col = c0 + wn * 64 + nt * 32 + l32;
       const bool cok = col < Wc;
       const size_t t = (size_t)r * Wc + col;
-      const float pn = cok ? pnorm[t] : 0.f;
+      const float4 cm = cok ? cmeta[t] : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int i = wm * 64 + mt * 32 + 8 * (q >> 2) + 4 * lhi + (q & 3);
-        const int g = kbase + i;
-        if (cok && g < nk) {
-          const float kn = kmeta[g0 + g].x;
-          dist[(size_t)g * ldd + t] = (kn - 2.0f * acc[mt][nt][q]) + pn;
-        }
+        const int gg = krow[i];
+        if (cok && gg >= 0)
+          dist[(size_t)(kbase + i) * ldd + t] = centred_dist(kmb[gg], cm, acc[mt][nt][q], D);
       }
     }
 }
 
 template <int P2>
-void launch_match_t(const glr_plan* pl, const float* xp, const float* A, const float* kmeta,
-                    const float* pnorm, int g0, int nk, float* dist, hipStream_t s) {
+void launch_match_t(const glr_plan* pl, const float* xp, const float* A, const float* kmb,
+                    const float* cmeta, const int32_t* kmap, int g0, int nk, float* dist,
+                    hipStream_t s) {
   const int Hc = pl->Hc, Wc = pl->Wc;
   const int ntc = (Wc + BN - 1) / BN;
   const int nkt = (nk + BM - 1) / BM;
   size_t blocks = (size_t)nkt * Hc * ntc;
   hipLaunchKernelGGL(k_match_f32<P2>, dim3((unsigned)blocks), dim3(256), 0, s, xp, pl->H, pl->W,
-                     pl->P, pl->Cp, A, pl->D, (const float2*)kmeta, pnorm, g0, nk, dist,
-                     (size_t)pl->ldd);
+                     pl->P, pl->Cp, A, pl->D, (const float4*)kmb, (const float4*)cmeta, kmap, g0,
+                     nk, dist, (size_t)pl->ldd);
 }
-
 
 // ---------------------------------------------------------------- BF16 form
 // Centred form of the same distance (exact identity):
@@ -212,10 +217,11 @@ __host__ __device__ constexpr int bf16_slices(int P) {
   return P <= 8 ? P + (P & 1) : (P <= 12 ? 24 : 32);
 }
 
-// Per key: Ab[g][c][t][0..8) = bf16(k - mu_k) (padding zero),
-// kmb[g] = (||a||^2, mu_k, sum a, ||a||).  One wave per key.
-__global__ void k_keys_bf16(const float* __restrict__ A, int D, int P, int Cp, int NS, int XS,
-                            int N, uint16_t* __restrict__ Ab, float4* __restrict__ kmb) {
+// Per key: kmb[g] = (||a||^2, mu_k, sum a, ||a||) with a = k - mu_k (FP32,
+// the values both matchers use); with Ab, also Ab[g][c][t][0..8) = bf16(a)
+// in the BF16 slice layout (padding zero).  One wave per key.
+__global__ void k_key_meta(const float* __restrict__ A, int D, int P, int Cp, int NS, int XS,
+                           int N, uint16_t* __restrict__ Ab, float4* __restrict__ kmb) {
   const int g = blockIdx.x;
   if (g >= N) return;
   const float* k = A + (size_t)g * D;
@@ -225,23 +231,24 @@ __global__ void k_keys_bf16(const float* __restrict__ A, int D, int P, int Cp, i
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
   const float mu = s / (float)D;
   float an = 0.f, sa = 0.f;
-  const int row = NS * 8;
-  for (int e = l; e < Cp * row; e += 64) {
-    const int c = e / row, rem = e - c * row, t = rem >> 3;
-    const int y = t / XS, dx = (t - y * XS) * 8 + (rem & 7);
-    float a = 0.f;
-    if (y < P && dx < P) {
-      a = k[(c * P + y) * P + dx] - mu;
-      an = fmaf(a, a, an);
-      sa += a;
-    }
-    Ab[(size_t)g * Cp * row + e] = (uint16_t)bf16_rne(a);
+  for (int d = l; d < D; d += 64) {
+    const float a = k[d] - mu;
+    an = fmaf(a, a, an);
+    sa += a;
   }
   for (int o = 32; o > 0; o >>= 1) {
     an += __shfl_xor(an, o, 64);
     sa += __shfl_xor(sa, o, 64);
   }
   if (l == 0) kmb[g] = make_float4(an, mu, sa, sqrtf(an));
+  if (!Ab) return;
+  const int row = NS * 8;
+  for (int e = l; e < Cp * row; e += 64) {
+    const int c = e / row, rem = e - c * row, t = rem >> 3;
+    const int y = t / XS, dx = (t - y * XS) * 8 + (rem & 7);
+    const float a = (y < P && dx < P) ? k[(c * P + y) * P + dx] - mu : 0.f;
+    Ab[(size_t)g * Cp * row + e] = (uint16_t)bf16_rne(a);
+  }
 }
 
 // Per candidate: cmeta[j] = (mu_p, ||pbar||^2, ||pbar||, sum pbar) with
@@ -277,6 +284,8 @@ __global__ void k_cand_meta(const float* __restrict__ xp, int Cp, int H, int W, 
 }
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 // BF16 MFMA matcher: 128 keys x 128 candidates per block (one grid-row
 // segment), one channel (NS slices of the padded patch block) per step.
@@ -314,6 +323,7 @@ k_match_bf16(const float* __restrict__ xp, int H, int W, int P, int Cp,
   const int wm = wave >> 1, wn = wave & 1;
   const int l32 = lane & 31, lhi = lane >> 5;
   const int D = Cp * P * P;
+  const bool full = P == RP && P == 8 * XS;   // no padding rows or columns
 
   if (tid < BN) {
     const int col = c0 + tid;
@@ -366,14 +376,20 @@ k_match_bf16(const float* __restrict__ xp, int H, int W, int P, int Cp,
       const int t = e / BN, j = e - t * BN;
       const int y = t / XS, xb = (t - y * XS) * 8;
       const float m = mup[j];
+      const float* src = seg + y * SEGW + j + xb;
+      float v[8];
+      if (full) {
+#pragma unroll
+        for (int h = 0; h < 8; ++h) v[h] = src[h] - m;
+      } else {
+#pragma unroll
+        for (int h = 0; h < 8; ++h) v[h] = (xb + h < P && y < P) ? src[h] - m : 0.f;
+      }
       uint32_t w[4];
 #pragma unroll
-      for (int h = 0; h < 4; ++h) {
-        const int dx0 = xb + 2 * h, dx1 = xb + 2 * h + 1;
-        const float v0 = (dx0 < P && y < P) ? seg[y * SEGW + j + dx0] - m : 0.f;
-        const float v1 = (dx1 < P && y < P) ? seg[y * SEGW + j + dx1] - m : 0.f;
-        w[h] = bf16_rne(v0) | (bf16_rne(v1) << 16);
-      }
+      for (int h = 0; h < 4; ++h)
+        w[h] = __builtin_bit_cast(uint32_t, __builtin_convertvector(
+                   (f32x2){v[2 * h], v[2 * h + 1]}, bf16x2));   // round to nearest even
       *reinterpret_cast<uint4*>(Bs + (size_t)e * 8) = make_uint4(w[0], w[1], w[2], w[3]);
     }
     __syncthreads();
@@ -412,12 +428,7 @@ k_match_bf16(const float* __restrict__ xp, int H, int W, int P, int Cp,
       for (int q = 0; q < 16; ++q) {
         const int i = wm * 64 + mt * 32 + 8 * (q >> 2) + 4 * lhi + (q & 3);
         const int g = kbase + i;
-        if (cok && g < nk) {
-          const float4 km = kmb[g0 + g];
-          const float dmu = km.y - cm.x;
-          const float base = (km.x + cm.y) - 2.0f * acc[mt][nt][q];
-          dist[(size_t)g * ldd + t] = (base + ((float)D * dmu) * dmu) + 2.0f * dmu * (km.z - cm.w);
-        }
+        if (cok && g < nk) dist[(size_t)g * ldd + t] = centred_dist(kmb[g0 + g], cm, acc[mt][nt][q], D);
       }
     }
 }
@@ -436,37 +447,16 @@ void launch_match_bf16_t(const glr_plan* pl, const float* xp, const uint16_t* Ab
 }  // namespace
 
 void launch_gather_keys(const glr_plan* pl, const float* xp, const int32_t* keys, float* A,
-                        float* kmeta, hipStream_t s) {
+                        hipStream_t s) {
   hipLaunchKernelGGL(k_gather_keys, dim3(pl->N), dim3(64), 0, s, xp, pl->H, pl->W, pl->P, pl->D,
-                     keys, pl->N, A, (float2*)kmeta);
-}
-
-void launch_cand_norms(const glr_plan* pl, const float* xp, float* pnorm, float* prt,
-                       hipStream_t s) {
-  int n = pl->Ncand;
-  hipLaunchKernelGGL(k_cand_norms, dim3((n + 255) / 256), dim3(256), 0, s, xp, pl->Cp, pl->H,
-                     pl->W, pl->P, pnorm, prt);
-}
-
-void launch_match_f32(const glr_plan* pl, const float* xp, const float* A, const float* kmeta,
-                      const float* pnorm, int g0, int nk, float* dist, hipStream_t s) {
-  switch ((pl->P + 1) / 2) {
-    case 1: launch_match_t<2>(pl, xp, A, kmeta, pnorm, g0, nk, dist, s); break;
-    case 2: launch_match_t<4>(pl, xp, A, kmeta, pnorm, g0, nk, dist, s); break;
-    case 3: launch_match_t<6>(pl, xp, A, kmeta, pnorm, g0, nk, dist, s); break;
-    case 4: launch_match_t<8>(pl, xp, A, kmeta, pnorm, g0, nk, dist, s); break;
-    case 5: launch_match_t<10>(pl, xp, A, kmeta, pnorm, g0, nk, dist, s); break;
-    case 6: launch_match_t<12>(pl, xp, A, kmeta, pnorm, g0, nk, dist, s); break;
-    case 7: launch_match_t<14>(pl, xp, A, kmeta, pnorm, g0, nk, dist, s); break;
-    default: launch_match_t<16>(pl, xp, A, kmeta, pnorm, g0, nk, dist, s); break;
-  }
+                     keys, pl->N, A);
 }
 
 int bf16_key_row(int P) { return bf16_slices(P) * 8; }
 
-void launch_keys_bf16(const glr_plan* pl, const float* A, uint16_t* Ab, float* kmb, hipStream_t s) {
+void launch_key_meta(const glr_plan* pl, const float* A, uint16_t* Ab, float* kmb, hipStream_t s) {
   const int NS = bf16_slices(pl->P);
-  hipLaunchKernelGGL(k_keys_bf16, dim3(pl->N), dim3(64), 0, s, A, pl->D, pl->P, pl->Cp, NS,
+  hipLaunchKernelGGL(k_key_meta, dim3(pl->N), dim3(64), 0, s, A, pl->D, pl->P, pl->Cp, NS,
                      NS > 8 ? 2 : 1, pl->N, Ab, (float4*)kmb);
 }
 
@@ -475,6 +465,21 @@ void launch_cand_meta(const glr_plan* pl, const float* xp, float* cmeta, float* 
   const int n = pl->Ncand;
   hipLaunchKernelGGL(k_cand_meta, dim3((n + 255) / 256), dim3(256), 0, s, xp, pl->Cp, pl->H,
                      pl->W, pl->P, (float4*)cmeta, (float2*)cm2);
+}
+
+void launch_match_f32(const glr_plan* pl, const float* xp, const float* A, const float* kmb,
+                      const float* cmeta, const int32_t* kmap, int g0, int nk, float* dist,
+                      hipStream_t s) {
+  switch ((pl->P + 1) / 2) {
+    case 1: launch_match_t<2>(pl, xp, A, kmb, cmeta, kmap, g0, nk, dist, s); break;
+    case 2: launch_match_t<4>(pl, xp, A, kmb, cmeta, kmap, g0, nk, dist, s); break;
+    case 3: launch_match_t<6>(pl, xp, A, kmb, cmeta, kmap, g0, nk, dist, s); break;
+    case 4: launch_match_t<8>(pl, xp, A, kmb, cmeta, kmap, g0, nk, dist, s); break;
+    case 5: launch_match_t<10>(pl, xp, A, kmb, cmeta, kmap, g0, nk, dist, s); break;
+    case 6: launch_match_t<12>(pl, xp, A, kmb, cmeta, kmap, g0, nk, dist, s); break;
+    case 7: launch_match_t<14>(pl, xp, A, kmb, cmeta, kmap, g0, nk, dist, s); break;
+    default: launch_match_t<16>(pl, xp, A, kmb, cmeta, kmap, g0, nk, dist, s); break;
+  }
 }
 
 void launch_match_bf16(const glr_plan* pl, const float* xp, const uint16_t* Ab, const float* kmb,

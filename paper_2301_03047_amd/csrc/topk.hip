@@ -1,20 +1,21 @@
 // Top-K grouping (eq. 1 with KNN grouping, searched over the whole image).
 //
-// The matcher's d~ carries a rounding error bounded by eps_j:
-//  FP32 form:  eps_j = 2 (D + 8) u (||k|| + ||p_j||)^2
-//    (dot product and norms in FP32, plus the epilogue roundings);
-//  BF16 form:  eps_j = 4 (2 b + b^2) ||a|| ||pbar_j|| + (3 D + 26) u R_j^2,
-//              R_j = ||a|| + ||pbar_j|| + sqrt(D) |mu_k - mu_j|
-//    (a, pbar_j the centred key and candidate, b = 2^-9 the BF16 operand
-//    rounding, FP32 accumulation and epilogue in the second term),
-// u = 2^-24, each with a safety factor of two.  With U_j = d~_j + eps_j and L_j = d~_j - eps_j, let T be
-// the K-th smallest U_j of a key: every member of the exact top-K has
-// L_j <= d_j <= T, so the margin set {j : L_j <= T} contains the exact
-// answer.  Stage 1 finds, per (key, candidate range), the range's margin set
-// against the range's own T (an upper bound of the key's T) in one streaming
-// pass; stage 2 merges the ranges, applies the key's T, recomputes the
-// distance of each margin member with compensated (double-float32)
-// arithmetic and sorts by (distance, position), lowest position winning ties.
+// The matcher's d~ (centred form) carries a rounding error bounded by
+//     eps_j = c1 ||a|| ||pbar_j|| + c2 R_j^2,
+//     R_j = ||a|| + ||pbar_j|| + sqrt(D) |mu_k - mu_j|,
+// with a, pbar_j the centred key and candidate, u = 2^-24, b = 2^-9 and
+//     c2 = (3 D + 26) u       (FP32 dot-product sums, centring, epilogue),
+//     c1 = 4 (2 b + b^2)      (BF16 operand rounding; 0 for the FP32 form),
+// each with a safety factor of two.  With U_j = d~_j + eps_j and
+// L_j = d~_j - eps_j, let T be the K-th smallest U_j of a key: every member
+// of the exact top-K has L_j <= d_j <= T, so the margin set {j : L_j <= T}
+// contains the exact answer.  Stage 1 finds, per (key, candidate range), the
+// range's margin set against an upper bound of T (the range's own K-th
+// smallest U, tightened by the best bound any range of the key has
+// published so far) in one streaming pass; stage 2 selects the key's T over
+// the range lists, recomputes the distance of each margin member with
+// compensated (double-float32) arithmetic and sorts by (distance, position),
+// lowest position winning ties.
 #include <cmath>
 
 #include "common.h"
@@ -131,15 +132,15 @@ __device__ int wave_compact(int* bj, float* bu, float* bl, int n, float T) {
   return w;
 }
 
-// BF = false: km = (||k||^2, ||k||) per key, cm = ||p_j|| per candidate.
-// BF = true:  km = (||a||^2, mu_k, sum a, ||a||) per key, cm = (mu_j, ||pbar_j||)
-//             per candidate.
-template <bool BF>
+// km = (||a||^2, mu_k, sum a, ||a||) per key (row kmap[g0+g] or g0+g);
+// cm = (mu_j, ||pbar_j||) per candidate.  tsh[g]: the key's shared bound of T
+// (ordered bits, +inf at launch), lowered with atomicMin by every range.
 __global__ void __launch_bounds__(256)
-k_topk_partial(const float* __restrict__ dist, size_t ldd, const float* __restrict__ km, int g0,
-               const float* __restrict__ cm, int Ncand, int split_len, int S, int nk, int K,
-               float coef, float coef2, float sqrtD, int32_t* __restrict__ lj,
-               float* __restrict__ lu, float* __restrict__ ll, int32_t* __restrict__ lcnt) {
+k_topk_partial(const float* __restrict__ dist, size_t ldd, const float4* __restrict__ km,
+               const int32_t* __restrict__ kmap, int g0, const float* __restrict__ cm, int Ncand,
+               int split_len, int S, int nk, int K, float coef, float coef2, float sqrtD,
+               uint32_t* __restrict__ tsh, int32_t* __restrict__ lj, float* __restrict__ lu,
+               float* __restrict__ ll, int32_t* __restrict__ lcnt) {
   __shared__ int sbj[4][CAP];
   __shared__ float sbu[4][CAP];
   __shared__ float sbl[4][CAP];
@@ -155,8 +156,15 @@ k_topk_partial(const float* __restrict__ dist, size_t ldd, const float* __restri
   const int g = item / S, sp = item - g * S;
   const int j0 = sp * split_len;
   const int j1 = min(Ncand, j0 + split_len);
-  const float kr = BF ? km[4 * (size_t)(g0 + g) + 3] : km[2 * (size_t)(g0 + g) + 1];
-  const float kmu = BF ? km[4 * (size_t)(g0 + g) + 1] : 0.f;
+  const float4 kmv = km[kmap ? kmap[g0 + g] : g0 + g];
+  const float kr = kmv.w, kmu = kmv.y;
+  // publish T to the key's shared bound and take the bound back
+  auto share = [&](float Tl) {
+    uint32_t old = 0u;
+    if (l == 0) old = atomicMin(&tsh[g], f2ord(Tl));
+    old = __shfl(old, 0, 64);
+    return fminf(Tl, ord2f(old));
+  };
   const float* drow = dist + (size_t)g * ldd;
   float T = __int_as_float(0x7f800000);     // +inf
   int cnt = 0;
@@ -167,7 +175,7 @@ k_topk_partial(const float* __restrict__ dist, size_t ldd, const float* __restri
   // element can enter the margin set.
   constexpr int U4 = 4;
   constexpr int CH = 256 * U4;
-  // pv: ||p_j|| (FP32 form) or ||pbar_j|| (BF16 form); mv: mu_j (BF16 form)
+  // pv: ||pbar_j||; mv: mu_j
   float dv[U4][4], pv[U4][4], mv[U4][4], dn[U4][4], pn[U4][4], mn[U4][4];
   auto load = [&](int base, float (&d)[U4][4], float (&p)[U4][4], float (&m)[U4][4]) {
 #pragma unroll
@@ -176,26 +184,17 @@ k_topk_partial(const float* __restrict__ dist, size_t ldd, const float* __restri
       if (j + 3 < j1) {
         const float4 a = *reinterpret_cast<const float4*>(drow + j);
         d[u][0] = a.x; d[u][1] = a.y; d[u][2] = a.z; d[u][3] = a.w;
-        if constexpr (BF) {
-          const float4 b0 = *reinterpret_cast<const float4*>(cm + 2 * (size_t)j);
-          const float4 b1 = *reinterpret_cast<const float4*>(cm + 2 * (size_t)j + 4);
-          m[u][0] = b0.x; p[u][0] = b0.y; m[u][1] = b0.z; p[u][1] = b0.w;
-          m[u][2] = b1.x; p[u][2] = b1.y; m[u][3] = b1.z; p[u][3] = b1.w;
-        } else {
-          const float4 b = *reinterpret_cast<const float4*>(cm + j);
-          p[u][0] = b.x; p[u][1] = b.y; p[u][2] = b.z; p[u][3] = b.w;
-        }
+        const float4 b0 = *reinterpret_cast<const float4*>(cm + 2 * (size_t)j);
+        const float4 b1 = *reinterpret_cast<const float4*>(cm + 2 * (size_t)j + 4);
+        m[u][0] = b0.x; p[u][0] = b0.y; m[u][1] = b0.z; p[u][1] = b0.w;
+        m[u][2] = b1.x; p[u][2] = b1.y; m[u][3] = b1.z; p[u][3] = b1.w;
       } else {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const bool ok = j + e < j1;
           d[u][e] = ok ? drow[j + e] : 0.f;
-          if constexpr (BF) {
-            m[u][e] = ok ? cm[2 * (size_t)(j + e)] : 0.f;
-            p[u][e] = ok ? cm[2 * (size_t)(j + e) + 1] : 0.f;
-          } else {
-            p[u][e] = ok ? cm[j + e] : 0.f;
-          }
+          m[u][e] = ok ? cm[2 * (size_t)(j + e)] : 0.f;
+          p[u][e] = ok ? cm[2 * (size_t)(j + e) + 1] : 0.f;
         }
       }
     }
@@ -212,14 +211,8 @@ k_topk_partial(const float* __restrict__ dist, size_t ldd, const float* __restri
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int j = base + u * 256 + 4 * l + e;
-        float eps;
-        if constexpr (BF) {
-          const float R = (kr + pv[u][e]) + sqrtD * fabsf(kmu - mv[u][e]);
-          eps = coef * (kr * pv[u][e]) + coef2 * (R * R);
-        } else {
-          const float sm = kr + pv[u][e];
-          eps = coef * (sm * sm);
-        }
+        const float R = (kr + pv[u][e]) + sqrtD * fabsf(kmu - mv[u][e]);
+        const float eps = coef * (kr * pv[u][e]) + coef2 * (R * R);
         ok[u][e] = j < j1;
         Uv[u][e] = dv[u][e] + eps;
         Lv[u][e] = dv[u][e] - eps;
@@ -232,7 +225,9 @@ k_topk_partial(const float* __restrict__ dist, size_t ldd, const float* __restri
 #pragma unroll
         for (int e = 0; e < 4; ++e)
           bu[(u * 64 + l) * 4 + e] = ok[u][e] ? Uv[u][e] : __int_as_float(0x7f800000);
-      T = wave_kth_smallest(bu, CH, K, hist);
+      T = share(wave_kth_smallest(bu, CH, K, hist));
+    } else if ((((base - j0) / CH) & 7) == 0) {
+      T = share(T);                         // take up other ranges' progress
     }
     bool any = false;
 #pragma unroll
@@ -257,7 +252,7 @@ k_topk_partial(const float* __restrict__ dist, size_t ldd, const float* __restri
         // room for the next 256 entries, else tighten T and compact
         if (cnt > CAP - 256) {
           const float Tn = wave_kth_smallest(bu, cnt, K, hist);
-          T = fminf(T, Tn);
+          T = share(fminf(T, Tn));
           cnt = wave_compact(bj, bu, bl, cnt, T);
           if (cnt > CAP - 256) {
             ovf = true;
@@ -273,12 +268,12 @@ k_topk_partial(const float* __restrict__ dist, size_t ldd, const float* __restri
       for (int e = 0; e < 4; ++e) {
         dv[u][e] = dn[u][e];
         pv[u][e] = pn[u][e];
-        if constexpr (BF) mv[u][e] = mn[u][e];
+        mv[u][e] = mn[u][e];
       }
   }
-  if (!ovf && cnt >= K) {
-    const float Tn = wave_kth_smallest(bu, cnt, K, hist);
-    T = fminf(T, Tn);
+  if (!ovf) {
+    if (cnt >= K) T = fminf(T, wave_kth_smallest(bu, cnt, K, hist));
+    T = share(T);
     cnt = wave_compact(bj, bu, bl, cnt, T);
   }
   const size_t o = (size_t)item * CAP;
@@ -304,18 +299,94 @@ __device__ int block_sum_i(int v, int* sh) {
   return s;
 }
 
-// exact (compensated) squared distance between key g's vector and patch j
-__device__ __forceinline__ df32 exact_dist(const float* __restrict__ xp, int H, int W, int P, int Cp,
-                                           const float* __restrict__ kvec, int j, int Wc) {
-  const int r = j / Wc, c = j - r * Wc;
-  df32 acc = {0.f, 0.f};
-  int d = 0;
-  for (int ch = 0; ch < Cp; ++ch)
-    for (int dy = 0; dy < P; ++dy) {
-      const float* row = xp + ((size_t)ch * H + r + dy) * W + c;
-      for (int dx = 0; dx < P; ++dx, ++d) df_add_sqdiff(acc, kvec[d], row[dx]);
+// ---------------------------------------------------------------- exact rescoring
+// The compensated (double-float32) distance of one candidate is computed by
+// L lanes together (L = 8..64, a power of two fixed by D): lane s of the
+// group owns the patch elements d = s + e L, holds the key's values and the
+// elements' image offsets in registers, accumulates its squared differences
+// with TwoSum/TwoProd, and the group combines its partial sums with a
+// butterfly of compensated additions (every lane of the group ends with the
+// same value).  Candidate rows are read as P-float segments, so a wave's
+// loads are coalesced, and the key is read once per key.
+template <int EM>
+struct KeySlice {
+  float kv[EM];
+  int off[EM];       // image offset of element d relative to the patch's top-left
+};
+
+// Elements past D get offset 0 and are masked to a zero difference, so every
+// load is unconditional (all of a lane's loads can be in flight at once).
+template <int EM>
+__device__ __forceinline__ void key_slice_load(KeySlice<EM>& ks, const float* __restrict__ kvec,
+                                               int D, int P, int H, int W, int L, int s) {
+#pragma unroll
+  for (int e = 0; e < EM; ++e) {
+    const int d = s + e * L;
+    if (d < D) {
+      const int c = d / (P * P), rem = d - c * (P * P);
+      const int dy = rem / P, dx = rem - dy * P;
+      ks.kv[e] = kvec[d];
+      ks.off[e] = (c * H + dy) * W + dx;
+    } else {
+      ks.kv[e] = 0.f;
+      ks.off[e] = -1;
     }
-  return acc;
+  }
+}
+
+// Compensated distances of two candidates (image offsets b0, b1 of their
+// top-left pixels; both valid positions) by the L-lane group; every lane of
+// the group returns the group's sums.
+template <int EM>
+__device__ __forceinline__ void coop_dist2(const KeySlice<EM>& ks, const float* __restrict__ xp,
+                                           int b0, int b1, int L, df32& r0, df32& r1) {
+  float p0[EM], p1[EM];
+#pragma unroll
+  for (int e = 0; e < EM; ++e) {
+    const int o = ks.off[e] < 0 ? 0 : ks.off[e];
+    p0[e] = xp[b0 + o];
+    p1[e] = xp[b1 + o];
+  }
+  df32 a0 = {0.f, 0.f}, a1 = {0.f, 0.f};
+#pragma unroll
+  for (int e = 0; e < EM; ++e) {
+    const bool ok = ks.off[e] >= 0;
+    df_add_sqdiff(a0, ks.kv[e], ok ? p0[e] : ks.kv[e]);
+    df_add_sqdiff(a1, ks.kv[e], ok ? p1[e] : ks.kv[e]);
+  }
+  for (int o = L >> 1; o > 0; o >>= 1) {
+    const float h0 = __shfl_xor(a0.hi, o, 64), l0 = __shfl_xor(a0.lo, o, 64);
+    const float h1 = __shfl_xor(a1.hi, o, 64), l1 = __shfl_xor(a1.lo, o, 64);
+    df_add(a0, h0, l0);
+    df_add(a1, h1, l1);
+  }
+  r0 = a0;
+  r1 = a1;
+}
+
+// Rescore entries i in [0, m) of a candidate list (pos(i) = image grid
+// position) into (hh[i], ll[i]).  Each step a wave takes 2 * (64 / L)
+// consecutive entries starting at i0 = first, first + stride, ...; the lane
+// groups take two entries each.  Invalid slots read position 0 and are not
+// written.
+template <int EM, typename PosF>
+__device__ __forceinline__ void coop_rescore(const KeySlice<EM>& ks, const float* __restrict__ xp,
+                                             PosF pos, int first, int m, int stride, int Wc,
+                                             int W, int L, float* hh, float* ll) {
+  const int l = lane_id();
+  const int s = l & (L - 1), grp = l / L, cpi = 64 / L;
+  for (int i0 = first; i0 < m; i0 += stride) {
+    const int ia = i0 + grp, ib = i0 + cpi + grp;
+    const bool va = ia < m, vb = ib < m;
+    const int ja = va ? pos(ia) : 0, jb = vb ? pos(ib) : 0;
+    const int ra = ja / Wc, rb = jb / Wc;
+    df32 da, db;
+    coop_dist2(ks, xp, ra * W + (ja - ra * Wc), rb * W + (jb - rb * Wc), L, da, db);
+    if (s == 0) {
+      if (va) { hh[ia] = da.hi; ll[ia] = da.lo; }
+      if (vb) { hh[ib] = db.hi; ll[ib] = db.lo; }
+    }
+  }
 }
 
 // bitonic sort of n (power of two) entries by (hi, lo, j) ascending
@@ -372,9 +443,11 @@ constexpr int UW = 1024;          // margin-set capacity per key (wave path)
 // is held in LDS, so the lists' union may be far larger than UW.  Keys
 // whose margin set exceeds UW, or whose range lists overflowed, are flagged
 // for the kernel below.
+template <int EM>
 __global__ void __launch_bounds__(256)
-k_select_rescore(const float* __restrict__ xp, int H, int W, int P, int Cp, int D,
-                 const float* __restrict__ A, int g0, int nk, int S, int Ncand, int K,
+k_select_rescore(const float* __restrict__ xp, int H, int W, int P, int Cp, int D, int L,
+                 const float* __restrict__ A, const int32_t* __restrict__ kmap, int g0, int nk,
+                 int S, int Ncand, int K,
                  const int32_t* __restrict__ lj, const float* __restrict__ lu,
                  const float* __restrict__ ll, const int32_t* __restrict__ lcnt,
                  int32_t* __restrict__ idx, float* __restrict__ dd, int32_t* __restrict__ oflag,
@@ -390,7 +463,7 @@ k_select_rescore(const float* __restrict__ xp, int H, int W, int P, int Cp, int 
   float* u = su[wave];
   float* lo = sl[wave];
   int* jj = sj[wave];
-  const int gg = g0 + g;
+  const int gg = kmap ? kmap[g0 + g] : g0 + g;
   const int Wc = W - P + 1;
   // split counts (S <= 64: one lane per split)
   const int c = l < S ? lcnt[g * S + l] : 0;
@@ -423,13 +496,13 @@ k_select_rescore(const float* __restrict__ xp, int H, int W, int P, int Cp, int 
   }
   if (l == 0) oflag[g] = 0;
   wave_sync_lds();
-  // compensated rescoring, one entry per lane
-  const float* kvec = A + (size_t)gg * D;
-  for (int i = l; i < m; i += 64) {
-    const df32 v = exact_dist(xp, H, W, P, Cp, kvec, jj[i], Wc);
-    u[i] = v.hi;
-    lo[i] = v.lo;
+  // compensated rescoring, L lanes per candidate, two candidates per group
+  {
+    KeySlice<EM> ks;
+    key_slice_load(ks, A + (size_t)gg * D, D, P, H, W, L, l & (L - 1));
+    coop_rescore(ks, xp, [&](int i) { return jj[i]; }, 0, m, 2 * (64 / L), Wc, W, L, u, lo);
   }
+  wave_sync_lds();
   int n2 = 1;
   while (n2 < m) n2 <<= 1;
   for (int i = m + l; i < n2; i += 64) {
@@ -450,31 +523,44 @@ k_select_rescore(const float* __restrict__ xp, int H, int W, int P, int Cp, int 
 }
 
 // Flagged keys, one block per key (unflagged keys exit at once):
-//  flag 1: the margin set exceeds the wave buffer; same threshold / rescore /
-//          sort as the wave path with up to UCAP margin entries in LDS;
-//  flag 2 (a range list overflowed) or a margin set above UCAP: exact
+//  flag 1: the margin set exceeds the wave buffer.  It is gathered into
+//          global scratch (up to mcap entries), rescored like the wave path,
+//          and the K smallest by (hi, lo, position) are found by a radix
+//          selection on the 96-bit key, then sorted in LDS;
+//  flag 2 (a range list overflowed) or a margin set above mcap: exact
 //          full-row path, every candidate rescored with compensated
 //          arithmetic and a running best list kept in LDS (flat images, where
 //          most distances lie within the error bound of each other).
+// With defer != 0 the full-row cases are left flagged for a later pass;
+// keys completed here get their flag cleared.
+template <int EM>
 __global__ void __launch_bounds__(ST)
-k_rescore_overflow(const float* __restrict__ xp, int H, int W, int P, int Cp, int D,
-                   const float* __restrict__ A, int g0, int S, int Ncand, int K,
+k_rescore_overflow(const float* __restrict__ xp, int H, int W, int P, int Cp, int D, int L,
+                   const float* __restrict__ A, const int32_t* __restrict__ kmap, int g0, int S,
+                   int Ncand, int K, int defer,
                    const int32_t* __restrict__ lj, const float* __restrict__ lu,
                    const float* __restrict__ ll, const int32_t* __restrict__ lcnt,
-                   const int32_t* __restrict__ oflag, int32_t* __restrict__ idx,
-                   float* __restrict__ dd, DevStats* st) {
+                   int32_t* __restrict__ oflag, int32_t* __restrict__ gpos,
+                   float* __restrict__ ghi, float* __restrict__ glo, int mcap,
+                   int32_t* __restrict__ idx, float* __restrict__ dd, DevStats* st) {
   __shared__ float su[UCAP];
   __shared__ float sl[UCAP];
   __shared__ int sj[UCAP];
   __shared__ int ssh[ST / 64 + 1];
   __shared__ int scnt[64];
+  __shared__ float fh[ST], fl[ST];           // full-row path: staged distances
+  __shared__ int hist[256];
+  __shared__ uint32_t sdig[2];
   const int g = blockIdx.x;
   const int flag = oflag[g];
-  if (flag == 0) return;                     // block-uniform
-  const int gg = g0 + g;
+  if (flag == 0 || (flag == 2 && defer)) return;   // block-uniform
+  const int gg = kmap ? kmap[g0 + g] : g0 + g;
   const int tid = threadIdx.x;
   const int Wc = W - P + 1;
-  const float* kvec = A + (size_t)gg * D;
+  const int wave = tid >> 6;
+  const int cpi = 64 / L;
+  KeySlice<EM> ks;
+  key_slice_load(ks, A + (size_t)gg * D, D, P, H, W, L, (tid & 63) & (L - 1));
   if (tid < S) scnt[tid] = lcnt[g * S + tid];
   __syncthreads();
   if (flag == 1) {
@@ -492,6 +578,7 @@ k_rescore_overflow(const float* __restrict__ xp, int H, int W, int P, int Cp, in
       if (c >= K) hi = mid; else lo = mid + 1;
     }
     const float T = ord2f(lo);
+    const size_t go = (size_t)g * mcap;
     int m = 0;
     for (int sp = 0; sp < S; ++sp) {
       const int csp = scnt[sp];
@@ -502,21 +589,78 @@ k_rescore_overflow(const float* __restrict__ xp, int H, int W, int P, int Cp, in
         const bool keep = i < csp && ll[o + i] <= T && jv >= 0 && jv < Ncand;
         int tc;
         const int pre = block_excl_scan(keep ? 1 : 0, ssh, &tc);
-        if (keep && m + pre < UCAP) sj[m + pre] = jv;
+        if (keep && m + pre < mcap) gpos[go + m + pre] = jv;
         m += tc;
       }
     }
     __syncthreads();
-    if (m > UCAP) goto full_row;
-    if (m < K) goto full_row;                 // cannot happen with valid lists; stay safe
-    for (int i = tid; i < m; i += ST) {
-      const df32 v = exact_dist(xp, H, W, P, Cp, kvec, sj[i], Wc);
-      su[i] = v.hi;
-      sl[i] = v.lo;
+    if (m > mcap || m < K) {                 // m < K cannot happen with valid lists
+      if (defer) return;
+      goto full_row;
     }
+    coop_rescore(ks, xp, [&](int i) { return gpos[go + i]; }, wave * 2 * cpi, m, 8 * cpi, Wc, W,
+                 L, ghi + go, glo + go);
+    __syncthreads();
+    // radix selection of the K-th smallest key (ord(hi), ord(lo + 0), position)
+    uint32_t pre[3] = {0u, 0u, 0u};
+    int remaining = K;
+    for (int p = 0; p < 12; ++p) {
+      const int w = p >> 2, shift = 24 - 8 * (p & 3);
+      const uint32_t hm = shift == 24 ? 0u : (0xffffffffu << (shift + 8));
+      hist[tid] = 0;
+      __syncthreads();
+      for (int i = tid; i < m; i += ST) {
+        const uint32_t k0 = f2ord(ghi[go + i]), k1 = f2ord(glo[go + i] + 0.f);
+        const uint32_t k2 = (uint32_t)gpos[go + i];
+        bool match = true;
+        if (w > 0) match = k0 == pre[0];
+        if (w > 1) match = match && k1 == pre[1];
+        const uint32_t kw = w == 0 ? k0 : (w == 1 ? k1 : k2);
+        if (match && (kw & hm) == (pre[w] & hm)) atomicAdd(&hist[(kw >> shift) & 255u], 1);
+      }
+      __syncthreads();
+      if (wave == 0) {
+        uint32_t pfx = 0u;
+        int rem = remaining;
+        wave_radix_digit(hist, shift, pfx, rem);
+        if (tid == 0) {
+          sdig[0] = pfx;
+          sdig[1] = (uint32_t)(remaining - rem);
+        }
+      }
+      __syncthreads();
+      pre[w] |= sdig[0];
+      remaining -= (int)sdig[1];
+      __syncthreads();
+    }
+    // the K entries with key <= the K-th key, in list order, then sorted
+    int n = 0;
+    for (int base = 0; base < m; base += ST) {
+      const int i = base + tid;
+      bool keep = false;
+      float h = 0.f, lw = 0.f;
+      int jv = 0;
+      if (i < m) {
+        h = ghi[go + i];
+        lw = glo[go + i] + 0.f;
+        jv = gpos[go + i];
+        const uint32_t k0 = f2ord(h), k1 = f2ord(lw), k2 = (uint32_t)jv;
+        keep = k0 < pre[0] || (k0 == pre[0] && (k1 < pre[1] || (k1 == pre[1] && k2 <= pre[2])));
+      }
+      int tc;
+      const int q = block_excl_scan(keep ? 1 : 0, ssh, &tc);
+      if (keep && n + q < 64) {
+        su[n + q] = h;
+        sl[n + q] = lw;
+        sj[n + q] = jv;
+      }
+      n += tc;
+    }
+    __syncthreads();
+    n = min(n, 64);                          // exactly K (positions are unique)
     int n2 = 1;
-    while (n2 < m) n2 <<= 1;
-    for (int i = m + tid; i < n2; i += ST) {
+    while (n2 < n) n2 <<= 1;
+    for (int i = n + tid; i < n2; i += ST) {
       su[i] = __int_as_float(0x7f800000);
       sl[i] = 0.f;
       sj[i] = 0x7fffffff;
@@ -527,9 +671,12 @@ k_rescore_overflow(const float* __restrict__ xp, int H, int W, int P, int Cp, in
       idx[(size_t)gg * K + q] = sj[q];
       dd[(size_t)gg * K + q] = su[q];
     }
-    if (tid == 0 && st) {
-      atomicAdd(&st->margin_sum, (unsigned long long)m);
-      atomicMax(&st->margin_max, m);
+    if (tid == 0) {
+      oflag[g] = 0;
+      if (st) {
+        atomicAdd(&st->margin_sum, (unsigned long long)m);
+        atomicMax(&st->margin_max, m);
+      }
     }
     return;
   }
@@ -539,11 +686,15 @@ full_row:
   float th = __int_as_float(0x7f800000), tl = 0.f;
   int tj = 0x7fffffff;
   for (int base = 0; base < Ncand; base += ST) {
+    coop_rescore(ks, xp, [&](int i) { return base + i; }, wave * 2 * cpi, min(ST, Ncand - base),
+                 8 * cpi, Wc, W, L, fh, fl);
+    __syncthreads();
     const int j = base + tid;
     df32 v = {0.f, 0.f};
     bool adm = false;
     if (j < Ncand) {
-      v = exact_dist(xp, H, W, P, Cp, kvec, j, Wc);
+      v.hi = fh[tid];
+      v.lo = fl[tid];
       adm = cur < K || df_less(v.hi, v.lo, j, th, tl, tj);
     }
     int tc;
@@ -578,42 +729,90 @@ full_row:
     idx[(size_t)gg * K + q] = sj[q];
     dd[(size_t)gg * K + q] = su[q];
   }
-  if (tid == 0 && st) atomicAdd(&st->overflow, 1);
+  if (tid == 0) {
+    oflag[g] = 0;
+    if (st) atomicAdd(&st->overflow, 1);
+  }
 }
 
 }  // namespace
 
-void launch_topk_partial(const glr_plan* pl, const float* dist, const float* km,
-                         const float* cm, int g0, int nk, int32_t* lj, float* lu, float* ll,
-                         int32_t* lcnt, hipStream_t s) {
+void launch_topk_partial(const glr_plan* pl, const float* dist, const float* kmb,
+                         const int32_t* kmap, int g0, const float* cm2, int nk, int bf16,
+                         uint32_t* tsh, int32_t* lj, float* lu, float* ll, int32_t* lcnt,
+                         hipStream_t s) {
   const double u = 5.9604644775390625e-08;      // 2^-24
   const double b = 0.001953125;                 // 2^-9
+  // coefficients rounded up so that the float values are not below the bound
+  const float coef = bf16 ? std::nextafter((float)(4.0 * (2.0 * b + b * b)), 1.f) : 0.f;
+  const float coef2 = std::nextafter((float)((3.0 * pl->D + 26.0) * u), 1.f);
+  const float sqrtD = std::nextafter((float)std::sqrt((double)pl->D), 1e9f);
+  launch_fill_u32(tsh, 0xffffffffu, (size_t)nk, s);
   const int items = nk * pl->n_split;
-  const dim3 grid((items + 3) / 4);
-  if (pl->precision == GLR_PREC_BF16_RESCORE) {
-    // coefficients rounded up so that the float values are not below the bound
-    const float coef = std::nextafter((float)(4.0 * (2.0 * b + b * b)), 1.f);
-    const float coef2 = std::nextafter((float)((3.0 * pl->D + 26.0) * u), 1.f);
-    const float sqrtD = std::nextafter((float)std::sqrt((double)pl->D), 1e9f);
-    hipLaunchKernelGGL(k_topk_partial<true>, grid, dim3(256), 0, s, dist, (size_t)pl->ldd, km, g0,
-                       cm, pl->Ncand, pl->split_len, pl->n_split, nk, pl->K, coef, coef2, sqrtD,
-                       lj, lu, ll, lcnt);
-  } else {
-    const float coef = std::nextafter((float)(2.0 * (pl->D + 8) * u), 1.f);
-    hipLaunchKernelGGL(k_topk_partial<false>, grid, dim3(256), 0, s, dist, (size_t)pl->ldd, km, g0,
-                       cm, pl->Ncand, pl->split_len, pl->n_split, nk, pl->K, coef, 0.f, 0.f, lj,
-                       lu, ll, lcnt);
+  hipLaunchKernelGGL(k_topk_partial, dim3((items + 3) / 4), dim3(256), 0, s, dist,
+                     (size_t)pl->ldd, (const float4*)kmb, kmap, g0, cm2, pl->Ncand, pl->split_len,
+                     pl->n_split, nk, pl->K, coef, coef2, sqrtD, tsh, lj, lu, ll, lcnt);
+}
+
+// Lanes per candidate of the exact rescoring: the fewest (>= 8) that keep
+// every lane at <= 32 patch elements; D <= 4096 needs at most 64 per lane.
+static int rescore_lanes(int D) {
+  int L = 64;
+  while (L > 8 && (D + L / 2 - 1) / (L / 2) <= 32) L >>= 1;
+  return L;
+}
+
+template <int EM>
+static void launch_select_t(const glr_plan* pl, const float* xp, const float* A,
+                            const int32_t* kmap, int g0, int nk, const int32_t* lj,
+                            const float* lu, const float* ll, const int32_t* lcnt, int32_t* idx,
+                            float* dd, int32_t* oflag, int defer, const BigMargin& bm,
+                            DevStats* st, int L, hipStream_t s) {
+  hipLaunchKernelGGL(k_select_rescore<EM>, dim3((nk + 3) / 4), dim3(256), 0, s, xp, pl->H, pl->W,
+                     pl->P, pl->Cp, pl->D, L, A, kmap, g0, nk, pl->n_split, pl->Ncand, pl->K, lj,
+                     lu, ll, lcnt, idx, dd, oflag, st);
+  hipLaunchKernelGGL(k_rescore_overflow<EM>, dim3(nk), dim3(ST), 0, s, xp, pl->H, pl->W, pl->P,
+                     pl->Cp, pl->D, L, A, kmap, g0, pl->n_split, pl->Ncand, pl->K, defer, lj, lu,
+                     ll, lcnt, oflag, bm.pos, bm.hi, bm.lo, bm.cap, idx, dd, st);
+}
+
+void launch_select_rescore(const glr_plan* pl, const float* xp, const float* A,
+                           const int32_t* kmap, int g0, int nk, const int32_t* lj,
+                           const float* lu, const float* ll, const int32_t* lcnt, int32_t* idx,
+                           float* dd, int32_t* oflag, int defer, const BigMargin& bm,
+                           DevStats* st, hipStream_t s) {
+  const int L = rescore_lanes(pl->D);
+  if ((pl->D + L - 1) / L <= 32)
+    launch_select_t<32>(pl, xp, A, kmap, g0, nk, lj, lu, ll, lcnt, idx, dd, oflag, defer, bm, st,
+                        L, s);
+  else
+    launch_select_t<64>(pl, xp, A, kmap, g0, nk, lj, lu, ll, lcnt, idx, dd, oflag, defer, bm, st,
+                        L, s);
+}
+
+// Append the chunk keys g0 + g with oflag[g] != 0 to klist at *kcount, in
+// key order (one block).
+__global__ void __launch_bounds__(1024)
+k_collect_flags(const int32_t* __restrict__ oflag, int g0, int nk, int32_t* __restrict__ klist,
+                int32_t* __restrict__ kcount, DevStats* st) {
+  __shared__ int sh[1024 / 64 + 1];
+  int base = kcount[0];
+  const int start = base;
+  for (int i0 = 0; i0 < nk; i0 += 1024) {
+    const int i = i0 + threadIdx.x;
+    const bool f = i < nk && oflag[i] != 0;
+    int tot;
+    const int pre = block_excl_scan(f ? 1 : 0, sh, &tot);
+    if (f) klist[base + pre] = g0 + i;
+    base += tot;
+  }
+  if (threadIdx.x == 0) {
+    kcount[0] = base;
+    if (st) atomicAdd(&st->rematch, base - start);
   }
 }
 
-void launch_select_rescore(const glr_plan* pl, const float* xp, const float* A, int g0, int nk,
-                           const int32_t* lj, const float* lu, const float* ll,
-                           const int32_t* lcnt, int32_t* idx, float* dd, int32_t* oflag,
-                           DevStats* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_select_rescore, dim3((nk + 3) / 4), dim3(256), 0, s, xp, pl->H, pl->W, pl->P,
-                     pl->Cp, pl->D, A, g0, nk, pl->n_split, pl->Ncand, pl->K, lj, lu, ll, lcnt, idx,
-                     dd, oflag, st);
-  hipLaunchKernelGGL(k_rescore_overflow, dim3(nk), dim3(ST), 0, s, xp, pl->H, pl->W, pl->P, pl->Cp,
-                     pl->D, A, g0, pl->n_split, pl->Ncand, pl->K, lj, lu, ll, lcnt, oflag, idx, dd,
-                     st);
+void launch_collect_flags(const int32_t* oflag, int g0, int nk, int32_t* klist, int32_t* kcount,
+                          DevStats* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_collect_flags, dim3(1), dim3(1024), 0, s, oflag, g0, nk, klist, kcount, st);
 }

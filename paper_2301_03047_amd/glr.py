@@ -44,7 +44,8 @@ class Stats(ctypes.Structure):
                 ("ms_topk", ctypes.c_float), ("ms_select", ctypes.c_float),
                 ("ms_lowrank", ctypes.c_float), ("ms_aggregate", ctypes.c_float),
                 ("ms_data", ctypes.c_float), ("ms_norms", ctypes.c_float),
-                ("match_launches", ctypes.c_int64), ("jacobi_sweeps_sum", ctypes.c_int64)]
+                ("match_launches", ctypes.c_int64), ("jacobi_sweeps_sum", ctypes.c_int64),
+                ("rematch_keys", ctypes.c_int64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -116,7 +117,7 @@ class Plan:
     """One problem shape: modality, image size, patch size, keys, K, solver."""
 
     def __init__(self, modality, H, W, C, patch, n_keys, k, iters=0, sigma=None, mask=None,
-                 rho=1.0, wnnm_c=None, wnnm_eps=None, precision="fp32", dist_chunk_mb=2048,
+                 rho=1.0, wnnm_c=None, wnnm_eps=None, precision="fp32", dist_chunk_mb=8192,
                  timing=False, device="cuda", allocate=True):
         import torch
         L = lib()

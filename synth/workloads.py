@@ -45,11 +45,14 @@ class Workload:
         return self.real_channels * self.patch * self.patch
 
 
+# Noise schedules: the first level is of the order of the initial estimate's
+# artefacts (mask modulation for CACTI, mosaic replication for MSFA, k-space
+# undersampling for MRI), decaying geometrically to the last.
 WORKLOADS = {
-    "cacti_128": Workload("cacti_128", "cacti", 128, 128, 8, 6, 128, 32, 5, 0.08, 0.02, seed=0),
+    "cacti_128": Workload("cacti_128", "cacti", 128, 128, 8, 6, 128, 32, 5, 1.0, 0.05, seed=0),
     "mri_256": Workload("mri_256", "mri", 256, 256, 1, 6, 1024, 45, 30, 0.05, 0.01, seed=1000),
-    "msfa_512": Workload("msfa_512", "msfa", 512, 512, 16, 6, 4096, 64, 40, 0.05, 0.01, seed=2000),
-    "cacti_1024": Workload("cacti_1024", "cacti", 1024, 1024, 24, 8, 16384, 64, 50, 0.08, 0.02,
+    "msfa_512": Workload("msfa_512", "msfa", 512, 512, 16, 6, 4096, 64, 40, 0.5, 0.05, seed=2000),
+    "cacti_1024": Workload("cacti_1024", "cacti", 1024, 1024, 24, 8, 16384, 64, 50, 1.0, 0.05,
                            precision="bf16", seed=3000),
 }
 

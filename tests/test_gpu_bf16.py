@@ -143,3 +143,26 @@ def test_bf16_cacti_1024_full_size_sampled_keys():
     out_f = host(pf.prior_step(xg, sigma))
     np.testing.assert_array_equal(out_b, out_f)
     assert np.isfinite(out_b).all()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_large_margin_path_periodic_image(precision):
+    # a texture of period 4 makes every patch recur ~1500 times at distance 0:
+    # the margin sets exceed the wave buffer and take the global-memory path
+    # (radix selection on (distance, low part, position)); ties resolve to the
+    # lowest positions, exactly as the oracle orders them
+    require_gpu()
+    C, H, W, P, N, K = 2, 128, 192, 4, 20, 32
+    tile = np.random.default_rng(4).uniform(size=(C, 4, 4)).astype(np.float32)
+    x = np.tile(tile, (1, H // 4, W // 4))
+    n_cand = (H - P + 1) * (W - P + 1)
+    keys = np.sort(np.random.default_rng(8).choice(n_cand, size=N, replace=False))
+    plan = _plan(C, H, W, P, N, K, precision=precision)
+    idx, dist = plan.match_topk(gpu(x), gpu(keys.astype(np.int32)))
+    st = plan.read_stats()
+    print("margin max", st["margin_max"], "overflow", st["overflow_keys"],
+          "rematch", st["rematch_keys"], flush=True)
+    ref_idx, ref_dist = om.topk_exact(x.astype(np.float64), P, keys, K)
+    np.testing.assert_array_equal(host(idx), ref_idx)
+    np.testing.assert_array_equal(host(dist), 0.0)
+    assert st["margin_max"] > 1024 and st["overflow_keys"] == 0
