@@ -198,6 +198,43 @@ GLR_API glr_status glr_reconstruct(glr_plan* plan, const void* y, void* state, i
  * them afterwards. */
 GLR_API glr_status glr_read_stats(glr_plan* plan, glr_stats* host_out, int32_t reset);
 
+/* --------------------------------------------------------------- CNN surrogate
+ * A learned stand-in for the prior step (not part of the paper's method; it
+ * is judged against the GLR step, see glr_params.surrogate):
+ *   x_out = x + f(x, sigma),  f = 3x3 conv 2->64, ReLU, 3 x (3x3 conv
+ *   64->64, ReLU), 3x3 conv 64->1, zero padding, cross-correlation taps.
+ * A slice is one 2-D image [h][w] (a CACTI frame, an MRI real or imaginary
+ * plane, an MSFA band); the network input is (slice, constant sigma map).
+ * params: device float [glr_cnn_param_count()] in the order W1 [64][2][3][3],
+ * b1 [64], W2 [64][64][3][3], b2, W3, b3, W4, b4, W5 [1][64][3][3], b5 [1].
+ * packed: device buffer of glr_cnn_packed_bytes() (256-byte aligned) holding
+ * the BF16 weights and FP32 biases the kernels read; glr_cnn_pack() fills
+ * it from params.  Weights and activations are BF16, sums FP32.  All
+ * buffers are caller-owned; ws is a workspace of glr_cnn_workspace_size(). */
+GLR_API int32_t glr_cnn_param_count(void);
+GLR_API size_t glr_cnn_packed_bytes(void);
+/* train != 0 sizes the workspace for glr_cnn_loss_grad. */
+GLR_API glr_status glr_cnn_workspace_size(int32_t B, int32_t h, int32_t w, int32_t train,
+                                          size_t* bytes);
+GLR_API glr_status glr_cnn_pack(const float* params, void* packed, void* stream);
+/* out[B][h][w] = x + f(x, sigma[b]) for slices x [B][h][w] (device float);
+ * sigma: device float [B]. */
+GLR_API glr_status glr_cnn_forward(const void* packed, const float* x, const float* sigma,
+                                   float* out, int32_t B, int32_t h, int32_t w, void* ws,
+                                   void* stream);
+/* Mean squared error loss of the surrogate estimate against target
+ * [B][h][w] into *loss (device float) and its gradient with respect to every
+ * parameter into grad (device float [param_count], the params layout);
+ * out [B][h][w] receives the surrogate estimate. */
+GLR_API glr_status glr_cnn_loss_grad(const void* packed, const float* x, const float* sigma,
+                                     const float* target, int32_t B, int32_t h, int32_t w,
+                                     float* loss, float* grad, float* out, void* ws,
+                                     void* stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8; step counts from 1) on
+ * params with moments m, v (device float [param_count]); repacks packed. */
+GLR_API glr_status glr_cnn_adam(float* params, float* m, float* v, const float* grad,
+                                int32_t step, float lr, void* packed, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -6,7 +6,7 @@ current HIP stream into the library calls; every step runs in the library's
 HIP kernels.  Importing works without a GPU; calls need the built
 ``libglr.so`` and a device.
 """
-from .glr import (Plan, GlrError, lib, library_path, CACTI, MRI, MSFA,
+from .glr import (Plan, Cnn, GlrError, lib, library_path, CACTI, MRI, MSFA,
                   STATUS_NAMES)
 
-__all__ = ["Plan", "GlrError", "lib", "library_path", "CACTI", "MRI", "MSFA", "STATUS_NAMES"]
+__all__ = ["Plan", "Cnn", "GlrError", "lib", "library_path", "CACTI", "MRI", "MSFA", "STATUS_NAMES"]

@@ -693,3 +693,69 @@ glr_status glr_read_stats(glr_plan* pl, glr_stats* out, int32_t reset) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- CNN surrogate
+namespace {
+glr_status cnn_shape(const char* fn, int32_t B, int32_t h, int32_t w) {
+  if (B < 1 || h < 1 || w < 1) return fail(GLR_ERR_SHAPE, "%s: B, h, w must be >= 1", fn);
+  if ((long long)B * h * w > (1LL << 31) / 64)
+    return fail(GLR_ERR_UNSUPPORTED, "%s: B*h*w too large", fn);
+  return GLR_OK;
+}
+}  // namespace
+
+int32_t glr_cnn_param_count(void) { return cnn_param_count(); }
+size_t glr_cnn_packed_bytes(void) { return cnn_packed_bytes(); }
+
+glr_status glr_cnn_workspace_size(int32_t B, int32_t h, int32_t w, int32_t train, size_t* bytes) {
+  if (!bytes) return fail(GLR_ERR_INVALID_ARG, "glr_cnn_workspace_size: NULL bytes");
+  glr_status e = cnn_shape(__func__, B, h, w);
+  if (e) return e;
+  *bytes = cnn_workspace_bytes(B, h, w, train ? 1 : 0);
+  return GLR_OK;
+}
+
+glr_status glr_cnn_pack(const float* params, void* packed, void* stream) {
+  if (!params || !packed) return fail(GLR_ERR_INVALID_ARG, "glr_cnn_pack: NULL argument");
+  if (!aligned(params, 16) || !aligned(packed, 256))
+    return fail(GLR_ERR_ALIGNMENT, "glr_cnn_pack: params 16-byte, packed 256-byte alignment");
+  cnn_pack(params, packed, (hipStream_t)stream);
+  return check_hip(__func__);
+}
+
+glr_status glr_cnn_forward(const void* packed, const float* x, const float* sigma, float* out,
+                           int32_t B, int32_t h, int32_t w, void* ws, void* stream) {
+  if (!packed || !x || !sigma || !out || !ws)
+    return fail(GLR_ERR_INVALID_ARG, "glr_cnn_forward: NULL argument");
+  glr_status e = cnn_shape(__func__, B, h, w);
+  if (e) return e;
+  if (!aligned(packed, 256) || !aligned(ws, 256) || !aligned(x, 16) || !aligned(out, 16))
+    return fail(GLR_ERR_ALIGNMENT, "glr_cnn_forward: packed/ws 256-byte, x/out 16-byte alignment");
+  cnn_forward(packed, x, sigma, out, B, h, w, ws, (hipStream_t)stream);
+  return check_hip(__func__);
+}
+
+glr_status glr_cnn_loss_grad(const void* packed, const float* x, const float* sigma,
+                             const float* target, int32_t B, int32_t h, int32_t w, float* loss,
+                             float* grad, float* out, void* ws, void* stream) {
+  if (!packed || !x || !sigma || !target || !loss || !grad || !out || !ws)
+    return fail(GLR_ERR_INVALID_ARG, "glr_cnn_loss_grad: NULL argument");
+  glr_status e = cnn_shape(__func__, B, h, w);
+  if (e) return e;
+  if (!aligned(packed, 256) || !aligned(ws, 256) || !aligned(x, 16) || !aligned(out, 16) ||
+      !aligned(grad, 16))
+    return fail(GLR_ERR_ALIGNMENT, "glr_cnn_loss_grad: packed/ws 256-byte, arrays 16-byte");
+  cnn_loss_grad(packed, x, sigma, target, B, h, w, loss, grad, out, ws, (hipStream_t)stream);
+  return check_hip(__func__);
+}
+
+glr_status glr_cnn_adam(float* params, float* m, float* v, const float* grad, int32_t step,
+                        float lr, void* packed, void* stream) {
+  if (!params || !m || !v || !grad || !packed)
+    return fail(GLR_ERR_INVALID_ARG, "glr_cnn_adam: NULL argument");
+  if (step < 1) return fail(GLR_ERR_INVALID_ARG, "glr_cnn_adam: step counts from 1");
+  if (!(lr > 0.f)) return fail(GLR_ERR_INVALID_ARG, "glr_cnn_adam: lr must be > 0");
+  if (!aligned(packed, 256)) return fail(GLR_ERR_ALIGNMENT, "glr_cnn_adam: packed 256-byte");
+  cnn_adam(params, m, v, grad, step, lr, packed, (hipStream_t)stream);
+  return check_hip(__func__);
+}

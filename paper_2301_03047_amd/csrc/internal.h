@@ -141,3 +141,16 @@ void launch_wnnm(const glr_plan* pl, const float* xp, const int32_t* idx, float 
 void launch_aggregate(const glr_plan* pl, const float* xbar, const int32_t* idx,
                       const float* xhat, unsigned long long* pairs, int32_t* offs, float* out,
                       hipStream_t s);
+
+// cnn.hip
+size_t cnn_packed_bytes();
+int cnn_param_count();
+size_t cnn_workspace_bytes(int B, int h, int w, int train);
+void cnn_pack(const float* params, void* packed, hipStream_t s);
+void cnn_forward(const void* packed, const float* x, const float* sigma, float* out, int B, int h,
+                 int w, void* ws, hipStream_t s);
+void cnn_loss_grad(const void* packed, const float* x, const float* sigma, const float* tgt,
+                   int B, int h, int w, float* loss, float* grad, float* out_tmp, void* ws,
+                   hipStream_t s);
+void cnn_adam(float* params, float* m, float* v, const float* grad, int step, float lr,
+              void* packed, hipStream_t s);

@@ -94,6 +94,15 @@ def lib():
         "glr_state_bytes": (st, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
         "glr_reconstruct": (st, [_vp, _vp, _vp, _c_i32, _c_i32, _vp, _vp, _vp]),
         "glr_read_stats": (st, [_vp, ctypes.POINTER(Stats), _c_i32]),
+        "glr_cnn_param_count": (_c_i32, []),
+        "glr_cnn_packed_bytes": (ctypes.c_size_t, []),
+        "glr_cnn_workspace_size": (st, [_c_i32, _c_i32, _c_i32, _c_i32,
+                                        ctypes.POINTER(ctypes.c_size_t)]),
+        "glr_cnn_pack": (st, [_vp, _vp, _vp]),
+        "glr_cnn_forward": (st, [_vp, _vp, _vp, _vp, _c_i32, _c_i32, _c_i32, _vp, _vp]),
+        "glr_cnn_loss_grad": (st, [_vp, _vp, _vp, _vp, _c_i32, _c_i32, _c_i32, _vp, _vp, _vp,
+                                   _vp, _vp]),
+        "glr_cnn_adam": (st, [_vp, _vp, _vp, _vp, _c_i32, ctypes.c_float, _vp, _vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -288,3 +297,87 @@ class Plan:
         s = Stats()
         _check(lib().glr_read_stats(self._h, ctypes.byref(s), 1 if reset else 0))
         return s.as_dict()
+
+
+class Cnn:
+    """The residual CNN surrogate: parameters (flat FP32), Adam moments and the
+    packed BF16 weights live in device tensors owned here; every call runs the
+    library's kernels on torch's current stream."""
+
+    def __init__(self, params, device="cuda"):
+        import torch
+        self.device = torch.device(device)
+        n = int(lib().glr_cnn_param_count())
+        p = torch.as_tensor(params, dtype=torch.float32).to(self.device).contiguous()
+        if p.numel() != n:
+            raise ValueError(f"need {n} parameters, got {p.numel()}")
+        self.params = p
+        self.m = torch.zeros_like(p)
+        self.v = torch.zeros_like(p)
+        self.grad = torch.zeros_like(p)
+        self.step = 0
+        self.packed = torch.empty(int(lib().glr_cnn_packed_bytes()), dtype=torch.uint8,
+                                  device=self.device)
+        self._ws = {}
+        self.repack()
+
+    @staticmethod
+    def param_count():
+        return int(lib().glr_cnn_param_count())
+
+    def _stream(self):
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _workspace(self, B, h, w, train):
+        import torch
+        key = (B, h, w, train)
+        if key not in self._ws:
+            b = ctypes.c_size_t()
+            _check(lib().glr_cnn_workspace_size(B, h, w, train, ctypes.byref(b)))
+            self._ws = {key: torch.empty(int(b.value), dtype=torch.uint8, device=self.device)}
+        return self._ws[key]
+
+    def repack(self):
+        _check(lib().glr_cnn_pack(_ptr(self.params), _ptr(self.packed), self._stream()))
+
+    def _shape(self, x, sigma):
+        import torch
+        if x.dim() != 3 or x.dtype != torch.float32 or not x.is_contiguous():
+            raise ValueError("x: contiguous float32 [B][h][w]")
+        sig = torch.as_tensor(sigma, dtype=torch.float32, device=self.device).reshape(-1)
+        if sig.numel() == 1:
+            sig = sig.expand(x.shape[0])
+        return x.shape[0], x.shape[1], x.shape[2], sig.contiguous()
+
+    def forward(self, x, sigma, out=None):
+        import torch
+        B, h, w, sig = self._shape(x, sigma)
+        out = torch.empty_like(x) if out is None else out
+        ws = self._workspace(B, h, w, 0)
+        _check(lib().glr_cnn_forward(_ptr(self.packed), _ptr(x), _ptr(sig), _ptr(out), B, h, w,
+                                     _ptr(ws), self._stream()))
+        return out
+
+    def loss_grad(self, x, sigma, target):
+        """Loss (device scalar), gradient (self.grad) and the estimate."""
+        import torch
+        B, h, w, sig = self._shape(x, sigma)
+        out = torch.empty_like(x)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        ws = self._workspace(B, h, w, 1)
+        _check(lib().glr_cnn_loss_grad(_ptr(self.packed), _ptr(x), _ptr(sig), _ptr(target),
+                                       B, h, w, _ptr(loss), _ptr(self.grad), _ptr(out),
+                                       _ptr(ws), self._stream()))
+        return loss, self.grad, out
+
+    def adam(self, lr):
+        self.step += 1
+        _check(lib().glr_cnn_adam(_ptr(self.params), _ptr(self.m), _ptr(self.v),
+                                  _ptr(self.grad), self.step, float(lr), _ptr(self.packed),
+                                  self._stream()))
+
+    def train_step(self, x, sigma, target, lr):
+        loss, _, _ = self.loss_grad(x, sigma, target)
+        self.adam(lr)
+        return loss
