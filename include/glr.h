@@ -91,6 +91,20 @@ typedef struct glr_params {
   int32_t dist_chunk_mb; /* max size of one distance-matrix chunk (MiB)         */
   int32_t timing;        /* nonzero: record per-stage HIP event pairs on the
                             stream (no host sync); glr_read_stats() sums them */
+  /* CNN surrogate (glr_cnn_*; not part of the paper's method).  With
+   * surrogate != 0, glr_reconstruct uses the network for the prior step
+   * while t < ceil(surrogate_frac * iters) and the surrogate is active; each
+   * use is judged: GLR runs on every judge_stride-th detected key and
+   *   delta = ||(x_cnn - x_glr)|cov|| / ||x_glr|cov||
+   * over the pixels those groups cover; delta > judge_delta_max or a
+   * non-finite estimate makes that iteration run the full GLR step and
+   * deactivates the surrogate for the rest of the run (the active flag is
+   * part of the loop state).  judge_delta_max = +inf skips the judge. */
+  int32_t surrogate;
+  float surrogate_frac;  /* default 0.6 (taken to 6 decimals)                    */
+  int32_t judge_stride;  /* default 8                                            */
+  float judge_delta_max; /* default 0.02                                         */
+  const void* cnn_packed; /* device, glr_cnn_packed_bytes(), from glr_cnn_pack()  */
 } glr_params;
 
 /* Counters of the last prior steps, read by glr_read_stats(). */
@@ -107,6 +121,10 @@ typedef struct glr_stats {
   int64_t match_launches;     /* matcher kernel launches timed in ms_match       */
   int64_t jacobi_sweeps_sum;  /* Jacobi sweeps summed over all groups            */
   int64_t rematch_keys;       /* BF16 form: keys re-matched with the FP32 form   */
+  int64_t surrogate_steps;    /* iterations whose prior step was the CNN         */
+  int64_t fallback_steps;     /* judged iterations that fell back to GLR         */
+  float judge_delta_last;     /* deviation measured by the last judge            */
+  float ms_cnn, ms_judge;     /* with timing: CNN forward, judge (subset GLR)    */
 } glr_stats;
 
 typedef struct glr_plan glr_plan;

@@ -106,7 +106,7 @@ constexpr int GX = 64;            // pixels per gather block (one image row segm
 __global__ void k_gather(const float* __restrict__ xbar, const float* __restrict__ xhat,
                          const unsigned long long* __restrict__ keys,
                          const int32_t* __restrict__ offs, int Cp, int H, int W, int P, int D,
-                         int K, float* __restrict__ out) {
+                         int K, float* __restrict__ out, int32_t* __restrict__ cover) {
   extern __shared__ float part[];          // [P][GX][CB + 1]
   const int tx = threadIdx.x, dy = threadIdx.y;
   const int r = blockIdx.y;
@@ -154,6 +154,7 @@ __global__ void k_gather(const float* __restrict__ xbar, const float* __restrict
       n += __float_as_int(pp[CB]);
     }
     const size_t HW = (size_t)H * W;
+    if (cover && cb == 0) cover[(size_t)r * W + c] = n;
     for (int u = 0; u < nch; ++u) {
       const size_t o = (size_t)(cb * CB + u) * HW + (size_t)r * W + c;
       out[o] = n ? sum[u] / (float)n : xbar[o];
@@ -165,7 +166,7 @@ __global__ void k_gather(const float* __restrict__ xbar, const float* __restrict
 
 void launch_aggregate(const glr_plan* pl, const float* xbar, const int32_t* idx,
                       const float* xhat, unsigned long long* pairs, int32_t* offs, float* out,
-                      hipStream_t s) {
+                      int32_t* cover, hipStream_t s) {
   const int M = pl->M, M2 = pl->M2;
   hipLaunchKernelGGL(k_pairs, dim3((M2 + 255) / 256), dim3(256), 0, s, idx, M, M2, pairs);
   hipLaunchKernelGGL(k_bitonic_local_sort, dim3(M2 / LN), dim3(LT), 0, s, pairs);
@@ -180,5 +181,5 @@ void launch_aggregate(const glr_plan* pl, const float* xbar, const int32_t* idx,
   dim3 grid((pl->W + GX - 1) / GX, pl->H, (pl->Cp + CB - 1) / CB);
   const size_t lds = (size_t)pl->P * GX * (CB + 1) * sizeof(float);
   hipLaunchKernelGGL(k_gather, grid, dim3(GX, pl->P), lds, s, xbar, xhat, pairs, offs, pl->Cp,
-                     pl->H, pl->W, pl->P, pl->D, pl->K, out);
+                     pl->H, pl->W, pl->P, pl->D, pl->K, out, cover);
 }

@@ -105,7 +105,8 @@ void fold_timers(glr_plan* pl) {
   }
   pl->ev_used = 0;
 }
-enum { T_DETECT = 0, T_MATCH, T_TOPK, T_SELECT, T_LOWRANK, T_AGG, T_DATA, T_NORMS, T_COUNT };
+enum { T_DETECT = 0, T_MATCH, T_TOPK, T_SELECT, T_LOWRANK, T_AGG, T_DATA, T_NORMS, T_CNN, T_JUDGE,
+       T_COUNT };
 
 // ---------------------------------------------------------------- prior step
 // xp: planar [Cp][H][W]; xo: planar output; keys_in: optional caller keys.
@@ -191,7 +192,7 @@ glr_status match_stage(glr_plan* pl, const float* xp, const int32_t* keys, int32
 }
 
 glr_status lowrank_stage(glr_plan* pl, const float* xp, const int32_t* idx, float sigma, float* xo,
-                         float* sv, char* ws, hipStream_t s) {
+                         float* sv, char* ws, hipStream_t s, int32_t* cover = nullptr) {
   float* xhat = (float*)(ws + pl->ws.xhat);
   DevStats* st = (DevStats*)(ws + pl->ws.stats);
   {
@@ -201,7 +202,7 @@ glr_status lowrank_stage(glr_plan* pl, const float* xp, const int32_t* idx, floa
   {
     StageTimer t(pl, s, T_AGG);
     launch_aggregate(pl, xp, idx, xhat, (unsigned long long*)(ws + pl->ws.pairs),
-                     (int32_t*)(ws + pl->ws.offs), xo, s);
+                     (int32_t*)(ws + pl->ws.offs), xo, cover, s);
   }
   return check_hip("glr_lowrank_aggregate");
 }
@@ -223,6 +224,71 @@ glr_status prior_planar(glr_plan* pl, const float* xp, float sigma, float* xo, c
   if (e) return e;
   launch_count_step((DevStats*)(ws + pl->ws.stats), s);
   return check_hip("prior step");
+}
+
+// The surrogate in place of the prior step on planar xp (Cp slices of H x W):
+// x_cnn = xp + f(xp, sigma); unless the judge is off, GLR on every
+// judge_stride-th detected key gives x_glr on the covered pixels and the
+// relative deviation decides.  *accepted: the CNN estimate was used (xo);
+// otherwise xo is the full GLR step.  One host read of the deviation.
+glr_status surrogate_prior(glr_plan* pl, const float* xp, float sigma, float* xo, char* ws,
+                           hipStream_t s, bool* accepted) {
+  const int HW = pl->H * pl->W;
+  float* xcnn = (float*)(ws + pl->ws.xcnn);
+  float* sigv = (float*)(ws + pl->ws.sigv);
+  {
+    StageTimer t(pl, s, T_CNN);
+    launch_fill_f32(sigv, sigma, (size_t)pl->Cp, s);
+    cnn_forward(pl->cnn_packed, xp, sigv, xcnn, pl->Cp, pl->H, pl->W, ws + pl->ws.cnn_ws, s);
+  }
+  glr_status e = check_hip("surrogate forward");
+  if (e) return e;
+  float delta = 0.f;
+  const bool judged = !std::isinf(pl->judge_delta_max);
+  if (judged) {
+    int32_t* keys = (int32_t*)(ws + pl->ws.keys);
+    int32_t* sub = (int32_t*)(ws + pl->ws.subkeys);
+    int32_t* idx = (int32_t*)(ws + pl->ws.idx);
+    float* dd = (float*)(ws + pl->ws.dd);
+    float* xglr = (float*)(ws + pl->ws.xglr);
+    int32_t* cover = (int32_t*)(ws + pl->ws.cover);
+    float* dptr = (float*)(ws + pl->ws.jdelta);
+    const int N = pl->N, M = pl->M, M2 = pl->M2;
+    const int ns = (N + pl->judge_stride - 1) / pl->judge_stride;
+    {
+      StageTimer t(pl, s, T_DETECT);
+      launch_detect(pl, xp, ws, keys, s);
+      launch_stride_keys(keys, N, pl->judge_stride, sub, s);
+    }
+    // the subset step reuses the plan's buffers with N = ns keys
+    pl->N = ns;
+    pl->M = ns * pl->K;
+    pl->M2 = 2048;
+    while (pl->M2 < pl->M) pl->M2 <<= 1;
+    e = match_stage(pl, xp, sub, idx, dd, ws, s);
+    if (!e) e = lowrank_stage(pl, xp, idx, sigma, xglr, (float*)(ws + pl->ws.sv), ws, s, cover);
+    pl->N = N;
+    pl->M = M;
+    pl->M2 = M2;
+    if (e) return e;
+    {
+      StageTimer t(pl, s, T_JUDGE);
+      launch_judge(xcnn, xglr, cover, pl->Cp, HW, (float*)(ws + pl->ws.jpart), dptr, s);
+    }
+    if (hipMemcpyAsync(&delta, dptr, sizeof delta, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return check_hip("judge");
+    pl->judge_delta_last = delta;
+  }
+  if (!judged || delta <= pl->judge_delta_max) {
+    hipMemcpyAsync(xo, xcnn, (size_t)pl->Cp * HW * 4, hipMemcpyDeviceToDevice, s);
+    pl->sur_steps++;
+    *accepted = true;
+    return check_hip("surrogate");
+  }
+  pl->fallback_steps++;
+  *accepted = false;
+  return prior_planar(pl, xp, sigma, xo, ws, s);
 }
 
 // input image (modality layout) -> planar pointer (complex data is split into ws.xp)
@@ -283,6 +349,11 @@ void glr_params_default(glr_params* p) {
   p->precision = GLR_PREC_FP32;
   p->dist_chunk_mb = 8192;
   p->timing = 0;
+  p->surrogate = 0;
+  p->surrogate_frac = 0.6f;
+  p->judge_stride = 8;
+  p->judge_delta_max = 0.02f;
+  p->cnn_packed = nullptr;
 }
 
 glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_params* pr,
@@ -317,6 +388,15 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
     return fail(GLR_ERR_INVALID_ARG, "unknown precision %d", pr->precision);
   if (!(pr->wnnm_c >= 0.f) || !(pr->wnnm_eps > 0.f) || !(pr->rho > 0.f))
     return fail(GLR_ERR_INVALID_ARG, "wnnm_c >= 0, wnnm_eps > 0 and rho > 0 required");
+  if (pr->surrogate) {
+    if (!pr->cnn_packed) return fail(GLR_ERR_INVALID_ARG, "surrogate needs cnn_packed");
+    if (!aligned(pr->cnn_packed, 256))
+      return fail(GLR_ERR_ALIGNMENT, "cnn_packed not 256-byte aligned");
+    if (pr->judge_stride < 1) return fail(GLR_ERR_INVALID_ARG, "judge_stride must be >= 1");
+    if (!(pr->surrogate_frac >= 0.f && pr->surrogate_frac <= 1.f))
+      return fail(GLR_ERR_INVALID_ARG, "surrogate_frac must be in [0, 1]");
+    if (!(pr->judge_delta_max >= 0.f)) return fail(GLR_ERR_INVALID_ARG, "judge_delta_max >= 0");
+  }
   if (pb->modality == GLR_MRI) {
     if (pb->C != 1) return fail(GLR_ERR_SHAPE, "MRI plans take C = 1 (complex image)");
     if (!pow2(pb->H) || !pow2(pb->W) || pb->H < 4 || pb->W < 4 || pb->H > 2048 || pb->W > 2048)
@@ -352,6 +432,13 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
   pl->rho = pr->rho;
   pl->wnnm_c = pr->wnnm_c;
   pl->wnnm_eps = pr->wnnm_eps;
+  pl->surrogate = pr->surrogate ? 1 : 0;
+  pl->surrogate_frac = pr->surrogate_frac;
+  pl->judge_stride = pr->judge_stride;
+  pl->judge_delta_max = pr->judge_delta_max;
+  pl->cnn_packed = pr->cnn_packed;
+  pl->sur_steps = pl->fallback_steps = 0;
+  pl->judge_delta_last = 0.f;
   if (pr->iters > 0) pl->sigma.assign(pr->sigma, pr->sigma + pr->iters);
   pl->Hc = Hc;
   pl->Wc = Wc;
@@ -419,6 +506,15 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
   L.cplx_a = c.take(pl->is_complex ? HW * 8 : 0);
   L.cplx_b = c.take(pl->is_complex ? HW * 8 : 0);
   L.red = c.take(256);
+  const bool sur = pl->surrogate != 0;
+  L.cnn_ws = c.take(sur ? cnn_workspace_bytes(Cp, pl->H, pl->W, 0) : 0);
+  L.xcnn = c.take(sur ? HW * Cp * 4 : 0);
+  L.xglr = c.take(sur ? HW * Cp * 4 : 0);
+  L.cover = c.take(sur ? HW * 4 : 0);
+  L.subkeys = c.take(sur ? (size_t)pl->N * 4 : 0);
+  L.sigv = c.take(sur ? (size_t)Cp * 4 : 0);
+  L.jpart = c.take(sur ? 512 * 3 * 4 : 0);
+  L.jdelta = c.take(sur ? 4 : 0);
   L.stats = c.take(sizeof(DevStats));
   L.total = c.off;
 
@@ -592,6 +688,7 @@ glr_status glr_state_bytes(const glr_plan* pl, size_t* bytes) {
   if (!pl || !bytes) return fail(GLR_ERR_INVALID_ARG, "glr_state_bytes: NULL argument");
   const size_t HW = (size_t)pl->H * pl->W;
   *bytes = pl->is_complex ? 3 * HW * 8 : (size_t)pl->C * HW * 4;
+  if (pl->surrogate) *bytes += 256;              // surrogate-active flag (int32)
   return GLR_OK;
 }
 
@@ -608,6 +705,33 @@ glr_status glr_reconstruct(glr_plan* pl, const void* y, void* state, int32_t t_b
   char* w = (char*)ws;
   ensure_stats(pl, w, s);
   const int H = pl->H, W = pl->W, HW = H * W;
+  // surrogate-active flag in the state tail
+  int32_t* flag = (int32_t*)((char*)state + (pl->is_complex ? 3 * (size_t)HW * 8
+                                                              : (size_t)pl->C * HW * 4));
+  int active = 0;
+  // ceil(frac * T) with frac taken to 6 decimals (0.6f must give 3 of 5, not 4)
+  const long long fr = std::llround((double)pl->surrogate_frac * 1e6);
+  const int t_sur = pl->surrogate ? (int)((fr * pl->T + 999999) / 1000000) : 0;
+  if (pl->surrogate) {
+    if (t_begin == 0) {
+      launch_fill_u32((uint32_t*)flag, 1u, 1, s);
+      active = 1;
+    } else if (hipMemcpyAsync(&active, flag, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+               hipStreamSynchronize(s) != hipSuccess) {
+      return check_hip(__func__);
+    }
+  }
+  // prior step of iteration t: the surrogate while allowed, else GLR
+  auto prior = [&](int t, const float* in, float* out) -> glr_status {
+    if (!(active && t < t_sur)) return prior_planar(pl, in, pl->sigma[t], out, w, s);
+    bool ok = false;
+    glr_status st = surrogate_prior(pl, in, pl->sigma[t], out, w, s, &ok);
+    if (!st && !ok) {
+      active = 0;
+      launch_fill_u32((uint32_t*)flag, 0u, 1, s);
+    }
+    return st;
+  };
   if (!pl->is_complex) {
     float* x = (float*)state;
     float* xb = (float*)(w + pl->ws.xp);
@@ -618,7 +742,7 @@ glr_status glr_reconstruct(glr_plan* pl, const void* y, void* state, int32_t t_b
     for (int t = t_begin; t < t_end; ++t) {
       e = data_step_impl(pl, y, x, nullptr, nullptr, xb, w, s);
       if (e) return e;
-      e = prior_planar(pl, xb, pl->sigma[t], x, w, s);
+      e = prior(t, xb, x);
       if (e) return e;
     }
     hipMemcpyAsync(x_out, x, (size_t)pl->C * HW * 4, hipMemcpyDeviceToDevice, s);
@@ -641,7 +765,7 @@ glr_status glr_reconstruct(glr_plan* pl, const void* y, void* state, int32_t t_b
       if (e) return e;
       launch_cplx_axpby(x, u, v, 1.0f, 1.0f, HW, s);
       launch_to_planar(v, vp, HW, s);
-      e = prior_planar(pl, vp, pl->sigma[t], zp, w, s);
+      e = prior(t, vp, zp);
       if (e) return e;
       launch_from_planar(zp, z, HW, s);
       launch_admm_dual(u, x, z, HW, s);
@@ -684,10 +808,16 @@ glr_status glr_read_stats(glr_plan* pl, glr_stats* out, int32_t reset) {
   out->ms_aggregate = (float)pl->ms[T_AGG];
   out->ms_data = (float)pl->ms[T_DATA];
   out->ms_norms = (float)pl->ms[T_NORMS];
+  out->ms_cnn = (float)pl->ms[T_CNN];
+  out->ms_judge = (float)pl->ms[T_JUDGE];
   out->match_launches = pl->match_launches;
+  out->surrogate_steps = pl->sur_steps;
+  out->fallback_steps = pl->fallback_steps;
+  out->judge_delta_last = pl->judge_delta_last;
   if (reset) {
     for (double& m : pl->ms) m = 0.0;
     pl->match_launches = 0;
+    pl->sur_steps = pl->fallback_steps = 0;
   }
   return GLR_OK;
 }

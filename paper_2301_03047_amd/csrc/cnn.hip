@@ -185,7 +185,10 @@ k_conv_mfma(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wpk,
         if (col < w) {
           const size_t o = (((size_t)b * h + r) * w + col) * CH + co;
           float v = acc[nt][q];
-          if (MODE == 0) v = fmaxf(v + bv, 0.f);
+          if (MODE == 0) {                    // ReLU that keeps NaN (a NaN weight must show)
+            v = v + bv;
+            v = (v > 0.f || v != v) ? v : 0.f;
+          }
           else v = from_bf16(mask[o]) > 0.f ? v : 0.f;
           out[o] = to_bf16(v);
         }

@@ -32,6 +32,7 @@ struct WsLayout {
   size_t tsh;                    // per-key shared threshold bound [n_chunk]
   size_t klist, kcount;          // BF16 form: keys re-matched in FP32 [N], their count
   size_t bpos, bhi, blo;         // large-margin scratch [n_chunk][mcap]
+  size_t cnn_ws, xcnn, xglr, cover, subkeys, sigv, jpart, jdelta;  // surrogate and judge
   size_t dist;                   // distance chunk [n_chunk][ldd]
   size_t lj, lu, ll, lcnt, oflag; // partial top-K lists, per-key overflow flags
   size_t idx, dd;                // groups [N][K], distances [N][K]
@@ -61,7 +62,13 @@ struct glr_plan {
   std::vector<int> ev_stage;      // stage of each recorded pair
   size_t ev_used;                 // pairs recorded since the last read
   // host-side timing accumulators (ms)
-  double ms[8];
+  double ms[10];
+  // CNN surrogate
+  int surrogate, judge_stride;
+  float surrogate_frac, judge_delta_max;
+  const void* cnn_packed;
+  long long sur_steps, fallback_steps;
+  float judge_delta_last;
   long long match_launches;
 };
 
@@ -138,9 +145,10 @@ void launch_wnnm(const glr_plan* pl, const float* xp, const int32_t* idx, float 
                  float* xhat, float* sv, DevStats* st, hipStream_t s);
 
 // aggregate.hip
+// cover (nullable): per-pixel count of covering estimates [H][W]
 void launch_aggregate(const glr_plan* pl, const float* xbar, const int32_t* idx,
                       const float* xhat, unsigned long long* pairs, int32_t* offs, float* out,
-                      hipStream_t s);
+                      int32_t* cover, hipStream_t s);
 
 // cnn.hip
 size_t cnn_packed_bytes();
@@ -154,3 +162,10 @@ void cnn_loss_grad(const void* packed, const float* x, const float* sigma, const
                    hipStream_t s);
 void cnn_adam(float* params, float* m, float* v, const float* grad, int step, float lr,
               void* packed, hipStream_t s);
+
+// judge (ops.hip)
+void launch_fill_f32(float* p, float v, size_t n, hipStream_t s);
+void launch_stride_keys(const int32_t* keys, int n, int stride, int32_t* sub, hipStream_t s);
+// delta = ||(a - b)|cov|| / ||b|cov|| over planar [C][HW] (inf if a is not finite or den = 0)
+void launch_judge(const float* a, const float* b, const int32_t* cover, int C, int HW,
+                  float* part, float* delta, hipStream_t s);

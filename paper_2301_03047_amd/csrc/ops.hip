@@ -308,3 +308,76 @@ void launch_to_planar(const float2* z, float* p, int n, hipStream_t s) {
 void launch_from_planar(const float* p, float2* z, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_from_planar, dim3(nblk(n)), dim3(TPB), 0, s, p, z, n);
 }
+
+// ---------------------------------------------------------------- surrogate judge
+namespace {
+__global__ void k_fill_f32(float* p, float v, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_stride_keys(const int32_t* __restrict__ keys, int n, int stride,
+                              int32_t* __restrict__ sub) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i * stride < n) sub[i] = keys[i * stride];
+}
+constexpr int JB = 256, JN = 512;
+// part[blk] = (sum over covered pixels and channels of (a - b)^2, of b^2,
+// count of non-finite a anywhere)
+__global__ void __launch_bounds__(JB)
+k_judge_part(const float* __restrict__ a, const float* __restrict__ b,
+             const int32_t* __restrict__ cover, int C, int HW, float* __restrict__ part) {
+  __shared__ float s0[JB], s1[JB], s2[JB];
+  float n = 0.f, d = 0.f, bad = 0.f;
+  const size_t tot = (size_t)C * HW;
+  for (size_t i = (size_t)blockIdx.x * JB + threadIdx.x; i < tot; i += (size_t)JN * JB) {
+    const float av = a[i], bv = b[i];
+    if (!isfinite(av)) bad += 1.f;
+    if (cover[i % HW] > 0) {
+      const float e = av - bv;
+      n = fmaf(e, e, n);
+      d = fmaf(bv, bv, d);
+    }
+  }
+  s0[threadIdx.x] = n;
+  s1[threadIdx.x] = d;
+  s2[threadIdx.x] = bad;
+  __syncthreads();
+  for (int o = JB / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      s0[threadIdx.x] += s0[threadIdx.x + o];
+      s1[threadIdx.x] += s1[threadIdx.x + o];
+      s2[threadIdx.x] += s2[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[3 * blockIdx.x] = s0[0];
+    part[3 * blockIdx.x + 1] = s1[0];
+    part[3 * blockIdx.x + 2] = s2[0];
+  }
+}
+__global__ void k_judge_final(const float* __restrict__ part, float* __restrict__ delta) {
+  if (threadIdx.x != 0) return;
+  double n = 0.0, d = 0.0, bad = 0.0;
+  for (int k = 0; k < JN; ++k) {
+    n += part[3 * k];
+    d += part[3 * k + 1];
+    bad += part[3 * k + 2];
+  }
+  const bool inf = bad > 0.0 || !(d > 0.0) || !isfinite(n);
+  delta[0] = inf ? __int_as_float(0x7f800000) : (float)(sqrt(n) / sqrt(d));
+}
+}  // namespace
+
+void launch_fill_f32(float* p, float v, size_t n, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
+}
+void launch_stride_keys(const int32_t* keys, int n, int stride, int32_t* sub, hipStream_t s) {
+  const int m = (n + stride - 1) / stride;
+  hipLaunchKernelGGL(k_stride_keys, dim3((m + 255) / 256), dim3(256), 0, s, keys, n, stride, sub);
+}
+void launch_judge(const float* a, const float* b, const int32_t* cover, int C, int HW,
+                  float* part, float* delta, hipStream_t s) {
+  hipLaunchKernelGGL(k_judge_part, dim3(JN), dim3(JB), 0, s, a, b, cover, C, HW, part);
+  hipLaunchKernelGGL(k_judge_final, dim3(1), dim3(64), 0, s, part, delta);
+}

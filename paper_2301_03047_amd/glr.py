@@ -33,7 +33,10 @@ class Params(ctypes.Structure):
                 ("solver", _c_i32), ("rho", ctypes.c_float),
                 ("sigma", ctypes.POINTER(ctypes.c_float)),
                 ("wnnm_c", ctypes.c_float), ("wnnm_eps", ctypes.c_float),
-                ("precision", _c_i32), ("dist_chunk_mb", _c_i32), ("timing", _c_i32)]
+                ("precision", _c_i32), ("dist_chunk_mb", _c_i32), ("timing", _c_i32),
+                ("surrogate", _c_i32), ("surrogate_frac", ctypes.c_float),
+                ("judge_stride", _c_i32), ("judge_delta_max", ctypes.c_float),
+                ("cnn_packed", _vp)]
 
 
 class Stats(ctypes.Structure):
@@ -45,7 +48,9 @@ class Stats(ctypes.Structure):
                 ("ms_lowrank", ctypes.c_float), ("ms_aggregate", ctypes.c_float),
                 ("ms_data", ctypes.c_float), ("ms_norms", ctypes.c_float),
                 ("match_launches", ctypes.c_int64), ("jacobi_sweeps_sum", ctypes.c_int64),
-                ("rematch_keys", ctypes.c_int64)]
+                ("rematch_keys", ctypes.c_int64), ("surrogate_steps", ctypes.c_int64),
+                ("fallback_steps", ctypes.c_int64), ("judge_delta_last", ctypes.c_float),
+                ("ms_cnn", ctypes.c_float), ("ms_judge", ctypes.c_float)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -127,7 +132,8 @@ class Plan:
 
     def __init__(self, modality, H, W, C, patch, n_keys, k, iters=0, sigma=None, mask=None,
                  rho=1.0, wnnm_c=None, wnnm_eps=None, precision="fp32", dist_chunk_mb=8192,
-                 timing=False, device="cuda", allocate=True):
+                 timing=False, device="cuda", allocate=True, cnn=None, surrogate_frac=0.6,
+                 judge_stride=8, judge_delta_max=0.02):
         import torch
         L = lib()
         self.modality = _MODALITY[modality] if isinstance(modality, str) else int(modality)
@@ -150,6 +156,13 @@ class Plan:
         par.precision = PREC[precision]
         par.dist_chunk_mb = int(dist_chunk_mb)
         par.timing = 1 if timing else 0
+        self.cnn = cnn                      # keeps the packed weights alive
+        if cnn is not None:
+            par.surrogate = 1
+            par.surrogate_frac = float(surrogate_frac)
+            par.judge_stride = int(judge_stride)
+            par.judge_delta_max = float(judge_delta_max)
+            par.cnn_packed = _vp(cnn.packed.data_ptr())
         self._sigma = np.ascontiguousarray(
             np.asarray(sigma if sigma is not None else [], dtype=np.float32))
         if self.iters > 0:
