@@ -52,6 +52,10 @@ WORKLOADS = {
     "cacti_128": Workload("cacti_128", "cacti", 128, 128, 8, 6, 128, 32, 5, 1.0, 0.05, seed=0),
     "mri_256": Workload("mri_256", "mri", 256, 256, 1, 6, 1024, 45, 30, 0.05, 0.01, seed=1000),
     "msfa_512": Workload("msfa_512", "msfa", 512, 512, 16, 6, 4096, 64, 40, 0.5, 0.05, seed=2000),
+    # evaluation instances of the CNN surrogate: the 128 x 128 CACTI generator
+    # at 512 x 512 (keys scaled with the area), 20 iterations
+    "cacti_512": Workload("cacti_512", "cacti", 512, 512, 8, 6, 2048, 32, 20, 1.0, 0.05,
+                          seed=4200),
     "cacti_1024": Workload("cacti_1024", "cacti", 1024, 1024, 24, 8, 16384, 64, 50, 1.0, 0.05,
                            precision="bf16", seed=3000),
 }
