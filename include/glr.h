@@ -142,7 +142,8 @@ GLR_API void glr_params_default(glr_params* p);
  * depend on data pointers and reports the workspace size every later call
  * needs (*workspace_bytes, 256-byte aligned buffer owned by the caller).
  * problem->mask is recorded (the caller keeps it alive).  Limits: K <= 64,
- * 1 <= N <= N_cand, K <= N_cand, P <= min(H, W), D = C'*P*P <= 4096;
+ * 1 <= N <= min(N_cand, 16384), K <= N_cand, N_cand < 4096^2,
+ * P <= min(H, W), P <= 16, D = C'*P*P <= 4096;
  * MRI needs H, W powers of two in [4, 2048]; MSFA needs C == 16 and H, W
  * multiples of 4. */
 GLR_API glr_status glr_plan_create(glr_plan** out, const glr_problem* problem,

@@ -3,161 +3,264 @@
 // Reading: every member estimate weighs 1; a pixel is the mean of all
 // estimates covering it; uncovered pixels keep the pre-prior value.
 //
-// Atomic-free and deterministic: entries e = g*K + q are sorted by
-// (position, e) with a bitonic network on unique 64-bit keys, CSR offsets per
-// position come from binary searches, and each pixel gathers its covering
-// estimates in a fixed order (dy, dx, e ascending).
+// Deterministic: entries e = g*K + q are bucketed by position with a
+// counting sort (integer counts, an exclusive scan for the CSR offsets, a
+// scatter, then each bucket sorted by e), and each pixel gathers its
+// covering estimates in a fixed order (dy, dx, e ascending); no
+// floating-point atomics.
 #include "common.h"
 #include "internal.h"
 
 namespace {
 
-constexpr int LT = 1024;          // threads of the local sort kernels
-constexpr int LN = 2 * LT;        // elements sorted in LDS per block
-
-__global__ void k_pairs(const int32_t* __restrict__ idx, int M, int M2,
-                        unsigned long long* __restrict__ keys) {
-  int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= M2) return;
-  keys[e] = e < M ? (((unsigned long long)(uint32_t)idx[e]) << 32) | (uint32_t)e : ~0ull;
+__global__ void k_count(const int32_t* __restrict__ idx, int M, int32_t* __restrict__ cnt) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < M) atomicAdd(&cnt[idx[e]], 1);
 }
 
-__device__ __forceinline__ void cmpx(unsigned long long* s, int i, int p, bool up) {
-  unsigned long long a = s[i], b = s[p];
-  if ((a > b) == up) {
-    s[i] = b;
-    s[p] = a;
+constexpr int SB = 1024;          // threads of the scan blocks
+constexpr int SPT = 4;            // elements per thread
+constexpr int SE = SB * SPT;      // elements per scan block
+
+// in-block exclusive scan of cnt[0..n) (4 per thread); block sums to bsum
+__global__ void __launch_bounds__(SB)
+k_scan_blocks(const int32_t* __restrict__ cnt, int n, int32_t* __restrict__ offs,
+              int32_t* __restrict__ bsum) {
+  __shared__ int sh[SB / 64 + 1];
+  const int base = blockIdx.x * SE + threadIdx.x * SPT;
+  int v[SPT], tot = 0;
+#pragma unroll
+  for (int k = 0; k < SPT; ++k) {
+    v[k] = base + k < n ? cnt[base + k] : 0;
+    tot += v[k];
+  }
+  int all;
+  int pre = block_excl_scan(tot, sh, &all);
+#pragma unroll
+  for (int k = 0; k < SPT; ++k) {
+    if (base + k < n) offs[base + k] = pre;
+    pre += v[k];
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = all;
+}
+
+// exclusive scan of the block sums (one block; nb <= SE)
+__global__ void __launch_bounds__(SB) k_scan_sums(int32_t* __restrict__ bsum, int nb) {
+  __shared__ int sh[SB / 64 + 1];
+  const int base = threadIdx.x * SPT;
+  int v[SPT], tot = 0;
+#pragma unroll
+  for (int k = 0; k < SPT; ++k) {
+    v[k] = base + k < nb ? bsum[base + k] : 0;
+    tot += v[k];
+  }
+  int all;
+  int pre = block_excl_scan(tot, sh, &all);
+#pragma unroll
+  for (int k = 0; k < SPT; ++k) {
+    if (base + k < nb) bsum[base + k] = pre;
+    pre += v[k];
   }
 }
 
-// all stages k <= LN within each 2048-element block
-__global__ void __launch_bounds__(LT) k_bitonic_local_sort(unsigned long long* __restrict__ keys) {
-  __shared__ unsigned long long s[LN];
-  const size_t base = (size_t)blockIdx.x * LN;
-  s[threadIdx.x] = keys[base + threadIdx.x];
-  s[threadIdx.x + LT] = keys[base + threadIdx.x + LT];
-  __syncthreads();
-  for (int k = 2; k <= LN; k <<= 1)
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int t = threadIdx.x; t < LN; t += LT) {
-        int p = t ^ j;
-        if (p > t) cmpx(s, t, p, (((size_t)base + t) & k) == 0);
+// offs += block prefix; cursor = offs (scatter slots)
+__global__ void k_scan_add(int32_t* __restrict__ offs, int n, const int32_t* __restrict__ bsum,
+                           int32_t* __restrict__ cursor) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int o = offs[i] + bsum[i / SE];
+  offs[i] = o;
+  cursor[i] = o;
+}
+
+__global__ void k_scatter(const int32_t* __restrict__ idx, int M, int32_t* __restrict__ cursor,
+                          int32_t* __restrict__ ent) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < M) ent[atomicAdd(&cursor[idx[e]], 1)] = e;
+}
+
+// each bucket in ascending entry order: buckets of up to SMALL entries by one
+// thread (insertion sort); longer ones are queued for k_bucket_sort_large
+constexpr int SMALL = 64;
+__global__ void k_bucket_sort(const int32_t* __restrict__ offs, int ncand,
+                              int32_t* __restrict__ ent, int32_t* __restrict__ big,
+                              int32_t* __restrict__ nbig) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ncand) return;
+  const int a = offs[t], b = offs[t + 1];
+  if (b - a > SMALL) {
+    big[atomicAdd(nbig, 1)] = t;           // queue order is irrelevant: each bucket
+    return;                                // is sorted on its own
+  }
+  for (int i = a + 1; i < b; ++i) {
+    const int v = ent[i];
+    int j = i - 1;
+    while (j >= a && ent[j] > v) {
+      ent[j + 1] = ent[j];
+      --j;
+    }
+    ent[j + 1] = v;
+  }
+}
+
+// one block per queued bucket (grid-stride over the queue): bitonic sort in
+// LDS.  A bucket holds at most one entry per group, so at most N <= LB.
+constexpr int LB = 16384;
+__global__ void __launch_bounds__(1024)
+k_bucket_sort_large(const int32_t* __restrict__ offs, int32_t* __restrict__ ent,
+                    const int32_t* __restrict__ big, const int32_t* __restrict__ nbig) {
+  __shared__ int v[LB];
+  const int nb = nbig[0];
+  for (int k = blockIdx.x; k < nb; k += gridDim.x) {
+    const int t = big[k];
+    const int a = offs[t], n = offs[t + 1] - a;
+    int n2 = 1;
+    while (n2 < n) n2 <<= 1;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n2; i += blockDim.x) v[i] = i < n ? ent[a + i] : 0x7fffffff;
+    __syncthreads();
+    for (int kk = 2; kk <= n2; kk <<= 1)
+      for (int j = kk >> 1; j > 0; j >>= 1) {
+        for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+          const int p = i ^ j;
+          if (p > i) {
+            const int x = v[i], y = v[p];
+            if ((x > y) == ((i & kk) == 0)) {
+              v[i] = y;
+              v[p] = x;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) ent[a + i] = v[i];
+  }
+}
+
+constexpr int GX = 64;            // pixels per block (one image row segment)
+constexpr int GT = 256;           // threads per block
+constexpr int CG = 32;            // channels per block (grid z covers the rest)
+constexpr int LDS_FLOATS = 12288; // staged estimate rows per chunk (48 KB)
+
+// One block per (image row r, 64-pixel segment, channel group).  Estimates
+// are stored per member patch as xhat[e][dy][dx][c], so the dy-row of an
+// entry is one contiguous run of P*Cp floats.  For each dy the entries of
+// the window of top-left positions (row r - dy, columns c0 - P + 1 ..
+// c0 + GX - 1) are contiguous in the CSR order; their dy-rows are staged in
+// LDS in chunks and every (pixel, channel) of the block sums its covering
+// values in the fixed order (dy, position, entry) ascending.  Lanes run over
+// the channels of a pixel, which all have the same trip counts.
+__global__ void __launch_bounds__(GT)
+k_gather(const float* __restrict__ xbar, const float* __restrict__ xhat,
+         const int32_t* __restrict__ ent, const int32_t* __restrict__ offs, int Cp, int H, int W,
+         int P, int D, float* __restrict__ out, int32_t* __restrict__ cover) {
+  __shared__ __align__(16) float lds[LDS_FLOATS];
+  __shared__ int spos[GX + 17];             // window bucket starts (P <= 16), + end
+  __shared__ int sent[LDS_FLOATS / 4];      // entry ids of the staged chunk
+  const int r = blockIdx.y;
+  const int c0 = blockIdx.x * GX;
+  const int cg0 = blockIdx.z * CG;
+  const int ncg = min(CG, Cp - cg0);
+  const int Hc = H - P + 1, Wc = W - P + 1;
+  const int tid = threadIdx.x;
+  const int npair = GX * ncg;
+  constexpr int NPT = GX * CG / GT;         // pairs per thread (max)
+  float acc[NPT];
+  int cnt[NPT];
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    acc[k] = 0.f;
+    cnt[k] = 0;
+  }
+  const int rowlen = ncg * P;               // floats staged per entry
+  const int cap = min(LDS_FLOATS / rowlen, LDS_FLOATS / 4);   // entries per chunk
+  const int lane = tid & 63, wave = tid >> 6;
+  // 16-byte staging when the block takes all channels (a staged row is one
+  // contiguous run) and every row start and length is a multiple of 4 floats
+  const bool vec4 = ncg == Cp && (rowlen & 3) == 0 && (D & 3) == 0;
+  const int tc0 = max(0, c0 - P + 1);
+  const int tc1 = min(Wc - 1, c0 + GX - 1);
+  for (int dy = 0; dy < P; ++dy) {
+    const int tr = r - dy;
+    if (tr < 0 || tr >= Hc || tc0 > tc1) continue;      // block-uniform
+    const int nwin = tc1 - tc0 + 1;
+    __syncthreads();                                     // previous users of spos / lds
+    for (int i = tid; i <= nwin; i += GT) spos[i] = offs[tr * Wc + tc0 + i];
+    __syncthreads();
+    const int ea = spos[0], eb = spos[nwin];
+    // bucket counts (once per dy; independent of the chunking)
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+      const int p = tid + k * GT;
+      if (p < npair) {
+        const int c = c0 + p / ncg;
+        const int lo = max(tc0, c - P + 1), hi = min(tc1, c);
+        if (c < W && lo <= hi) cnt[k] += spos[hi - tc0 + 1] - spos[lo - tc0];
+      }
+    }
+    for (int ia = ea; ia < eb; ia += cap) {
+      const int ib = min(eb, ia + cap);
+      __syncthreads();
+      for (int i = tid; i < ib - ia; i += GT) sent[i] = ent[ia + i];
+      __syncthreads();
+      // each wave stages whole entry rows: lane -> (entry le, 16-byte word w);
+      // LDS row i holds [dx][c - cg0]
+      {
+        const int nrow = ib - ia;
+        const size_t roff = (size_t)dy * P * Cp;
+        if (vec4) {
+          const int r4 = rowlen >> 2;
+          const int epw = r4 >= 64 ? 1 : 64 / r4;
+          const int le = lane / r4, w0 = lane - le * r4;
+          if (le < epw)
+            for (int i = wave * epw + le; i < nrow; i += 4 * epw)
+              for (int w = w0; w < r4; w += 64) {
+                const float4 v = *reinterpret_cast<const float4*>(
+                    xhat + (size_t)sent[i] * D + roff + 4 * w);
+                *reinterpret_cast<float4*>(lds + i * rowlen + 4 * w) = v;
+              }
+        } else {
+          for (int i = wave; i < nrow; i += 4)
+            for (int w = lane; w < rowlen; w += 64) {
+              const int dx = w / ncg, c = w - dx * ncg;
+              lds[i * rowlen + w] = xhat[(size_t)sent[i] * D + roff + (size_t)dx * Cp + cg0 + c];
+            }
+        }
       }
       __syncthreads();
-    }
-  keys[base + threadIdx.x] = s[threadIdx.x];
-  keys[base + threadIdx.x + LT] = s[threadIdx.x + LT];
-}
-
-// stage (k, j) with j >= LN: pairs span blocks
-__global__ void k_bitonic_global(unsigned long long* __restrict__ keys, size_t n, size_t k, size_t j) {
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  size_t p = i ^ j;
-  if (p > i) {
-    bool up = (i & k) == 0;
-    unsigned long long a = keys[i], b = keys[p];
-    if ((a > b) == up) {
-      keys[i] = b;
-      keys[p] = a;
-    }
-  }
-}
-
-// stages j < LN of merge step k (k > LN) inside each block
-__global__ void __launch_bounds__(LT) k_bitonic_local_merge(unsigned long long* __restrict__ keys,
-                                                            size_t k) {
-  __shared__ unsigned long long s[LN];
-  const size_t base = (size_t)blockIdx.x * LN;
-  s[threadIdx.x] = keys[base + threadIdx.x];
-  s[threadIdx.x + LT] = keys[base + threadIdx.x + LT];
-  __syncthreads();
-  const bool up = (base & k) == 0;      // constant within the block since k > LN
-  for (int j = LN >> 1; j > 0; j >>= 1) {
-    for (int t = threadIdx.x; t < LN; t += LT) {
-      int p = t ^ j;
-      if (p > t) cmpx(s, t, p, up);
-    }
-    __syncthreads();
-  }
-  keys[base + threadIdx.x] = s[threadIdx.x];
-  keys[base + threadIdx.x + LT] = s[threadIdx.x + LT];
-}
-
-// offs[t] = first sorted entry whose position is >= t, t in [0, Ncand]
-__global__ void k_offsets(const unsigned long long* __restrict__ keys, int M, int Ncand,
-                          int32_t* __restrict__ offs) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t > Ncand) return;
-  int lo = 0, hi = M;
-  while (lo < hi) {
-    int mid = (lo + hi) >> 1;
-    if ((int)(keys[mid] >> 32) < t) lo = mid + 1; else hi = mid;
-  }
-  offs[t] = lo;
-}
-
-constexpr int CB = 8;             // channels per gather block
-constexpr int GX = 64;            // pixels per gather block (one image row segment)
-
-// One thread per (pixel, dy): sums the estimates of the patches whose top
-// row covers the pixel at offset dy, over dx and the CSR bucket; the P
-// partial sums of a pixel are then added in dy order (fixed order).
-__global__ void k_gather(const float* __restrict__ xbar, const float* __restrict__ xhat,
-                         const unsigned long long* __restrict__ keys,
-                         const int32_t* __restrict__ offs, int Cp, int H, int W, int P, int D,
-                         int K, float* __restrict__ out, int32_t* __restrict__ cover) {
-  extern __shared__ float part[];          // [P][GX][CB + 1]
-  const int tx = threadIdx.x, dy = threadIdx.y;
-  const int r = blockIdx.y;
-  const int c = blockIdx.x * GX + tx;
-  const int cb = blockIdx.z;
-  const int Hc = H - P + 1, Wc = W - P + 1;
-  const int PP = P * P;
-  const int nch = min(CB, Cp - cb * CB);
-  float acc[CB];
 #pragma unroll
-  for (int u = 0; u < CB; ++u) acc[u] = 0.f;
-  int cnt = 0;
-  const int gr = r - dy;
-  if (c < W && gr >= 0 && gr < Hc) {
-    for (int dx = 0; dx < P; ++dx) {
-      const int gc = c - dx;
-      if (gc < 0 || gc >= Wc) continue;
-      const int t = gr * Wc + gc;
-      const int a = offs[t], b = offs[t + 1];
-      cnt += b - a;
-      for (int i = a; i < b; ++i) {
-        // entry e = g*K + j; estimates are entry-major: xhat[e*D + d]
-        const uint32_t e = (uint32_t)(keys[i] & 0xffffffffull);
-        const float* src = xhat + (size_t)e * D + (size_t)(cb * CB) * PP + dy * P + dx;
-#pragma unroll
-        for (int u = 0; u < CB; ++u)
-          if (u < nch) acc[u] += src[(size_t)u * PP];
+      for (int k = 0; k < NPT; ++k) {
+        const int p = tid + k * GT;
+        if (p < npair) {
+          const int px = p / ncg, ch = p - px * ncg;
+          const int c = c0 + px;
+          const int lo = max(tc0, c - P + 1), hi = min(tc1, c);
+          if (c < W) {
+            float a = acc[k];
+            for (int tc = lo; tc <= hi; ++tc) {
+              const int dx = c - tc;
+              const int b0 = max(spos[tc - tc0], ia), b1 = min(spos[tc - tc0 + 1], ib);
+              for (int i = b0; i < b1; ++i) a += lds[(i - ia) * rowlen + dx * ncg + ch];
+            }
+            acc[k] = a;
+          }
+        }
       }
     }
   }
-  float* mine = part + ((size_t)dy * GX + tx) * (CB + 1);
+  const size_t HW = (size_t)H * W;
 #pragma unroll
-  for (int u = 0; u < CB; ++u) mine[u] = acc[u];
-  mine[CB] = __int_as_float(cnt);
-  __syncthreads();
-  if (dy == 0 && c < W) {
-    float sum[CB];
-#pragma unroll
-    for (int u = 0; u < CB; ++u) sum[u] = 0.f;
-    int n = 0;
-    for (int y = 0; y < P; ++y) {
-      const float* pp = part + ((size_t)y * GX + tx) * (CB + 1);
-#pragma unroll
-      for (int u = 0; u < CB; ++u) sum[u] += pp[u];
-      n += __float_as_int(pp[CB]);
-    }
-    const size_t HW = (size_t)H * W;
-    if (cover && cb == 0) cover[(size_t)r * W + c] = n;
-    for (int u = 0; u < nch; ++u) {
-      const size_t o = (size_t)(cb * CB + u) * HW + (size_t)r * W + c;
-      out[o] = n ? sum[u] / (float)n : xbar[o];
+  for (int k = 0; k < NPT; ++k) {
+    const int p = tid + k * GT;
+    if (p < npair) {
+      const int px = p / ncg, ch = p - px * ncg;
+      const int c = c0 + px;
+      if (c < W) {
+        const int n = cnt[k];
+        if (cover && cg0 == 0 && ch == 0) cover[(size_t)r * W + c] = n;
+        const size_t o = (size_t)(cg0 + ch) * HW + (size_t)r * W + c;
+        out[o] = n ? acc[k] / (float)n : xbar[o];
+      }
     }
   }
 }
@@ -165,21 +268,26 @@ __global__ void k_gather(const float* __restrict__ xbar, const float* __restrict
 }  // namespace
 
 void launch_aggregate(const glr_plan* pl, const float* xbar, const int32_t* idx,
-                      const float* xhat, unsigned long long* pairs, int32_t* offs, float* out,
+                      const float* xhat, int32_t* sortbuf, int32_t* offs, float* out,
                       int32_t* cover, hipStream_t s) {
-  const int M = pl->M, M2 = pl->M2;
-  hipLaunchKernelGGL(k_pairs, dim3((M2 + 255) / 256), dim3(256), 0, s, idx, M, M2, pairs);
-  hipLaunchKernelGGL(k_bitonic_local_sort, dim3(M2 / LN), dim3(LT), 0, s, pairs);
-  for (size_t k = 2 * LN; k <= (size_t)M2; k <<= 1) {
-    for (size_t j = k >> 1; j >= (size_t)LN; j >>= 1)
-      hipLaunchKernelGGL(k_bitonic_global, dim3((M2 + 255) / 256), dim3(256), 0, s, pairs,
-                         (size_t)M2, k, j);
-    hipLaunchKernelGGL(k_bitonic_local_merge, dim3(M2 / LN), dim3(LT), 0, s, pairs, k);
-  }
-  hipLaunchKernelGGL(k_offsets, dim3((pl->Ncand + 1 + 255) / 256), dim3(256), 0, s, pairs, M,
-                     pl->Ncand, offs);
-  dim3 grid((pl->W + GX - 1) / GX, pl->H, (pl->Cp + CB - 1) / CB);
-  const size_t lds = (size_t)pl->P * GX * (CB + 1) * sizeof(float);
-  hipLaunchKernelGGL(k_gather, grid, dim3(GX, pl->P), lds, s, xbar, xhat, pairs, offs, pl->Cp,
-                     pl->H, pl->W, pl->P, pl->D, pl->K, out, cover);
+  const int M = pl->M, n = pl->Ncand + 1;
+  int32_t* ent = sortbuf;                       // [M]
+  int32_t* cnt = sortbuf + pl->M2;              // [Ncand + 1], later the scatter cursor
+  int32_t* bsum = cnt + ((size_t)n + 63) / 64 * 64;
+  const int nb = (n + SE - 1) / SE;
+  launch_fill_u32((uint32_t*)cnt, 0u, (size_t)n, s);
+  hipLaunchKernelGGL(k_count, dim3((M + 255) / 256), dim3(256), 0, s, idx, M, cnt);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(SB), 0, s, cnt, n, offs, bsum);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SB), 0, s, bsum, nb);
+  hipLaunchKernelGGL(k_scan_add, dim3((n + 255) / 256), dim3(256), 0, s, offs, n, bsum, cnt);
+  hipLaunchKernelGGL(k_scatter, dim3((M + 255) / 256), dim3(256), 0, s, idx, M, cnt, ent);
+  int32_t* nbig = bsum + nb;                    // [1] queue length, then the queue
+  int32_t* big = nbig + 1;
+  launch_fill_u32((uint32_t*)nbig, 0u, 1, s);
+  hipLaunchKernelGGL(k_bucket_sort, dim3((pl->Ncand + 255) / 256), dim3(256), 0, s, offs,
+                     pl->Ncand, ent, big, nbig);
+  hipLaunchKernelGGL(k_bucket_sort_large, dim3(256), dim3(1024), 0, s, offs, ent, big, nbig);
+  dim3 grid((pl->W + GX - 1) / GX, pl->H, (pl->Cp + CG - 1) / CG);
+  hipLaunchKernelGGL(k_gather, grid, dim3(GT), 0, s, xbar, xhat, ent, offs, pl->Cp, pl->H, pl->W,
+                     pl->P, pl->D, out, cover);
 }

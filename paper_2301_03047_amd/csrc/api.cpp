@@ -201,7 +201,7 @@ glr_status lowrank_stage(glr_plan* pl, const float* xp, const int32_t* idx, floa
   }
   {
     StageTimer t(pl, s, T_AGG);
-    launch_aggregate(pl, xp, idx, xhat, (unsigned long long*)(ws + pl->ws.pairs),
+    launch_aggregate(pl, xp, idx, xhat, (int32_t*)(ws + pl->ws.pairs),
                      (int32_t*)(ws + pl->ws.offs), xo, cover, s);
   }
   return check_hip("glr_lowrank_aggregate");
@@ -380,6 +380,10 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
   if (pr->k > 64) return fail(GLR_ERR_UNSUPPORTED, "K=%d > 64", pr->k);
   if (pr->n_keys < 1 || pr->n_keys > Ncand)
     return fail(GLR_ERR_SHAPE, "n_keys=%d must be in [1, N_cand=%lld]", pr->n_keys, Ncand);
+  if (pr->n_keys > 16384)
+    return fail(GLR_ERR_UNSUPPORTED, "n_keys=%d above 16384", pr->n_keys);
+  if (Ncand + 1 > 4096LL * 4096LL)
+    return fail(GLR_ERR_UNSUPPORTED, "N_cand=%lld above 4096^2 - 1", Ncand);
   if ((long long)pr->n_keys * pr->k > (1LL << 30))
     return fail(GLR_ERR_UNSUPPORTED, "n_keys*K too large");
   if (pr->iters < 0) return fail(GLR_ERR_INVALID_ARG, "iters < 0");
@@ -501,7 +505,7 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
   L.dd = c.take((size_t)pl->M * 4);
   L.xhat = c.take((size_t)pl->M * D * 4);
   L.sv = c.take((size_t)pl->M * 4);
-  L.pairs = c.take((size_t)pl->M2 * 8);
+  L.pairs = c.take(agg_sort_ints(pl) * 4);
   L.offs = c.take(((size_t)Ncand + 1) * 4);
   L.cplx_a = c.take(pl->is_complex ? HW * 8 : 0);
   L.cplx_b = c.take(pl->is_complex ? HW * 8 : 0);

@@ -145,10 +145,16 @@ void launch_wnnm(const glr_plan* pl, const float* xp, const int32_t* idx, float 
                  float* xhat, float* sv, DevStats* st, hipStream_t s);
 
 // aggregate.hip
+// sortbuf: aggregation sort scratch (agg_sort_ints(pl) int32); offs [Ncand + 1];
 // cover (nullable): per-pixel count of covering estimates [H][W]
 void launch_aggregate(const glr_plan* pl, const float* xbar, const int32_t* idx,
-                      const float* xhat, unsigned long long* pairs, int32_t* offs, float* out,
+                      const float* xhat, int32_t* sortbuf, int32_t* offs, float* out,
                       int32_t* cover, hipStream_t s);
+inline size_t agg_sort_ints(const glr_plan* pl) {
+  const size_t n = (size_t)pl->Ncand + 1;
+  // entries [M2], counts/cursor [n], block sums, queue length, large-bucket queue
+  return (size_t)pl->M2 + (n + 63) / 64 * 64 + (n + 4095) / 4096 + 1 + (size_t)pl->M / 65 + 64;
+}
 
 // cnn.hip
 size_t cnn_packed_bytes();

@@ -20,8 +20,8 @@
 //  4. X = Y - Yc W, W = V diag(w) V^T: the residual sum_i (s_i - s'_i) u_i v_i^T
 //     accumulated in FP64 (sigma = 0 gives w = 0, W = 0, X = Y exactly).
 // Data and the SVD are FP32; only the angles and the residual use FP64.
-// Estimates are written entry-major: xhat[(g*K + j)*D + d] (one member
-// patch's D values contiguous), staged through LDS so the stores coalesce.
+// Estimates are written per member patch in (dy, dx, channel) order:
+// xhat[(g*K + j)*D + (dy*P + dx)*Cp + c], staged through LDS.
 #include "common.h"
 #include "internal.h"
 
@@ -43,12 +43,20 @@ __device__ __forceinline__ float bcast(float v, int lane) {
 }
 
 // Lane i < nb loads row d0+i of Y into B[i][0..K) (raw values) and its mean.
+// With Cp > 0 the rows are taken in the output order e = (dy P + dx) Cp + c
+// instead of d = (c P + dy) P + dx.
 __device__ __forceinline__ void load_rows(const float* __restrict__ xp, const int* spos, int d0,
                                           int nb, int K, int P, int W, size_t HW, float* B,
-                                          float* smu) {
+                                          float* smu, int Cp = 0) {
   const int i = threadIdx.x;
   if (i < nb) {
-    const size_t o = elem_off(d0 + i, P, W, HW);
+    size_t o;
+    if (Cp > 0) {
+      const int e = d0 + i, c = e % Cp, pix = e / Cp;
+      o = (size_t)c * HW + (size_t)(pix / P) * W + pix % P;
+    } else {
+      o = elem_off(d0 + i, P, W, HW);
+    }
     float s = 0.f;
 #pragma unroll 8
     for (int j = 0; j < K; ++j) {
@@ -64,7 +72,7 @@ __device__ __forceinline__ void load_rows(const float* __restrict__ xp, const in
 // FP64 Jacobi rotation annihilating gamma for column norms a1 (first) and a2:
 // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), zeta = (a2 - a1) / (2 gamma),
 // written with one division; c = 1/sqrt(1 + t^2), s = c t.
-__device__ __forceinline__ void jacobi_angle(float a1, float a2, float ga, float& c, float& s) {
+__device__ __forceinline__ double jacobi_angle(float a1, float a2, float ga, float& c, float& s) {
   const double d = (double)a2 - (double)a1;
   const double g2 = 2.0 * (double)ga;
   const double sg = ((d >= 0.0) == (g2 >= 0.0)) ? 1.0 : -1.0;     // sign(zeta), zeta = 0 -> +1
@@ -72,6 +80,7 @@ __device__ __forceinline__ void jacobi_angle(float a1, float a2, float ga, float
   const double cs = 1.0 / sqrt(1.0 + t * t);
   c = (float)cs;
   s = (float)(cs * t);
+  return t;
 }
 
 // LDS ordering between lanes of the one wave that runs a group.
@@ -185,14 +194,12 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
   int sweeps = 0;
   for (int swp = 0; swp < max_sweeps; ++swp) {
     bool rotated = false;
-    for (int r = 0; r < Kp - 1; ++r) {
-      // round-robin partner: position 0 fixed, the others rotate by one per round
-      int q = -1;
-      if (lane < Kp) {
-        const int mpos = lane == 0 ? 0 : 1 + ((lane - 1 - r) % (Kp - 1) + (Kp - 1)) % (Kp - 1);
-        const int ppos = Kp - 1 - mpos;
-        q = ppos == 0 ? 0 : 1 + ((ppos - 1 + r) % (Kp - 1));
-      }
+    // squared column norm, exact at the start of a sweep; within the sweep a
+    // rotation updates it in closed form (||a'||^2 = a1 - t g, ||b'||^2 =
+    // a2 + t g), which only steers the angles: the singular values are
+    // recomputed from the columns at the end
+    float al;
+    {
       float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
 #pragma unroll
       for (int k = 0; k < KP; k += 4) {
@@ -201,7 +208,16 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
         a2 = fmaf(m[k + 2], m[k + 2], a2);
         a3 = fmaf(m[k + 3], m[k + 3], a3);
       }
-      const float al = (a0 + a1) + (a2 + a3);
+      al = (a0 + a1) + (a2 + a3);
+    }
+    for (int r = 0; r < Kp - 1; ++r) {
+      // round-robin partner: position 0 fixed, the others rotate by one per round
+      int q = -1;
+      if (lane < Kp) {
+        const int mpos = lane == 0 ? 0 : 1 + ((lane - 1 - r) % (Kp - 1) + (Kp - 1)) % (Kp - 1);
+        const int ppos = Kp - 1 - mpos;
+        q = ppos == 0 ? 0 : 1 + ((ppos - 1 + r) % (Kp - 1));
+      }
       store_vec(xrow, m);
       xrow[KP] = al;
       wave_sync();
@@ -226,13 +242,15 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
                        fabsf(ga) > tol * sqrtf(n1) * sqrtf(n2);
       if (act) {
         float c, s;
-        jacobi_angle(n1, n2, ga, c, s);
+        const double t = jacobi_angle(n1, n2, ga, c, s);
         if (first) {
 #pragma unroll
           for (int k = 0; k < KP; ++k) m[k] = fmaf(c, m[k], -s * o[k]);
+          al = fmaxf((float)((double)n1 - t * (double)ga), 0.f);
         } else {
 #pragma unroll
           for (int k = 0; k < KP; ++k) m[k] = fmaf(s, o[k], c * m[k]);
+          al = fmaxf((float)((double)n2 + t * (double)ga), 0.f);
         }
       }
       rotated = rotated || act;
@@ -300,9 +318,12 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
 
   // ---- 4. X = Y - Yc W (residual in FP64); the chunk's results go to Rl
   // (free once W is in registers) as [j][i], then out as contiguous rows
+  // rows in the output order (dy, dx, c); each row's result is independent
+  // of the order, so the chunks are written out as contiguous runs
+  const int Cp = D / (P * P);
   for (int d0 = 0; d0 < D; d0 += BR) {
     const int nb = min(BR, D - d0);
-    load_rows(xp, spos, d0, nb, K, P, W, HW, Bl, smu);
+    load_rows(xp, spos, d0, nb, K, P, W, HW, Bl, smu, Cp);
     if (lane < K) {
       for (int i = 0; i < nb; ++i) {
         const float mu = smu[i];

@@ -64,7 +64,7 @@ k_match_f32(const float* __restrict__ xp, int H, int W, int P, int Cp,
   constexpr int AST = P2 + 1;   // odd LDS stride for the key slab
   __shared__ float seg[2][SEG];
   __shared__ float As[2][BM * AST];
-  __shared__ float muk[BM];
+  __shared__ float4 skm[BM];
   __shared__ int krow[BM];
   __shared__ float mub[BN];
 
@@ -87,7 +87,7 @@ k_match_f32(const float* __restrict__ xp, int H, int W, int P, int Cp,
     const int g = kbase + tid;
     const int gg = g < nk ? (kmap ? kmap[g0 + g] : g0 + g) : -1;
     krow[tid] = gg;
-    muk[tid] = gg >= 0 ? kmb[gg].y : 0.f;
+    skm[tid] = gg >= 0 ? kmb[gg] : make_float4(0.f, 0.f, 0.f, 0.f);
   }
   if (tid < BN) {
     const int col = c0 + tid;
@@ -114,7 +114,7 @@ k_match_f32(const float* __restrict__ xp, int H, int W, int P, int Cp,
       if (e < BM * P2) {
         int m = e / P2, dx = e - m * P2;
         const int gg = krow[m];
-        if (dx < P && gg >= 0) v = A[(size_t)gg * D + (size_t)s * P + dx] - muk[m];
+        if (dx < P && gg >= 0) v = A[(size_t)gg * D + (size_t)s * P + dx] - skm[m].y;
       }
       ra[u] = v;
     }
@@ -174,9 +174,8 @@ k_match_f32(const float* __restrict__ xp, int H, int W, int P, int Cp,
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int i = wm * 64 + mt * 32 + 8 * (q >> 2) + 4 * lhi + (q & 3);
-        const int gg = krow[i];
-        if (cok && gg >= 0)
-          dist[(size_t)(kbase + i) * ldd + t] = centred_dist(kmb[gg], cm, acc[mt][nt][q], D);
+        if (cok && krow[i] >= 0)
+          dist[(size_t)(kbase + i) * ldd + t] = centred_dist(skm[i], cm, acc[mt][nt][q], D);
       }
     }
 }
@@ -308,6 +307,7 @@ k_match_bf16(const float* __restrict__ xp, int H, int W, int P, int Cp,
   __shared__ __align__(16) uint16_t Bs[NS * BN * 8];
   __shared__ float seg[RP * SEGW];
   __shared__ float mup[BN];
+  __shared__ float4 skm[BM];
 
   const int Hc = H - P + 1, Wc = W - P + 1;
   const int ntc = (Wc + BN - 1) / BN;
@@ -328,6 +328,10 @@ k_match_bf16(const float* __restrict__ xp, int H, int W, int P, int Cp,
   if (tid < BN) {
     const int col = c0 + tid;
     mup[tid] = col < Wc ? cmeta[(size_t)r * Wc + col].x : 0.f;
+  }
+  if (tid < BM) {
+    const int g = kbase + tid;
+    skm[tid] = g < nk ? kmb[g0 + g] : make_float4(0.f, 0.f, 0.f, 0.f);
   }
   uint4 ra[NAU];
   float rs[NSEG];
@@ -428,7 +432,7 @@ k_match_bf16(const float* __restrict__ xp, int H, int W, int P, int Cp,
       for (int q = 0; q < 16; ++q) {
         const int i = wm * 64 + mt * 32 + 8 * (q >> 2) + 4 * lhi + (q & 3);
         const int g = kbase + i;
-        if (cok && g < nk) dist[(size_t)g * ldd + t] = centred_dist(kmb[g0 + g], cm, acc[mt][nt][q], D);
+        if (cok && g < nk) dist[(size_t)g * ldd + t] = centred_dist(skm[i], cm, acc[mt][nt][q], D);
       }
     }
 }
