@@ -45,9 +45,11 @@ __device__ __forceinline__ float bcast(float v, int lane) {
 // Lane i < nb loads row d0+i of Y into B[i][0..K) (raw values) and its mean.
 // With Cp > 0 the rows are taken in the output order e = (dy P + dx) Cp + c
 // instead of d = (c P + dy) P + dx.
+// Row stride RS (LS by default); with kpad > K the entries K..kpad-1 of a
+// row are zeroed.
 __device__ __forceinline__ void load_rows(const float* __restrict__ xp, const int* spos, int d0,
                                           int nb, int K, int P, int W, size_t HW, float* B,
-                                          float* smu, int Cp = 0) {
+                                          float* smu, int Cp = 0, int RS = LS, int kpad = 0) {
   const int i = threadIdx.x;
   if (i < nb) {
     size_t o;
@@ -61,9 +63,10 @@ __device__ __forceinline__ void load_rows(const float* __restrict__ xp, const in
 #pragma unroll 8
     for (int j = 0; j < K; ++j) {
       const float v = xp[o + spos[j]];
-      B[i * LS + j] = v;
+      B[i * RS + j] = v;
       s += v;
     }
+    for (int j = K; j < kpad; ++j) B[i * RS + j] = 0.f;
     smu[i] = s / (float)K;
   }
   __syncthreads();
@@ -72,12 +75,31 @@ __device__ __forceinline__ void load_rows(const float* __restrict__ xp, const in
 // FP64 Jacobi rotation annihilating gamma for column norms a1 (first) and a2:
 // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), zeta = (a2 - a1) / (2 gamma),
 // written with one division; c = 1/sqrt(1 + t^2), s = c t.
+// FP64 reciprocal and reciprocal square root from the hardware estimates
+// plus two Newton steps (relative error far below the FP32 rounding the
+// rotation is applied with).
+__device__ __forceinline__ double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = r * fma(-x, r, 2.0);
+  return r * fma(-x, r, 2.0);
+}
+__device__ __forceinline__ double rsq64(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  r = r * fma(-0.5 * x, r * r, 1.5);
+  return r * fma(-0.5 * x, r * r, 1.5);
+}
+
+// Rotation of the column pair (a, b) with squared norms a1, a2 and inner
+// product ga that makes them orthogonal (Hestenes): zeta = (a2 - a1) / (2 ga),
+// t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1 / sqrt(1 + t^2),
+// s = c t; computed in FP64 in the overflow-free form below.  Needs ga != 0.
 __device__ __forceinline__ double jacobi_angle(float a1, float a2, float ga, float& c, float& s) {
   const double d = (double)a2 - (double)a1;
   const double g2 = 2.0 * (double)ga;
   const double sg = ((d >= 0.0) == (g2 >= 0.0)) ? 1.0 : -1.0;     // sign(zeta), zeta = 0 -> +1
-  const double t = sg * fabs(g2) / (fabs(d) + sqrt(d * d + g2 * g2));
-  const double cs = 1.0 / sqrt(1.0 + t * t);
+  const double q = d * d + g2 * g2;
+  const double t = sg * fabs(g2) * rcp64(fabs(d) + q * rsq64(q));
+  const double cs = rsq64(1.0 + t * t);
   c = (float)cs;
   s = (float)(cs * t);
   return t;
@@ -111,9 +133,9 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
        int K, float sigma, float wc, float weps, int max_sweeps, float* __restrict__ xhat,
        float* __restrict__ sv, DevStats* st) {
   constexpr int XS = KP + 4;       // row stride of the column-exchange buffer (16-byte rows)
-  __shared__ float Rl[64 * LS];    // R columns (Rl[j*LS + i]); later W columns
-  // chunk rows Bl[i*LS + j]; then exchange rows and V rows with stride XS
   constexpr int BLN = 64 * (XS > LS ? XS : LS);
+  __shared__ __align__(16) float Rl[BLN];   // R columns (Rl[j*LS + i]); exchange rows; W columns
+  // chunk rows Bl[i*LS + j]; then exchange rows and V rows with stride XS
   __shared__ __align__(16) float Bl[BLN];
   __shared__ __align__(16) float Cb[BR + 4];    // broadcast column, its squared norm at [BR]
   __shared__ float smu[64];
@@ -190,7 +212,7 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
   for (int k = 0; k < KP; ++k) m[k] = (lane < K && k < K) ? Rl[k * LS + lane] : 0.f;
   const int Kp = K + (K & 1);
   const float tol = (float)K * 5.9604644775390625e-08f;
-  float* xrow = Bl + lane * XS;              // this lane's exchange row
+  // exchange rows, double-buffered across rounds (Rl is free until phase 3)
   int sweeps = 0;
   for (int swp = 0; swp < max_sweeps; ++swp) {
     bool rotated = false;
@@ -210,19 +232,25 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
       }
       al = (a0 + a1) + (a2 + a3);
     }
+    // round-robin tournament: position 0 holds lane 0, positions 1..Kp-1
+    // rotate by one per round; position p meets position Kp-1-p
+    int mpos = lane;                          // this lane's position (lane < Kp)
+    int roff = 0;                             // r mod (Kp - 1)
     for (int r = 0; r < Kp - 1; ++r) {
-      // round-robin partner: position 0 fixed, the others rotate by one per round
       int q = -1;
       if (lane < Kp) {
-        const int mpos = lane == 0 ? 0 : 1 + ((lane - 1 - r) % (Kp - 1) + (Kp - 1)) % (Kp - 1);
         const int ppos = Kp - 1 - mpos;
-        q = ppos == 0 ? 0 : 1 + ((ppos - 1 + r) % (Kp - 1));
+        int v = ppos - 1 + roff;
+        if (v >= Kp - 1) v -= Kp - 1;
+        q = ppos == 0 ? 0 : 1 + v;
       }
+      float* xb = (r & 1) ? Rl : Bl;
+      float* xrow = xb + lane * XS;
       store_vec(xrow, m);
       xrow[KP] = al;
       wave_sync();
       float o[KP];
-      const float* prow = Bl + (q < 0 ? lane : q) * XS;
+      const float* prow = xb + (q < 0 ? lane : q) * XS;
       load_vec(o, prow);
       const float be = prow[KP];
       float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f;
@@ -234,26 +262,25 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
         g3 = fmaf(m[k + 3], o[k + 3], g3);
       }
       const float ga = (g0 + g1) + (g2 + g3);    // same products and order in both lanes
-      wave_sync();                               // exchange rows are rewritten next round
       const bool first = lane < q;
       const float n1 = first ? al : be;          // norm^2 of the lower-index column
       const float n2 = first ? be : al;
       const bool act = q >= 0 && lane < K && q < K && ga != 0.f &&
                        fabsf(ga) > tol * sqrtf(n1) * sqrtf(n2);
+      // branch-free rotation: the lower-index column takes c m - s o, the
+      // other s o + c m (both lanes of a pair share c, s)
+      float c = 1.f, sn = 0.f;
       if (act) {
-        float c, s;
+        float s;
         const double t = jacobi_angle(n1, n2, ga, c, s);
-        if (first) {
-#pragma unroll
-          for (int k = 0; k < KP; ++k) m[k] = fmaf(c, m[k], -s * o[k]);
-          al = fmaxf((float)((double)n1 - t * (double)ga), 0.f);
-        } else {
-#pragma unroll
-          for (int k = 0; k < KP; ++k) m[k] = fmaf(s, o[k], c * m[k]);
-          al = fmaxf((float)((double)n2 + t * (double)ga), 0.f);
-        }
+        sn = first ? -s : s;
+        al = fmaxf((float)(first ? (double)n1 - t * (double)ga : (double)n2 + t * (double)ga), 0.f);
       }
+#pragma unroll
+      for (int k = 0; k < KP; ++k) m[k] = fmaf(sn, o[k], c * m[k]);
       rotated = rotated || act;
+      if (lane > 0 && lane < Kp) mpos = mpos == 1 ? Kp - 1 : mpos - 1;
+      roff = roff + 1 == Kp - 1 ? 0 : roff + 1;
     }
     sweeps = swp + 1;
     if (__ballot(rotated) == 0) break;
@@ -320,21 +347,27 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
   // (free once W is in registers) as [j][i], then out as contiguous rows
   // rows in the output order (dy, dx, c); each row's result is independent
   // of the order, so the chunks are written out as contiguous runs
+  // sum_a (y_a - mu) w_a = sum_a y_a w_a - mu sum_a w_a (FP64); rows staged
+  // with a 16-byte stride and zero padding so the inner loop is branch-free
   const int Cp = D / (P * P);
+  double wsum = 0.0;
+#pragma unroll
+  for (int a = 0; a < KP; ++a) wsum += wcol[a];
   for (int d0 = 0; d0 < D; d0 += BR) {
     const int nb = min(BR, D - d0);
-    load_rows(xp, spos, d0, nb, K, P, W, HW, Bl, smu, Cp);
+    load_rows(xp, spos, d0, nb, K, P, W, HW, Bl, smu, Cp, XS, KP);
     if (lane < K) {
       for (int i = 0; i < nb; ++i) {
-        const float mu = smu[i];
-        const float* row = Bl + i * LS;
+        float row[KP];
+        load_vec(row, Bl + i * XS);
         double r0 = 0.0, r1 = 0.0;
 #pragma unroll
         for (int a = 0; a < KP; a += 2) {
-          if (a < K) r0 = fma((double)(row[a] - mu), wcol[a], r0);
-          if (a + 1 < K) r1 = fma((double)(row[a + 1] - mu), wcol[a + 1], r1);
+          r0 = fma((double)row[a], wcol[a], r0);
+          r1 = fma((double)row[a + 1], wcol[a + 1], r1);
         }
-        Rl[lane * LS + i] = (float)((double)row[lane] - (r0 + r1));
+        const double r = (r0 + r1) - (double)smu[i] * wsum;
+        Rl[lane * LS + i] = (float)((double)Bl[i * XS + lane] - r);
       }
     }
     __syncthreads();
