@@ -112,6 +112,12 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
 template <int N>
 __device__ __forceinline__ void store_vec(float* dst, const float (&v)[N]) {
 #pragma unroll
@@ -137,7 +143,7 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
   __shared__ __align__(16) float Rl[BLN];   // R columns (Rl[j*LS + i]); exchange rows; W columns
   // chunk rows Bl[i*LS + j]; then exchange rows and V rows with stride XS
   __shared__ __align__(16) float Bl[BLN];
-  __shared__ __align__(16) float Cb[BR + 4];    // broadcast column, its squared norm at [BR]
+  __shared__ __align__(16) float Cb[BR + 4];    // broadcast reflector u, its scale tau at [BR]
   __shared__ float smu[64];
   __shared__ int spos[64];
   __shared__ float sw[64];
@@ -156,14 +162,39 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
   for (int i = 0; i < 64; ++i) Rl[lane * LS + i] = 0.f;
   __syncthreads();
 
-  // ---- 1. streamed Householder QR of Yc
+  // ---- 1. streamed Householder QR of Yc, scaled by the power of two 2^fe
+  // that brings the first non-zero chunk's largest entry into [1, 2): exact,
+  // and it keeps squares and inner products of tiny groups out of the FP32
+  // subnormal range (phases 1-3 work on the scaled group; the singular values
+  // are scaled back before the shrinkage, and phase 4 reads the raw rows)
+  int fe = 0;
+  bool fset = false;
   for (int d0 = 0; d0 < D; d0 += BR) {
     const int nb = min(BR, D - d0);
     load_rows(xp, spos, d0, nb, K, P, W, HW, Bl, smu);
     float b[BR];
 #pragma unroll
     for (int i = 0; i < BR; ++i) b[i] = (i < nb && lane < K) ? Bl[i * LS + lane] - smu[i] : 0.f;
+    if (!fset) {
+      float mx = 0.f;
+#pragma unroll
+      for (int i = 0; i < BR; ++i) mx = fmaxf(mx, fabsf(b[i]));
+      mx = wave_max(mx);
+      if (mx > 0.f) {
+        int e;
+        frexpf(mx, &e);                       // mx = f 2^e, f in [0.5, 1)
+        fe = min(1 - e, 126);
+        fset = true;
+      }
+    }
+    const float fs = ldexpf(1.f, fe);
+#pragma unroll
+    for (int i = 0; i < BR; ++i) b[i] *= fs;
     for (int k = 0; k < K; ++k) {
+      // lane k builds the reflector that zeroes its chunk column below
+      // R[k][k], normalised to a unit leading entry (u = v / v0, scale
+      // tau = |v0| / ||v|| in [1, 2]) so that no step overflows however
+      // small the column's residual is
       if (lane == k) {
         float q0 = 0.f, q1 = 0.f;
 #pragma unroll
@@ -171,35 +202,41 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
           q0 = fmaf(b[i], b[i], q0);
           q1 = fmaf(b[i + 1], b[i + 1], q1);
         }
-        store_vec(Cb, b);
-        Cb[BR] = q0 + q1;
+        const float sig2 = q0 + q1;
+        const float x0 = Rl[k * LS + k];
+        const float nrm = sqrtf(fmaf(x0, x0, sig2));
+        float rv = 0.f, tau = 0.f, alpha = x0;
+        if (sig2 > 0.f && nrm > 0.f) {
+          alpha = x0 >= 0.f ? -nrm : nrm;
+          const float v0 = x0 - alpha;        // |v0| = |x0| + nrm >= nrm
+          rv = 1.0f / v0;
+          tau = fabsf(v0) / nrm;
+        }
+        float u[BR];
+#pragma unroll
+        for (int i = 0; i < BR; ++i) u[i] = b[i] * rv;
+        store_vec(Cb, u);
+        Cb[BR] = tau;
+        Rl[k * LS + k] = alpha;
       }
       wave_sync();
-      const float sig2 = Cb[BR];
-      if (sig2 > 0.f) {
-        const float x0 = Rl[k * LS + k];
-        const float nrm = sqrtf(x0 * x0 + sig2);
-        const float alpha = x0 >= 0.f ? -nrm : nrm;
-        const float v0 = x0 - alpha;
-        const float beta = 2.0f / (v0 * v0 + sig2);
-        if (lane > k && lane < K) {
-          float v[BR];
-          load_vec(v, Cb);
-          float w0 = 0.f, w1 = 0.f, w2 = 0.f, w3 = 0.f;
+      const float tau = Cb[BR];
+      if (tau > 0.f && lane > k && lane < K) {
+        float u[BR];
+        load_vec(u, Cb);
+        float w0 = 0.f, w1 = 0.f, w2 = 0.f, w3 = 0.f;
 #pragma unroll
-          for (int i = 0; i < BR; i += 4) {
-            w0 = fmaf(v[i], b[i], w0);
-            w1 = fmaf(v[i + 1], b[i + 1], w1);
-            w2 = fmaf(v[i + 2], b[i + 2], w2);
-            w3 = fmaf(v[i + 3], b[i + 3], w3);
-          }
-          const float rk = Rl[lane * LS + k];
-          const float bw = beta * fmaf(v0, rk, (w0 + w1) + (w2 + w3));
-#pragma unroll
-          for (int i = 0; i < BR; ++i) b[i] = fmaf(-bw, v[i], b[i]);
-          Rl[lane * LS + k] = fmaf(-bw, v0, rk);
+        for (int i = 0; i < BR; i += 4) {
+          w0 = fmaf(u[i], b[i], w0);
+          w1 = fmaf(u[i + 1], b[i + 1], w1);
+          w2 = fmaf(u[i + 2], b[i + 2], w2);
+          w3 = fmaf(u[i + 3], b[i + 3], w3);
         }
-        if (lane == k) Rl[k * LS + k] = alpha;
+        const float rk = Rl[lane * LS + k];
+        const float sc = tau * (rk + ((w0 + w1) + (w2 + w3)));
+#pragma unroll
+        for (int i = 0; i < BR; ++i) b[i] = fmaf(-sc, u[i], b[i]);
+        Rl[lane * LS + k] = rk - sc;
       }
       wave_sync();
     }
@@ -294,14 +331,15 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
     s2a = fmaf(m[k], m[k], s2a);
     s2b = fmaf(m[k + 1], m[k + 1], s2b);
   }
-  const float s = sqrtf(s2a + s2b);
+  const float ss = sqrtf(s2a + s2b);           // singular value of the scaled group
+  const float s = ldexpf(ss, -fe);
   if (lane < K) {
     const float shat = sqrtf(fmaxf(s * s - (float)K * sigma * sigma, 0.f));
     const float tau = wc * sqrtf((float)K) * sigma * sigma / (shat + weps);
     const float sn = fmaxf(s - tau, 0.f);
-    ssig[lane] = s;
+    ssig[lane] = ss;
     sw[lane] = s > 0.f ? (s - sn) / s : 0.f;
-    const float inv = s > 0.f ? 1.0f / s : 0.f;
+    const float inv = ss > 0.f ? 1.0f / ss : 0.f;
 #pragma unroll
     for (int k = 0; k < KP; ++k)
       if (k < K) Bl[k * XS + lane] = m[k] * inv;
@@ -309,7 +347,7 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
   __syncthreads();
   if (sv && lane < K) {
     int rank = 0;
-    for (int i = 0; i < K; ++i) rank += (ssig[i] > s || (ssig[i] == s && i < lane)) ? 1 : 0;
+    for (int i = 0; i < K; ++i) rank += (ssig[i] > ss || (ssig[i] == ss && i < lane)) ? 1 : 0;
     sv[(size_t)g * K + rank] = s;
   }
   if (lane == 0 && st) {

@@ -93,7 +93,7 @@ def make_instance(wl):
         m = None
     else:
         raise ValueError(wl.modality)
-    return {"x_true": x, "mask": m}
+    return {"x_true": np.ascontiguousarray(x), "mask": m}
 
 
 def random_image(C, H, W, seed, kind="smooth"):

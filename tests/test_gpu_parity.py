@@ -127,6 +127,34 @@ def test_lowrank_aggregate_vs_oracle(shape):
     assert np.abs(svg - sv_ref).max() <= 1e-5 * sv_ref.max()
 
 
+@pytest.mark.parametrize("shape", [(8, 40, 40, 6, 60, 32), (16, 32, 32, 6, 20, 64)])
+def test_lowrank_tiny_scale_image(shape):
+    # an image scaled by 2^-66: column norms near 1e-20, squared norms
+    # subnormal in FP32.  A Householder reflector scaled by 2 / ||v||^2
+    # overflows there; the unit-leading form must stay finite and match the
+    # oracle on the same scaled input (to the precision subnormal squares
+    # leave, about 2^-17 of the largest singular value)
+    require_gpu()
+    C, H, W, P, N, K = shape
+    print("tiny scale", shape, flush=True)
+    s = 2.0 ** -66
+    x = (random_image(C, H, W, seed=C + H, kind="smooth") * np.float32(s)).astype(np.float32)
+    x64 = x.astype(np.float64)
+    keys = odet.detect_keys(x, P, N)
+    idx, _ = om.topk_exact(x64, P, keys, K)
+    sigma = 0.05 * s
+    plan = _plan(C, H, W, P, N, K)
+    out, sv = plan.lowrank_aggregate(gpu(x), gpu(idx.astype(np.int32)), sigma, want_sv=True)
+    out, svg = host(out), host(sv)[:, :K]
+    assert np.isfinite(out).all() and np.isfinite(svg).all()
+    Xhat, sv_ref = olr.shrink_groups(x64, P, idx, sigma, WNNM_C, WNNM_EPS)
+    ref, _ = oag.aggregate(x64, P, idx, Xhat)
+    err = metrics.rel_l2(out, ref)
+    sv_err = np.abs(svg - sv_ref).max() / sv_ref.max()
+    print(f"  rel-L2 {err:.2e}, sv err {sv_err:.2e}", flush=True)
+    assert err <= 1e-5 and sv_err <= 1e-3
+
+
 def test_identity_shrink_returns_input_exactly():
     require_gpu()
     C, H, W, P, N, K = 3, 30, 30, 4, 40, 12
@@ -191,3 +219,38 @@ def test_prior_step_deterministic():
     a = host(plan.prior_step(gpu(x), 0.04))
     b = host(plan.prior_step(gpu(x), 0.04))
     np.testing.assert_array_equal(a, b)
+
+
+def test_msfa_512_full_size_sampled_keys():
+    # the 512 x 512 x 16-band MSFA workload at its real size (4096 keys over
+    # 507^2 candidates, FP32 matcher): sampled keys against the oracle's
+    # direct-sum distance map; the prior step of the whole image is finite
+    # and moves the iterate
+    require_gpu()
+    from oracle import operators as ops
+    wl = synth.WORKLOADS["msfa_512"]
+    inst = synth.make_instance(wl)
+    y = ops.msfa_forward(inst["x_true"].astype(np.float64))
+    x0 = ops.msfa_init(y, wl.C)
+    xb = ops.gap_update(x0, y, ops.msfa_forward, lambda r: ops.msfa_adjoint(r, wl.C),
+                        np.ones_like(y)).astype(np.float32)
+    plan = glr.Plan("msfa", wl.H, wl.W, wl.C, wl.patch, wl.n_keys, wl.k)
+    xg = gpu(xb)
+    keys = host(plan.detect_keys(xg))
+    np.testing.assert_array_equal(keys, odet.detect_keys(xb.astype(np.float64), wl.patch,
+                                                         wl.n_keys))
+    idx, dist = plan.match_topk(xg, gpu(keys))
+    idx, dist = host(idx), host(dist)
+    st = plan.read_stats()
+    print("msfa_512 margins mean", st["margin_sum"] / wl.n_keys, "max", st["margin_max"],
+          "overflow", st["overflow_keys"], flush=True)
+    x64 = xb.astype(np.float64)
+    rng = np.random.default_rng(23)
+    for a in sorted(rng.choice(wl.n_keys, size=4, replace=False).tolist()):
+        ref_idx, ref_d, _ = om.topk_one(x64, wl.patch, int(keys[a]), wl.k)
+        if not np.array_equal(idx[a], ref_idx):
+            dmap = om.distance_map(x64, wl.patch, int(keys[a]))
+            assert np.abs(np.sort(dmap[idx[a]]) - ref_d).max() <= 1e-9 * float(ref_d.max()), a
+        np.testing.assert_allclose(dist[a], ref_d, rtol=1e-6, atol=1e-30)
+    out = host(plan.prior_step(xg, float(synth.sigma_schedule(wl)[0])))
+    assert np.isfinite(out).all() and metrics.rel_l2(out, xb) > 0
