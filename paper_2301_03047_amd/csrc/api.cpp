@@ -118,6 +118,12 @@ glr_status match_stage(glr_plan* pl, const float* xp, const int32_t* keys, int32
   float* cmeta = (float*)(ws + pl->ws.cmeta);
   float* cm2 = (float*)(ws + pl->ws.cm2);
   uint16_t* Ab = (uint16_t*)(ws + pl->ws.Ab);
+  float* Ac = (float*)(ws + pl->ws.Ac);
+  float* kn = (float*)(ws + pl->ws.kn);
+  float* kc = (float*)(ws + pl->ws.kc);
+  float* pn = (float*)(ws + pl->ws.pn);
+  float* pc = (float*)(ws + pl->ws.pc);
+  float* pq = (float*)(ws + pl->ws.pq);
   uint32_t* tsh = (uint32_t*)(ws + pl->ws.tsh);
   float* dist = (float*)(ws + pl->ws.dist);
   int32_t* lj = (int32_t*)(ws + pl->ws.lj);
@@ -134,8 +140,13 @@ glr_status match_stage(glr_plan* pl, const float* xp, const int32_t* keys, int32
   {
     StageTimer t(pl, s, T_NORMS);
     launch_gather_keys(pl, xp, keys, A, s);
-    launch_key_meta(pl, A, bf ? Ab : nullptr, kmb, s);
-    launch_cand_meta(pl, xp, cmeta, cm2, s);
+    if (bf) {
+      launch_key_meta(pl, A, Ab, kmb, s);
+      launch_cand_meta(pl, xp, cmeta, cm2, s);
+    } else {
+      launch_key_meta_pc(pl, A, Ac, kn, kc, s);
+      launch_cand_meta_pc(pl, xp, pn, pc, pq, s);
+    }
   }
   // FP32 pass over keys (kmap == null: rows 0..n) or over a key list
   auto fp32_pass = [&](const int32_t* kmap, int n) {
@@ -143,12 +154,12 @@ glr_status match_stage(glr_plan* pl, const float* xp, const int32_t* keys, int32
       const int nk = std::min(pl->n_chunk, n - g0);
       {
         StageTimer t(pl, s, T_MATCH);
-        launch_match_f32(pl, xp, A, kmb, cmeta, kmap, g0, nk, dist, s);
+        launch_match_f32(pl, xp, Ac, kn, kc, pn, pc, kmap, g0, nk, dist, s);
         if (pl->timing) pl->match_launches++;
       }
       {
         StageTimer t(pl, s, T_TOPK);
-        launch_topk_partial(pl, dist, kmb, kmap, g0, cm2, nk, 0, tsh, lj, lu, ll, lcnt, s);
+        launch_topk_partial(pl, dist, kn, kmap, g0, pq, nk, 0, tsh, lj, lu, ll, lcnt, s);
       }
       {
         StageTimer t(pl, s, T_SELECT);
@@ -187,7 +198,14 @@ glr_status match_stage(glr_plan* pl, const float* xp, const int32_t* keys, int32
   if (hipMemcpyAsync(&n_re, kcount, sizeof(n_re), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return check_hip("glr_match_topk");
-  if (n_re > 0) fp32_pass(klist, n_re);
+  if (n_re > 0) {
+    {
+      StageTimer t(pl, s, T_NORMS);
+      launch_key_meta_pc(pl, A, Ac, kn, kc, s);
+      launch_cand_meta_pc(pl, xp, pn, pc, pq, s);
+    }
+    fp32_pass(klist, n_re);
+  }
   return check_hip("glr_match_topk");
 }
 
@@ -483,9 +501,15 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
   L.keys = c.take((size_t)pl->N * 4);
   L.A = c.take((size_t)pl->N * D * 4);
   const bool bf = pr->precision == GLR_PREC_BF16_RESCORE;
-  L.kmb = c.take((size_t)pl->N * 16);
-  L.cmeta = c.take((size_t)Ncand * 16);
-  L.cm2 = c.take((size_t)Ncand * 8);
+  L.kmb = c.take(bf ? (size_t)pl->N * 16 : 0);
+  L.cmeta = c.take(bf ? (size_t)Ncand * 16 : 0);
+  L.cm2 = c.take(bf ? (size_t)Ncand * 8 : 0);
+  L.Ac = c.take((size_t)pl->N * D * 4);
+  L.kn = c.take((size_t)pl->N * 16);
+  L.kc = c.take((size_t)pl->N * Cp * 4);
+  L.pn = c.take((size_t)Ncand * 4);
+  L.pc = c.take((size_t)Cp * Ncand * 8);
+  L.pq = c.take((size_t)Ncand * 8);
   L.Ab = c.take(bf ? (size_t)pl->N * Cp * bf16_key_row(P) * 2 : 0);
   L.tsh = c.take((size_t)pl->n_chunk * 4);
   L.klist = c.take(bf ? (size_t)pl->N * 4 : 0);

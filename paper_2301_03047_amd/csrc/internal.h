@@ -27,7 +27,8 @@ struct WsLayout {
   size_t cflag, slist, sval;     // detector candidate flags / survivor list, scores
   size_t keys;                   // detected keys [N]
   size_t A;                      // key matrix [N][D] f32
-  size_t kmb, cmeta, cm2;        // centred key / candidate metadata
+  size_t kmb, cmeta, cm2;        // BF16 form: centred key / candidate metadata (one mean)
+  size_t Ac, kn, kc, pn, pc, pq; // FP32 form: channel-centred keys and metadata
   size_t Ab;                     // BF16 form: centred keys in the BF16 slice layout
   size_t tsh;                    // per-key shared threshold bound [n_chunk]
   size_t klist, kcount;          // BF16 form: keys re-matched in FP32 [N], their count
@@ -112,14 +113,23 @@ void launch_key_meta(const glr_plan* pl, const float* A, uint16_t* Ab, float* km
 // cmeta[Ncand] float4 (mu, ||pbar||^2, ||pbar||, sum pbar); cm2[Ncand] float2 (mu, ||pbar||)
 void launch_cand_meta(const glr_plan* pl, const float* xp, float* cmeta, float* cm2,
                       hipStream_t s);
-// keys: rows g0..g0+nk of A, or rows kmap[g0..g0+nk) when kmap is not null
-void launch_match_f32(const glr_plan* pl, const float* xp, const float* A, const float* kmb,
-                      const float* cmeta, const int32_t* kmap, int g0, int nk, float* dist,
-                      hipStream_t s);
+// FP32 form, channel-centred: Ac[N][D] (a~), kn[N] float4 (||a~||^2, h_k, 0, ||a~||),
+// kc[N][Cp] (fl(P mu_kc)); pn[Ncand] (||p~||^2), pc[Cp][Ncand] float2
+// (mu_pc, fl(P mu_pc)), pq[Ncand] float2 (h_p, ||p~||)
+void launch_key_meta_pc(const glr_plan* pl, const float* A, float* Ac, float* kn, float* kc,
+                        hipStream_t s);
+void launch_cand_meta_pc(const glr_plan* pl, const float* xp, float* pn, float* pc, float* pq,
+                         hipStream_t s);
+// keys: rows g0..g0+nk of Ac, or rows kmap[g0..g0+nk) when kmap is not null
+void launch_match_f32(const glr_plan* pl, const float* xp, const float* Ac, const float* kn,
+                      const float* kc, const float* pn, const float* pc, const int32_t* kmap,
+                      int g0, int nk, float* dist, hipStream_t s);
 void launch_match_bf16(const glr_plan* pl, const float* xp, const uint16_t* Ab, const float* kmb,
                        const float* cmeta, int g0, int nk, float* dist, hipStream_t s);
 
 // topk.hip
+// bf16 = 1: BF16 form (kmb/cm2 of launch_key_meta/launch_cand_meta); 0: the
+// channel-centred FP32 form (kn/pq of launch_key_meta_pc/launch_cand_meta_pc)
 void launch_topk_partial(const glr_plan* pl, const float* dist, const float* kmb,
                          const int32_t* kmap, int g0, const float* cm2, int nk, int bf16,
                          uint32_t* tsh, int32_t* lj, float* lu, float* ll, int32_t* lcnt,

@@ -41,8 +41,9 @@ __global__ void k_gather_keys(const float* __restrict__ xp, int H, int W, int P,
 // ---------------------------------------------------------------- FP32 MFMA matcher
 constexpr int BM = 128;   // keys per block
 constexpr int BN = 128;   // candidates per block (one grid-row segment)
+constexpr int CB = 32;    // channels per epilogue pass
 
-// d~ from the centred dot product S (both forms)
+// d~ from the centred dot product S (BF16 form, one mean per patch)
 __device__ __forceinline__ float centred_dist(float4 km, float4 cm, float S, int D) {
   // km = (||a||^2, mu_k, sum a, ||a||), cm = (mu_p, ||pbar||^2, ||pbar||, sum pbar)
   const float dmu = km.y - cm.x;
@@ -50,23 +51,37 @@ __device__ __forceinline__ float centred_dist(float4 km, float4 cm, float S, int
   return (base + ((float)D * dmu) * dmu) + 2.0f * dmu * (km.z - cm.w);
 }
 
-// P2 = P rounded up to even (the K=2 step of v_mfma_f32_32x32x2f32).  Keys
-// are rows g0 + g of A, or rows kmap[g0 + g] when kmap is given; output row
-// g of dist.  A is centred while staged (padding stays zero); the candidate
-// operand is centred in registers (seg[j + dx] - mu_j).
+// FP32 form: every channel block of n = P^2 elements is centred on its own
+// mean.  With a~ = fl(k - mu_kc), p~ = fl(p - mu_pc) per channel c (means
+// correctly rounded from FP64 sums) and dmu_c = mu_kc - mu_pc,
+//   ||k - p||^2 = ||a~||^2 + ||p~||^2 - 2 <a~, p~> + n sum_c dmu_c^2
+// up to the residues of the centring (the channel sums of a~ and p~ and the
+// subtraction roundings), which the error bound of the top-K pass covers.
+// The kernel adds sum_c (P mu_kc - P mu_pc)^2 with P mu rounded to FP32.
+// Removing each channel's own level (a band's brightness, a frame's
+// exposure) keeps ||a~||, ||p~||, and with them the rounding error, at the
+// scale of the texture.
+//
+// Key data: Ac[g] = a~ (rows g or kmap[g0+g]), kn[g] = (||a~||^2, h_k, 0,
+// ||a~||) with h the norm of the channels' mean |values| (a bound term),
+// kc[g][c] = fl(P mu_kc).  Candidate data: pn[j] = ||p~_j||^2, pc[c][j] =
+// (mu_pc, fl(P mu_pc)) (channel-major, so lanes of consecutive candidates
+// read consecutive entries).
 template <int P2>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 3)
 k_match_f32(const float* __restrict__ xp, int H, int W, int P, int Cp,
-            const float* __restrict__ A, int D, const float4* __restrict__ kmb,
-            const float4* __restrict__ cmeta, const int32_t* __restrict__ kmap, int g0, int nk,
-            float* __restrict__ dist, size_t ldd) {
+            const float* __restrict__ Ac, int D, const float4* __restrict__ kn,
+            const float* __restrict__ kc, const float* __restrict__ pn,
+            const float2* __restrict__ pc, size_t ncand, const int32_t* __restrict__ kmap,
+            int g0, int nk, float* __restrict__ dist, size_t ldd) {
   constexpr int SEG = BN + P2;
   constexpr int AST = P2 + 1;   // odd LDS stride for the key slab
   __shared__ float seg[2][SEG];
   __shared__ float As[2][BM * AST];
-  __shared__ float4 skm[BM];
   __shared__ int krow[BM];
-  __shared__ float mub[BN];
+  __shared__ float skn[BM];
+  __shared__ __align__(16) float skc[CB * BM];   // epilogue: [channel of the pass][key]
+  __shared__ float spc[CB * BN];                 // epilogue: [channel of the pass][candidate]
 
   const int Hc = H - P + 1, Wc = W - P + 1;
   const int ntc = (Wc + BN - 1) / BN;
@@ -87,18 +102,19 @@ k_match_f32(const float* __restrict__ xp, int H, int W, int P, int Cp,
     const int g = kbase + tid;
     const int gg = g < nk ? (kmap ? kmap[g0 + g] : g0 + g) : -1;
     krow[tid] = gg;
-    skm[tid] = gg >= 0 ? kmb[gg] : make_float4(0.f, 0.f, 0.f, 0.f);
-  }
-  if (tid < BN) {
-    const int col = c0 + tid;
-    mub[tid] = col < Wc ? cmeta[(size_t)r * Wc + col].x : 0.f;
+    skn[tid] = gg >= 0 ? kn[gg].x : 0.f;
   }
   __syncthreads();
+
+  const int l32 = lane & 31, lhi = lane >> 5;
+  const int colA = c0 + wn * 64 + l32, colB = colA + 32;
+  const size_t tA = (size_t)r * Wc + colA, tB = tA + 32;
 
   // register staging of the next stage
   float rseg = 0.f;
   constexpr int APT = (BM * P2 + 255) / 256;
   float ra[APT];
+  float nb0 = 0.f, nb1 = 0.f;
 
   auto load_stage = [&](int s) {
     const int ch = s / P, dy = s - ch * P;
@@ -114,9 +130,13 @@ k_match_f32(const float* __restrict__ xp, int H, int W, int P, int Cp,
       if (e < BM * P2) {
         int m = e / P2, dx = e - m * P2;
         const int gg = krow[m];
-        if (dx < P && gg >= 0) v = A[(size_t)gg * D + (size_t)s * P + dx] - skm[m].y;
+        if (dx < P && gg >= 0) v = Ac[(size_t)gg * D + (size_t)s * P + dx];
       }
       ra[u] = v;
+    }
+    if (dy == 0) {                           // the channel's candidate means
+      nb0 = colA < Wc ? pc[(size_t)ch * ncand + tA].x : 0.f;
+      nb1 = colB < Wc ? pc[(size_t)ch * ncand + tB].x : 0.f;
     }
   };
   auto store_stage = [&](int buf) {
@@ -139,10 +159,9 @@ k_match_f32(const float* __restrict__ xp, int H, int W, int P, int Cp,
 #pragma unroll
       for (int q = 0; q < 16; ++q) acc[i][j][q] = 0.f;
 
-  const int l32 = lane & 31, lhi = lane >> 5;
-  const float mb0 = mub[wn * 64 + l32], mb1 = mub[wn * 64 + 32 + l32];
   load_stage(0);
   store_stage(0);
+  float mb0 = nb0, mb1 = nb1;                // the current channel's candidate means
   __syncthreads();
   for (int s = 0; s < S; ++s) {
     const int cur = s & 1;
@@ -160,37 +179,162 @@ k_match_f32(const float* __restrict__ xp, int H, int W, int P, int Cp,
       acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
     }
     if (s + 1 < S) store_stage(cur ^ 1);
+    if ((s + 1) % P == 0) {
+      mb0 = nb0;
+      mb1 = nb1;
+    }
     __syncthreads();
   }
 
+  // epilogue: d~ = ((||a~||^2 + ||p~||^2) - 2 S) + sum_c (P mu_kc - P mu_pc)^2,
+  // one 32 x 32 tile at a time, channels in passes of CB (staged once when
+  // Cp <= CB)
+  auto stage_means = [&](int cb) {
+    const int nc = min(CB, Cp - cb);
+    for (int e = tid; e < nc * BM; e += 256) {
+      const int c = e / BM, m = e - c * BM;
+      const int gg = krow[m];
+      skc[e] = gg >= 0 ? kc[(size_t)gg * Cp + cb + c] : 0.f;
+    }
+    for (int e = tid; e < nc * BN; e += 256) {
+      const int c = e / BN, j = e - c * BN;
+      spc[e] = c0 + j < Wc ? pc[(size_t)(cb + c) * ncand + (size_t)r * Wc + c0 + j].y : 0.f;
+    }
+  };
+  const bool one_pass = Cp <= CB;
+  if (one_pass) {
+    stage_means(0);
+    __syncthreads();
+  }
 #pragma unroll
-  for (int mt = 0; mt < 2; ++mt)
+  for (int nt = 0; nt < 2; ++nt) {
+    const float pp = (nt ? colB : colA) < Wc ? pn[nt ? tB : tA] : 0.f;
 #pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
-      const int col = c0 + wn * 64 + nt * 32 + l32;
-      const bool cok = col < Wc;
-      const size_t t = (size_t)r * Wc + col;
-      const float4 cm = cok ? cmeta[t] : make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int mt = 0; mt < 2; ++mt) {
+      const int i0 = wm * 64 + mt * 32 + 4 * lhi;   // rows i0 + 8 j + h, h < 4
+      __builtin_amdgcn_sched_barrier(0);   // read this tile's accumulators only now
+      float v[16];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int i = wm * 64 + mt * 32 + 8 * (q >> 2) + 4 * lhi + (q & 3);
-        if (cok && krow[i] >= 0)
-          dist[(size_t)(kbase + i) * ldd + t] = centred_dist(skm[i], cm, acc[mt][nt][q], D);
+      for (int q = 0; q < 16; ++q)
+        v[q] = fmaf(-2.0f, acc[mt][nt][q], skn[i0 + 8 * (q >> 2) + (q & 3)] + pp);
+      for (int cb = 0; cb < Cp; cb += CB) {
+        if (!one_pass) {
+          __syncthreads();
+          stage_means(cb);
+          __syncthreads();
+        }
+        const int nc = min(CB, Cp - cb);
+#pragma unroll 1
+        for (int c = 0; c < nc; ++c) {
+          const float qv = spc[c * BN + wn * 64 + nt * 32 + l32];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const float4 kv = *reinterpret_cast<const float4*>(skc + c * BM + i0 + 8 * j);
+            const float d0 = kv.x - qv, d1 = kv.y - qv, d2 = kv.z - qv, d3 = kv.w - qv;
+            v[4 * j] = fmaf(d0, d0, v[4 * j]);
+            v[4 * j + 1] = fmaf(d1, d1, v[4 * j + 1]);
+            v[4 * j + 2] = fmaf(d2, d2, v[4 * j + 2]);
+            v[4 * j + 3] = fmaf(d3, d3, v[4 * j + 3]);
+          }
+        }
+      }
+      if ((nt ? colB : colA) < Wc) {
+        const size_t t = nt ? tB : tA;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int i = i0 + 8 * (q >> 2) + (q & 3);
+          if (krow[i] >= 0) dist[(size_t)(kbase + i) * ldd + t] = v[q];
+        }
       }
     }
+  }
 }
 
 template <int P2>
-void launch_match_t(const glr_plan* pl, const float* xp, const float* A, const float* kmb,
-                    const float* cmeta, const int32_t* kmap, int g0, int nk, float* dist,
-                    hipStream_t s) {
+void launch_match_t(const glr_plan* pl, const float* xp, const float* Ac, const float* kn,
+                    const float* kc, const float* pn, const float* pc, const int32_t* kmap,
+                    int g0, int nk, float* dist, hipStream_t s) {
   const int Hc = pl->Hc, Wc = pl->Wc;
   const int ntc = (Wc + BN - 1) / BN;
   const int nkt = (nk + BM - 1) / BM;
   size_t blocks = (size_t)nkt * Hc * ntc;
   hipLaunchKernelGGL(k_match_f32<P2>, dim3((unsigned)blocks), dim3(256), 0, s, xp, pl->H, pl->W,
-                     pl->P, pl->Cp, A, pl->D, (const float4*)kmb, (const float4*)cmeta, kmap, g0,
-                     nk, dist, (size_t)pl->ldd);
+                     pl->P, pl->Cp, Ac, pl->D, (const float4*)kn, kc, pn, (const float2*)pc,
+                     (size_t)pl->Ncand, kmap, g0, nk, dist, (size_t)pl->ldd);
+}
+
+// Per key of the FP32 form (one wave per key): Ac, kn, kc as described at
+// k_match_f32.  Channel means from FP64 sums, correctly rounded to FP32.
+__global__ void k_key_meta_pc(const float* __restrict__ A, int D, int P, int Cp, int N,
+                              float* __restrict__ Ac, float4* __restrict__ kn,
+                              float* __restrict__ kc) {
+  const int g = blockIdx.x;
+  if (g >= N) return;
+  const int n = P * P;
+  const float* k = A + (size_t)g * D;
+  float* ac = Ac + (size_t)g * D;
+  const int l = threadIdx.x;
+  float an = 0.f, h = 0.f;
+  for (int c = 0; c < Cp; ++c) {
+    double s = 0.0, sb = 0.0;
+    for (int i = l; i < n; i += 64) {
+      const double v = k[c * n + i];
+      s += v;
+      sb += fabs(v);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      s += __shfl_xor(s, o, 64);
+      sb += __shfl_xor(sb, o, 64);
+    }
+    const float mu = (float)(s / n);
+    for (int i = l; i < n; i += 64) {
+      const float a = k[c * n + i] - mu;
+      ac[c * n + i] = a;
+      an = fmaf(a, a, an);
+    }
+    if (l == 0) kc[(size_t)g * Cp + c] = (float)P * mu;
+    const float ma = (float)(sb / n);
+    h = fmaf(ma, ma, h);
+  }
+  for (int o = 32; o > 0; o >>= 1) an += __shfl_xor(an, o, 64);
+  if (l == 0) kn[g] = make_float4(an, sqrtf(h), 0.f, sqrtf(an));
+}
+
+// Per candidate of the FP32 form (one thread per candidate): pn[j] = ||p~||^2,
+// pc[c][j] = (mu_pc, fl(P mu_pc)), pq[j] = (h_p, ||p~||) for the top-K bound.
+__global__ void k_cand_meta_pc(const float* __restrict__ xp, int Cp, int H, int W, int P,
+                               float* __restrict__ pn, float2* __restrict__ pc,
+                               float2* __restrict__ pq) {
+  const int Wc = W - P + 1, Hc = H - P + 1;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t ncand = (size_t)Hc * Wc;
+  if (j >= (int)ncand) return;
+  const int r = j / Wc, c = j - r * Wc;
+  const int n = P * P;
+  float sq = 0.f, h = 0.f;
+  for (int ch = 0; ch < Cp; ++ch) {
+    double s = 0.0, sb = 0.0;
+    for (int dy = 0; dy < P; ++dy) {
+      const float* row = xp + ((size_t)ch * H + r + dy) * W + c;
+      for (int dx = 0; dx < P; ++dx) {
+        s += (double)row[dx];
+        sb += fabs((double)row[dx]);
+      }
+    }
+    const float mu = (float)(s / n);
+    for (int dy = 0; dy < P; ++dy) {
+      const float* row = xp + ((size_t)ch * H + r + dy) * W + c;
+      for (int dx = 0; dx < P; ++dx) {
+        const float v = row[dx] - mu;
+        sq = fmaf(v, v, sq);
+      }
+    }
+    pc[(size_t)ch * ncand + j] = make_float2(mu, (float)P * mu);
+    const float ma = (float)(sb / n);
+    h = fmaf(ma, ma, h);
+  }
+  pn[j] = sq;
+  pq[j] = make_float2(sqrtf(h), sqrtf(sq));
 }
 
 // ---------------------------------------------------------------- BF16 form
@@ -471,19 +615,35 @@ void launch_cand_meta(const glr_plan* pl, const float* xp, float* cmeta, float* 
                      pl->W, pl->P, (float4*)cmeta, (float2*)cm2);
 }
 
-void launch_match_f32(const glr_plan* pl, const float* xp, const float* A, const float* kmb,
-                      const float* cmeta, const int32_t* kmap, int g0, int nk, float* dist,
-                      hipStream_t s) {
+void launch_key_meta_pc(const glr_plan* pl, const float* A, float* Ac, float* kn, float* kc,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_key_meta_pc, dim3(pl->N), dim3(64), 0, s, A, pl->D, pl->P, pl->Cp, pl->N,
+                     Ac, (float4*)kn, kc);
+}
+
+void launch_cand_meta_pc(const glr_plan* pl, const float* xp, float* pn, float* pc, float* pq,
+                         hipStream_t s) {
+  const int n = pl->Ncand;
+  hipLaunchKernelGGL(k_cand_meta_pc, dim3((n + 255) / 256), dim3(256), 0, s, xp, pl->Cp, pl->H,
+                     pl->W, pl->P, pn, (float2*)pc, (float2*)pq);
+}
+
+void launch_match_f32(const glr_plan* pl, const float* xp, const float* Ac, const float* kn,
+                      const float* kc, const float* pn, const float* pc, const int32_t* kmap,
+                      int g0, int nk, float* dist, hipStream_t s) {
+#define GLR_MATCH_CASE(c, p2) \
+  case c: launch_match_t<p2>(pl, xp, Ac, kn, kc, pn, pc, kmap, g0, nk, dist, s); break;
   switch ((pl->P + 1) / 2) {
-    case 1: launch_match_t<2>(pl, xp, A, kmb, cmeta, kmap, g0, nk, dist, s); break;
-    case 2: launch_match_t<4>(pl, xp, A, kmb, cmeta, kmap, g0, nk, dist, s); break;
-    case 3: launch_match_t<6>(pl, xp, A, kmb, cmeta, kmap, g0, nk, dist, s); break;
-    case 4: launch_match_t<8>(pl, xp, A, kmb, cmeta, kmap, g0, nk, dist, s); break;
-    case 5: launch_match_t<10>(pl, xp, A, kmb, cmeta, kmap, g0, nk, dist, s); break;
-    case 6: launch_match_t<12>(pl, xp, A, kmb, cmeta, kmap, g0, nk, dist, s); break;
-    case 7: launch_match_t<14>(pl, xp, A, kmb, cmeta, kmap, g0, nk, dist, s); break;
-    default: launch_match_t<16>(pl, xp, A, kmb, cmeta, kmap, g0, nk, dist, s); break;
+    GLR_MATCH_CASE(1, 2)
+    GLR_MATCH_CASE(2, 4)
+    GLR_MATCH_CASE(3, 6)
+    GLR_MATCH_CASE(4, 8)
+    GLR_MATCH_CASE(5, 10)
+    GLR_MATCH_CASE(6, 12)
+    GLR_MATCH_CASE(7, 14)
+    default: launch_match_t<16>(pl, xp, Ac, kn, kc, pn, pc, kmap, g0, nk, dist, s); break;
   }
+#undef GLR_MATCH_CASE
 }
 
 void launch_match_bf16(const glr_plan* pl, const float* xp, const uint16_t* Ab, const float* kmb,

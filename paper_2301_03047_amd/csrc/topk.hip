@@ -132,13 +132,21 @@ __device__ int wave_compact(int* bj, float* bu, float* bl, int n, float T) {
   return w;
 }
 
-// km = (||a||^2, mu_k, sum a, ||a||) per key (row kmap[g0+g] or g0+g);
-// cm = (mu_j, ||pbar_j||) per candidate.  tsh[g]: the key's shared bound of T
-// (ordered bits, +inf at launch), lowered with atomicMin by every range.
+// Error bound of d~ per candidate (key row kmap[g0+g] or g0+g):
+//  pc == 0 (BF16 form, one mean per patch): km = (||a||^2, mu_k, sum a, ||a||),
+//    cm = (mu_j, ||pbar_j||); eps = coef ||a|| ||pbar|| + coef2 R^2 with
+//    R = ||a|| + ||pbar|| + cz |mu_k - mu_j|, cz = sqrt(D);
+//  pc == 1 (channel-centred FP32 form): km = (||a~||^2, h_k, 0, ||a~||),
+//    cm = (h_j, ||p~_j||); with w = cz (h_k + h_j) (the centring residues)
+//    and y = ||a~|| + ||p~|| + sqrt(max(d~, 0)) + w, eps = y (coef2 y + w) + w^2:
+//    the channel-mean part of the bound is itself bounded through the
+//    distance.
+// tsh[g]: the key's shared bound of T (ordered bits, +inf at launch), lowered
+// with atomicMin by every range.
 __global__ void __launch_bounds__(256)
 k_topk_partial(const float* __restrict__ dist, size_t ldd, const float4* __restrict__ km,
                const int32_t* __restrict__ kmap, int g0, const float* __restrict__ cm, int Ncand,
-               int split_len, int S, int nk, int K, float coef, float coef2, float sqrtD,
+               int split_len, int S, int nk, int K, int pc, float coef, float coef2, float cz,
                uint32_t* __restrict__ tsh, int32_t* __restrict__ lj, float* __restrict__ lu,
                float* __restrict__ ll, int32_t* __restrict__ lcnt) {
   __shared__ int sbj[4][CAP];
@@ -211,8 +219,15 @@ k_topk_partial(const float* __restrict__ dist, size_t ldd, const float4* __restr
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int j = base + u * 256 + 4 * l + e;
-        const float R = (kr + pv[u][e]) + sqrtD * fabsf(kmu - mv[u][e]);
-        const float eps = coef * (kr * pv[u][e]) + coef2 * (R * R);
+        float eps;
+        if (pc) {
+          const float w = cz * (kmu + mv[u][e]);
+          const float y = ((kr + pv[u][e]) + sqrtf(fmaxf(dv[u][e], 0.f))) + w;
+          eps = fmaf(y, fmaf(coef2, y, w), w * w);
+        } else {
+          const float R = (kr + pv[u][e]) + cz * fabsf(kmu - mv[u][e]);
+          eps = coef * (kr * pv[u][e]) + coef2 * (R * R);
+        }
         ok[u][e] = j < j1;
         Uv[u][e] = dv[u][e] + eps;
         Lv[u][e] = dv[u][e] - eps;
@@ -744,14 +759,20 @@ void launch_topk_partial(const glr_plan* pl, const float* dist, const float* kmb
   const double u = 5.9604644775390625e-08;      // 2^-24
   const double b = 0.001953125;                 // 2^-9
   // coefficients rounded up so that the float values are not below the bound
-  const float coef = bf16 ? std::nextafter((float)(4.0 * (2.0 * b + b * b)), 1.f) : 0.f;
-  const float coef2 = std::nextafter((float)((3.0 * pl->D + 26.0) * u), 1.f);
-  const float sqrtD = std::nextafter((float)std::sqrt((double)pl->D), 1e9f);
+  float coef = 0.f, coef2, cz;
+  if (bf16) {
+    coef = std::nextafter((float)(4.0 * (2.0 * b + b * b)), 1.f);
+    coef2 = std::nextafter((float)((3.0 * pl->D + 26.0) * u), 1.f);
+    cz = std::nextafter((float)std::sqrt((double)pl->D), 1e9f);
+  } else {
+    coef2 = std::nextafter((float)(2.02 * (pl->D + pl->Cp + 4.0) * u), 1.f);
+    cz = std::nextafter((float)(8.02 * pl->P * u), 1.f);
+  }
   launch_fill_u32(tsh, 0xffffffffu, (size_t)nk, s);
   const int items = nk * pl->n_split;
   hipLaunchKernelGGL(k_topk_partial, dim3((items + 3) / 4), dim3(256), 0, s, dist,
                      (size_t)pl->ldd, (const float4*)kmb, kmap, g0, cm2, pl->Ncand, pl->split_len,
-                     pl->n_split, nk, pl->K, coef, coef2, sqrtD, tsh, lj, lu, ll, lcnt);
+                     pl->n_split, nk, pl->K, bf16 ? 0 : 1, coef, coef2, cz, tsh, lj, lu, ll, lcnt);
 }
 
 // Lanes per candidate of the exact rescoring: the fewest (>= 8) that keep
