@@ -435,7 +435,7 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 // The candidate operand is built in LDS per step from the staged image rows:
 // Bs[t][j][0..8) = bf16(x[c][r+y][c0+j+dx] - mu_p(j)) for slice t = (y, dx/8).
 template <int NS>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 3)
 k_match_bf16(const float* __restrict__ xp, int H, int W, int P, int Cp,
              const uint16_t* __restrict__ Ab, const float4* __restrict__ kmb,
              const float4* __restrict__ cmeta, int g0, int nk, float* __restrict__ dist,
