@@ -140,16 +140,20 @@ k_bucket_sort_large(const int32_t* __restrict__ offs, int32_t* __restrict__ ent,
 constexpr int GX = 64;            // pixels per block (one image row segment)
 constexpr int GT = 256;           // threads per block
 constexpr int CG = 32;            // channels per block (grid z covers the rest)
-constexpr int LDS_FLOATS = 12288; // staged estimate rows per chunk (48 KB)
+constexpr int LDS_FLOATS = 8192;  // staged estimate rows per chunk (32 KB)
+constexpr int UB = 4;             // 16-byte staging loads in flight per thread
 
 // One block per (image row r, 64-pixel segment, channel group).  Estimates
 // are stored per member patch as xhat[e][dy][dx][c], so the dy-row of an
 // entry is one contiguous run of P*Cp floats.  For each dy the entries of
 // the window of top-left positions (row r - dy, columns c0 - P + 1 ..
 // c0 + GX - 1) are contiguous in the CSR order; their dy-rows are staged in
-// LDS in chunks and every (pixel, channel) of the block sums its covering
-// values in the fixed order (dy, position, entry) ascending.  Lanes run over
-// the channels of a pixel, which all have the same trip counts.
+// LDS in chunks (all loads of a thread's batch issued before its stores)
+// and every (pixel, channel) of the block sums its covering values in the
+// fixed order (dy, position, entry) ascending: the covering entries of a
+// pixel are one contiguous run of the staged list, whose column is kept per
+// entry.  Lanes run over the channels of a pixel, which all have the same
+// trip counts.
 __global__ void __launch_bounds__(GT)
 k_gather(const float* __restrict__ xbar, const float* __restrict__ xhat,
          const int32_t* __restrict__ ent, const int32_t* __restrict__ offs, int Cp, int H, int W,
@@ -157,6 +161,7 @@ k_gather(const float* __restrict__ xbar, const float* __restrict__ xhat,
   __shared__ __align__(16) float lds[LDS_FLOATS];
   __shared__ int spos[GX + 17];             // window bucket starts (P <= 16), + end
   __shared__ int sent[LDS_FLOATS / 4];      // entry ids of the staged chunk
+  __shared__ int scol[LDS_FLOATS / 4];      // their top-left columns
   const int r = blockIdx.y;
   const int c0 = blockIdx.x * GX;
   const int cg0 = blockIdx.z * CG;
@@ -174,7 +179,6 @@ k_gather(const float* __restrict__ xbar, const float* __restrict__ xhat,
   }
   const int rowlen = ncg * P;               // floats staged per entry
   const int cap = min(LDS_FLOATS / rowlen, LDS_FLOATS / 4);   // entries per chunk
-  const int lane = tid & 63, wave = tid >> 6;
   // 16-byte staging when the block takes all channels (a staged row is one
   // contiguous run) and every row start and length is a multiple of 4 floats
   const bool vec4 = ncg == Cp && (rowlen & 3) == 0 && (D & 3) == 0;
@@ -200,31 +204,51 @@ k_gather(const float* __restrict__ xbar, const float* __restrict__ xhat,
     }
     for (int ia = ea; ia < eb; ia += cap) {
       const int ib = min(eb, ia + cap);
+      const int nrow = ib - ia;
       __syncthreads();
-      for (int i = tid; i < ib - ia; i += GT) sent[i] = ent[ia + i];
+      for (int i = tid; i < nrow; i += GT) sent[i] = ent[ia + i];
+      for (int k = tid; k < nwin; k += GT) {
+        const int i0 = max(spos[k], ia), i1 = min(spos[k + 1], ib);
+        for (int i = i0; i < i1; ++i) scol[i - ia] = tc0 + k;
+      }
       __syncthreads();
-      // each wave stages whole entry rows: lane -> (entry le, 16-byte word w);
       // LDS row i holds [dx][c - cg0]
       {
-        const int nrow = ib - ia;
         const size_t roff = (size_t)dy * P * Cp;
         if (vec4) {
           const int r4 = rowlen >> 2;
-          const int epw = r4 >= 64 ? 1 : 64 / r4;
-          const int le = lane / r4, w0 = lane - le * r4;
-          if (le < epw)
-            for (int i = wave * epw + le; i < nrow; i += 4 * epw)
-              for (int w = w0; w < r4; w += 64) {
-                const float4 v = *reinterpret_cast<const float4*>(
-                    xhat + (size_t)sent[i] * D + roff + 4 * w);
-                *reinterpret_cast<float4*>(lds + i * rowlen + 4 * w) = v;
-              }
-        } else {
-          for (int i = wave; i < nrow; i += 4)
-            for (int w = lane; w < rowlen; w += 64) {
-              const int dx = w / ncg, c = w - dx * ncg;
-              lds[i * rowlen + w] = xhat[(size_t)sent[i] * D + roff + (size_t)dx * Cp + cg0 + c];
+          const int nw = nrow * r4;
+          for (int base = tid; base < nw; base += GT * UB) {
+            // every load is issued (past the end it re-reads the last word)
+            // before the stores, so UB loads per thread are in flight
+            float4 v[UB];
+            int dst[UB];
+#pragma unroll
+            for (int u = 0; u < UB; ++u) {
+              const int q = min(base + u * GT, nw - 1);
+              const int i = q / r4, w = q - i * r4;
+              v[u] = *reinterpret_cast<const float4*>(xhat + (size_t)sent[i] * D + roff + 4 * w);
+              dst[u] = i * rowlen + 4 * w;
             }
+#pragma unroll
+            for (int u = 0; u < UB; ++u)
+              if (base + u * GT < nw) *reinterpret_cast<float4*>(lds + dst[u]) = v[u];
+          }
+        } else {
+          const int nw = nrow * rowlen;
+          for (int base = tid; base < nw; base += GT * UB) {
+            float v[UB];
+#pragma unroll
+            for (int u = 0; u < UB; ++u) {
+              const int q = min(base + u * GT, nw - 1);
+              const int i = q / rowlen, w = q - i * rowlen;
+              const int dx = w / ncg, c = w - dx * ncg;
+              v[u] = xhat[(size_t)sent[i] * D + roff + (size_t)dx * Cp + cg0 + c];
+            }
+#pragma unroll
+            for (int u = 0; u < UB; ++u)
+              if (base + u * GT < nw) lds[base + u * GT] = v[u];
+          }
         }
       }
       __syncthreads();
@@ -235,13 +259,11 @@ k_gather(const float* __restrict__ xbar, const float* __restrict__ xhat,
           const int px = p / ncg, ch = p - px * ncg;
           const int c = c0 + px;
           const int lo = max(tc0, c - P + 1), hi = min(tc1, c);
-          if (c < W) {
+          if (c < W && lo <= hi) {
+            const int b0 = max(spos[lo - tc0], ia), b1 = min(spos[hi - tc0 + 1], ib);
             float a = acc[k];
-            for (int tc = lo; tc <= hi; ++tc) {
-              const int dx = c - tc;
-              const int b0 = max(spos[tc - tc0], ia), b1 = min(spos[tc - tc0 + 1], ib);
-              for (int i = b0; i < b1; ++i) a += lds[(i - ia) * rowlen + dx * ncg + ch];
-            }
+            for (int i = b0; i < b1; ++i)
+              a += lds[(i - ia) * rowlen + (c - scol[i - ia]) * ncg + ch];
             acc[k] = a;
           }
         }

@@ -249,7 +249,6 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
   for (int k = 0; k < KP; ++k) m[k] = (lane < K && k < K) ? Rl[k * LS + lane] : 0.f;
   const int Kp = K + (K & 1);
   const float tol = (float)K * 5.9604644775390625e-08f;
-  // exchange rows, double-buffered across rounds (Rl is free until phase 3)
   int sweeps = 0;
   for (int swp = 0; swp < max_sweeps; ++swp) {
     bool rotated = false;
@@ -281,15 +280,13 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
         if (v >= Kp - 1) v -= Kp - 1;
         q = ppos == 0 ? 0 : 1 + v;
       }
-      float* xb = (r & 1) ? Rl : Bl;
-      float* xrow = xb + lane * XS;
-      store_vec(xrow, m);
-      xrow[KP] = al;
-      wave_sync();
+      // the partner's column and squared norm through the cross-lane
+      // permute (no LDS round trip, no barrier)
+      const int src = q < 0 ? lane : q;
       float o[KP];
-      const float* prow = xb + (q < 0 ? lane : q) * XS;
-      load_vec(o, prow);
-      const float be = prow[KP];
+#pragma unroll
+      for (int k = 0; k < KP; ++k) o[k] = __shfl(m[k], src, 64);
+      const float be = __shfl(al, src, 64);
       float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f;
 #pragma unroll
       for (int k = 0; k < KP; k += 4) {
@@ -339,10 +336,13 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
     const float sn = fmaxf(s - tau, 0.f);
     ssig[lane] = ss;
     sw[lane] = s > 0.f ? (s - sn) / s : 0.f;
-    const float inv = ss > 0.f ? 1.0f / ss : 0.f;
+  }
+  // V rows and columns past K are written as zeros: the products below run
+  // over all KP entries, and 0 times stale LDS contents could be NaN
+  if (lane < KP) {
+    const float inv = (lane < K && ss > 0.f) ? 1.0f / ss : 0.f;
 #pragma unroll
-    for (int k = 0; k < KP; ++k)
-      if (k < K) Bl[k * XS + lane] = m[k] * inv;
+    for (int k = 0; k < KP; ++k) Bl[k * XS + lane] = (lane < K && k < K) ? m[k] * inv : 0.f;
   }
   __syncthreads();
   if (sv && lane < K) {
