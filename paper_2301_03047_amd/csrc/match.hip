@@ -430,48 +430,60 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 
-// BF16 MFMA matcher: 128 keys x 128 candidates per block (one grid-row
+// Candidates per block of the BF16 matcher: 256 (each wave 64 keys x 128
+// candidates, four 32 x 32 tiles per key tile) while the operand buffers fit
+// LDS (NS <= 8), else 128.
+__host__ __device__ constexpr int bf16_nt(int NS) { return NS <= 8 ? 4 : 2; }
+
+// BF16 MFMA matcher: 128 keys x 64 NT candidates per block (one grid-row
 // segment), one channel (NS slices of the padded patch block) per step.
 // The candidate operand is built in LDS per step from the staged image rows:
-// Bs[t][j][0..8) = bf16(x[c][r+y][c0+j+dx] - mu_p(j)) for slice t = (y, dx/8).
+// Bs[t][j][0..8) = bf16(x[c][r+y][c0+j+dx] - mu_p(j)) for slice t = (y, dx/8);
+// a thread builds four consecutive candidates of one slice from three
+// 16-byte reads of the row (their eight-value windows overlap).  Bs rows
+// get 16 bytes of padding after every 16 candidates, so the stores (lanes
+// four candidates apart) and the fragment reads (consecutive candidates)
+// are both free of bank conflicts.
 template <int NS>
-__global__ void __launch_bounds__(256, 3)
+__global__ void __launch_bounds__(256, 2)
 k_match_bf16(const float* __restrict__ xp, int H, int W, int P, int Cp,
              const uint16_t* __restrict__ Ab, const float4* __restrict__ kmb,
              const float4* __restrict__ cmeta, int g0, int nk, float* __restrict__ dist,
              size_t ldd) {
+  constexpr int NT = bf16_nt(NS);         // 32-candidate tiles per wave
+  constexpr int BNB = 64 * NT;            // candidates per block
   constexpr int XS = NS > 8 ? 2 : 1;      // slices per patch row
   constexpr int RP = NS / XS;             // padded rows
   constexpr int ROWB = NS * 8;            // bf16 per key and channel
   constexpr int AST = ROWB + 8;           // LDS row stride of the key slab (bf16)
-  constexpr int SEGW = BN + 8 * XS;       // staged image row length
+  constexpr int SEGW = BNB + 8 * XS;      // staged image row length (multiple of 4)
   constexpr int NAU = ROWB / 16;          // uint4 per thread for the key slab (2 threads/key)
   constexpr int NSEG = (RP * SEGW + 255) / 256;
+  constexpr int QW = BNB / 4;             // four-candidate groups per slice
   __shared__ __align__(16) uint16_t As[BM * AST];
-  __shared__ __align__(16) uint16_t Bs[NS * BN * 8];
-  __shared__ float seg[RP * SEGW];
-  __shared__ float mup[BN];
+  __shared__ __align__(16) uint16_t Bs[NS * BNB * 8 + NS * BNB / 2];
+  __shared__ __align__(16) float seg[RP * SEGW];
+  __shared__ __align__(16) float mup[BNB];
   __shared__ float4 skm[BM];
 
   const int Hc = H - P + 1, Wc = W - P + 1;
-  const int ntc = (Wc + BN - 1) / BN;
+  const int ntc = (Wc + BNB - 1) / BNB;
   int b = blockIdx.x;
   const int ct = b % ntc;
   b /= ntc;
   const int r = b % Hc;
   const int kt = b / Hc;
-  const int c0 = ct * BN;
+  const int c0 = ct * BNB;
   const int kbase = kt * BM;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int l32 = lane & 31, lhi = lane >> 5;
   const int D = Cp * P * P;
-  const bool full = P == RP && P == 8 * XS;   // no padding rows or columns
 
-  if (tid < BN) {
-    const int col = c0 + tid;
-    mup[tid] = col < Wc ? cmeta[(size_t)r * Wc + col].x : 0.f;
+  for (int j = tid; j < BNB; j += 256) {
+    const int col = c0 + j;
+    mup[j] = col < Wc ? cmeta[(size_t)r * Wc + col].x : 0.f;
   }
   if (tid < BM) {
     const int g = kbase + tid;
@@ -501,11 +513,11 @@ k_match_bf16(const float* __restrict__ xp, int H, int W, int P, int Cp,
     }
   };
 
-  f32x16 acc[2][2];
+  f32x16 acc[2][NT];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < NT; ++j)
 #pragma unroll
       for (int q = 0; q < 16; ++q) acc[i][j][q] = 0.f;
 
@@ -520,72 +532,82 @@ k_match_bf16(const float* __restrict__ xp, int H, int W, int P, int Cp,
       if (e < RP * SEGW) seg[e] = rs[u];
     }
     __syncthreads();
-    for (int e = tid; e < NS * BN; e += 256) {
-      const int t = e / BN, j = e - t * BN;
+    // padding entries (dx >= P, or rows y >= P, staged as zeros) take
+    // finite values here and meet zeros in the key slices
+#pragma unroll
+    for (int w = tid; w < NS * QW; w += 256) {
+      const int t = w / QW, j0 = 4 * (w - t * QW);
       const int y = t / XS, xb = (t - y * XS) * 8;
-      const float m = mup[j];
-      const float* src = seg + y * SEGW + j + xb;
-      float v[8];
-      if (full) {
+      const float4* src = reinterpret_cast<const float4*>(seg + y * SEGW + j0 + xb);
+      const float4 f0 = src[0], f1 = src[1], f2 = src[2];
+      const float f[12] = {f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w,
+                           f2.x, f2.y, f2.z, f2.w};
+      const float4 m4 = *reinterpret_cast<const float4*>(mup + j0);
+      const float mm[4] = {m4.x, m4.y, m4.z, m4.w};
 #pragma unroll
-        for (int h = 0; h < 8; ++h) v[h] = src[h] - m;
-      } else {
+      for (int u = 0; u < 4; ++u) {
+        uint32_t wd[4];
 #pragma unroll
-        for (int h = 0; h < 8; ++h) v[h] = (xb + h < P && y < P) ? src[h] - m : 0.f;
+        for (int h = 0; h < 4; ++h)
+          wd[h] = __builtin_bit_cast(uint32_t, __builtin_convertvector(
+                      (f32x2){f[u + 2 * h] - mm[u], f[u + 2 * h + 1] - mm[u]},
+                      bf16x2));   // round to nearest even
+        const int row = t * BNB + j0 + u;
+        *reinterpret_cast<uint4*>(Bs + row * 8 + (row >> 4) * 8) =
+            make_uint4(wd[0], wd[1], wd[2], wd[3]);
       }
-      uint32_t w[4];
-#pragma unroll
-      for (int h = 0; h < 4; ++h)
-        w[h] = __builtin_bit_cast(uint32_t, __builtin_convertvector(
-                   (f32x2){v[2 * h], v[2 * h + 1]}, bf16x2));   // round to nearest even
-      *reinterpret_cast<uint4*>(Bs + (size_t)e * 8) = make_uint4(w[0], w[1], w[2], w[3]);
     }
     __syncthreads();
     if (ch + 1 < Cp) load_stage(ch + 1);
 #pragma unroll
     for (int kk = 0; kk < NS / 2; ++kk) {
       const int t = 2 * kk + lhi;
-      bf16x8 a[2], bb[2];
+      bf16x8 a[2], bb[NT];
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt)
         a[mt] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(
                     As + (wm * 64 + mt * 32 + l32) * AST + t * 8));
 #pragma unroll
-      for (int nt = 0; nt < 2; ++nt)
+      for (int nt = 0; nt < NT; ++nt) {
+        const int row = t * BNB + wn * (32 * NT) + nt * 32 + l32;
         bb[nt] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(
-                     Bs + ((size_t)t * BN + wn * 64 + nt * 32 + l32) * 8));
+                     Bs + row * 8 + (row >> 4) * 8));
+      }
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < 2; ++nt)
+        for (int nt = 0; nt < NT; ++nt)
           acc[mt][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mt], bb[nt], acc[mt][nt], 0, 0, 0);
     }
     __syncthreads();
   }
 
   // epilogue: d~ = ||a||^2 + ||pbar||^2 - 2 S + D dmu^2 + 2 dmu (sum a - sum pbar)
+  const bool all_keys = kbase + BM <= nk;   // block-uniform: no per-row test
 #pragma unroll
-  for (int mt = 0; mt < 2; ++mt)
+  for (int nt = 0; nt < NT; ++nt) {
+    const int col = c0 + wn * (32 * NT) + nt * 32 + l32;
+    if (col >= Wc) continue;
+    const size_t t = (size_t)r * Wc + col;
+    const float4 cm = cmeta[t];
 #pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
-      const int col = c0 + wn * 64 + nt * 32 + l32;
-      const bool cok = col < Wc;
-      const size_t t = (size_t)r * Wc + col;
-      const float4 cm = cok ? cmeta[t] : make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int i = wm * 64 + mt * 32 + 8 * (q >> 2) + 4 * lhi + (q & 3);
         const int g = kbase + i;
-        if (cok && g < nk) dist[(size_t)g * ldd + t] = centred_dist(skm[i], cm, acc[mt][nt][q], D);
+        if (all_keys || g < nk)
+          dist[(size_t)g * ldd + t] = centred_dist(skm[i], cm, acc[mt][nt][q], D);
       }
-    }
+  }
 }
 
 template <int NS>
 void launch_match_bf16_t(const glr_plan* pl, const float* xp, const uint16_t* Ab,
                          const float* kmb, const float* cmeta, int g0, int nk, float* dist,
                          hipStream_t s) {
-  const int ntc = (pl->Wc + BN - 1) / BN;
+  constexpr int BNB = 64 * bf16_nt(NS);
+  const int ntc = (pl->Wc + BNB - 1) / BNB;
   const int nkt = (nk + BM - 1) / BM;
   const size_t blocks = (size_t)nkt * pl->Hc * ntc;
   hipLaunchKernelGGL(k_match_bf16<NS>, dim3((unsigned)blocks), dim3(256), 0, s, xp, pl->H, pl->W,
