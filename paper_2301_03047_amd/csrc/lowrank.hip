@@ -249,9 +249,14 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
   for (int k = 0; k < KP; ++k) m[k] = (lane < K && k < K) ? Rl[k * LS + lane] : 0.f;
   const int Kp = K + (K & 1);
   const float tol = (float)K * 5.9604644775390625e-08f;
+  // a sweep whose rotations all had |cos| <= sqrt(tol) / 2 leaves
+  // off-diagonal terms of order tol / 4 (cyclic Jacobi converges
+  // quadratically), below the threshold: the sweep that would only confirm
+  // convergence is skipped
+  const float tol_last = 0.5f * sqrtf(tol);
   int sweeps = 0;
   for (int swp = 0; swp < max_sweeps; ++swp) {
-    bool rotated = false;
+    bool big = false;
     // squared column norm, exact at the start of a sweep; within the sweep a
     // rotation updates it in closed form (||a'||^2 = a1 - t g, ||b'||^2 =
     // a2 + t g), which only steers the angles: the singular values are
@@ -312,12 +317,12 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
       }
 #pragma unroll
       for (int k = 0; k < KP; ++k) m[k] = fmaf(sn, o[k], c * m[k]);
-      rotated = rotated || act;
+      big = big || (act && fabsf(ga) > tol_last * sqrtf(n1) * sqrtf(n2));
       if (lane > 0 && lane < Kp) mpos = mpos == 1 ? Kp - 1 : mpos - 1;
       roff = roff + 1 == Kp - 1 ? 0 : roff + 1;
     }
     sweeps = swp + 1;
-    if (__ballot(rotated) == 0) break;
+    if (__ballot(big) == 0) break;
   }
   __syncthreads();
 
