@@ -126,10 +126,15 @@ __global__ void k_nms(const long long* __restrict__ R, int H, int W, int P, uint
 }
 
 constexpr int SEL_T = 1024;
-constexpr int RUN = 16;           // consecutive positions per thread per scan step
+constexpr int RUN = 64;           // consecutive positions per thread per scan step
 
-// Ordered compaction of the positions t < n with flag[t] != 0 into list[];
-// optionally records their scores.  Returns the count (block-uniform).
+// number of non-zero bytes of a word whose bytes are 0 or 1
+__device__ __forceinline__ int ones4(uint32_t w) { return (int)((w * 0x01010101u) >> 24); }
+
+// Ordered compaction of the positions t < n with flag[t] != 0 (flags are 0
+// or 1) into list[]; optionally records their scores.  Each thread takes 64
+// consecutive flags, read as four 16-byte words.  Returns the count
+// (block-uniform).
 __device__ int ordered_compact(const uint8_t* __restrict__ flag, int n, int32_t* __restrict__ list,
                                int cap, long long* __restrict__ vals,
                                const long long* __restrict__ R, int W, int Wc, int o,
@@ -137,25 +142,44 @@ __device__ int ordered_compact(const uint8_t* __restrict__ flag, int n, int32_t*
   int S = 0;
   for (int base = 0; base < n; base += SEL_T * RUN) {
     const int t0 = base + threadIdx.x * RUN;
-    int c = 0;
-    for (int u = 0; u < RUN; ++u) {
-      const int t = t0 + u;
-      c += (t < n && flag[t]) ? 1 : 0;
-    }
-    int tot;
-    const int pre = block_excl_scan(c, scan_sh, &tot);
-    int w = S + pre;
-    for (int u = 0; u < RUN; ++u) {
-      const int t = t0 + u;
-      if (t < n && flag[t] && w < cap) {
-        list[w] = t;
-        if (vals) {
-          const int gr = t / Wc, gc = t - gr * Wc;
-          vals[w] = R[(size_t)(gr + o) * W + gc + o];
+    uint32_t w[RUN / 4];
+    if (t0 + RUN <= n) {
+#pragma unroll
+      for (int q = 0; q < RUN / 16; ++q) {
+        const uint4 v = *reinterpret_cast<const uint4*>(flag + t0 + 16 * q);
+        w[4 * q] = v.x; w[4 * q + 1] = v.y; w[4 * q + 2] = v.z; w[4 * q + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < RUN / 4; ++q) {
+        uint32_t x = 0u;
+        for (int b = 0; b < 4; ++b) {
+          const int t = t0 + 4 * q + b;
+          if (t < n) x |= (uint32_t)flag[t] << (8 * b);
         }
-        ++w;
+        w[q] = x;
       }
     }
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < RUN / 4; ++q) c += ones4(w[q]);
+    int tot;
+    const int pre = block_excl_scan(c, scan_sh, &tot);
+    int wr = S + pre;
+    if (c > 0)
+      for (int q = 0; q < RUN / 4; ++q)
+        for (int b = 0; b < 4; ++b)
+          if ((w[q] >> (8 * b)) & 0xffu) {
+            const int t = t0 + 4 * q + b;
+            if (wr < cap) {
+              list[wr] = t;
+              if (vals) {
+                const int gr = t / Wc, gc = t - gr * Wc;
+                vals[wr] = R[(size_t)(gr + o) * W + gc + o];
+              }
+            }
+            ++wr;
+          }
     S += tot;
   }
   return S;
@@ -172,7 +196,8 @@ __global__ void __launch_bounds__(SEL_T) k_select(uint8_t* __restrict__ flag,
   __shared__ int scan_sh[SEL_T / 64 + 1];
   __shared__ int hist[256];
   __shared__ unsigned long long s_prefix;
-  __shared__ int s_remaining;
+  __shared__ int s_remaining, s_top;
+  __shared__ unsigned long long s_mn[SEL_T / 64], s_mx[SEL_T / 64];
   const int o = (P - 1) / 2;
   const int Hc = H - P + 1, Wc = W - P + 1;
   const int Ncand = Hc * Wc;
@@ -180,21 +205,48 @@ __global__ void __launch_bounds__(SEL_T) k_select(uint8_t* __restrict__ flag,
   // A. ordered list of survivors and their scores
   const int S = ordered_compact(flag, Ncand, slist, Ncand, sval, R, W, Wc, o, scan_sh);
   __syncthreads();
-  // B. radix select (8 bits per pass, most significant first) of the N-th
-  //    largest score v*; need_eq = how many survivors equal to v* are taken
+  // B. radix select of the N-th largest score v* (scores are positive): the
+  //    bits above the highest bit in which the survivors' scores differ are
+  //    common, the rest is resolved in digits of up to 8 bits, most
+  //    significant first; need_eq = how many survivors equal to v* are taken
   if (S > N) {
-    if (tid == 0) {
-      s_prefix = 0ull;
-      s_remaining = N;
+    unsigned long long mn = ~0ull, mx = 0ull;
+    for (int i = tid; i < S; i += SEL_T) {
+      const unsigned long long v = (unsigned long long)sval[i];
+      mn = v < mn ? v : mn;
+      mx = v > mx ? v : mx;
     }
-    for (int shift = 56; shift >= 0; shift -= 8) {
+    for (int o2 = 32; o2 > 0; o2 >>= 1) {
+      const unsigned long long a = __shfl_xor(mn, o2, 64), b = __shfl_xor(mx, o2, 64);
+      mn = a < mn ? a : mn;
+      mx = b > mx ? b : mx;
+    }
+    if ((tid & 63) == 0) {
+      s_mn[tid >> 6] = mn;
+      s_mx[tid >> 6] = mx;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      unsigned long long a = s_mn[0], b = s_mx[0];
+      for (int i = 1; i < SEL_T / 64; ++i) {
+        a = s_mn[i] < a ? s_mn[i] : a;
+        b = s_mx[i] > b ? s_mx[i] : b;
+      }
+      const int top = a == b ? -1 : 63 - __builtin_clzll(a ^ b);
+      s_prefix = top < 0 ? a : (top == 63 ? 0ull : a & ~((2ull << top) - 1ull));
+      s_remaining = N;
+      s_top = top;
+    }
+    __syncthreads();
+    for (int top = s_top; top >= 0;) {
+      const int shift = top >= 7 ? top - 7 : 0;
+      const unsigned long long hmask = top == 63 ? 0ull : ~((2ull << top) - 1ull);
       if (tid < 256) hist[tid] = 0;
       __syncthreads();
       const unsigned long long prefix = s_prefix;
       for (int i = tid; i < S; i += SEL_T) {
         const unsigned long long v = (unsigned long long)sval[i];
-        const bool match = shift == 56 || ((v >> (shift + 8)) == (prefix >> (shift + 8)));
-        if (match) atomicAdd(&hist[(v >> shift) & 255u], 1);
+        if ((v & hmask) == (prefix & hmask)) atomicAdd(&hist[(v >> shift) & 255u], 1);
       }
       __syncthreads();
       if (tid < 64) {
@@ -218,6 +270,7 @@ __global__ void __launch_bounds__(SEL_T) k_select(uint8_t* __restrict__ flag,
         }
       }
       __syncthreads();
+      top = shift - 1;
     }
     const long long vstar = (long long)s_prefix;
     const int need_eq = s_remaining;
