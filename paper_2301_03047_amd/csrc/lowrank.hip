@@ -76,16 +76,15 @@ __device__ __forceinline__ void load_rows(const float* __restrict__ xp, const in
 // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), zeta = (a2 - a1) / (2 gamma),
 // written with one division; c = 1/sqrt(1 + t^2), s = c t.
 // FP64 reciprocal and reciprocal square root from the hardware estimates
-// plus two Newton steps (relative error far below the FP32 rounding the
-// rotation is applied with).
+// plus one Newton step (the estimates carry at least 22 correct bits, so the
+// relative error after the step is below 2^-40, far below the FP32 rounding
+// the rotation is applied with).
 __device__ __forceinline__ double rcp64(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = r * fma(-x, r, 2.0);
+  const double r = __builtin_amdgcn_rcp(x);
   return r * fma(-x, r, 2.0);
 }
 __device__ __forceinline__ double rsq64(double x) {
-  double r = __builtin_amdgcn_rsq(x);
-  r = r * fma(-0.5 * x, r * r, 1.5);
+  const double r = __builtin_amdgcn_rsq(x);
   return r * fma(-0.5 * x, r * r, 1.5);
 }
 
@@ -255,8 +254,17 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
   // convergence is skipped
   const float tol_last = 0.5f * sqrtf(tol);
   int sweeps = 0;
+  // Each column is held as sc * m: a rotation scales the pair by c and
+  // updates m with one FMA per entry (m += f o, f = -+t sc_o / sc); the scale
+  // is folded back into m at the start of every sweep (within a sweep it
+  // shrinks by at most 2^-(Kp-1)/2, far from underflow).
+  const float tol2 = tol * tol, tol_last2 = tol_last * tol_last;
+  float sc = 1.f;
   for (int swp = 0; swp < max_sweeps; ++swp) {
     bool big = false;
+#pragma unroll
+    for (int k = 0; k < KP; ++k) m[k] *= sc;
+    sc = 1.f;
     // squared column norm, exact at the start of a sweep; within the sweep a
     // rotation updates it in closed form (||a'||^2 = a1 - t g, ||b'||^2 =
     // a2 + t g), which only steers the angles: the singular values are
@@ -292,6 +300,7 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
 #pragma unroll
       for (int k = 0; k < KP; ++k) o[k] = __shfl(m[k], src, 64);
       const float be = __shfl(al, src, 64);
+      const float osc = __shfl(sc, src, 64);
       float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f;
 #pragma unroll
       for (int k = 0; k < KP; k += 4) {
@@ -300,30 +309,34 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
         g2 = fmaf(m[k + 2], o[k + 2], g2);
         g3 = fmaf(m[k + 3], o[k + 3], g3);
       }
-      const float ga = (g0 + g1) + (g2 + g3);    // same products and order in both lanes
+      // same products, order and scales in both lanes of a pair
+      const float ga = ((g0 + g1) + (g2 + g3)) * (sc * osc);
       const bool first = lane < q;
       const float n1 = first ? al : be;          // norm^2 of the lower-index column
       const float n2 = first ? be : al;
-      const bool act = q >= 0 && lane < K && q < K && ga != 0.f &&
-                       fabsf(ga) > tol * sqrtf(n1) * sqrtf(n2);
-      // branch-free rotation: the lower-index column takes c m - s o, the
-      // other s o + c m (both lanes of a pair share c, s)
-      float c = 1.f, sn = 0.f;
+      const float gg = ga * ga, nn = n1 * n2;
+      const bool act = q >= 0 && lane < K && q < K && ga != 0.f && gg > tol2 * nn;
+      // branch-free rotation: the lower-index column becomes c (a - t b),
+      // the other c (b + t a) (both lanes of a pair share c, t)
+      float c = 1.f, f = 0.f;
       if (act) {
         float s;
         const double t = jacobi_angle(n1, n2, ga, c, s);
-        sn = first ? -s : s;
+        f = (float)(first ? -t : t) * (osc / sc);
         al = fmaxf((float)(first ? (double)n1 - t * (double)ga : (double)n2 + t * (double)ga), 0.f);
       }
 #pragma unroll
-      for (int k = 0; k < KP; ++k) m[k] = fmaf(sn, o[k], c * m[k]);
-      big = big || (act && fabsf(ga) > tol_last * sqrtf(n1) * sqrtf(n2));
+      for (int k = 0; k < KP; ++k) m[k] = fmaf(f, o[k], m[k]);
+      sc *= c;
+      big = big || (act && gg > tol_last2 * nn);
       if (lane > 0 && lane < Kp) mpos = mpos == 1 ? Kp - 1 : mpos - 1;
       roff = roff + 1 == Kp - 1 ? 0 : roff + 1;
     }
     sweeps = swp + 1;
     if (__ballot(big) == 0) break;
   }
+#pragma unroll
+  for (int k = 0; k < KP; ++k) m[k] *= sc;
   __syncthreads();
 
   // ---- 3. singular values, WNNM factors, V into LDS (V[k][i] = column i / sigma_i)
