@@ -76,9 +76,10 @@ __device__ __forceinline__ void load_rows(const float* __restrict__ xp, const in
 // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), zeta = (a2 - a1) / (2 gamma),
 // written with one division; c = 1/sqrt(1 + t^2), s = c t.
 // FP64 reciprocal and reciprocal square root from the hardware estimates
-// plus one Newton step (the estimates carry at least 22 correct bits, so the
-// relative error after the step is below 2^-40, far below the FP32 rounding
-// the rotation is applied with).
+// plus one Newton step: the estimates are within about 2^-24 relative
+// (largest error over 2^20 inputs spread over 2^-40..2^40 on gfx950), so the
+// step leaves an error near 2^-48, far below the FP32 rounding the rotation
+// is applied with.
 __device__ __forceinline__ double rcp64(double x) {
   const double r = __builtin_amdgcn_rcp(x);
   return r * fma(-x, r, 2.0);
@@ -195,13 +196,10 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
       // tau = |v0| / ||v|| in [1, 2]) so that no step overflows however
       // small the column's residual is
       if (lane == k) {
-        float q0 = 0.f, q1 = 0.f;
+        float q[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};   // short dependency chains
 #pragma unroll
-        for (int i = 0; i < BR; i += 2) {
-          q0 = fmaf(b[i], b[i], q0);
-          q1 = fmaf(b[i + 1], b[i + 1], q1);
-        }
-        const float sig2 = q0 + q1;
+        for (int i = 0; i < BR; ++i) q[i & 7] = fmaf(b[i], b[i], q[i & 7]);
+        const float sig2 = ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
         const float x0 = Rl[k * LS + k];
         const float nrm = sqrtf(fmaf(x0, x0, sig2));
         float rv = 0.f, tau = 0.f, alpha = x0;
@@ -223,16 +221,11 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
       if (tau > 0.f && lane > k && lane < K) {
         float u[BR];
         load_vec(u, Cb);
-        float w0 = 0.f, w1 = 0.f, w2 = 0.f, w3 = 0.f;
+        float w[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int i = 0; i < BR; i += 4) {
-          w0 = fmaf(u[i], b[i], w0);
-          w1 = fmaf(u[i + 1], b[i + 1], w1);
-          w2 = fmaf(u[i + 2], b[i + 2], w2);
-          w3 = fmaf(u[i + 3], b[i + 3], w3);
-        }
+        for (int i = 0; i < BR; ++i) w[i & 7] = fmaf(u[i], b[i], w[i & 7]);
         const float rk = Rl[lane * LS + k];
-        const float sc = tau * (rk + ((w0 + w1) + (w2 + w3)));
+        const float sc = tau * (rk + (((w[0] + w[1]) + (w[2] + w[3])) + ((w[4] + w[5]) + (w[6] + w[7]))));
 #pragma unroll
         for (int i = 0; i < BR; ++i) b[i] = fmaf(-sc, u[i], b[i]);
         Rl[lane * LS + k] = rk - sc;
@@ -301,16 +294,12 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
       for (int k = 0; k < KP; ++k) o[k] = __shfl(m[k], src, 64);
       const float be = __shfl(al, src, 64);
       const float osc = __shfl(sc, src, 64);
-      float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f;
+      float gp[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int k = 0; k < KP; k += 4) {
-        g0 = fmaf(m[k], o[k], g0);
-        g1 = fmaf(m[k + 1], o[k + 1], g1);
-        g2 = fmaf(m[k + 2], o[k + 2], g2);
-        g3 = fmaf(m[k + 3], o[k + 3], g3);
-      }
+      for (int k = 0; k < KP; ++k) gp[k & 7] = fmaf(m[k], o[k], gp[k & 7]);
       // same products, order and scales in both lanes of a pair
-      const float ga = ((g0 + g1) + (g2 + g3)) * (sc * osc);
+      const float ga = ((((gp[0] + gp[1]) + (gp[2] + gp[3])) + ((gp[4] + gp[5]) + (gp[6] + gp[7])))) *
+                       (sc * osc);
       const bool first = lane < q;
       const float n1 = first ? al : be;          // norm^2 of the lower-index column
       const float n2 = first ? be : al;
