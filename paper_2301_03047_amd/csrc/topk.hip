@@ -222,7 +222,10 @@ k_topk_partial(const float* __restrict__ dist, size_t ldd, const float4* __restr
         float eps;
         if (pc) {
           const float w = cz * (kmu + mv[u][e]);
-          const float y = ((kr + pv[u][e]) + sqrtf(fmaxf(dv[u][e], 0.f))) + w;
+          // hardware square root (within 1 ulp; the bound's slack covers it)
+          // of max(d~, smallest normal), which is never below sqrt(max(d~, 0))
+          const float y =
+              ((kr + pv[u][e]) + __builtin_amdgcn_sqrtf(fmaxf(dv[u][e], 0x1p-126f))) + w;
           eps = fmaf(y, fmaf(coef2, y, w), w * w);
         } else {
           const float R = (kr + pv[u][e]) + cz * fabsf(kmu - mv[u][e]);
