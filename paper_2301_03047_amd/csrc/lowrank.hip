@@ -59,12 +59,19 @@ __device__ __forceinline__ void load_rows(const float* __restrict__ xp, const in
     } else {
       o = elem_off(d0 + i, P, W, HW);
     }
+    // all of a row's loads in flight at once (indices past K re-read the
+    // last member and are not stored); the sum runs in member order
     float s = 0.f;
-#pragma unroll 8
-    for (int j = 0; j < K; ++j) {
-      const float v = xp[o + spos[j]];
-      B[i * RS + j] = v;
-      s += v;
+    for (int jb = 0; jb < K; jb += 64) {
+      float v[64];
+#pragma unroll
+      for (int u = 0; u < 64; ++u) v[u] = xp[o + spos[min(jb + u, K - 1)]];
+#pragma unroll
+      for (int u = 0; u < 64; ++u)
+        if (jb + u < K) {
+          B[i * RS + jb + u] = v[u];
+          s += v[u];
+        }
     }
     for (int j = K; j < kpad; ++j) B[i * RS + j] = 0.f;
     smu[i] = s / (float)K;
@@ -201,13 +208,15 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
         for (int i = 0; i < BR; ++i) q[i & 7] = fmaf(b[i], b[i], q[i & 7]);
         const float sig2 = ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
         const float x0 = Rl[k * LS + k];
-        const float nrm = sqrtf(fmaf(x0, x0, sig2));
+        // hardware square root and reciprocals (within 1 ulp): the
+        // reflector stays orthogonal to working precision
+        const float nrm = __builtin_amdgcn_sqrtf(fmaf(x0, x0, sig2));
         float rv = 0.f, tau = 0.f, alpha = x0;
         if (sig2 > 0.f && nrm > 0.f) {
           alpha = x0 >= 0.f ? -nrm : nrm;
           const float v0 = x0 - alpha;        // |v0| = |x0| + nrm >= nrm
-          rv = 1.0f / v0;
-          tau = fabsf(v0) / nrm;
+          rv = __builtin_amdgcn_rcpf(v0);
+          tau = fabsf(v0) * __builtin_amdgcn_rcpf(nrm);
         }
         float u[BR];
 #pragma unroll
