@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-quality", action="store_true",
                     help="skip the full-length reconstruction that reports PSNR")
-    ap.add_argument("--cpu-iters", type=int, default=5, help="oracle iterations in the CPU sample")
+    ap.add_argument("--cpu-iters", type=int, default=16, help="oracle iterations in the CPU sample")
     ap.add_argument("--workload", default=WORKLOAD, choices=["mri_256", "cacti_1024", "msfa_512",
                                                               "cacti_128", "surrogate"])
     ap.add_argument("--precision", default=None, choices=["fp32", "bf16"],
