@@ -59,20 +59,25 @@ __device__ __forceinline__ void load_rows(const float* __restrict__ xp, const in
     } else {
       o = elem_off(d0 + i, P, W, HW);
     }
-    // all of a row's loads in flight at once (indices past K re-read the
-    // last member and are not stored); the sum runs in member order
-    float s = 0.f;
-    for (int jb = 0; jb < K; jb += 64) {
-      float v[64];
+    // all of a row's loads in flight at once: the 64 member positions come
+    // in 16-byte LDS reads (entries past K repeat the last member; their
+    // values are not stored); the sum runs in member order
+    int sp[64];
 #pragma unroll
-      for (int u = 0; u < 64; ++u) v[u] = xp[o + spos[min(jb + u, K - 1)]];
-#pragma unroll
-      for (int u = 0; u < 64; ++u)
-        if (jb + u < K) {
-          B[i * RS + jb + u] = v[u];
-          s += v[u];
-        }
+    for (int u = 0; u < 64; u += 4) {
+      const int4 t = *reinterpret_cast<const int4*>(spos + u);
+      sp[u] = t.x; sp[u + 1] = t.y; sp[u + 2] = t.z; sp[u + 3] = t.w;
     }
+    float v[64];
+#pragma unroll
+    for (int u = 0; u < 64; ++u) v[u] = xp[o + sp[u]];
+    float s = 0.f;
+#pragma unroll
+    for (int u = 0; u < 64; ++u)
+      if (u < K) {
+        B[i * RS + u] = v[u];
+        s += v[u];
+      }
     for (int j = K; j < kpad; ++j) B[i * RS + j] = 0.f;
     smu[i] = s / (float)K;
   }
@@ -140,6 +145,78 @@ __device__ __forceinline__ void load_vec(float (&v)[N], const float* src) {
   }
 }
 
+// Folds one streamed chunk of nb <= NB rows (in Bl, row means in smu) into
+// the running triangular factor R (Rl[j*LS + i] = R[i][j]) by K Householder
+// reflections on [R; chunk].  NB is the chunk height rounded up to a power
+// of two, so a short last chunk does not run the full-height loops (the
+// padding rows are zero and would not change any sum).
+template <int NB>
+__device__ __forceinline__ void qr_chunk(float* Rl, const float* Bl, const float* smu, float* Cb,
+                                         int nb, int K, int lane, int& fe, bool& fset) {
+  float b[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) b[i] = (i < nb && lane < K) ? Bl[i * LS + lane] - smu[i] : 0.f;
+  if (!fset) {
+    float mx = 0.f;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) mx = fmaxf(mx, fabsf(b[i]));
+    mx = wave_max(mx);
+    if (mx > 0.f) {
+      int e;
+      frexpf(mx, &e);                       // mx = f 2^e, f in [0.5, 1)
+      fe = min(1 - e, 126);
+      fset = true;
+    }
+  }
+  const float fs = ldexpf(1.f, fe);
+#pragma unroll
+  for (int i = 0; i < NB; ++i) b[i] *= fs;
+  for (int k = 0; k < K; ++k) {
+    // lane k builds the reflector that zeroes its chunk column below
+    // R[k][k], normalised to a unit leading entry (u = v / v0, scale
+    // tau = |v0| / ||v|| in [1, 2]) so that no step overflows however
+    // small the column's residual is
+    if (lane == k) {
+      float q[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};   // short dependency chains
+#pragma unroll
+      for (int i = 0; i < NB; ++i) q[i & 7] = fmaf(b[i], b[i], q[i & 7]);
+      const float sig2 = ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
+      const float x0 = Rl[k * LS + k];
+      // hardware square root and reciprocals (within 1 ulp): the
+      // reflector stays orthogonal to working precision
+      const float nrm = __builtin_amdgcn_sqrtf(fmaf(x0, x0, sig2));
+      float rv = 0.f, tau = 0.f, alpha = x0;
+      if (sig2 > 0.f && nrm > 0.f) {
+        alpha = x0 >= 0.f ? -nrm : nrm;
+        const float v0 = x0 - alpha;        // |v0| = |x0| + nrm >= nrm
+        rv = __builtin_amdgcn_rcpf(v0);
+        tau = fabsf(v0) * __builtin_amdgcn_rcpf(nrm);
+      }
+      float u[NB];
+#pragma unroll
+      for (int i = 0; i < NB; ++i) u[i] = b[i] * rv;
+      store_vec(Cb, u);
+      Cb[NB] = tau;
+      Rl[k * LS + k] = alpha;
+    }
+    wave_sync();
+    const float tau = Cb[NB];
+    if (tau > 0.f && lane > k && lane < K) {
+      float u[NB];
+      load_vec(u, Cb);
+      float w[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int i = 0; i < NB; ++i) w[i & 7] = fmaf(u[i], b[i], w[i & 7]);
+      const float rk = Rl[lane * LS + k];
+      const float sc = tau * (rk + (((w[0] + w[1]) + (w[2] + w[3])) + ((w[4] + w[5]) + (w[6] + w[7]))));
+#pragma unroll
+      for (int i = 0; i < NB; ++i) b[i] = fmaf(-sc, u[i], b[i]);
+      Rl[lane * LS + k] = rk - sc;
+    }
+    wave_sync();
+  }
+}
+
 template <int KP>
 __global__ void __launch_bounds__(64)
 k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* __restrict__ idx,
@@ -152,7 +229,7 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
   __shared__ __align__(16) float Bl[BLN];
   __shared__ __align__(16) float Cb[BR + 4];    // broadcast reflector u, its scale tau at [BR]
   __shared__ float smu[64];
-  __shared__ int spos[64];
+  __shared__ __align__(16) int spos[64];
   __shared__ float sw[64];
   __shared__ float ssig[64];
 
@@ -161,8 +238,9 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
   const int Wc = W - P + 1;
   const size_t HW = (size_t)H * W;
 
-  if (lane < K) {
-    const int t = idx[(size_t)g * K + lane];
+  {
+    // lanes past K repeat the last member's position (K <= 64)
+    const int t = idx[(size_t)g * K + min(lane, K - 1)];
     const int r = t / Wc, c = t - r * Wc;
     spos[lane] = r * W + c;
   }
@@ -179,68 +257,10 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
   for (int d0 = 0; d0 < D; d0 += BR) {
     const int nb = min(BR, D - d0);
     load_rows(xp, spos, d0, nb, K, P, W, HW, Bl, smu);
-    float b[BR];
-#pragma unroll
-    for (int i = 0; i < BR; ++i) b[i] = (i < nb && lane < K) ? Bl[i * LS + lane] - smu[i] : 0.f;
-    if (!fset) {
-      float mx = 0.f;
-#pragma unroll
-      for (int i = 0; i < BR; ++i) mx = fmaxf(mx, fabsf(b[i]));
-      mx = wave_max(mx);
-      if (mx > 0.f) {
-        int e;
-        frexpf(mx, &e);                       // mx = f 2^e, f in [0.5, 1)
-        fe = min(1 - e, 126);
-        fset = true;
-      }
-    }
-    const float fs = ldexpf(1.f, fe);
-#pragma unroll
-    for (int i = 0; i < BR; ++i) b[i] *= fs;
-    for (int k = 0; k < K; ++k) {
-      // lane k builds the reflector that zeroes its chunk column below
-      // R[k][k], normalised to a unit leading entry (u = v / v0, scale
-      // tau = |v0| / ||v|| in [1, 2]) so that no step overflows however
-      // small the column's residual is
-      if (lane == k) {
-        float q[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};   // short dependency chains
-#pragma unroll
-        for (int i = 0; i < BR; ++i) q[i & 7] = fmaf(b[i], b[i], q[i & 7]);
-        const float sig2 = ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
-        const float x0 = Rl[k * LS + k];
-        // hardware square root and reciprocals (within 1 ulp): the
-        // reflector stays orthogonal to working precision
-        const float nrm = __builtin_amdgcn_sqrtf(fmaf(x0, x0, sig2));
-        float rv = 0.f, tau = 0.f, alpha = x0;
-        if (sig2 > 0.f && nrm > 0.f) {
-          alpha = x0 >= 0.f ? -nrm : nrm;
-          const float v0 = x0 - alpha;        // |v0| = |x0| + nrm >= nrm
-          rv = __builtin_amdgcn_rcpf(v0);
-          tau = fabsf(v0) * __builtin_amdgcn_rcpf(nrm);
-        }
-        float u[BR];
-#pragma unroll
-        for (int i = 0; i < BR; ++i) u[i] = b[i] * rv;
-        store_vec(Cb, u);
-        Cb[BR] = tau;
-        Rl[k * LS + k] = alpha;
-      }
-      wave_sync();
-      const float tau = Cb[BR];
-      if (tau > 0.f && lane > k && lane < K) {
-        float u[BR];
-        load_vec(u, Cb);
-        float w[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int i = 0; i < BR; ++i) w[i & 7] = fmaf(u[i], b[i], w[i & 7]);
-        const float rk = Rl[lane * LS + k];
-        const float sc = tau * (rk + (((w[0] + w[1]) + (w[2] + w[3])) + ((w[4] + w[5]) + (w[6] + w[7]))));
-#pragma unroll
-        for (int i = 0; i < BR; ++i) b[i] = fmaf(-sc, u[i], b[i]);
-        Rl[lane * LS + k] = rk - sc;
-      }
-      wave_sync();
-    }
+    if (nb > 32) qr_chunk<64>(Rl, Bl, smu, Cb, nb, K, lane, fe, fset);
+    else if (nb > 16) qr_chunk<32>(Rl, Bl, smu, Cb, nb, K, lane, fe, fset);
+    else if (nb > 8) qr_chunk<16>(Rl, Bl, smu, Cb, nb, K, lane, fe, fset);
+    else qr_chunk<8>(Rl, Bl, smu, Cb, nb, K, lane, fe, fset);
     __syncthreads();
   }
 
@@ -320,7 +340,7 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
       if (act) {
         float s;
         const double t = jacobi_angle(n1, n2, ga, c, s);
-        f = (float)(first ? -t : t) * (osc / sc);
+        f = (float)(first ? -t : t) * (osc * __builtin_amdgcn_rcpf(sc));   // rcp within 1 ulp
         al = fmaxf((float)(first ? (double)n1 - t * (double)ga : (double)n2 + t * (double)ga), 0.f);
       }
 #pragma unroll
