@@ -25,6 +25,8 @@
 #include "common.h"
 #include "internal.h"
 
+#include <type_traits>
+
 namespace {
 
 constexpr int LS = 65;           // LDS stride (conflict-free column/row access)
@@ -115,6 +117,20 @@ __device__ __forceinline__ double jacobi_angle(float a1, float a2, float ga, flo
   c = (float)cs;
   s = (float)(cs * t);
   return t;
+}
+
+// The value held by lane ^ 1 (a DPP quad permutation: no LDS traffic).
+__device__ __forceinline__ float lane_xor1(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, true));
+}
+
+// The value held by lane + 1 where up, else by lane - 1 (DPP shifts of the
+// whole wave by one lane); a read past either end of the wave gives 0.
+__device__ __forceinline__ float lane_shift_pair(float v, bool up) {
+  const int x = __builtin_bit_cast(int, v);
+  const int hi = __builtin_amdgcn_mov_dpp(x, 0x130, 0xF, 0xF, true);   // wave_shl:1, zero fill
+  const int lo = __builtin_amdgcn_mov_dpp(x, 0x138, 0xF, 0xF, true);   // wave_shr:1, zero fill
+  return __builtin_bit_cast(float, up ? hi : lo);
 }
 
 // LDS ordering between lanes of the one wave that runs a group.
@@ -277,11 +293,12 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
   const float tol_last = 0.5f * sqrtf(tol);
   int sweeps = 0;
   // Each column is held as sc * m: a rotation scales the pair by c and
-  // updates m with one FMA per entry (m += f o, f = -+t sc_o / sc); the scale
-  // is folded back into m at the start of every sweep (within a sweep it
-  // shrinks by at most 2^-(Kp-1)/2, far from underflow).
+  // updates m with one FMA per entry (m' = o + f m, f = +-t sc / sc_o); the
+  // scale is folded back into m at the start of every sweep (within a sweep
+  // it shrinks by at most 2^-Kp/2, far from underflow).
   const float tol2 = tol * tol, tol_last2 = tol_last * tol_last;
   float sc = 1.f;
+  int cid = lane;                              // the column of M this lane holds
   for (int swp = 0; swp < max_sweeps; ++swp) {
     bool big = false;
 #pragma unroll
@@ -303,26 +320,37 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
       }
       al = (a0 + a1) + (a2 + a3);
     }
-    // round-robin tournament: position 0 holds lane 0, positions 1..Kp-1
-    // rotate by one per round; position p meets position Kp-1-p
-    int mpos = lane;                          // this lane's position (lane < Kp)
-    int roff = 0;                             // r mod (Kp - 1)
-    for (int r = 0; r < Kp - 1; ++r) {
-      int q = -1;
-      if (lane < Kp) {
-        const int ppos = Kp - 1 - mpos;
-        int v = ppos - 1 + roff;
-        if (v >= Kp - 1) v -= Kp - 1;
-        q = ppos == 0 ? 0 : 1 + v;
-      }
-      // the partner's column and squared norm through the cross-lane
-      // permute (no LDS round trip, no barrier)
-      const int src = q < 0 ? lane : q;
+    // odd-even transposition ordering: even rounds pair lanes (2i, 2i+1),
+    // odd rounds (2i+1, 2i+2); after its rotation a pair's two columns trade
+    // lanes, so in Kp rounds every column passes every other exactly once
+    // (the ordering is equivalent to the cyclic one).  The partner column
+    // arrives by a DPP lane shift (no LDS traffic); lanes at or past Kp hold
+    // zero columns that stay zero, and the out-of-range lanes of a shift read 0.
+    // (an even and an odd round per iteration, so the rotated columns stay
+    // in the registers the exchange wrote, with no copy per round)
+    auto round = [&](auto oddc) {
+      constexpr bool odd = decltype(oddc)::value;
+      const int q = odd ? ((lane & 1) ? lane + 1 : lane - 1) : (lane ^ 1);
+      const bool paired = lane < Kp && q >= 0 && q < Kp;
+      // odd rounds: odd lanes (and the idle ones past Kp) read lane + 1,
+      // even lanes lane - 1
+      const bool up = (lane & 1) || lane >= Kp;
       float o[KP];
+      float be, osc;
+      int ocid;
+      if constexpr (odd) {
 #pragma unroll
-      for (int k = 0; k < KP; ++k) o[k] = __shfl(m[k], src, 64);
-      const float be = __shfl(al, src, 64);
-      const float osc = __shfl(sc, src, 64);
+        for (int k = 0; k < KP; ++k) o[k] = lane_shift_pair(m[k], up);
+        be = lane_shift_pair(al, up);
+        osc = lane_shift_pair(sc, up);
+        ocid = __builtin_bit_cast(int, lane_shift_pair(__builtin_bit_cast(float, cid), up));
+      } else {
+#pragma unroll
+        for (int k = 0; k < KP; ++k) o[k] = lane_xor1(m[k]);
+        be = lane_xor1(al);
+        osc = lane_xor1(sc);
+        ocid = __builtin_bit_cast(int, lane_xor1(__builtin_bit_cast(float, cid)));
+      }
       float gp[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int k = 0; k < KP; ++k) gp[k & 7] = fmaf(m[k], o[k], gp[k & 7]);
@@ -330,25 +358,32 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
       const float ga = ((((gp[0] + gp[1]) + (gp[2] + gp[3])) + ((gp[4] + gp[5]) + (gp[6] + gp[7])))) *
                        (sc * osc);
       const bool first = lane < q;
-      const float n1 = first ? al : be;          // norm^2 of the lower-index column
+      const float n1 = first ? al : be;          // norm^2 of the lower lane's column
       const float n2 = first ? be : al;
       const float gg = ga * ga, nn = n1 * n2;
-      const bool act = q >= 0 && lane < K && q < K && ga != 0.f && gg > tol2 * nn;
-      // branch-free rotation: the lower-index column becomes c (a - t b),
-      // the other c (b + t a) (both lanes of a pair share c, t)
+      const bool act = paired && ga != 0.f && gg > tol2 * nn;
+      // the lower lane takes the other column's update c (b + t a), the upper
+      // lane c (a - t b): new m = o + f m, new scale c times the partner's
       float c = 1.f, f = 0.f;
+      double t = 0.0;
       if (act) {
         float s;
-        const double t = jacobi_angle(n1, n2, ga, c, s);
-        f = (float)(first ? -t : t) * (osc * __builtin_amdgcn_rcpf(sc));   // rcp within 1 ulp
-        al = fmaxf((float)(first ? (double)n1 - t * (double)ga : (double)n2 + t * (double)ga), 0.f);
+        t = jacobi_angle(n1, n2, ga, c, s);
+        f = (float)(first ? t : -t) * (sc * __builtin_amdgcn_rcpf(osc));   // rcp within 1 ulp
       }
+      if (!paired) f = 1.f;                      // o is 0 here: m stays
 #pragma unroll
-      for (int k = 0; k < KP; ++k) m[k] = fmaf(f, o[k], m[k]);
-      sc *= c;
+      for (int k = 0; k < KP; ++k) m[k] = fmaf(f, m[k], o[k]);
+      if (paired) {
+        al = fmaxf((float)(first ? (double)n2 + t * (double)ga : (double)n1 - t * (double)ga), 0.f);
+        sc = c * osc;
+        cid = ocid;
+      }
       big = big || (act && gg > tol_last2 * nn);
-      if (lane > 0 && lane < Kp) mpos = mpos == 1 ? Kp - 1 : mpos - 1;
-      roff = roff + 1 == Kp - 1 ? 0 : roff + 1;
+    };
+    for (int r = 0; r < Kp; r += 2) {
+      round(std::false_type{});
+      round(std::true_type{});
     }
     sweeps = swp + 1;
     if (__ballot(big) == 0) break;
@@ -366,24 +401,27 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
   }
   const float ss = sqrtf(s2a + s2b);           // singular value of the scaled group
   const float s = ldexpf(ss, -fe);
-  if (lane < K) {
+  // the columns sit in lanes 0..Kp-1 in some order; for odd K one of them
+  // is the zero padding column (cid == K), whose w is 0 and which is left
+  // out of the singular-value list
+  if (lane < Kp) {
     const float shat = sqrtf(fmaxf(s * s - (float)K * sigma * sigma, 0.f));
     const float tau = wc * sqrtf((float)K) * sigma * sigma / (shat + weps);
     const float sn = fmaxf(s - tau, 0.f);
-    ssig[lane] = ss;
+    ssig[lane] = cid < K ? ss : -1.f;
     sw[lane] = s > 0.f ? (s - sn) / s : 0.f;
   }
-  // V rows and columns past K are written as zeros: the products below run
-  // over all KP entries, and 0 times stale LDS contents could be NaN
+  // V rows and columns past K (past Kp) are written as zeros: the products
+  // below run over all KP entries, and 0 times stale LDS contents could be NaN
   if (lane < KP) {
-    const float inv = (lane < K && ss > 0.f) ? 1.0f / ss : 0.f;
+    const float inv = (lane < Kp && ss > 0.f) ? 1.0f / ss : 0.f;
 #pragma unroll
-    for (int k = 0; k < KP; ++k) Bl[k * XS + lane] = (lane < K && k < K) ? m[k] * inv : 0.f;
+    for (int k = 0; k < KP; ++k) Bl[k * XS + lane] = (lane < Kp && k < K) ? m[k] * inv : 0.f;
   }
   __syncthreads();
-  if (sv && lane < K) {
+  if (sv && lane < Kp && cid < K) {
     int rank = 0;
-    for (int i = 0; i < K; ++i) rank += (ssig[i] > ss || (ssig[i] == ss && i < lane)) ? 1 : 0;
+    for (int i = 0; i < Kp; ++i) rank += (ssig[i] > ss || (ssig[i] == ss && i < lane)) ? 1 : 0;
     sv[(size_t)g * K + rank] = s;
   }
   if (lane == 0 && st) {
@@ -396,7 +434,7 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
     float vb[KP];
     load_vec(vb, Bl + lane * XS);
 #pragma unroll
-    for (int i = 0; i < KP; ++i) vb[i] = (lane < K && i < K) ? vb[i] * sw[i] : 0.f;
+    for (int i = 0; i < KP; ++i) vb[i] = (lane < K && i < Kp) ? vb[i] * sw[i] : 0.f;
     if (lane < K)
       for (int a = 0; a < K; ++a) {
         float va[KP];
