@@ -143,15 +143,17 @@ __device__ int wave_compact(int* bj, float* bu, float* bl, int n, float T) {
 //    distance.
 // tsh[g]: the key's shared bound of T (ordered bits, +inf at launch), lowered
 // with atomicMin by every range.
+template <int U4, int WCAP>
 __global__ void __launch_bounds__(256)
 k_topk_partial(const float* __restrict__ dist, size_t ldd, const float4* __restrict__ km,
                const int32_t* __restrict__ kmap, int g0, const float* __restrict__ cm, int Ncand,
                int split_len, int S, int nk, int K, int pc, float coef, float coef2, float cz,
                uint32_t* __restrict__ tsh, int32_t* __restrict__ lj, float* __restrict__ lu,
                float* __restrict__ ll, int32_t* __restrict__ lcnt) {
-  __shared__ int sbj[4][CAP];
-  __shared__ float sbu[4][CAP];
-  __shared__ float sbl[4][CAP];
+  static_assert(WCAP >= 512 && WCAP <= CAP, "wave buffer size");
+  __shared__ int sbj[4][WCAP];
+  __shared__ float sbu[4][WCAP];
+  __shared__ float sbl[4][WCAP];
   __shared__ int shist[4][256];
   const int wave = threadIdx.x >> 6;
   const int l = lane_id();
@@ -177,12 +179,13 @@ k_topk_partial(const float* __restrict__ dist, size_t ldd, const float4* __restr
   float T = __int_as_float(0x7f800000);     // +inf
   int cnt = 0;
   bool ovf = false;
-  // 1024 candidates per chunk (four float4 loads of d~ and of ||p|| per
-  // lane); the next chunk's loads are issued before the current chunk is
-  // processed.  One ballot rejects a chunk in the common case where no
-  // element can enter the margin set.
-  constexpr int U4 = 4;
+  // 256 U4 candidates per chunk (U4 float4 loads of d~ and 2 U4 of the
+  // candidate bound terms per lane); the next chunk's loads are issued before
+  // the current chunk is processed.  One ballot rejects a chunk in the common
+  // case where no element can enter the margin set.  WCAP entries of wave
+  // buffer: the first chunk's first WCAP candidates seed T.
   constexpr int CH = 256 * U4;
+  constexpr int SU = WCAP / 256 < U4 ? WCAP / 256 : U4;   // chunk blocks that seed T
   // pv: ||pbar_j||; mv: mu_j
   float dv[U4][4], pv[U4][4], mv[U4][4], dn[U4][4], pn[U4][4], mn[U4][4];
   auto load = [&](int base, float (&d)[U4][4], float (&p)[U4][4], float (&m)[U4][4]) {
@@ -239,11 +242,11 @@ k_topk_partial(const float* __restrict__ dist, size_t ldd, const float4* __restr
       // seed T with the K-th smallest U of the first chunk (an upper bound of
       // the range's K-th smallest U)
 #pragma unroll
-      for (int u = 0; u < U4; ++u)
+      for (int u = 0; u < SU; ++u)
 #pragma unroll
         for (int e = 0; e < 4; ++e)
           bu[(u * 64 + l) * 4 + e] = ok[u][e] ? Uv[u][e] : __int_as_float(0x7f800000);
-      T = share(wave_kth_smallest(bu, CH, K, hist));
+      T = share(wave_kth_smallest(bu, SU * 256, K, hist));
     } else if ((((base - j0) / CH) & 7) == 0) {
       T = share(T);                         // take up other ranges' progress
     }
@@ -268,11 +271,11 @@ k_topk_partial(const float* __restrict__ dist, size_t ldd, const float4* __restr
           cnt += __popcll(m);
         }
         // room for the next 256 entries, else tighten T and compact
-        if (cnt > CAP - 256) {
+        if (cnt > WCAP - 256) {
           const float Tn = wave_kth_smallest(bu, cnt, K, hist);
           T = share(fminf(T, Tn));
           cnt = wave_compact(bj, bu, bl, cnt, T);
-          if (cnt > CAP - 256) {
+          if (cnt > WCAP - 256) {
             ovf = true;
             break;
           }
@@ -773,9 +776,19 @@ void launch_topk_partial(const glr_plan* pl, const float* dist, const float* kmb
   }
   launch_fill_u32(tsh, 0xffffffffu, (size_t)nk, s);
   const int items = nk * pl->n_split;
-  hipLaunchKernelGGL(k_topk_partial, dim3((items + 3) / 4), dim3(256), 0, s, dist,
-                     (size_t)pl->ldd, (const float4*)kmb, kmap, g0, cm2, pl->Ncand, pl->split_len,
-                     pl->n_split, nk, pl->K, bf16 ? 0 : 1, coef, coef2, cz, tsh, lj, lu, ll, lcnt);
+  // the FP32 form's margin sets stay far below the BF16 form's: a smaller
+  // wave buffer and 768-candidate steps (fewer registers) fit four waves per
+  // SIMD instead of three
+  if (bf16)
+    hipLaunchKernelGGL((k_topk_partial<4, CAP>), dim3((items + 3) / 4), dim3(256), 0, s, dist,
+                       (size_t)pl->ldd, (const float4*)kmb, kmap, g0, cm2, pl->Ncand,
+                       pl->split_len, pl->n_split, nk, pl->K, 0, coef, coef2, cz, tsh, lj, lu, ll,
+                       lcnt);
+  else
+    hipLaunchKernelGGL((k_topk_partial<3, 512>), dim3((items + 3) / 4),
+                       dim3(256), 0, s, dist, (size_t)pl->ldd, (const float4*)kmb, kmap, g0, cm2,
+                       pl->Ncand, pl->split_len, pl->n_split, nk, pl->K, 1, coef, coef2, cz, tsh,
+                       lj, lu, ll, lcnt);
 }
 
 // Lanes per candidate of the exact rescoring: the fewest (>= 8) that keep
