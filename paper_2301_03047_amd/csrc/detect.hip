@@ -185,9 +185,12 @@ __device__ int ordered_compact(const uint8_t* __restrict__ flag, int n, int32_t*
   return S;
 }
 
+constexpr int SEL_R = 4;          // survivor scores held in registers per thread
+
 // Single workgroup: ordered selection of the best N survivors by
 // (R25 desc, position asc), uniform raster fill, ascending key list.
-// `flag` holds the NMS survivors on entry and the chosen set on exit.
+// `flag` holds the NMS survivors on entry (and, when there are fewer than N,
+// the survivors plus the raster fill on exit).
 __global__ void __launch_bounds__(SEL_T) k_select(uint8_t* __restrict__ flag,
                                                   const long long* __restrict__ R, int H, int W,
                                                   int P, int N, int32_t* __restrict__ slist,
@@ -202,20 +205,58 @@ __global__ void __launch_bounds__(SEL_T) k_select(uint8_t* __restrict__ flag,
   const int Hc = H - P + 1, Wc = W - P + 1;
   const int Ncand = Hc * Wc;
   const int tid = threadIdx.x;
-  // A. ordered list of survivors and their scores
-  const int S = ordered_compact(flag, Ncand, slist, Ncand, sval, R, W, Wc, o, scan_sh);
+  // A. ordered list of survivors, then their scores: survivor i = tid +
+  //    k SEL_T is read by this thread (all reads in flight together) and kept
+  //    in registers when S <= SEL_T SEL_R, else written to sval
+  const int S = ordered_compact(flag, Ncand, slist, Ncand, nullptr, R, W, Wc, o, scan_sh);
   __syncthreads();
+  const bool in_reg = S <= SEL_T * SEL_R;
+  unsigned long long rv[SEL_R];
+  if (S > N) {
+    for (int base = 0; base < S; base += SEL_T * SEL_R) {
+      int pos[SEL_R];
+#pragma unroll
+      for (int k = 0; k < SEL_R; ++k) {
+        const int i = base + k * SEL_T + tid;
+        pos[k] = i < S ? slist[i] : -1;
+      }
+#pragma unroll
+      for (int k = 0; k < SEL_R; ++k) {
+        const int t = pos[k] < 0 ? 0 : pos[k];
+        const int gr = t / Wc, gc = t - gr * Wc;
+        rv[k] = pos[k] < 0 ? 0ull : (unsigned long long)R[(size_t)(gr + o) * W + gc + o];
+      }
+      if (!in_reg)
+#pragma unroll
+        for (int k = 0; k < SEL_R; ++k) {
+          const int i = base + k * SEL_T + tid;
+          if (i < S) sval[i] = (long long)rv[k];
+        }
+    }
+    if (!in_reg) __syncthreads();
+  }
+  // visits every survivor score of this thread (i ascending per thread)
+  auto each = [&](auto&& f) {
+    if (in_reg) {
+#pragma unroll
+      for (int k = 0; k < SEL_R; ++k) {
+        const int i = k * SEL_T + tid;
+        if (i < S) f(rv[k]);
+      }
+    } else {
+      for (int i = tid; i < S; i += SEL_T) f((unsigned long long)sval[i]);
+    }
+  };
   // B. radix select of the N-th largest score v* (scores are positive): the
   //    bits above the highest bit in which the survivors' scores differ are
   //    common, the rest is resolved in digits of up to 8 bits, most
   //    significant first; need_eq = how many survivors equal to v* are taken
   if (S > N) {
     unsigned long long mn = ~0ull, mx = 0ull;
-    for (int i = tid; i < S; i += SEL_T) {
-      const unsigned long long v = (unsigned long long)sval[i];
+    each([&](unsigned long long v) {
       mn = v < mn ? v : mn;
       mx = v > mx ? v : mx;
-    }
+    });
     for (int o2 = 32; o2 > 0; o2 >>= 1) {
       const unsigned long long a = __shfl_xor(mn, o2, 64), b = __shfl_xor(mx, o2, 64);
       mn = a < mn ? a : mn;
@@ -244,10 +285,9 @@ __global__ void __launch_bounds__(SEL_T) k_select(uint8_t* __restrict__ flag,
       if (tid < 256) hist[tid] = 0;
       __syncthreads();
       const unsigned long long prefix = s_prefix;
-      for (int i = tid; i < S; i += SEL_T) {
-        const unsigned long long v = (unsigned long long)sval[i];
+      each([&](unsigned long long v) {
         if ((v & hmask) == (prefix & hmask)) atomicAdd(&hist[(v >> shift) & 255u], 1);
-      }
+      });
       __syncthreads();
       if (tid < 64) {
         // wave 0: lane l owns bins 255-4l .. 252-4l (descending), so a prefix
@@ -272,29 +312,42 @@ __global__ void __launch_bounds__(SEL_T) k_select(uint8_t* __restrict__ flag,
       __syncthreads();
       top = shift - 1;
     }
-    const long long vstar = (long long)s_prefix;
+    const unsigned long long vstar = s_prefix;
     const int need_eq = s_remaining;
-    // C. drop survivors below v* and the surplus ties (highest positions)
-    int eq_seen = 0;
-    for (int base = 0; base < S; base += SEL_T) {
-      const int i = base + tid;
-      const long long v = (i < S) ? sval[i] : 0;
+    // C. keep the survivors above v* and the first need_eq equal to it (the
+    //    lowest positions); they are the key list, in ascending position
+    int eq_seen = 0, sel_seen = 0;
+    for (int k = 0; k * SEL_T < S; ++k) {
+      const int i = k * SEL_T + tid;
+      unsigned long long v = 0ull;
+      if (in_reg) {
+#pragma unroll
+        for (int q = 0; q < SEL_R; ++q)
+          if (q == k) v = rv[q];
+      } else if (i < S) {
+        v = (unsigned long long)sval[i];
+      }
       const int is_eq = (i < S && v == vstar) ? 1 : 0;
       int tot;
       const int pre = block_excl_scan(is_eq, scan_sh, &tot);
-      if (i < S) {
-        const bool sel = v > vstar || (is_eq && eq_seen + pre < need_eq);
-        if (!sel) flag[slist[i]] = 0;
-      }
+      const int sel = (i < S && (v > vstar || (is_eq && eq_seen + pre < need_eq))) ? 1 : 0;
+      int tsel;
+      const int spre = block_excl_scan(sel, scan_sh, &tsel);
+      if (sel) keys[sel_seen + spre] = slist[i];
       eq_seen += tot;
+      sel_seen += tsel;
     }
+    if (tid == 0 && st) st->keys_selected = N;
+    return;
   }
-  const int n_sel = S < N ? S : N;
-  if (tid == 0 && st) st->keys_selected = n_sel;
-  __syncthreads();
+  if (tid == 0 && st) st->keys_selected = S;
+  if (S == N) {
+    for (int i = tid; i < S; i += SEL_T) keys[i] = slist[i];
+    return;
+  }
   // D. uniform raster fill (step s, then step 1) of positions not chosen
-  int need = N - n_sel;
-  if (need > 0) {
+  int need = N - S;
+  {
     int s = 1;
     while ((long long)s * s * N < (long long)Ncand) ++s;
     for (int pass = 0; pass < 2 && need > 0; ++pass) {
