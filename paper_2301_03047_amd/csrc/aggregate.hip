@@ -297,7 +297,6 @@ void launch_aggregate(const glr_plan* pl, const float* xbar, const int32_t* idx,
   int32_t* cnt = sortbuf + pl->M2;              // [Ncand + 1], later the scatter cursor
   int32_t* bsum = cnt + ((size_t)n + 63) / 64 * 64;
   const int nb = (n + SE - 1) / SE;
-  launch_fill_u32((uint32_t*)cnt, 0u, (size_t)n, s);
   hipLaunchKernelGGL(k_count, dim3((M + 255) / 256), dim3(256), 0, s, idx, M, cnt);
   hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(SB), 0, s, cnt, n, offs, bsum);
   hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SB), 0, s, bsum, nb);
@@ -305,7 +304,6 @@ void launch_aggregate(const glr_plan* pl, const float* xbar, const int32_t* idx,
   hipLaunchKernelGGL(k_scatter, dim3((M + 255) / 256), dim3(256), 0, s, idx, M, cnt, ent);
   int32_t* nbig = bsum + nb;                    // [1] queue length, then the queue
   int32_t* big = nbig + 1;
-  launch_fill_u32((uint32_t*)nbig, 0u, 1, s);
   hipLaunchKernelGGL(k_bucket_sort, dim3((pl->Ncand + 255) / 256), dim3(256), 0, s, offs,
                      pl->Ncand, ent, big, nbig);
   hipLaunchKernelGGL(k_bucket_sort_large, dim3(256), dim3(1024), 0, s, offs, ent, big, nbig);

@@ -61,10 +61,12 @@ glr_status check_plan_ws(const glr_plan* pl, const void* ws, const char* fn) {
   return GLR_OK;
 }
 
-// Stats live in the workspace: clear them the first time a workspace is seen.
+// Stats live in the workspace: clear them the first time a workspace is seen,
+// and set the top-K scan's shared bounds to +inf (each scan leaves them so).
 void ensure_stats(glr_plan* pl, char* ws, hipStream_t s) {
   if (pl->stats_ws != ws) {
     launch_fill_u32((uint32_t*)(ws + pl->ws.stats), 0u, sizeof(DevStats) / 4, s);
+    launch_fill_u32((uint32_t*)(ws + pl->ws.tsh), 0xffffffffu, (size_t)pl->n_chunk, s);
     pl->stats_ws = ws;
   }
   pl->last_stream = s;
@@ -164,7 +166,7 @@ glr_status match_stage(glr_plan* pl, const float* xp, const int32_t* keys, int32
       {
         StageTimer t(pl, s, T_SELECT);
         launch_select_rescore(pl, xp, A, kmap, g0, nk, lj, lu, ll, lcnt, idx_out, dd_out, oflag,
-                              0, bm, st, s);
+                              tsh, 0, bm, st, s);
       }
     }
   };
@@ -190,7 +192,7 @@ glr_status match_stage(glr_plan* pl, const float* xp, const int32_t* keys, int32
     {
       StageTimer t(pl, s, T_SELECT);
       launch_select_rescore(pl, xp, A, nullptr, g0, nk, lj, lu, ll, lcnt, idx_out, dd_out, oflag,
-                            1, bm, st, s);
+                            tsh, 1, bm, st, s);
       launch_collect_flags(oflag, g0, nk, klist, kcount, st, s);
     }
   }
@@ -210,12 +212,15 @@ glr_status match_stage(glr_plan* pl, const float* xp, const int32_t* keys, int32
 }
 
 glr_status lowrank_stage(glr_plan* pl, const float* xp, const int32_t* idx, float sigma, float* xo,
-                         float* sv, char* ws, hipStream_t s, int32_t* cover = nullptr) {
+                         float* sv, char* ws, hipStream_t s, int32_t* cover = nullptr,
+                         bool count_step = false) {
   float* xhat = (float*)(ws + pl->ws.xhat);
   DevStats* st = (DevStats*)(ws + pl->ws.stats);
   {
     StageTimer t(pl, s, T_LOWRANK);
-    launch_wnnm(pl, xp, idx, sigma, xhat, sv, st, s);
+    int zn = 0;
+    int32_t* z = agg_zero_range(pl, (int32_t*)(ws + pl->ws.pairs), &zn);
+    launch_wnnm(pl, xp, idx, sigma, xhat, sv, st, z, zn, count_step ? 1 : 0, s);
   }
   {
     StageTimer t(pl, s, T_AGG);
@@ -238,9 +243,8 @@ glr_status prior_planar(glr_plan* pl, const float* xp, float sigma, float* xo, c
   if (e) return e;
   e = match_stage(pl, xp, keys, idx, dd, ws, s);
   if (e) return e;
-  e = lowrank_stage(pl, xp, idx, sigma, xo, (float*)(ws + pl->ws.sv), ws, s);
+  e = lowrank_stage(pl, xp, idx, sigma, xo, (float*)(ws + pl->ws.sv), ws, s, nullptr, true);
   if (e) return e;
-  launch_count_step((DevStats*)(ws + pl->ws.stats), s);
   return check_hip("prior step");
 }
 
@@ -533,7 +537,7 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
   L.offs = c.take(((size_t)Ncand + 1) * 4);
   L.cplx_a = c.take(pl->is_complex ? HW * 8 : 0);
   L.cplx_b = c.take(pl->is_complex ? HW * 8 : 0);
-  L.red = c.take(256);
+  L.red = c.take(1024);
   const bool sur = pl->surrogate != 0;
   L.cnn_ws = c.take(sur ? cnn_workspace_bytes(Cp, pl->H, pl->W, 0) : 0);
   L.xcnn = c.take(sur ? HW * Cp * 4 : 0);

@@ -24,31 +24,41 @@ __global__ void k_quant_real(const float* __restrict__ x, int C, int HW, uint8_t
   q[p] = (uint8_t)((s + C / 2) / C);
 }
 
-// largest squared magnitude (non-negative floats order like their bit patterns)
-__global__ void k_mag2_max(const float* __restrict__ xp, int HW, uint32_t* __restrict__ out) {
-  __shared__ uint32_t red[TPB / 64];
-  int p = blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t b = 0;
-  if (p < HW) {
-    float re = xp[p], im = xp[HW + p];
-    b = __float_as_uint(re * re + im * im);
-  }
+constexpr int MAXB = 256;         // blocks of the magnitude maximum (one partial each)
+static_assert(MAXB <= TPB, "one partial per thread of a block");
+
+// block maximum of a TPB-thread block (all threads get it)
+__device__ __forceinline__ uint32_t block_max_u32(uint32_t b, uint32_t* red) {
   for (int o = 32; o > 0; o >>= 1) b = max(b, (uint32_t)__shfl_xor((int)b, o, 64));
   if (lane_id() == 0) red[threadIdx.x >> 6] = b;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t m = red[0];
-    for (int i = 1; i < TPB / 64; ++i) m = max(m, red[i]);
-    atomicMax(out, m);
-  }
+  uint32_t m = red[0];
+  for (int i = 1; i < TPB / 64; ++i) m = max(m, red[i]);
+  return m;
 }
 
-// q = clamp(rint(255 * (m * (1/max m))), 0, 255); all zero if max m == 0
-__global__ void k_quant_cplx(const float* __restrict__ xp, int HW, const uint32_t* __restrict__ mx,
-                             uint8_t* __restrict__ q) {
+// largest squared magnitude (non-negative floats order like their bit
+// patterns): one partial maximum per block, over a grid-stride range
+__global__ void k_mag2_max(const float* __restrict__ xp, int HW, uint32_t* __restrict__ part) {
+  __shared__ uint32_t red[TPB / 64];
+  uint32_t b = 0;
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < HW; p += gridDim.x * blockDim.x) {
+    const float re = xp[p], im = xp[HW + p];
+    b = max(b, __float_as_uint(re * re + im * im));
+  }
+  const uint32_t m = block_max_u32(b, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = m;
+}
+
+// q = clamp(rint(255 * (m * (1/max m))), 0, 255); all zero if max m == 0.
+// Every block folds the nb <= TPB partial maxima itself.
+__global__ void k_quant_cplx(const float* __restrict__ xp, int HW, const uint32_t* __restrict__ part,
+                             int nb, uint8_t* __restrict__ q) {
+  __shared__ uint32_t red[TPB / 64];
+  const uint32_t mx = block_max_u32(threadIdx.x < nb ? part[threadIdx.x] : 0u, red);
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= HW) return;
-  float m_max = __uint_as_float(*mx);
+  float m_max = __uint_as_float(mx);
   if (!(m_max > 0.0f)) {
     q[p] = 0;
     return;
@@ -385,10 +395,10 @@ void launch_detect(const glr_plan* pl, const float* xp, char* ws, int32_t* keys,
   long long* sval = (long long*)(ws + pl->ws.sval);
   DevStats* st = (DevStats*)(ws + pl->ws.stats);
   if (pl->is_complex) {
-    uint32_t* mx = (uint32_t*)(ws + pl->ws.red);
-    launch_fill_u32(mx, 0u, 1, s);
-    hipLaunchKernelGGL(k_mag2_max, dim3(nblk(HW)), dim3(TPB), 0, s, xp, HW, mx);
-    hipLaunchKernelGGL(k_quant_cplx, dim3(nblk(HW)), dim3(TPB), 0, s, xp, HW, mx, q);
+    uint32_t* part = (uint32_t*)(ws + pl->ws.red);      // [MAXB]
+    const int nb = std::min(nblk(HW), MAXB);
+    hipLaunchKernelGGL(k_mag2_max, dim3(nb), dim3(TPB), 0, s, xp, HW, part);
+    hipLaunchKernelGGL(k_quant_cplx, dim3(nblk(HW)), dim3(TPB), 0, s, xp, HW, part, nb, q);
   } else {
     hipLaunchKernelGGL(k_quant_real, dim3(nblk(HW)), dim3(TPB), 0, s, xp, pl->Cp, HW, q);
   }

@@ -80,7 +80,6 @@ struct glr_plan {
 // ------------------------------------------------------------------ launchers
 // ops.hip
 void launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
-void launch_count_step(DevStats* st, hipStream_t s);
 void launch_cacti_forward(const float* x, const uint8_t* m, float* y, int F, int HW, hipStream_t s);
 void launch_cacti_adjoint(const float* y, const uint8_t* m, float* x, int F, int HW, hipStream_t s);
 void launch_cacti_init(const float* y, const uint8_t* m, float* x, int F, int HW, hipStream_t s);
@@ -145,21 +144,31 @@ struct BigMargin {
 void launch_select_rescore(const glr_plan* pl, const float* xp, const float* A,
                            const int32_t* kmap, int g0, int nk, const int32_t* lj,
                            const float* lu, const float* ll, const int32_t* lcnt, int32_t* idx,
-                           float* dd, int32_t* oflag, int defer, const BigMargin& bm,
-                           DevStats* st, hipStream_t s);
+                           float* dd, int32_t* oflag, uint32_t* tsh, int defer,
+                           const BigMargin& bm, DevStats* st, hipStream_t s);
 void launch_collect_flags(const int32_t* oflag, int g0, int nk, int32_t* klist, int32_t* kcount,
                           DevStats* st, hipStream_t s);
 
 // lowrank.hip
+// zbuf[0..zn) is set to zero (nullable); bump != 0 counts a prior step
 void launch_wnnm(const glr_plan* pl, const float* xp, const int32_t* idx, float sigma,
-                 float* xhat, float* sv, DevStats* st, hipStream_t s);
+                 float* xhat, float* sv, DevStats* st, int32_t* zbuf, int zn, int bump,
+                 hipStream_t s);
 
 // aggregate.hip
 // sortbuf: aggregation sort scratch (agg_sort_ints(pl) int32); offs [Ncand + 1];
 // cover (nullable): per-pixel count of covering estimates [H][W]
+// The counters at agg_zero_range(pl, sortbuf) must be zero on entry.
 void launch_aggregate(const glr_plan* pl, const float* xbar, const int32_t* idx,
                       const float* xhat, int32_t* sortbuf, int32_t* offs, float* out,
                       int32_t* cover, hipStream_t s);
+// counts, block sums and queue length of the aggregation sort: one contiguous
+// range of sortbuf (returns its start; *n its length)
+inline int32_t* agg_zero_range(const glr_plan* pl, int32_t* sortbuf, int* n) {
+  const size_t nc = (size_t)pl->Ncand + 1;
+  *n = (int)((nc + 63) / 64 * 64 + (nc + 4095) / 4096 + 1);
+  return sortbuf + pl->M2;
+}
 inline size_t agg_sort_ints(const glr_plan* pl) {
   const size_t n = (size_t)pl->Ncand + 1;
   // entries [M2], counts/cursor [n], block sums, queue length, large-bucket queue

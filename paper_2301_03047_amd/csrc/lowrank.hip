@@ -237,7 +237,7 @@ template <int KP>
 __global__ void __launch_bounds__(64)
 k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* __restrict__ idx,
        int K, float sigma, float wc, float weps, int max_sweeps, float* __restrict__ xhat,
-       float* __restrict__ sv, DevStats* st) {
+       float* __restrict__ sv, DevStats* st, int32_t* __restrict__ zbuf, int zn, int bump) {
   constexpr int XS = KP + 4;       // row stride of the column-exchange buffer (16-byte rows)
   constexpr int BLN = 64 * (XS > LS ? XS : LS);
   __shared__ __align__(16) float Rl[BLN];   // R columns (Rl[j*LS + i]); exchange rows; W columns
@@ -253,6 +253,11 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
   const int lane = threadIdx.x;
   const int Wc = W - P + 1;
   const size_t HW = (size_t)H * W;
+  // side duties of the step, folded in to save launches: clear the
+  // aggregation's counters (read only by the kernels after this one) and
+  // count the prior step
+  for (int i = g * 64 + lane; i < zn; i += gridDim.x * 64) zbuf[i] = 0;
+  if (bump && g == 0 && lane == 0) st->steps += 1;
 
   {
     // lanes past K repeat the last member's position (K <= 64)
@@ -494,15 +499,16 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
 }  // namespace
 
 void launch_wnnm(const glr_plan* pl, const float* xp, const int32_t* idx, float sigma,
-                 float* xhat, float* sv, DevStats* st, hipStream_t s) {
+                 float* xhat, float* sv, DevStats* st, int32_t* zbuf, int zn, int bump,
+                 hipStream_t s) {
   const int K = pl->K;
   if (K <= 32)
     hipLaunchKernelGGL(k_wnnm<32>, dim3(pl->N), dim3(64), 0, s, xp, pl->H, pl->W, pl->P, pl->D,
-                       idx, K, sigma, pl->wnnm_c, pl->wnnm_eps, 30, xhat, sv, st);
+                       idx, K, sigma, pl->wnnm_c, pl->wnnm_eps, 30, xhat, sv, st, zbuf, zn, bump);
   else if (K <= 48)
     hipLaunchKernelGGL(k_wnnm<48>, dim3(pl->N), dim3(64), 0, s, xp, pl->H, pl->W, pl->P, pl->D,
-                       idx, K, sigma, pl->wnnm_c, pl->wnnm_eps, 30, xhat, sv, st);
+                       idx, K, sigma, pl->wnnm_c, pl->wnnm_eps, 30, xhat, sv, st, zbuf, zn, bump);
   else
     hipLaunchKernelGGL(k_wnnm<64>, dim3(pl->N), dim3(64), 0, s, xp, pl->H, pl->W, pl->P, pl->D,
-                       idx, K, sigma, pl->wnnm_c, pl->wnnm_eps, 30, xhat, sv, st);
+                       idx, K, sigma, pl->wnnm_c, pl->wnnm_eps, 30, xhat, sv, st, zbuf, zn, bump);
 }

@@ -14,7 +14,6 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t n) {
   if (i < n) p[i] = v;
 }
 
-__global__ void k_count_step(DevStats* st) { st->steps += 1; }
 
 // ---------------------------------------------------------------- CACTI (eq. 2)
 // y = sum_t A_t x_t, summed in frame order.
@@ -243,9 +242,6 @@ __global__ void k_from_planar(const float* __restrict__ p, float2* __restrict__ 
 
 void launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s) {
   if (n) hipLaunchKernelGGL(k_fill_u32, dim3(nblk(n)), dim3(TPB), 0, s, p, v, n);
-}
-void launch_count_step(DevStats* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_count_step, dim3(1), dim3(1), 0, s, st);
 }
 void launch_cacti_forward(const float* x, const uint8_t* m, float* y, int F, int HW, hipStream_t s) {
   hipLaunchKernelGGL(k_cacti_forward, dim3(nblk(HW)), dim3(TPB), 0, s, x, m, y, F, HW);

@@ -472,7 +472,7 @@ k_select_rescore(const float* __restrict__ xp, int H, int W, int P, int Cp, int 
                  const int32_t* __restrict__ lj, const float* __restrict__ lu,
                  const float* __restrict__ ll, const int32_t* __restrict__ lcnt,
                  int32_t* __restrict__ idx, float* __restrict__ dd, int32_t* __restrict__ oflag,
-                 DevStats* st) {
+                 uint32_t* __restrict__ tsh, DevStats* st) {
   __shared__ float su[4][UW];
   __shared__ float sl[4][UW];
   __shared__ int sj[4][UW];
@@ -481,6 +481,9 @@ k_select_rescore(const float* __restrict__ xp, int H, int W, int P, int Cp, int 
   const int l = lane_id();
   const int g = blockIdx.x * 4 + wave;
   if (g >= nk) return;                      // wave-uniform
+  // the scan that used the key's shared bound has finished: restore it to
+  // +inf for the next chunk or call
+  if (l == 0) tsh[g] = 0xffffffffu;
   float* u = su[wave];
   float* lo = sl[wave];
   int* jj = sj[wave];
@@ -774,7 +777,8 @@ void launch_topk_partial(const glr_plan* pl, const float* dist, const float* kmb
     coef2 = std::nextafter((float)(2.02 * (pl->D + pl->Cp + 4.0) * u), 1.f);
     cz = std::nextafter((float)(8.02 * pl->P * u), 1.f);
   }
-  launch_fill_u32(tsh, 0xffffffffu, (size_t)nk, s);
+  // tsh[0..nk) holds +inf here: set when the workspace is first used and
+  // restored by the rescoring kernel after every scan
   const int items = nk * pl->n_split;
   // the FP32 form's margin sets stay far below the BF16 form's: a smaller
   // wave buffer and 768-candidate steps (fewer registers) fit four waves per
@@ -803,11 +807,11 @@ template <int EM>
 static void launch_select_t(const glr_plan* pl, const float* xp, const float* A,
                             const int32_t* kmap, int g0, int nk, const int32_t* lj,
                             const float* lu, const float* ll, const int32_t* lcnt, int32_t* idx,
-                            float* dd, int32_t* oflag, int defer, const BigMargin& bm,
-                            DevStats* st, int L, hipStream_t s) {
+                            float* dd, int32_t* oflag, uint32_t* tsh, int defer,
+                            const BigMargin& bm, DevStats* st, int L, hipStream_t s) {
   hipLaunchKernelGGL(k_select_rescore<EM>, dim3((nk + 3) / 4), dim3(256), 0, s, xp, pl->H, pl->W,
                      pl->P, pl->Cp, pl->D, L, A, kmap, g0, nk, pl->n_split, pl->Ncand, pl->K, lj,
-                     lu, ll, lcnt, idx, dd, oflag, st);
+                     lu, ll, lcnt, idx, dd, oflag, tsh, st);
   hipLaunchKernelGGL(k_rescore_overflow<EM>, dim3(nk), dim3(ST), 0, s, xp, pl->H, pl->W, pl->P,
                      pl->Cp, pl->D, L, A, kmap, g0, pl->n_split, pl->Ncand, pl->K, defer, lj, lu,
                      ll, lcnt, oflag, bm.pos, bm.hi, bm.lo, bm.cap, idx, dd, st);
@@ -816,15 +820,15 @@ static void launch_select_t(const glr_plan* pl, const float* xp, const float* A,
 void launch_select_rescore(const glr_plan* pl, const float* xp, const float* A,
                            const int32_t* kmap, int g0, int nk, const int32_t* lj,
                            const float* lu, const float* ll, const int32_t* lcnt, int32_t* idx,
-                           float* dd, int32_t* oflag, int defer, const BigMargin& bm,
-                           DevStats* st, hipStream_t s) {
+                           float* dd, int32_t* oflag, uint32_t* tsh, int defer,
+                           const BigMargin& bm, DevStats* st, hipStream_t s) {
   const int L = rescore_lanes(pl->D);
   if ((pl->D + L - 1) / L <= 32)
-    launch_select_t<32>(pl, xp, A, kmap, g0, nk, lj, lu, ll, lcnt, idx, dd, oflag, defer, bm, st,
-                        L, s);
+    launch_select_t<32>(pl, xp, A, kmap, g0, nk, lj, lu, ll, lcnt, idx, dd, oflag, tsh, defer, bm,
+                        st, L, s);
   else
-    launch_select_t<64>(pl, xp, A, kmap, g0, nk, lj, lu, ll, lcnt, idx, dd, oflag, defer, bm, st,
-                        L, s);
+    launch_select_t<64>(pl, xp, A, kmap, g0, nk, lj, lu, ll, lcnt, idx, dd, oflag, tsh, defer, bm,
+                        st, L, s);
 }
 
 // Append the chunk keys g0 + g with oflag[g] != 0 to klist at *kcount, in
