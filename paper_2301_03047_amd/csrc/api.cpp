@@ -321,8 +321,10 @@ const float* planar_in(glr_plan* pl, const void* x, char* ws, hipStream_t s) {
   return xp;
 }
 
+// For MRI with vp, also vp = planar form of x_out + u (the prior's input).
 glr_status data_step_impl(glr_plan* pl, const void* y, const void* x, const void* z,
-                          const void* u, void* x_out, char* ws, hipStream_t s) {
+                          const void* u, void* x_out, char* ws, hipStream_t s,
+                          float* vp = nullptr) {
   StageTimer t(pl, s, T_DATA);
   const int H = pl->H, W = pl->W, HW = H * W;
   if (pl->modality == GLR_CACTI) {
@@ -330,11 +332,21 @@ glr_status data_step_impl(glr_plan* pl, const void* y, const void* x, const void
   } else if (pl->modality == GLR_MSFA) {
     launch_msfa_gap((const float*)x, (const float*)y, (float*)x_out, H, W, s);
   } else {
+    // F(z - u) with the k-space update fused into the transform's passes
     float2* a = (float2*)(ws + pl->ws.cplx_a);
-    launch_cplx_axpby((const float2*)z, (const float2*)u, a, 1.0f, -1.0f, HW, s);
-    launch_fft2d(a, a, H, W, 0, s);
-    launch_admm_kspace((const float2*)y, pl->mask, a, a, pl->rho, H, W, s);
-    launch_fft2d(a, (float2*)x_out, H, W, 1, s);
+    FftFuse fw;
+    fw.in2 = (const float2*)u;
+    fw.beta = -1.0f;
+    fw.ky = (const float2*)y;
+    fw.lines = pl->mask;
+    fw.rho = pl->rho;
+    launch_fft2d((const float2*)z, a, H, W, 0, s, &fw);
+    FftFuse iv;
+    if (vp) {
+      iv.pu = (const float2*)u;
+      iv.vp = vp;
+    }
+    launch_fft2d(a, (float2*)x_out, H, W, 1, s, &iv);
   }
   return check_hip("glr_data_step");
 }
@@ -782,7 +794,6 @@ glr_status glr_reconstruct(glr_plan* pl, const void* y, void* state, int32_t t_b
     float2* x = (float2*)state;
     float2* z = x + HW;
     float2* u = z + HW;
-    float2* v = (float2*)(w + pl->ws.cplx_b);
     float* vp = (float*)(w + pl->ws.xp);
     float* zp = (float*)(w + pl->ws.xo);
     if (t_begin == 0) {
@@ -793,14 +804,11 @@ glr_status glr_reconstruct(glr_plan* pl, const void* y, void* state, int32_t t_b
       launch_cplx_axpby(z, z, u, 0.0f, 0.0f, HW, s);
     }
     for (int t = t_begin; t < t_end; ++t) {
-      e = data_step_impl(pl, y, nullptr, z, u, x, w, s);
+      e = data_step_impl(pl, y, nullptr, z, u, x, w, s, vp);     // also vp = planar(x + u)
       if (e) return e;
-      launch_cplx_axpby(x, u, v, 1.0f, 1.0f, HW, s);
-      launch_to_planar(v, vp, HW, s);
       e = prior(t, vp, zp);
       if (e) return e;
-      launch_from_planar(zp, z, HW, s);
-      launch_admm_dual(u, x, z, HW, s);
+      launch_admm_dual(u, x, zp, z, HW, s);
     }
     hipMemcpyAsync(x_out, z, (size_t)HW * 8, hipMemcpyDeviceToDevice, s);
   }

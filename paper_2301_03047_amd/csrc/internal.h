@@ -89,14 +89,27 @@ void launch_msfa_forward(const float* x, float* y, int H, int W, hipStream_t s);
 void launch_msfa_adjoint(const float* y, float* x, int H, int W, hipStream_t s);
 void launch_msfa_init(const float* y, float* x, int H, int W, hipStream_t s);
 void launch_msfa_gap(const float* x, const float* y, float* xo, int H, int W, hipStream_t s);
-void launch_fft2d(const float2* in, float2* out, int H, int W, int inverse, hipStream_t s);
+// Optional fusions of the 2-D FFT (see k_fft_rows / k_fft_cols): the rows pass
+// transforms in + beta in2; the columns pass applies the ADMM k-space update
+// (ky, lines, rho) and/or writes vp = planar(result + pu).
+struct FftFuse {
+  const float2* in2 = nullptr;
+  float beta = 0.f;
+  const float2* ky = nullptr;
+  const uint8_t* lines = nullptr;
+  float rho = 0.f;
+  const float2* pu = nullptr;
+  float* vp = nullptr;
+};
+void launch_fft2d(const float2* in, float2* out, int H, int W, int inverse, hipStream_t s,
+                  const FftFuse* f = nullptr);
 void launch_kspace_mask(const float2* in, const uint8_t* lines, float2* out, int H, int W,
                         hipStream_t s);
 void launch_cplx_axpby(const float2* a, const float2* b, float2* out, float alpha, float beta,
                        int n, hipStream_t s);
-void launch_admm_kspace(const float2* y, const uint8_t* lines, const float2* fz, float2* out,
-                        float rho, int H, int W, hipStream_t s);
-void launch_admm_dual(float2* u, const float2* x, const float2* z, int n, hipStream_t s);
+// z = complex form of the planar zp, then u += x - z
+void launch_admm_dual(float2* u, const float2* x, const float* zp, float2* z, int n,
+                      hipStream_t s);
 void launch_to_planar(const float2* z, float* p, int n, hipStream_t s);
 void launch_from_planar(const float* p, float2* z, int n, hipStream_t s);
 

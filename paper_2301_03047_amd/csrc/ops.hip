@@ -113,8 +113,9 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// One workgroup per row of length n (power of two).
-__global__ void k_fft_rows(const float2* in, float2* out, int n,
+// One workgroup per row of length n (power of two).  With in2, the row
+// transformed is in + beta in2 (the ADMM data step's z - u, fused).
+__global__ void k_fft_rows(const float2* in, const float2* in2, float beta, float2* out, int n,
                            int inverse, float scale) {
   extern __shared__ float2 sm[];
   float2* a = sm;
@@ -122,7 +123,14 @@ __global__ void k_fft_rows(const float2* in, float2* out, int n,
   float2* tw = sm + 2 * n;
   const size_t row = blockIdx.x;
   const int half = n >> 1;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) a[i] = in[row * n + i];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    float2 v = in[row * n + i];
+    if (in2) {
+      const float2 w = in2[row * n + i];
+      v = make_float2(1.0f * v.x + beta * w.x, 1.0f * v.y + beta * w.y);
+    }
+    a[i] = v;
+  }
   for (int i = threadIdx.x; i < half; i += blockDim.x) {
     float s, c;
     sincospif(-2.0f * (float)i / (float)n, &s, &c);
@@ -148,8 +156,20 @@ __global__ void k_fft_rows(const float2* in, float2* out, int n,
     out[row * n + i] = make_float2(a[i].x * scale, a[i].y * scale);
 }
 
+// k-space part of the ADMM x-update: (M y + rho F(z - u)) / (M + rho).
+__device__ __forceinline__ float2 admm_kspace(float2 f, bool m, float2 yv, float rho) {
+  const float2 yy = m ? yv : make_float2(0.f, 0.f);
+  const float den = (m ? 1.f : 0.f) + rho;
+  return make_float2((yy.x + rho * f.x) / den, (yy.y + rho * f.y) / den);
+}
+
 // One workgroup per `cb` adjacent columns of an n-row array with row stride W.
-__global__ void k_fft_cols(float2* data, int n, int W, int cb, int inverse, float scale) {
+// Fused epilogues of the ADMM loop (each optional): with ky, the k-space
+// update above (lines: the sampled-line mask); with pu, also vp = planar
+// form of (result + pu) in [2][n][W].
+__global__ void k_fft_cols(float2* data, int n, int W, int cb, int inverse, float scale,
+                           const float2* __restrict__ ky, const uint8_t* __restrict__ lines,
+                           float rho, const float2* __restrict__ pu, float* __restrict__ vp) {
   extern __shared__ float2 sm[];
   float2* a = sm;
   float2* b = sm + (size_t)n * cb;
@@ -182,9 +202,18 @@ __global__ void k_fft_cols(float2* data, int n, int W, int cb, int inverse, floa
     a = b;
     b = t;
   }
+  const size_t HW = (size_t)n * W;
   for (int t = threadIdx.x; t < n * cb; t += blockDim.x) {
     int r = t / cb, cc = t - r * cb;
-    data[(size_t)r * W + c0 + cc] = make_float2(a[t].x * scale, a[t].y * scale);
+    const size_t p = (size_t)r * W + c0 + cc;
+    float2 v = make_float2(a[t].x * scale, a[t].y * scale);
+    if (ky) v = admm_kspace(v, lines[r] != 0, ky[p], rho);
+    data[p] = v;
+    if (pu) {
+      const float2 w = pu[p];
+      vp[p] = 1.0f * v.x + 1.0f * w.x;
+      vp[HW + p] = 1.0f * v.y + 1.0f * w.y;
+    }
   }
 }
 
@@ -203,24 +232,14 @@ __global__ void k_cplx_axpby(const float2* a, const float2* b, float2* out, floa
   out[p] = make_float2(alpha * u.x + beta * v.x, alpha * u.y + beta * v.y);
 }
 
-// k-space part of the ADMM x-update: (M y + rho F(z - u)) / (M + rho).
-__global__ void k_admm_kspace(const float2* __restrict__ y, const uint8_t* __restrict__ lines,
-                              const float2* fz, float2* out, float rho, int H, int W) {
-  int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= H * W) return;
-  const bool m = lines[p / W] != 0;
-  float2 f = fz[p];
-  float2 yy = m ? y[p] : make_float2(0.f, 0.f);
-  float den = (m ? 1.f : 0.f) + rho;
-  out[p] = make_float2((yy.x + rho * f.x) / den, (yy.y + rho * f.y) / den);
-}
-
-// u <- u + x - z
-__global__ void k_admm_dual(float2* u, const float2* __restrict__ x, const float2* __restrict__ z,
-                            int n) {
+// z <- complex form of the planar zp, then u <- u + x - z
+__global__ void k_admm_dual(float2* u, const float2* __restrict__ x, const float* __restrict__ zp,
+                            float2* __restrict__ z, int n) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
-  float2 a = u[p], b = x[p], c = z[p];
+  const float2 c = make_float2(zp[p], zp[n + p]);
+  z[p] = c;
+  float2 a = u[p], b = x[p];
   u[p] = make_float2((a.x + b.x) - c.x, (a.y + b.y) - c.y);
 }
 
@@ -270,17 +289,20 @@ void launch_msfa_gap(const float* x, const float* y, float* xo, int H, int W, hi
 }
 
 // Orthonormal 2-D DFT: rows then columns, each scaled by 1/sqrt(length).
-void launch_fft2d(const float2* in, float2* out, int H, int W, int inverse, hipStream_t s) {
+void launch_fft2d(const float2* in, float2* out, int H, int W, int inverse, hipStream_t s,
+                  const FftFuse* f) {
+  const FftFuse none{};
+  if (!f) f = &none;
   size_t lds_r = (size_t)(2 * W + W / 2) * sizeof(float2);
-  hipLaunchKernelGGL(k_fft_rows, dim3(H), dim3(TPB), lds_r, s, in, out, W, inverse,
-                     1.0f / sqrtf((float)W));
+  hipLaunchKernelGGL(k_fft_rows, dim3(H), dim3(TPB), lds_r, s, in, f->in2, f->beta, out, W,
+                     inverse, 1.0f / sqrtf((float)W));
   int cb = 1;
   while (cb * 2 <= 16 && (size_t)(cb * 2) * H * 2 * sizeof(float2) + (size_t)H / 2 * sizeof(float2) <= 48 * 1024 &&
          W % (cb * 2) == 0)
     cb *= 2;
   size_t lds_c = ((size_t)2 * H * cb + H / 2) * sizeof(float2);
   hipLaunchKernelGGL(k_fft_cols, dim3(W / cb), dim3(TPB), lds_c, s, out, H, W, cb, inverse,
-                     1.0f / sqrtf((float)H));
+                     1.0f / sqrtf((float)H), f->ky, f->lines, f->rho, f->pu, f->vp);
 }
 void launch_kspace_mask(const float2* in, const uint8_t* lines, float2* out, int H, int W,
                         hipStream_t s) {
@@ -290,13 +312,9 @@ void launch_cplx_axpby(const float2* a, const float2* b, float2* out, float alph
                        int n, hipStream_t s) {
   hipLaunchKernelGGL(k_cplx_axpby, dim3(nblk(n)), dim3(TPB), 0, s, a, b, out, alpha, beta, n);
 }
-void launch_admm_kspace(const float2* y, const uint8_t* lines, const float2* fz, float2* out,
-                        float rho, int H, int W, hipStream_t s) {
-  hipLaunchKernelGGL(k_admm_kspace, dim3(nblk((size_t)H * W)), dim3(TPB), 0, s, y, lines, fz, out,
-                     rho, H, W);
-}
-void launch_admm_dual(float2* u, const float2* x, const float2* z, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_admm_dual, dim3(nblk(n)), dim3(TPB), 0, s, u, x, z, n);
+void launch_admm_dual(float2* u, const float2* x, const float* zp, float2* z, int n,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_admm_dual, dim3(nblk(n)), dim3(TPB), 0, s, u, x, zp, z, n);
 }
 void launch_to_planar(const float2* z, float* p, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_to_planar, dim3(nblk(n)), dim3(TPB), 0, s, z, p, n);
