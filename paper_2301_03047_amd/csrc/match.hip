@@ -74,14 +74,22 @@ k_match_f32(const float* __restrict__ xp, int H, int W, int P, int Cp,
             const float* __restrict__ kc, const float* __restrict__ pn,
             const float2* __restrict__ pc, size_t ncand, const int32_t* __restrict__ kmap,
             int g0, int nk, float* __restrict__ dist, size_t ldd) {
+  // The K dimension runs in stages of GM patch rows of one channel (GM fixed
+  // by P2: the most rows whose staging registers fit three waves per SIMD
+  // without spills): one barrier per stage, and the next stage's loads are
+  // in flight during a stage's MFMAs.
+  constexpr int GM = (P2 == 12 || P2 == 14) ? 1 : (P2 == 6 ? 3 : (P2 >= 10 ? 2 : (P2 <= 2 ? 2 : 4)));
   constexpr int SEG = BN + P2;
-  constexpr int AST = P2 + 1;   // odd LDS stride for the key slab
-  __shared__ float seg[2][SEG];
-  __shared__ float As[2][BM * AST];
+  constexpr int AST = GM * P2 + 1;   // odd LDS stride for the key slab
+  constexpr int MAIN = 2 * GM * SEG + 2 * BM * AST;
+  constexpr int EPI = CB * BM + CB * BN;
+  __shared__ __align__(16) float lds[MAIN > EPI ? MAIN : EPI];
+  float* const seg0 = lds;                    // [2][GM][SEG] image rows
+  float* const As0 = lds + 2 * GM * SEG;      // [2][BM][AST] key slab
+  float* const skc = lds;                     // epilogue: [channel of the pass][key]
+  float* const spc = lds + CB * BM;           // epilogue: [channel of the pass][candidate]
   __shared__ int krow[BM];
   __shared__ float skn[BM];
-  __shared__ __align__(16) float skc[CB * BM];   // epilogue: [channel of the pass][key]
-  __shared__ float spc[CB * BN];                 // epilogue: [channel of the pass][candidate]
 
   const int Hc = H - P + 1, Wc = W - P + 1;
   const int ntc = (Wc + BN - 1) / BN;
@@ -97,7 +105,8 @@ k_match_f32(const float* __restrict__ xp, int H, int W, int P, int Cp,
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int S = Cp * P;                      // (channel, dy) stages
+  const int SPC = (P + GM - 1) / GM;         // stages per channel
+  const int S = Cp * SPC;
   if (tid < BM) {
     const int g = kbase + tid;
     const int gg = g < nk ? (kmap ? kmap[g0 + g] : g0 + g) : -1;
@@ -111,42 +120,51 @@ k_match_f32(const float* __restrict__ xp, int H, int W, int P, int Cp,
   const size_t tA = (size_t)r * Wc + colA, tB = tA + 32;
 
   // register staging of the next stage
-  float rseg = 0.f;
-  constexpr int APT = (BM * P2 + 255) / 256;
+  float rseg[GM];
+  constexpr int APT = (BM * GM * P2 + 255) / 256;
   float ra[APT];
   float nb0 = 0.f, nb1 = 0.f;
 
-  auto load_stage = [&](int s) {
-    const int ch = s / P, dy = s - ch * P;
-    const float* row = xp + ((size_t)ch * H + r + dy) * W;
-    if (tid < SEG) {
-      int cc = c0 + tid;
-      rseg = (cc < W) ? row[cc] : 0.f;
+  auto load_stage = [&](int st) {
+    const int ch = st / SPC, dy0 = (st - ch * SPC) * GM;
+#pragma unroll
+    for (int q = 0; q < GM; ++q) {
+      rseg[q] = 0.f;
+      if (tid < SEG && dy0 + q < P) {
+        const int cc = c0 + tid;
+        if (cc < W) rseg[q] = xp[((size_t)ch * H + r + dy0 + q) * W + cc];
+      }
     }
 #pragma unroll
     for (int u = 0; u < APT; ++u) {
-      int e = tid + u * 256;
+      const int e = tid + u * 256;
       float v = 0.f;
-      if (e < BM * P2) {
-        int m = e / P2, dx = e - m * P2;
+      if (e < BM * GM * P2) {
+        const int m = e / (GM * P2), rem = e - m * (GM * P2);
+        const int q = rem / P2, dx = rem - q * P2;
         const int gg = krow[m];
-        if (dx < P && gg >= 0) v = Ac[(size_t)gg * D + (size_t)s * P + dx];
+        if (dx < P && dy0 + q < P && gg >= 0)
+          v = Ac[(size_t)gg * D + (size_t)(ch * P + dy0 + q) * P + dx];
       }
       ra[u] = v;
     }
-    if (dy == 0) {                           // the channel's candidate means
+    if (dy0 == 0) {                          // the channel's candidate means
       nb0 = colA < Wc ? pc[(size_t)ch * ncand + tA].x : 0.f;
       nb1 = colB < Wc ? pc[(size_t)ch * ncand + tB].x : 0.f;
     }
   };
   auto store_stage = [&](int buf) {
-    if (tid < SEG) seg[buf][tid] = rseg;
+    float* sg = seg0 + buf * GM * SEG;
+    if (tid < SEG)
+#pragma unroll
+      for (int q = 0; q < GM; ++q) sg[q * SEG + tid] = rseg[q];
+    float* as = As0 + buf * BM * AST;
 #pragma unroll
     for (int u = 0; u < APT; ++u) {
-      int e = tid + u * 256;
-      if (e < BM * P2) {
-        int m = e / P2, dx = e - m * P2;
-        As[buf][m * AST + dx] = ra[u];
+      const int e = tid + u * 256;
+      if (e < BM * GM * P2) {
+        const int m = e / (GM * P2), rem = e - m * (GM * P2);
+        as[m * AST + rem] = ra[u];
       }
     }
   };
@@ -163,23 +181,31 @@ k_match_f32(const float* __restrict__ xp, int H, int W, int P, int Cp,
   store_stage(0);
   float mb0 = nb0, mb1 = nb1;                // the current channel's candidate means
   __syncthreads();
-  for (int s = 0; s < S; ++s) {
-    const int cur = s & 1;
-    if (s + 1 < S) load_stage(s + 1);
+  for (int st = 0; st < S; ++st) {
+    const int cur = st & 1;
+    if (st + 1 < S) load_stage(st + 1);
+    const float* sg = seg0 + cur * GM * SEG;
+    const float* as = As0 + cur * BM * AST;
+    const int rows = min(GM, P - (st % SPC) * GM);
+#pragma unroll 1
+    for (int q = 0; q < rows; ++q) {
+      {
 #pragma unroll
-    for (int kk = 0; kk < P2 / 2; ++kk) {
-      const int dx = 2 * kk + lhi;
-      float a0 = As[cur][(wm * 64 + l32) * AST + dx];
-      float a1 = As[cur][(wm * 64 + 32 + l32) * AST + dx];
-      float b0 = seg[cur][wn * 64 + l32 + dx] - mb0;
-      float b1 = seg[cur][wn * 64 + 32 + l32 + dx] - mb1;
-      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+        for (int kk = 0; kk < P2 / 2; ++kk) {
+          const int dx = 2 * kk + lhi;
+          float a0 = as[(wm * 64 + l32) * AST + q * P2 + dx];
+          float a1 = as[(wm * 64 + 32 + l32) * AST + q * P2 + dx];
+          float b0 = sg[q * SEG + wn * 64 + l32 + dx] - mb0;
+          float b1 = sg[q * SEG + wn * 64 + 32 + l32 + dx] - mb1;
+          acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
+          acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
+          acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
+          acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+        }
+      }
     }
-    if (s + 1 < S) store_stage(cur ^ 1);
-    if ((s + 1) % P == 0) {
+    if (st + 1 < S) store_stage(cur ^ 1);
+    if ((st + 1) % SPC == 0) {
       mb0 = nb0;
       mb1 = nb1;
     }
