@@ -107,17 +107,41 @@ k_match_f32(const float* __restrict__ xp, int H, int W, int P, int Cp,
   const int wm = wave >> 1, wn = wave & 1;
   const int SPC = (P + GM - 1) / GM;         // stages per channel
   const int S = Cp * SPC;
+  auto key_row = [&](int m) {
+    const int g = kbase + m;
+    return g < nk ? (kmap ? kmap[g0 + g] : g0 + g) : -1;
+  };
+  // the epilogue's key and candidate terms are loaded now and staged after
+  // the main loop (for up to four channels), so their latency overlaps it
+  float knr = 0.f;
   if (tid < BM) {
-    const int g = kbase + tid;
-    const int gg = g < nk ? (kmap ? kmap[g0 + g] : g0 + g) : -1;
+    const int gg = key_row(tid);
     krow[tid] = gg;
-    skn[tid] = gg >= 0 ? kn[gg].x : 0.f;
+    knr = gg >= 0 ? kn[gg].x : 0.f;
+  }
+  const bool pre = Cp <= 4;
+  float pkc[2] = {0.f, 0.f}, ppc[2] = {0.f, 0.f};
+  if (pre) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int e = tid + k * 256;
+      if (e < Cp * BM) {
+        const int c = e / BM, m = e - c * BM;
+        const int gg = key_row(m);
+        pkc[k] = gg >= 0 ? kc[(size_t)gg * Cp + c] : 0.f;
+      }
+      if (e < Cp * BN) {
+        const int c = e / BN, j = e - c * BN;
+        ppc[k] = c0 + j < Wc ? pc[(size_t)c * ncand + (size_t)r * Wc + c0 + j].y : 0.f;
+      }
+    }
   }
   __syncthreads();
 
   const int l32 = lane & 31, lhi = lane >> 5;
   const int colA = c0 + wn * 64 + l32, colB = colA + 32;
   const size_t tA = (size_t)r * Wc + colA, tB = tA + 32;
+  const float pnA = colA < Wc ? pn[tA] : 0.f, pnB = colB < Wc ? pn[tB] : 0.f;
 
   // register staging of the next stage
   float rseg[GM];
@@ -228,13 +252,21 @@ k_match_f32(const float* __restrict__ xp, int H, int W, int P, int Cp,
     }
   };
   const bool one_pass = Cp <= CB;
-  if (one_pass) {
+  if (tid < BM) skn[tid] = knr;
+  if (pre) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int e = tid + k * 256;
+      if (e < Cp * BM) skc[e] = pkc[k];
+      if (e < Cp * BN) spc[e] = ppc[k];
+    }
+  } else if (one_pass) {
     stage_means(0);
-    __syncthreads();
   }
+  __syncthreads();
 #pragma unroll
   for (int nt = 0; nt < 2; ++nt) {
-    const float pp = (nt ? colB : colA) < Wc ? pn[nt ? tB : tA] : 0.f;
+    const float pp = nt ? pnB : pnA;
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt) {
       const int i0 = wm * 64 + mt * 32 + 4 * lhi;   // rows i0 + 8 j + h, h < 4
