@@ -157,13 +157,16 @@ k_topk_partial(const float* __restrict__ dist, size_t ldd, const float4* __restr
   __shared__ int shist[4][256];
   const int wave = threadIdx.x >> 6;
   const int l = lane_id();
-  const int item = blockIdx.x * 4 + wave;
-  if (item >= nk * S) return;               // wave-uniform; no block barriers below
+  // the four waves of a block take four keys over the same candidate range,
+  // so they read the same candidate bound terms (mostly from L1)
+  const int sp = blockIdx.x % S;
+  const int g = (blockIdx.x / S) * 4 + wave;
+  if (g >= nk) return;                      // wave-uniform; no block barriers below
+  const int item = g * S + sp;
   int* bj = sbj[wave];
   float* bu = sbu[wave];
   float* bl = sbl[wave];
   int* hist = shist[wave];
-  const int g = item / S, sp = item - g * S;
   const int j0 = sp * split_len;
   const int j1 = min(Ncand, j0 + split_len);
   const float4 kmv = km[kmap ? kmap[g0 + g] : g0 + g];
@@ -779,17 +782,16 @@ void launch_topk_partial(const glr_plan* pl, const float* dist, const float* kmb
   }
   // tsh[0..nk) holds +inf here: set when the workspace is first used and
   // restored by the rescoring kernel after every scan
-  const int items = nk * pl->n_split;
   // the FP32 form's margin sets stay far below the BF16 form's: a smaller
   // wave buffer and 768-candidate steps (fewer registers) fit four waves per
   // SIMD instead of three
+  const dim3 grid((nk + 3) / 4 * pl->n_split);
   if (bf16)
-    hipLaunchKernelGGL((k_topk_partial<4, CAP>), dim3((items + 3) / 4), dim3(256), 0, s, dist,
-                       (size_t)pl->ldd, (const float4*)kmb, kmap, g0, cm2, pl->Ncand,
-                       pl->split_len, pl->n_split, nk, pl->K, 0, coef, coef2, cz, tsh, lj, lu, ll,
-                       lcnt);
+    hipLaunchKernelGGL((k_topk_partial<4, CAP>), grid, dim3(256), 0, s, dist, (size_t)pl->ldd,
+                       (const float4*)kmb, kmap, g0, cm2, pl->Ncand, pl->split_len, pl->n_split,
+                       nk, pl->K, 0, coef, coef2, cz, tsh, lj, lu, ll, lcnt);
   else
-    hipLaunchKernelGGL((k_topk_partial<3, 512>), dim3((items + 3) / 4),
+    hipLaunchKernelGGL((k_topk_partial<3, 512>), grid,
                        dim3(256), 0, s, dist, (size_t)pl->ldd, (const float4*)kmb, kmap, g0, cm2,
                        pl->Ncand, pl->split_len, pl->n_split, nk, pl->K, 1, coef, coef2, cz, tsh,
                        lj, lu, ll, lcnt);
