@@ -221,20 +221,33 @@ def main():
         n_it = args.cpu_iters
         y64 = y.cpu().numpy().astype(np.complex128)
         wl_cpu = synth.workloads.small(wl, wnnm_c=float(np.float32(wl.wnnm_c)))
+        n_cmp = min(5, n_it)                         # tight comparison point
+        early = {}
+
+        def keep(t, _v, z):
+            if t + 1 == n_cmp:
+                early["z"] = z.copy()
+
         t0 = time.perf_counter()
-        ref = orc.reconstruct(wl_cpu, y64, inst["mask"], sig.astype(np.float64), iters=n_it)
+        ref = orc.reconstruct(wl_cpu, y64, inst["mask"], sig.astype(np.float64), iters=n_it,
+                              callback=keep)
         dt = time.perf_counter() - t0
         threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
         cpu = {"value": round(n_it / dt, 4), "unit": "iterations/s", "cores": threads,
                "kind": "oracle",
                "sample": f"first {n_it} of {T} ADMM iterations of {wname} (same input), "
                          f"{dt:.1f} s on {os.cpu_count()} host CPUs"}
-        g5, _ = plan.reconstruct(y, 0, n_it)
-        pg = om_metrics.psnr(g5.cpu().numpy(), xt)
-        pr = om_metrics.psnr(ref, xt)
-        psnr_cmp = {"iters": n_it, "gpu_db": round(pg, 4), "oracle_db": round(pr, 4),
-                    "delta_db": round(pg - pr, 5),
-                    "rel_l2_vs_oracle": float(f"{om_metrics.rel_l2(g5.cpu().numpy(), ref):.3e}")}
+        # the first n_cmp iterations agree to FP32 rounding; later ones drift
+        # apart once a rounding difference flips a discrete choice (a key or
+        # a group member), which the per-iteration parity tests allow for
+        psnr_cmp = {}
+        for name, n, r in (("first", n_cmp, early["z"]), ("sample", n_it, ref)):
+            g, _ = plan.reconstruct(y, 0, n)
+            g = g.cpu().numpy()
+            pg, pr = om_metrics.psnr(g, xt), om_metrics.psnr(r, xt)
+            psnr_cmp[name] = {"iters": n, "gpu_db": round(pg, 4), "oracle_db": round(pr, 4),
+                              "delta_db": round(pg - pr, 5),
+                              "rel_l2_vs_oracle": float(f"{om_metrics.rel_l2(g, r):.3e}")}
 
     rec = {
         "metric": METRIC, "value": round(value, 3), "unit": "iterations/s", "n_gpus": 1,
