@@ -308,6 +308,198 @@ k_match_f32(const float* __restrict__ xp, int H, int W, int P, int Cp,
   }
 }
 
+// Small-D variant of the same contraction (D' = Cp P P2 <= SD_MAX, Cp <= 4):
+// a persistent block keeps its key tile's whole centred slab in LDS and
+// streams candidate tiles (one grid-row segment of BN candidates each)
+// through it; a tile's image rows, candidate means and norms are loaded
+// into registers while the previous tile computes, so a tile costs its
+// MFMAs, its epilogue and two barriers.  Same arithmetic and output as
+// k_match_f32.
+constexpr int SD_MAX = 72;
+constexpr int SD_CP = 4;
+
+template <int P2>
+__global__ void __launch_bounds__(256, 2)
+k_match_f32_slab(const float* __restrict__ xp, int H, int W, int P, int Cp,
+                 const float* __restrict__ Ac, int D, const float4* __restrict__ kn,
+                 const float* __restrict__ kc, const float* __restrict__ pn,
+                 const float2* __restrict__ pc, size_t ncand, const int32_t* __restrict__ kmap,
+                 int g0, int nk, int npb, float* __restrict__ dist, size_t ldd) {
+  constexpr int SEG = BN + P2;
+  constexpr int AST = SD_MAX + 1;            // odd LDS stride of the key slab
+  constexpr int NR = SD_MAX / P2;            // image rows per tile (Cp P), at most
+  __shared__ float As[BM * AST];
+  __shared__ float seg[NR * SEG];
+  __shared__ __align__(16) float skc[SD_CP * BM];
+  __shared__ float spc[SD_CP * BN];          // fl(P mu_pc) of the tile's candidates
+  __shared__ float smu[SD_CP * BN];          // mu_pc
+  __shared__ float spn[BN];
+  __shared__ int krow[BM];
+  __shared__ float skn[BM];
+
+  const int Hc = H - P + 1, Wc = W - P + 1;
+  const int ntc = (Wc + BN - 1) / BN;
+  const int ntile = Hc * ntc;
+  const int kt = blockIdx.x / npb, part = blockIdx.x - kt * npb;
+  const int kbase = kt * BM;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int l32 = lane & 31, lhi = lane >> 5;
+  const int NRr = Cp * P;                    // image rows of a tile
+  const int DP = Cp * P * P2;                // padded key length in LDS
+
+  // ---- key tile: rows, norms, scaled channel means, centred slab
+  if (tid < BM) {
+    const int g = kbase + tid;
+    const int gg = g < nk ? (kmap ? kmap[g0 + g] : g0 + g) : -1;
+    krow[tid] = gg;
+    skn[tid] = gg >= 0 ? kn[gg].x : 0.f;
+  }
+  __syncthreads();
+  for (int e = tid; e < Cp * BM; e += 256) {
+    const int c = e / BM, m = e - c * BM;
+    const int gg = krow[m];
+    skc[e] = gg >= 0 ? kc[(size_t)gg * Cp + c] : 0.f;
+  }
+  for (int e = tid; e < BM * DP; e += 256) {
+    const int m = e / DP, rem = e - m * DP;
+    const int row = rem / P2, dx = rem - row * P2;  // row = ch P + dy
+    const int gg = krow[m];
+    As[m * AST + rem] = (dx < P && gg >= 0) ? Ac[(size_t)gg * D + (size_t)row * P + dx] : 0.f;
+  }
+
+  // ---- per-tile operands, staged through registers (the rows' elements
+  // spread over all threads)
+  constexpr int RR = (NR * SEG + 255) / 256;
+  float rseg[RR];
+  float rmu[2], rpc[2], rpn = 0.f;
+  auto fetch = [&](int tile) {
+    const int r = tile / ntc, c0 = (tile - r * ntc) * BN;
+#pragma unroll
+    for (int k = 0; k < RR; ++k) {
+      const int e = tid + k * 256;
+      const int q = e / SEG, x = e - q * SEG;
+      rseg[k] = 0.f;
+      if (q < NRr) {
+        const int ch = q / P, dy = q - ch * P;
+        const int cc = c0 + x;
+        if (cc < W) rseg[k] = xp[((size_t)ch * H + r + dy) * W + cc];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int e = tid + k * 256;
+      rmu[k] = 0.f;
+      rpc[k] = 0.f;
+      if (e < Cp * BN) {
+        const int c = e / BN, j = e - c * BN;
+        if (c0 + j < Wc) {
+          const float2 v = pc[(size_t)c * ncand + (size_t)r * Wc + c0 + j];
+          rmu[k] = v.x;
+          rpc[k] = v.y;
+        }
+      }
+    }
+    rpn = (tid < BN && c0 + tid < Wc) ? pn[(size_t)r * Wc + c0 + tid] : 0.f;
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int k = 0; k < RR; ++k) {
+      const int e = tid + k * 256;
+      if (e < NRr * SEG) seg[e] = rseg[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int e = tid + k * 256;
+      if (e < Cp * BN) {
+        smu[e] = rmu[k];
+        spc[e] = rpc[k];
+      }
+    }
+    if (tid < BN) spn[tid] = rpn;
+  };
+
+  if (part < ntile) {
+    fetch(part);
+    stage();
+  }
+  __syncthreads();
+  for (int tile = part; tile < ntile; tile += npb) {
+    const int r = tile / ntc, c0 = (tile - r * ntc) * BN;
+    const int next = tile + npb;
+    if (next < ntile) fetch(next);
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[i][j][q] = 0.f;
+    for (int ch = 0; ch < Cp; ++ch) {
+      const float mb0 = smu[ch * BN + wn * 64 + l32], mb1 = smu[ch * BN + wn * 64 + 32 + l32];
+#pragma unroll 1
+      for (int dy = 0; dy < P; ++dy) {
+        const int row = ch * P + dy;
+        const float* sg = seg + row * SEG;
+#pragma unroll
+        for (int kk = 0; kk < P2 / 2; ++kk) {
+          const int dx = 2 * kk + lhi;
+          float a0 = As[(wm * 64 + l32) * AST + row * P2 + dx];
+          float a1 = As[(wm * 64 + 32 + l32) * AST + row * P2 + dx];
+          float b0 = sg[wn * 64 + l32 + dx] - mb0;
+          float b1 = sg[wn * 64 + 32 + l32 + dx] - mb1;
+          acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
+          acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
+          acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
+          acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+        }
+      }
+    }
+    // epilogue: d~ = ((||a~||^2 + ||p~||^2) - 2 S) + sum_c (P mu_kc - P mu_pc)^2
+    const int colA = c0 + wn * 64 + l32, colB = colA + 32;
+    const size_t tA = (size_t)r * Wc + colA, tB = tA + 32;
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+      const float pp = spn[wn * 64 + nt * 32 + l32];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+        const int i0 = wm * 64 + mt * 32 + 4 * lhi;   // rows i0 + 8 j + h, h < 4
+        __builtin_amdgcn_sched_barrier(0);
+        float v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+          v[q] = fmaf(-2.0f, acc[mt][nt][q], skn[i0 + 8 * (q >> 2) + (q & 3)] + pp);
+#pragma unroll 1
+        for (int c = 0; c < Cp; ++c) {
+          const float qv = spc[c * BN + wn * 64 + nt * 32 + l32];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const float4 kv = *reinterpret_cast<const float4*>(skc + c * BM + i0 + 8 * j);
+            const float d0 = kv.x - qv, d1 = kv.y - qv, d2 = kv.z - qv, d3 = kv.w - qv;
+            v[4 * j] = fmaf(d0, d0, v[4 * j]);
+            v[4 * j + 1] = fmaf(d1, d1, v[4 * j + 1]);
+            v[4 * j + 2] = fmaf(d2, d2, v[4 * j + 2]);
+            v[4 * j + 3] = fmaf(d3, d3, v[4 * j + 3]);
+          }
+        }
+        if ((nt ? colB : colA) < Wc) {
+          const size_t t = nt ? tB : tA;
+#pragma unroll
+          for (int q = 0; q < 16; ++q) {
+            const int i = i0 + 8 * (q >> 2) + (q & 3);
+            if (krow[i] >= 0) dist[(size_t)(kbase + i) * ldd + t] = v[q];
+          }
+        }
+      }
+    }
+    __syncthreads();                         // every wave is done with this tile
+    if (next < ntile) stage();
+    __syncthreads();
+  }
+}
+
 template <int P2>
 void launch_match_t(const glr_plan* pl, const float* xp, const float* Ac, const float* kn,
                     const float* kc, const float* pn, const float* pc, const int32_t* kmap,
@@ -315,6 +507,18 @@ void launch_match_t(const glr_plan* pl, const float* xp, const float* Ac, const 
   const int Hc = pl->Hc, Wc = pl->Wc;
   const int ntc = (Wc + BN - 1) / BN;
   const int nkt = (nk + BM - 1) / BM;
+  if constexpr (P2 >= 4 && P2 <= 8) {
+    if (pl->Cp * pl->P * P2 <= SD_MAX && pl->Cp <= SD_CP) {
+      // persistent blocks: about two per CU over all key tiles
+      const int ntile = Hc * ntc;
+      const int npb = std::max(1, std::min(ntile, (2 * 256 + nkt - 1) / nkt));
+      hipLaunchKernelGGL(k_match_f32_slab<P2>, dim3((unsigned)(nkt * npb)), dim3(256), 0, s, xp,
+                         pl->H, pl->W, pl->P, pl->Cp, Ac, pl->D, (const float4*)kn, kc, pn,
+                         (const float2*)pc, (size_t)pl->Ncand, kmap, g0, nk, npb, dist,
+                         (size_t)pl->ldd);
+      return;
+    }
+  }
   size_t blocks = (size_t)nkt * Hc * ntc;
   hipLaunchKernelGGL(k_match_f32<P2>, dim3((unsigned)blocks), dim3(256), 0, s, xp, pl->H, pl->W,
                      pl->P, pl->Cp, Ac, pl->D, (const float4*)kn, kc, pn, (const float2*)pc,
