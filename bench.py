@@ -59,6 +59,7 @@ def parse():
 KERNEL_SOURCES = {
     "k_wnnm": "paper_2301_03047_amd/csrc/lowrank.hip",
     "k_match_f32": "paper_2301_03047_amd/csrc/match.hip",
+    "k_match_f32_slab": "paper_2301_03047_amd/csrc/match.hip",
     "k_match_bf16": "paper_2301_03047_amd/csrc/match.hip",
     "k_topk_partial": "paper_2301_03047_amd/csrc/topk.hip",
 }
@@ -175,7 +176,13 @@ def main():
     dominant = max(stages, key=stages.get)
 
     # roofline of the dominant kernel
-    match_kernel = "k_match_bf16" if prec == "bf16" else "k_match_f32"
+    # the FP32 form runs its small-patch variant when a key tile's padded
+    # slab (Cp P P2 <= 72 values per key, Cp <= 4) fits in LDS
+    P, P2 = wl.patch, wl.patch + (wl.patch & 1)
+    Cp = wl.dim // (P * P)
+    small = Cp * P * P2 <= 72 and Cp <= 4
+    match_kernel = "k_match_bf16" if prec == "bf16" else (
+        "k_match_f32_slab" if small else "k_match_f32")
     match_peak = PEAK_BF16_MFMA_TFLOPS if prec == "bf16" else PEAK_FP32_MFMA_TFLOPS
     if dominant == "match":
         roof = {"kernel": match_kernel, "bound": "mfma", "achieved": round(match_tflops, 3),
