@@ -501,20 +501,62 @@ k_select_rescore(const float* __restrict__ xp, int H, int W, int P, int Cp, int 
     return;
   }
   const size_t o0 = (size_t)g * S * CAP;
-  const float T = wave_kth_lists(lu + o0, c, S, K, shist[wave]);
-  // margin set: ordered compaction of the entries with L <= T
   int m = 0;
-  for (int sp = 0; sp < S; ++sp) {
-    const int csp = __shfl(c, sp, 64);
-    const size_t o = o0 + (size_t)sp * CAP;
-    for (int base = 0; base < csp; base += 64) {
-      const int i = base + l;
-      const int jv = i < csp ? lj[o + i] : -1;
-      const bool keep = i < csp && ll[o + i] <= T && jv >= 0 && jv < Ncand;
-      const uint64_t msk = __ballot(keep);
-      const int pos = m + lanes_below(msk);
-      if (keep && pos < UW) jj[pos] = jv;
-      m += __popcll(msk);
+  if (tot <= UW) {
+    // every list entry into LDS in list order (entry e of the concatenation
+    // is in the last list whose offset is <= e), up to four loads per lane in
+    // flight; an invalid position gets L = NaN, so it is never kept
+    const int excl = wave_incl_scan(c) - c;  // lanes >= S hold c = 0
+    for (int e0 = 0; e0 < tot; e0 += 256) {
+      int sp[4] = {0, 0, 0, 0}, ex[4] = {0, 0, 0, 0};
+      for (int q = 1; q < S; ++q) {
+        const int eq = __builtin_amdgcn_readlane(excl, q);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (e0 + 64 * k + l >= eq) {
+            sp[k] = q;
+            ex[k] = eq;
+          }
+      }
+      int jv[4];
+      float uv[4], lv[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int e = e0 + 64 * k + l;
+        const size_t o = o0 + (size_t)sp[k] * CAP + (e - ex[k]);
+        jv[k] = e < tot ? lj[o] : -1;
+        uv[k] = e < tot ? lu[o] : 0.f;
+        lv[k] = e < tot ? ll[o] : 0.f;
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int e = e0 + 64 * k + l;
+        if (e < tot) {
+          jj[e] = jv[k];
+          u[e] = uv[k];
+          lo[e] = (jv[k] >= 0 && jv[k] < Ncand) ? lv[k] : __int_as_float(0x7fc00000);
+        }
+      }
+    }
+    wave_sync_lds();
+    const float T = wave_kth_smallest(u, tot, K, shist[wave]);
+    // margin set: ordered compaction of the entries with L <= T
+    m = wave_compact(jj, u, lo, tot, T);
+  } else {
+    const float T = wave_kth_lists(lu + o0, c, S, K, shist[wave]);
+    // margin set: ordered compaction of the entries with L <= T
+    for (int sp = 0; sp < S; ++sp) {
+      const int csp = __shfl(c, sp, 64);
+      const size_t o = o0 + (size_t)sp * CAP;
+      for (int base = 0; base < csp; base += 64) {
+        const int i = base + l;
+        const int jv = i < csp ? lj[o + i] : -1;
+        const bool keep = i < csp && ll[o + i] <= T && jv >= 0 && jv < Ncand;
+        const uint64_t msk = __ballot(keep);
+        const int pos = m + lanes_below(msk);
+        if (keep && pos < UW) jj[pos] = jv;
+        m += __popcll(msk);
+      }
     }
   }
   if (m > UW || m < K) {                     // m < K cannot happen with valid lists
