@@ -30,6 +30,11 @@ MATCH_CASES = [
     (2, 30, 30, 1, 40, 9, "uniform"),
     (1, 40, 40, 16, 20, 8, "smooth"),
     (4, 24, 24, 4, 30, 11, "dup"),
+    # stage heights of the tiled FP32 matcher for P2 = 10 and 12, and the
+    # small-patch (persistent) matcher with P2 = 8
+    (2, 40, 60, 9, 40, 10, "smooth"),
+    (1, 40, 40, 11, 30, 8, "uniform"),
+    (1, 45, 140, 7, 70, 12, "smooth"),
 ]
 
 
