@@ -369,18 +369,19 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
       const bool act = paired && ga != 0.f && gg > tol2 * nn;
       // the lower lane takes the other column's update c (b + t a), the upper
       // lane c (a - t b): new m = o + f m, new scale c times the partner's
-      float c = 1.f, f = 0.f;
-      double t = 0.0;
+      float c = 1.f, f = 0.f, tf = 0.f;
       if (act) {
         float s;
-        t = jacobi_angle(n1, n2, ga, c, s);
-        f = (float)(first ? t : -t) * (sc * __builtin_amdgcn_rcpf(osc));   // rcp within 1 ulp
+        tf = (float)jacobi_angle(n1, n2, ga, c, s);
+        f = (first ? tf : -tf) * (sc * __builtin_amdgcn_rcpf(osc));   // rcp within 1 ulp
       }
       if (!paired) f = 1.f;                      // o is 0 here: m stays
 #pragma unroll
       for (int k = 0; k < KP; ++k) m[k] = fmaf(f, m[k], o[k]);
       if (paired) {
-        al = fmaxf((float)(first ? (double)n2 + t * (double)ga : (double)n1 - t * (double)ga), 0.f);
+        // the tracked norm only steers the next angles (FP32 is enough;
+        // every sweep starts from the exact norms)
+        al = fmaxf(first ? fmaf(tf, ga, n2) : fmaf(-tf, ga, n1), 0.f);
         sc = c * osc;
         cid = ocid;
       }
