@@ -188,45 +188,46 @@ __device__ __forceinline__ void qr_chunk(float* Rl, const float* Bl, const float
 #pragma unroll
   for (int i = 0; i < NB; ++i) b[i] *= fs;
   for (int k = 0; k < K; ++k) {
-    // lane k builds the reflector that zeroes its chunk column below
-    // R[k][k], normalised to a unit leading entry (u = v / v0, scale
-    // tau = |v0| / ||v|| in [1, 2]) so that no step overflows however
-    // small the column's residual is
-    if (lane == k) {
-      float q[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};   // short dependency chains
+    // lane k's chunk column goes to LDS for every lane; each lane's dot
+    // product with it is, in lane k, the squared norm of that column below
+    // R[k][k].  Lane k then builds the reflector that zeroes the column,
+    // normalised to a unit leading entry (v = (x0 - alpha, b) / v0, scale
+    // tau = |v0| / ||v|| in [1, 2]) so that no step overflows however small
+    // the column's residual is; its 1 / v0 and tau reach the other lanes as
+    // scalars
+    if (lane == k) store_vec(Cb, b);
+    wave_sync();
+    float bk[NB];
+    load_vec(bk, Cb);
+    float w[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};   // short dependency chains
 #pragma unroll
-      for (int i = 0; i < NB; ++i) q[i & 7] = fmaf(b[i], b[i], q[i & 7]);
-      const float sig2 = ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
+    for (int i = 0; i < NB; ++i) w[i & 7] = fmaf(bk[i], b[i], w[i & 7]);
+    const float dot = ((w[0] + w[1]) + (w[2] + w[3])) + ((w[4] + w[5]) + (w[6] + w[7]));
+    float rv = 0.f, tau = 0.f;
+    if (lane == k) {
       const float x0 = Rl[k * LS + k];
       // hardware square root and reciprocals (within 1 ulp): the
       // reflector stays orthogonal to working precision
-      const float nrm = __builtin_amdgcn_sqrtf(fmaf(x0, x0, sig2));
-      float rv = 0.f, tau = 0.f, alpha = x0;
-      if (sig2 > 0.f && nrm > 0.f) {
+      const float nrm = __builtin_amdgcn_sqrtf(fmaf(x0, x0, dot));
+      float alpha = x0;
+      if (dot > 0.f && nrm > 0.f) {
         alpha = x0 >= 0.f ? -nrm : nrm;
-        const float v0 = x0 - alpha;        // |v0| = |x0| + nrm >= nrm
+        const float v0 = x0 - alpha;          // |v0| = |x0| + nrm >= nrm
         rv = __builtin_amdgcn_rcpf(v0);
         tau = fabsf(v0) * __builtin_amdgcn_rcpf(nrm);
       }
-      float u[NB];
-#pragma unroll
-      for (int i = 0; i < NB; ++i) u[i] = b[i] * rv;
-      store_vec(Cb, u);
-      Cb[NB] = tau;
       Rl[k * LS + k] = alpha;
     }
-    wave_sync();
-    const float tau = Cb[NB];
+    rv = bcast(rv, k);
+    tau = bcast(tau, k);
+    // column j: R[k][j] -= sc, chunk column -= sc rv b_k with
+    // sc = tau (R[k][j] + rv (b_k . b_j))
     if (tau > 0.f && lane > k && lane < K) {
-      float u[NB];
-      load_vec(u, Cb);
-      float w[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int i = 0; i < NB; ++i) w[i & 7] = fmaf(u[i], b[i], w[i & 7]);
       const float rk = Rl[lane * LS + k];
-      const float sc = tau * (rk + (((w[0] + w[1]) + (w[2] + w[3])) + ((w[4] + w[5]) + (w[6] + w[7]))));
+      const float sc = tau * fmaf(rv, dot, rk);
+      const float f = -sc * rv;
 #pragma unroll
-      for (int i = 0; i < NB; ++i) b[i] = fmaf(-sc, u[i], b[i]);
+      for (int i = 0; i < NB; ++i) b[i] = fmaf(f, bk[i], b[i]);
       Rl[lane * LS + k] = rk - sc;
     }
     wave_sync();
