@@ -3,17 +3,17 @@
 // minimisation [Gu et al. 2014]).
 //
 // One wave per group Y (D x K, column j = member patch j); lane j owns
-// column j and keeps it in registers; columns move between lanes through LDS
-// with 16-byte accesses (many in flight per wave):
-//  1. rows are streamed in chunks of 64 (each lane loads one row and removes
-//     its mean, Yc = Y - mu 1^T); the chunk is folded into the running
-//     triangular factor R by Householder reflections on [R; chunk]; the
-//     reflector column is broadcast through LDS;
-//  2. one-sided Jacobi on the columns of R^T (round-robin pairs, partner
-//     columns exchanged through LDS, rotation angles computed in FP64); the
-//     converged columns are sigma_i v_i with v_i the right singular vectors
-//     of R, hence of Yc, so V is read off them without accumulating
-//     rotations;
+// column j and keeps it in registers:
+//  1. rows are streamed in chunks of up to 64 (each lane loads one row and
+//     removes its mean, Yc = Y - mu 1^T); the chunk is folded into the
+//     running triangular factor R by Householder reflections on [R; chunk];
+//     the reflector's column is broadcast through LDS, its scalars by lane
+//     reads;
+//  2. one-sided Jacobi on the columns of R^T (odd-even transposition
+//     ordering, partner columns moved between lanes by DPP, rotation angles
+//     computed in FP64); the converged columns are sigma_i v_i with v_i the
+//     right singular vectors of R, hence of Yc, so V is read off them
+//     without accumulating rotations;
 //  3. WNNM: sigma_hat = sqrt(max(s^2 - K sigma^2, 0)),
 //     tau = c sqrt(K) sigma^2 / (sigma_hat + eps), s' = max(s - tau, 0),
 //     w = (s - s') / s;
