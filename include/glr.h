@@ -23,6 +23,11 @@
  *   unspecified; the status is returned and a detail string is available from
  *   glr_last_error_message().  No C++ exception crosses this interface.
  * - Device pointers must be 16-byte aligned; the workspace 256-byte aligned.
+ * - The workspace carries state from one call of a plan to the next (the
+ *   statistics and the top-K scan's per-key bounds, which every scan leaves
+ *   at +inf).  A plan initialises a workspace the first time it is given it
+ *   (a pointer different from the last one it saw); between calls the
+ *   caller must not write the workspace or use it for another plan.
  * - Image layouts: real data is planar float32 [C][H][W] (C = frames for
  *   CACTI, bands for MSFA); MRI data is complex64 interleaved [H][W]
  *   (re, im pairs).  "Real channels" C' is C for real data and 2 for MRI.
