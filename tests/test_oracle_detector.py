@@ -150,3 +150,39 @@ def test_keys_on_workload_are_distinct_sorted_in_range():
     assert len(keys) == wl.n_keys
     assert np.all(np.diff(keys) > 0)
     assert keys[0] >= 0 and keys[-1] < wl.n_cand
+
+
+def test_quantise_complex_by_hand():
+    """Hand-worked values of the complex quantiser q = rint(255 (m / max m)),
+    m = re^2 + im^2 (squared magnitude, not magnitude), every FP32 step exact
+    here except the one sum that lands on a half-way point.
+
+    Pixel by pixel (max m = 1, so 1/max = 1):
+      (1, 0)            m = 1        255 m = 255
+      (0.5, b)          m = 0.25 + b^2 rounds to t with 255 t = 126.5 exactly
+                        -> round half to even gives 126 (half-up would give 127)
+      (0, 0.5)          m = 0.25     63.75    -> 64
+      (0.5, 0.5)        m = 0.5      127.5    -> 128 (half to even)
+      (0.25, 0.25)      m = 0.125    31.875   -> 32
+      (0.75, 0)         m = 0.5625   143.4375 -> 143
+      (0, 0), (0, 0)    0
+      (0.125, 0)        m = 1/64     3.984375 -> 4
+    The magnitude |z| would give 180 for (0.5, 0.5); a missing 1/max scale
+    fails on the same image scaled by 2 (max m = 4, same q); floor instead
+    of rint gives 63 for (0, 0.5)."""
+    from fractions import Fraction
+    f32 = np.float32
+    b = f32(0.4960629343986511)
+    re = np.array([[1, 0.5, 0], [0.5, 0.25, 0.75], [0, 0, 0.125]], dtype=f32)
+    im = np.array([[0, b, 0.5], [0.5, 0.25, 0], [0, 0, 0]], dtype=f32)
+    t = f32(0.25) + b * b
+    assert Fraction(float(f32(255) * t)) == Fraction(253, 2)     # the half-way case
+    expect = [[255, 126, 64], [128, 32, 143], [0, 0, 4]]
+    assert det.quantise_complex(re, im).tolist() == expect
+    # scaling by two multiplies m and max m by four: q is unchanged
+    assert det.quantise_complex(2 * re, 2 * im).tolist() == expect
+    # a non-power-of-two maximum: s = fl(1/max) is applied as a product
+    # (255/9 = 28.33 is far from a rounding boundary: 28)
+    re3 = np.array([[3, 1, 0]], dtype=f32)          # m = 9, 1, 0
+    im3 = np.zeros_like(re3)
+    assert det.quantise_complex(re3, im3).tolist() == [[255, 28, 0]]

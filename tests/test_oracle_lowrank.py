@@ -112,3 +112,57 @@ def test_aggregate_single_member_by_hand():
     out, cnt = ag.aggregate(xbar, P, idx, est)
     assert out[0, 1, 1] == 3.0 and out[0, 0, 0] == 2.0 and out[0, 2, 2] == 4.0
     assert cnt[1, 1] == 2 and cnt[3, 3] == 0
+
+
+def test_shrink_groups_orientation_closed_form():
+    """Group orientation of shrink_groups: members are the columns of the
+    D x K group and the mean is taken over members.  The group's members are
+    planted as p_j = m + alpha_j u, so Y = m 1^T + u alpha^T has rank 2 and
+    only the member-mean removal leaves a rank-1 matrix:
+    Y - mean = u (alpha - mean(alpha))^T with singular value
+    ||u|| ||alpha - mean(alpha)|| = 1.5 * 2 = 3.  With K = 4, sigma = 0.5,
+    c = 2 sqrt(2) the WNNM weight is tau = c sqrt(K) sigma^2 / sqrt(s^2 - K
+    sigma^2) = 2 sqrt(2) * 2 * 0.25 / sqrt(8) = 0.5 (the golden rank-1
+    value), so s' = 2.5 and the estimate of member j is
+    m + mean(alpha) u + (2.5 / 3) (alpha_j - mean(alpha)) u.
+    A transposed group (K x D) or a mean over patch elements gives other
+    singular values (the second one is not zero) and another estimate."""
+    C, P, H, W = 2, 2, 6, 9
+    D, K = C * P * P, 4
+    Wc = W - P + 1
+    rng = np.random.default_rng(21)
+    x = rng.uniform(size=(C, H, W))
+    m = np.linspace(0.1, 0.8, D)                       # d = (c P + dy) P + dx
+    u = np.array([0.75, 0.75, 0.75, 0.75, 0.0, 0.0, 0.0, 0.0])   # ||u|| = 1.5
+    alpha = np.array([2.0, 0.0, 2.0, 0.0])             # mean 1, centred norm 2
+    tops = [(0, 0), (0, 3), (0, 6), (3, 2)]            # disjoint 2 x 2 patches
+    for j, (r, c0) in enumerate(tops):
+        for ch in range(C):
+            for dy in range(P):
+                for dx in range(P):
+                    d = (ch * P + dy) * P + dx
+                    x[ch, r + dy, c0 + dx] = m[d] + alpha[j] * u[d]
+    idx = np.array([[r * Wc + c0 for (r, c0) in tops]])
+    Xhat, sv = lr.shrink_groups(x, P, idx, 0.5, 2 * np.sqrt(2), 1e-16)
+    assert Xhat.shape == (1, K, D) and sv.shape == (1, K)
+    np.testing.assert_allclose(sv[0], [3.0, 0.0, 0.0, 0.0], atol=1e-12)
+    for j in range(K):
+        expect = m + 1.0 * u + (2.5 / 3.0) * (alpha[j] - 1.0) * u
+        np.testing.assert_allclose(Xhat[0, j], expect, atol=1e-12)
+
+
+def test_gather_groups_loop_by_loop():
+    """gather_groups returns member-major [N][K][D] with d = (c P + dy) P + dx,
+    compared with an explicit loop over members and patch elements."""
+    C, P, H, W = 3, 3, 7, 8
+    Wc = W - P + 1
+    x = np.random.default_rng(22).uniform(size=(C, H, W))
+    idx = np.array([[0, 5, 17], [29, 3, 11]])
+    G = lr.gather_groups(x, P, idx)
+    for g in range(idx.shape[0]):
+        for j in range(idx.shape[1]):
+            r, c0 = divmod(int(idx[g, j]), Wc)
+            for ch in range(C):
+                for dy in range(P):
+                    for dx in range(P):
+                        assert G[g, j, (ch * P + dy) * P + dx] == x[ch, r + dy, c0 + dx]
