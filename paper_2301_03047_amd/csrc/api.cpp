@@ -61,12 +61,11 @@ glr_status check_plan_ws(const glr_plan* pl, const void* ws, const char* fn) {
   return GLR_OK;
 }
 
-// Stats live in the workspace: clear them the first time a workspace is seen,
-// and set the top-K scan's shared bounds to +inf (each scan leaves them so).
+// Stats live in the workspace: clear them the first time a workspace is seen.
+// (The top-K scan's per-key bounds are reset by every match call itself.)
 void ensure_stats(glr_plan* pl, char* ws, hipStream_t s) {
   if (pl->stats_ws != ws) {
     launch_fill_u32((uint32_t*)(ws + pl->ws.stats), 0u, sizeof(DevStats) / 4, s);
-    launch_fill_u32((uint32_t*)(ws + pl->ws.tsh), 0xffffffffu, (size_t)pl->n_chunk, s);
     pl->stats_ws = ws;
   }
   pl->last_stream = s;
@@ -141,7 +140,7 @@ glr_status match_stage(glr_plan* pl, const float* xp, const int32_t* keys, int32
                         (float*)(ws + pl->ws.blo), pl->mcap};
   {
     StageTimer t(pl, s, T_NORMS);
-    launch_gather_keys(pl, xp, keys, A, s);
+    launch_gather_keys(pl, xp, keys, A, tsh, s);
     if (bf) {
       launch_key_meta(pl, A, Ab, kmb, s);
       launch_cand_meta(pl, xp, cmeta, cm2, s);

@@ -117,8 +117,9 @@ void launch_from_planar(const float* p, float2* z, int n, hipStream_t s);
 void launch_detect(const glr_plan* pl, const float* xp, char* ws, int32_t* keys, hipStream_t s);
 
 // match.hip
+// also resets the top-K scan's per-key bounds tsh[0..min(n_chunk, N)) to +inf
 void launch_gather_keys(const glr_plan* pl, const float* xp, const int32_t* keys, float* A,
-                        hipStream_t s);
+                        uint32_t* tsh, hipStream_t s);
 int bf16_key_row(int P);     // bf16 values per key and channel in the BF16 key layout
 // kmb[N] float4 (||a||^2, mu_k, sum a, ||a||); Ab (BF16 key slices) may be null
 void launch_key_meta(const glr_plan* pl, const float* A, uint16_t* Ab, float* kmb, hipStream_t s);

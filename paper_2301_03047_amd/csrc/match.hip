@@ -14,6 +14,8 @@
 // The candidate operand is never materialised: a 128-candidate tile lies on
 // one row of the top-left grid, so for each (channel, dy) the tile's patch
 // rows are one image row segment of 128 + P - 1 values staged in LDS.
+#include <algorithm>
+
 #include "common.h"
 #include "internal.h"
 
@@ -23,10 +25,14 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // ---------------------------------------------------------------- key matrix
 // A[g][d] = x[c][r_g + dy][c_g + dx], d = (c*P + dy)*P + dx.  One wave per key.
+// Also sets the top-K scan's per-key bounds tsh[0..n_tsh) to +inf, so every
+// match call starts from them whatever an earlier call left.
 __global__ void k_gather_keys(const float* __restrict__ xp, int H, int W, int P, int D,
-                              const int32_t* __restrict__ keys, int N, float* __restrict__ A) {
+                              const int32_t* __restrict__ keys, int N, float* __restrict__ A,
+                              uint32_t* __restrict__ tsh, int n_tsh) {
   const int g = blockIdx.x;
   if (g >= N) return;
+  if (threadIdx.x == 0 && g < n_tsh) tsh[g] = 0xffffffffu;
   const int Wc = W - P + 1;
   const int t = keys[g];
   const int gr = t / Wc, gc = t - gr * Wc;
@@ -879,9 +885,9 @@ void launch_match_bf16_t(const glr_plan* pl, const float* xp, const uint16_t* Ab
 }  // namespace
 
 void launch_gather_keys(const glr_plan* pl, const float* xp, const int32_t* keys, float* A,
-                        hipStream_t s) {
+                        uint32_t* tsh, hipStream_t s) {
   hipLaunchKernelGGL(k_gather_keys, dim3(pl->N), dim3(64), 0, s, xp, pl->H, pl->W, pl->P, pl->D,
-                     keys, pl->N, A);
+                     keys, pl->N, A, tsh, std::min(pl->n_chunk, pl->N));
 }
 
 int bf16_key_row(int P) { return bf16_slices(P) * 8; }

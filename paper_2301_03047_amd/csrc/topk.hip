@@ -3,9 +3,13 @@
 // The matcher's d~ (centred form) carries a rounding error bounded by
 //     eps_j = c1 ||a|| ||pbar_j|| + c2 R_j^2,
 //     R_j = ||a|| + ||pbar_j|| + sqrt(D) |mu_k - mu_j|,
-// with a, pbar_j the centred key and candidate, u = 2^-24, b = 2^-9 and
+// with a, pbar_j the centred key and candidate, u = 2^-24 (FP32 unit
+// round-off), b = 2^-8 (BF16 round-to-nearest-even unit round-off: 8
+// significant bits) and
 //     c2 = (3 D + 26) u       (FP32 dot-product sums, centring, epilogue),
-//     c1 = 4 (2 b + b^2)      (BF16 operand rounding; 0 for the FP32 form),
+//     c1 = 4 (2 b + b^2)      (BF16 operand rounding of both factors, whose
+//                              worst case is 2 (2 b + b^2) ||a|| ||pbar||
+//                              on -2 S; 0 for the FP32 form),
 // each with a safety factor of two.  With U_j = d~_j + eps_j and
 // L_j = d~_j - eps_j, let T be the K-th smallest U_j of a key: every member
 // of the exact top-K has L_j <= d_j <= T, so the margin set {j : L_j <= T}
@@ -811,7 +815,7 @@ void launch_topk_partial(const glr_plan* pl, const float* dist, const float* kmb
                          uint32_t* tsh, int32_t* lj, float* lu, float* ll, int32_t* lcnt,
                          hipStream_t s) {
   const double u = 5.9604644775390625e-08;      // 2^-24
-  const double b = 0.001953125;                 // 2^-9
+  const double b = 0.00390625;                  // 2^-8, BF16 unit round-off
   // coefficients rounded up so that the float values are not below the bound
   float coef = 0.f, coef2, cz;
   if (bf16) {
@@ -822,8 +826,8 @@ void launch_topk_partial(const glr_plan* pl, const float* dist, const float* kmb
     coef2 = std::nextafter((float)(2.02 * (pl->D + pl->Cp + 4.0) * u), 1.f);
     cz = std::nextafter((float)(8.02 * pl->P * u), 1.f);
   }
-  // tsh[0..nk) holds +inf here: set when the workspace is first used and
-  // restored by the rescoring kernel after every scan
+  // tsh[0..nk) holds +inf here: set by the key gather at the start of every
+  // match call and restored by the rescoring kernel after every scan
   // the FP32 form's margin sets stay far below the BF16 form's: a smaller
   // wave buffer and 768-candidate steps (fewer registers) fit four waves per
   // SIMD instead of three
