@@ -23,11 +23,12 @@
  *   unspecified; the status is returned and a detail string is available from
  *   glr_last_error_message().  No C++ exception crosses this interface.
  * - Device pointers must be 16-byte aligned; the workspace 256-byte aligned.
- * - The workspace carries state from one call of a plan to the next (the
- *   statistics and the top-K scan's per-key bounds, which every scan leaves
- *   at +inf).  A plan initialises a workspace the first time it is given it
- *   (a pointer different from the last one it saw); between calls the
- *   caller must not write the workspace or use it for another plan.
+ * - The workspace carries one piece of state from one call of a plan to the
+ *   next: the statistics read by glr_read_stats().  A plan clears them the
+ *   first time it is given a workspace (a pointer different from the last
+ *   one it saw); every other buffer is written by a call before it is read.
+ *   Between calls the caller may reuse the workspace for anything else, at
+ *   the cost of those statistics.
  * - Image layouts: real data is planar float32 [C][H][W] (C = frames for
  *   CACTI, bands for MSFA); MRI data is complex64 interleaved [H][W]
  *   (re, im pairs).  "Real channels" C' is C for real data and 2 for MRI.
@@ -204,6 +205,29 @@ GLR_API glr_status glr_lowrank_aggregate(glr_plan* plan, const void* x_in, const
  * not alias x_in. */
 GLR_API glr_status glr_prior_step(glr_plan* plan, const void* x_in, float sigma, void* x_out,
                           void* ws, void* stream);
+
+/* Allocation-free glr_prior_step, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  The workspace is a library-owned static device array
+ * of GLR_STATIC_SCRATCH_BYTES per GPU (held from the library's load on that
+ * GPU until the process ends), looked up on the CURRENT device at the first
+ * call there; stream must belong to that device.  The caller still passes
+ * x_in and x_out (layouts as for glr_prior_step; x_out must not alias x_in).
+ * The call reaches no hipMalloc, hipFree or allocating library routine.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (any plans, any streams) race and must be serialised by the caller.
+ * The statistics region is cleared by each call, so glr_read_stats() after
+ * it reports that call alone, until the next call on the same GPU.
+ * BF16-form plans read one 4-byte counter back to the host (a stream
+ * synchronisation), as glr_prior_step does.
+ * Errors: GLR_ERR_WORKSPACE_TOO_SMALL when the plan's workspace
+ * (glr_workspace_size) exceeds GLR_STATIC_SCRATCH_BYTES; GLR_ERR_UNSUPPORTED
+ * for plans created with timing != 0 (their event pairs are created on
+ * demand); GLR_ERR_HIP if the array's address cannot be obtained; otherwise
+ * as glr_prior_step.  Nothing is launched on an error. */
+#define GLR_STATIC_SCRATCH_BYTES (64u << 20)
+GLR_API glr_status glr_prior_step_static(glr_plan* plan, const void* x_in, float sigma,
+                                         void* x_out, void* stream);
 
 /* --------------------------------------------------------------- loop
  * Run outer iterations t_begin .. t_end-1 of the GAP/ADMM loop with the GLR

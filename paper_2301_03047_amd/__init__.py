@@ -7,6 +7,7 @@ HIP kernels.  Importing works without a GPU; calls need the built
 ``libglr.so`` and a device.
 """
 from .glr import (Plan, Cnn, GlrError, lib, library_path, CACTI, MRI, MSFA,
-                  STATUS_NAMES)
+                  STATUS_NAMES, STATIC_SCRATCH_BYTES)
 
-__all__ = ["Plan", "Cnn", "GlrError", "lib", "library_path", "CACTI", "MRI", "MSFA", "STATUS_NAMES"]
+__all__ = ["Plan", "Cnn", "GlrError", "lib", "library_path", "CACTI", "MRI", "MSFA", "STATUS_NAMES",
+           "STATIC_SCRATCH_BYTES"]

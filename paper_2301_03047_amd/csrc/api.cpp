@@ -352,6 +352,11 @@ glr_status data_step_impl(glr_plan* pl, const void* y, const void* x, const void
 
 }  // namespace
 
+glr_status glr_set_error(glr_status s, const char* msg) {
+  g_err = msg ? msg : "";
+  return s;
+}
+
 // ================================================================== ABI
 extern "C" {
 

@@ -73,6 +73,9 @@ struct glr_plan {
   long long match_launches;
 };
 
+// Sets the thread-local detail string of glr_last_error_message(); returns s.
+glr_status glr_set_error(glr_status s, const char* msg);
+
 // list capacity of one top-K split (entries) and of the union per key
 #define GLR_SPLIT_CAP 1024
 #define GLR_UNION_CAP 4096

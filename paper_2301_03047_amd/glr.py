@@ -18,6 +18,7 @@ STATUS_NAMES = {0: "GLR_OK", 1: "GLR_ERR_INVALID_ARG", 2: "GLR_ERR_SHAPE",
                 3: "GLR_ERR_ALIGNMENT", 4: "GLR_ERR_UNSUPPORTED",
                 5: "GLR_ERR_WORKSPACE_TOO_SMALL", 6: "GLR_ERR_HIP"}
 _MODALITY = {"cacti": CACTI, "mri": MRI, "msfa": MSFA}
+STATIC_SCRATCH_BYTES = 64 << 20          # GLR_STATIC_SCRATCH_BYTES
 
 _c_i32 = ctypes.c_int32
 _vp = ctypes.c_void_p
@@ -96,6 +97,7 @@ def lib():
         "glr_match_topk": (st, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
         "glr_lowrank_aggregate": (st, [_vp, _vp, _vp, ctypes.c_float, _vp, _vp, _vp, _vp]),
         "glr_prior_step": (st, [_vp, _vp, ctypes.c_float, _vp, _vp, _vp]),
+        "glr_prior_step_static": (st, [_vp, _vp, ctypes.c_float, _vp, _vp]),
         "glr_state_bytes": (st, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
         "glr_reconstruct": (st, [_vp, _vp, _vp, _c_i32, _c_i32, _vp, _vp, _vp]),
         "glr_read_stats": (st, [_vp, ctypes.POINTER(Stats), _c_i32]),
@@ -285,6 +287,15 @@ class Plan:
         out = self._empty_image() if out is None else out
         _check(lib().glr_prior_step(self._h, _ptr(x), float(sigma), _ptr(out), _ptr(self.ws),
                                     self._stream()))
+        return out
+
+    def prior_step_static(self, x, sigma, out=None):
+        """The prior step on the library's static per-GPU scratch (no workspace
+        argument; the plan's workspace must fit in STATIC_SCRATCH_BYTES)."""
+        self._image(x)
+        out = self._empty_image() if out is None else out
+        _check(lib().glr_prior_step_static(self._h, _ptr(x), float(sigma), _ptr(out),
+                                           self._stream()))
         return out
 
     # ------------------------------------------------------------ loop

@@ -102,3 +102,43 @@ def test_library_fails_loudly_when_missing(tmp_path, monkeypatch):
     monkeypatch.setattr(g, "library_path", lambda: str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError):
         g.lib()
+
+
+def _plan_handle(**kw):
+    L = glr.lib()
+    prob = Problem(glr.CACTI, kw.pop("H"), kw.pop("W"), kw.pop("C"), FAKE_MASK)
+    par = Params()
+    L.glr_params_default(ctypes.byref(par))
+    par.patch, par.n_keys, par.k = kw.pop("P"), kw.pop("N"), kw.pop("K")
+    for k, v in kw.items():
+        setattr(par, k, v)
+    h = ctypes.c_void_p()
+    ws = ctypes.c_size_t()
+    assert L.glr_plan_create(ctypes.byref(h), ctypes.byref(prob), ctypes.byref(par),
+                             ctypes.byref(ws)) == 0
+    return h, ws.value
+
+
+def test_static_prior_step_refuses_on_the_host():
+    """The allocation-free prior step checks the plan against its fixed
+    scratch size (and refuses timing plans) before any device call."""
+    L = glr.lib()
+    fake = ctypes.c_void_p(FAKE_MASK)
+    h, ws = _plan_handle(H=256, W=256, C=8, P=6, N=512, K=32)
+    try:
+        assert ws > glr.STATIC_SCRATCH_BYTES
+        st = L.glr_prior_step_static(h, fake, ctypes.c_float(0.05), ctypes.c_void_p(2 * FAKE_MASK),
+                                     None)
+        assert st == 5, L.glr_last_error_message()
+        assert b"static scratch" in L.glr_last_error_message()
+    finally:
+        L.glr_plan_destroy(h)
+    h, ws = _plan_handle(H=64, W=64, C=4, P=6, N=32, K=16, timing=1)
+    try:
+        assert ws <= glr.STATIC_SCRATCH_BYTES
+        st = L.glr_prior_step_static(h, fake, ctypes.c_float(0.05), ctypes.c_void_p(2 * FAKE_MASK),
+                                     None)
+        assert st == 4, L.glr_last_error_message()
+    finally:
+        L.glr_plan_destroy(h)
+    assert L.glr_prior_step_static(None, fake, ctypes.c_float(0.05), fake, None) == 1
