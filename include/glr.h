@@ -131,6 +131,12 @@ typedef struct glr_stats {
   int64_t fallback_steps;     /* judged iterations that fell back to GLR         */
   float judge_delta_last;     /* deviation measured by the last judge            */
   float ms_cnn, ms_judge;     /* with timing: CNN forward, judge (subset GLR)    */
+  int64_t regather_keys;      /* keys whose margin set was re-derived from their
+                                 distance row (a candidate-range list of the
+                                 top-K scan overflowed)                          */
+  float ms_rematch;           /* with timing: the BF16 form's FP32 re-match
+                                 matcher launches (not in ms_match)              */
+  int64_t rematch_launches;   /* those launches                                  */
 } glr_stats;
 
 typedef struct glr_plan glr_plan;

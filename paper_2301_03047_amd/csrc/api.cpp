@@ -107,7 +107,8 @@ void fold_timers(glr_plan* pl) {
   pl->ev_used = 0;
 }
 enum { T_DETECT = 0, T_MATCH, T_TOPK, T_SELECT, T_LOWRANK, T_AGG, T_DATA, T_NORMS, T_CNN, T_JUDGE,
-       T_COUNT };
+       T_REMATCH, T_COUNT };
+static_assert(T_COUNT <= GLR_STAGE_SLOTS, "stage timer slots");
 
 // ---------------------------------------------------------------- prior step
 // xp: planar [Cp][H][W]; xo: planar output; keys_in: optional caller keys.
@@ -126,6 +127,7 @@ glr_status match_stage(glr_plan* pl, const float* xp, const int32_t* keys, int32
   float* pc = (float*)(ws + pl->ws.pc);
   float* pq = (float*)(ws + pl->ws.pq);
   uint32_t* tsh = (uint32_t*)(ws + pl->ws.tsh);
+  float* tkey = (float*)(ws + pl->ws.tkey);
   float* dist = (float*)(ws + pl->ws.dist);
   int32_t* lj = (int32_t*)(ws + pl->ws.lj);
   float* lu = (float*)(ws + pl->ws.lu);
@@ -149,14 +151,15 @@ glr_status match_stage(glr_plan* pl, const float* xp, const int32_t* keys, int32
       launch_cand_meta_pc(pl, xp, pn, pc, pq, s);
     }
   }
-  // FP32 pass over keys (kmap == null: rows 0..n) or over a key list
+  // FP32 pass over keys (kmap == null: rows 0..n) or over a key list (the
+  // BF16 form's re-matched keys, whose matcher time is kept apart)
   auto fp32_pass = [&](const int32_t* kmap, int n) {
     for (int g0 = 0; g0 < n; g0 += pl->n_chunk) {
       const int nk = std::min(pl->n_chunk, n - g0);
       {
-        StageTimer t(pl, s, T_MATCH);
+        StageTimer t(pl, s, kmap ? T_REMATCH : T_MATCH);
         launch_match_f32(pl, xp, Ac, kn, kc, pn, pc, kmap, g0, nk, dist, s);
-        if (pl->timing) pl->match_launches++;
+        if (pl->timing) (kmap ? pl->rematch_launches : pl->match_launches)++;
       }
       {
         StageTimer t(pl, s, T_TOPK);
@@ -165,7 +168,7 @@ glr_status match_stage(glr_plan* pl, const float* xp, const int32_t* keys, int32
       {
         StageTimer t(pl, s, T_SELECT);
         launch_select_rescore(pl, xp, A, kmap, g0, nk, lj, lu, ll, lcnt, idx_out, dd_out, oflag,
-                              tsh, 0, bm, st, s);
+                              tsh, 0, bm, dist, kn, pq, 0, tkey, st, s);
       }
     }
   };
@@ -191,7 +194,7 @@ glr_status match_stage(glr_plan* pl, const float* xp, const int32_t* keys, int32
     {
       StageTimer t(pl, s, T_SELECT);
       launch_select_rescore(pl, xp, A, nullptr, g0, nk, lj, lu, ll, lcnt, idx_out, dd_out, oflag,
-                            tsh, 1, bm, st, s);
+                            tsh, 1, bm, dist, kmb, cm2, 1, tkey, st, s);
       launch_collect_flags(oflag, g0, nk, klist, kcount, st, s);
     }
   }
@@ -532,6 +535,7 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
   L.pq = c.take((size_t)Ncand * 8);
   L.Ab = c.take(bf ? (size_t)pl->N * Cp * bf16_key_row(P) * 2 : 0);
   L.tsh = c.take((size_t)pl->n_chunk * 4);
+  L.tkey = c.take((size_t)pl->n_chunk * 4);
   L.klist = c.take(bf ? (size_t)pl->N * 4 : 0);
   L.kcount = c.take(bf ? 4 : 0);
   pl->mcap = (int)std::min<long long>(Ncand, 32768);
@@ -571,6 +575,7 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
   pl->last_stream = nullptr;
   for (double& m : pl->ms) m = 0.0;
   pl->match_launches = 0;
+  pl->rematch_launches = 0;
   if (workspace_bytes) *workspace_bytes = L.total;
   *out = pl;
   return GLR_OK;
@@ -838,6 +843,7 @@ glr_status glr_read_stats(glr_plan* pl, glr_stats* out, int32_t reset) {
     out->jacobi_sweeps_sum = (int64_t)d.sweeps_sum;
     out->keys_selected = d.keys_selected;
     out->rematch_keys = (int64_t)d.rematch;
+    out->regather_keys = (int64_t)d.regather;
     if (reset) {
       launch_fill_u32((uint32_t*)((char*)pl->stats_ws + pl->ws.stats), 0u, sizeof(DevStats) / 4,
                       pl->last_stream);
@@ -854,6 +860,8 @@ glr_status glr_read_stats(glr_plan* pl, glr_stats* out, int32_t reset) {
   out->ms_norms = (float)pl->ms[T_NORMS];
   out->ms_cnn = (float)pl->ms[T_CNN];
   out->ms_judge = (float)pl->ms[T_JUDGE];
+  out->ms_rematch = (float)pl->ms[T_REMATCH];
+  out->rematch_launches = pl->rematch_launches;
   out->match_launches = pl->match_launches;
   out->surrogate_steps = pl->sur_steps;
   out->fallback_steps = pl->fallback_steps;
@@ -861,6 +869,7 @@ glr_status glr_read_stats(glr_plan* pl, glr_stats* out, int32_t reset) {
   if (reset) {
     for (double& m : pl->ms) m = 0.0;
     pl->match_launches = 0;
+    pl->rematch_launches = 0;
     pl->sur_steps = pl->fallback_steps = 0;
   }
   return GLR_OK;

@@ -18,7 +18,10 @@ struct DevStats {
   int sweeps_max;
   int keys_selected;
   int rematch;
+  int regather;                  // keys whose margin set was re-derived from the distance row
 };
+
+#define GLR_STAGE_SLOTS 12
 
 // Byte offsets of the workspace buffers (all 256-aligned).
 struct WsLayout {
@@ -31,6 +34,7 @@ struct WsLayout {
   size_t Ac, kn, kc, pn, pc, pq; // FP32 form: channel-centred keys and metadata
   size_t Ab;                     // BF16 form: centred keys in the BF16 slice layout
   size_t tsh;                    // per-key shared threshold bound [n_chunk]
+  size_t tkey;                   // the bound each key's scan left, float [n_chunk]
   size_t klist, kcount;          // BF16 form: keys re-matched in FP32 [N], their count
   size_t bpos, bhi, blo;         // large-margin scratch [n_chunk][mcap]
   size_t cnn_ws, xcnn, xglr, cover, subkeys, sigv, jpart, jdelta;  // surrogate and judge
@@ -62,8 +66,8 @@ struct glr_plan {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;   // timing event pairs
   std::vector<int> ev_stage;      // stage of each recorded pair
   size_t ev_used;                 // pairs recorded since the last read
-  // host-side timing accumulators (ms)
-  double ms[10];
+  // host-side timing accumulators (ms), one per stage
+  double ms[GLR_STAGE_SLOTS];
   // CNN surrogate
   int surrogate, judge_stride;
   float surrogate_frac, judge_delta_max;
@@ -71,6 +75,7 @@ struct glr_plan {
   long long sur_steps, fallback_steps;
   float judge_delta_last;
   long long match_launches;
+  long long rematch_launches;     // FP32 re-match launches of the BF16 form
 };
 
 // Sets the thread-local detail string of glr_last_error_message(); returns s.
@@ -158,11 +163,26 @@ struct BigMargin {
   float* lo;
   int cap;
 };
+// What the large-margin path needs to re-derive a key's margin set from its
+// distance row when a range list overflowed: the chunk's d~ rows and the key
+// and candidate bound terms the scan used (same arguments as
+// launch_topk_partial), and tkey, where the select kernel leaves the bound
+// each key's scan published.
+struct RowBound {
+  const float* dist;
+  size_t ldd;
+  const float* km;
+  const float* cm;
+  int pc;
+  float coef, coef2, cz;
+  float* tkey;
+};
 void launch_select_rescore(const glr_plan* pl, const float* xp, const float* A,
                            const int32_t* kmap, int g0, int nk, const int32_t* lj,
                            const float* lu, const float* ll, const int32_t* lcnt, int32_t* idx,
                            float* dd, int32_t* oflag, uint32_t* tsh, int defer,
-                           const BigMargin& bm, DevStats* st, hipStream_t s);
+                           const BigMargin& bm, const float* dist, const float* kmb,
+                           const float* cm2, int bf16, float* tkey, DevStats* st, hipStream_t s);
 void launch_collect_flags(const int32_t* oflag, int g0, int nk, int32_t* klist, int32_t* kcount,
                           DevStats* st, hipStream_t s);
 

@@ -136,6 +136,22 @@ __device__ int wave_compact(int* bj, float* bu, float* bl, int n, float T) {
   return w;
 }
 
+// Error bound eps of one candidate's d~ (see k_topk_partial for the two
+// forms); d: d~, p: the candidate's centred norm, m: its mean (BF16 form) or
+// channel-mean term h_j (FP32 form); kr, kmu: the key's.
+__device__ __forceinline__ float margin_eps(float d, float p, float m, float kr, float kmu, int pc,
+                                            float coef, float coef2, float cz) {
+  if (pc) {
+    const float w = cz * (kmu + m);
+    // hardware square root (within 1 ulp; the bound's slack covers it)
+    // of max(d~, smallest normal), which is never below sqrt(max(d~, 0))
+    const float y = ((kr + p) + __builtin_amdgcn_sqrtf(fmaxf(d, 0x1p-126f))) + w;
+    return fmaf(y, fmaf(coef2, y, w), w * w);
+  }
+  const float R = (kr + p) + cz * fabsf(kmu - m);
+  return coef * (kr * p) + coef2 * (R * R);
+}
+
 // Error bound of d~ per candidate (key row kmap[g0+g] or g0+g):
 //  pc == 0 (BF16 form, one mean per patch): km = (||a||^2, mu_k, sum a, ||a||),
 //    cm = (mu_j, ||pbar_j||); eps = coef ||a|| ||pbar|| + coef2 R^2 with
@@ -229,18 +245,8 @@ k_topk_partial(const float* __restrict__ dist, size_t ldd, const float4* __restr
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int j = base + u * 256 + 4 * l + e;
-        float eps;
-        if (pc) {
-          const float w = cz * (kmu + mv[u][e]);
-          // hardware square root (within 1 ulp; the bound's slack covers it)
-          // of max(d~, smallest normal), which is never below sqrt(max(d~, 0))
-          const float y =
-              ((kr + pv[u][e]) + __builtin_amdgcn_sqrtf(fmaxf(dv[u][e], 0x1p-126f))) + w;
-          eps = fmaf(y, fmaf(coef2, y, w), w * w);
-        } else {
-          const float R = (kr + pv[u][e]) + cz * fabsf(kmu - mv[u][e]);
-          eps = coef * (kr * pv[u][e]) + coef2 * (R * R);
-        }
+        const float eps =
+            margin_eps(dv[u][e], pv[u][e], mv[u][e], kr, kmu, pc, coef, coef2, cz);
         ok[u][e] = j < j1;
         Uv[u][e] = dv[u][e] + eps;
         Lv[u][e] = dv[u][e] - eps;
@@ -479,7 +485,7 @@ k_select_rescore(const float* __restrict__ xp, int H, int W, int P, int Cp, int 
                  const int32_t* __restrict__ lj, const float* __restrict__ lu,
                  const float* __restrict__ ll, const int32_t* __restrict__ lcnt,
                  int32_t* __restrict__ idx, float* __restrict__ dd, int32_t* __restrict__ oflag,
-                 uint32_t* __restrict__ tsh, DevStats* st) {
+                 uint32_t* __restrict__ tsh, float* __restrict__ tkey, DevStats* st) {
   __shared__ float su[4][UW];
   __shared__ float sl[4][UW];
   __shared__ int sj[4][UW];
@@ -488,9 +494,10 @@ k_select_rescore(const float* __restrict__ xp, int H, int W, int P, int Cp, int 
   const int l = lane_id();
   const int g = blockIdx.x * 4 + wave;
   if (g >= nk) return;                      // wave-uniform
-  // the scan that used the key's shared bound has finished: restore it to
-  // +inf for the next chunk or call
-  if (l == 0) tsh[g] = 0xffffffffu;
+  // the scan that used the key's shared bound has finished: keep its value
+  // (an upper bound of the key's T, for the large-margin path) and restore
+  // it to +inf for the next chunk or call
+  if (l == 0) tkey[g] = ord2f(atomicExch(&tsh[g], 0xffffffffu));
   float* u = su[wave];
   float* lo = sl[wave];
   int* jj = sj[wave];
@@ -595,17 +602,125 @@ k_select_rescore(const float* __restrict__ xp, int H, int W, int P, int Cp, int 
   }
 }
 
+// Rescore the margin set held in global scratch (positions gp[0..m)) and
+// write the key's K smallest by (hi, lo, position), sorted, to idx/dd row gg:
+// compensated distances into gh/gl, a radix selection of the K-th smallest
+// 96-bit key (ord(hi), ord(lo + 0), position), the K entries at or below it
+// gathered and sorted in LDS.  Every thread of the block calls it.
+template <int EM>
+__device__ void rescore_select_set(const KeySlice<EM>& ks, const float* __restrict__ xp,
+                                   const int32_t* gp, float* gh, float* gl, int m, int K, int Wc,
+                                   int W, int L, int gg, int32_t* __restrict__ idx,
+                                   float* __restrict__ dd, float* su, float* sl, int* sj,
+                                   int* ssh, int* hist, uint32_t* sdig) {
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int cpi = 64 / L;
+  coop_rescore(ks, xp, [&](int i) { return gp[i]; }, wave * 2 * cpi, m, 8 * cpi, Wc, W, L, gh,
+               gl);
+  __syncthreads();
+  uint32_t pre[3] = {0u, 0u, 0u};
+  int remaining = K;
+  for (int p = 0; p < 12; ++p) {
+    const int w = p >> 2, shift = 24 - 8 * (p & 3);
+    const uint32_t hm = shift == 24 ? 0u : (0xffffffffu << (shift + 8));
+    hist[tid] = 0;
+    __syncthreads();
+    for (int i = tid; i < m; i += ST) {
+      const uint32_t k0 = f2ord(gh[i]), k1 = f2ord(gl[i] + 0.f);
+      const uint32_t k2 = (uint32_t)gp[i];
+      bool match = true;
+      if (w > 0) match = k0 == pre[0];
+      if (w > 1) match = match && k1 == pre[1];
+      const uint32_t kw = w == 0 ? k0 : (w == 1 ? k1 : k2);
+      if (match && (kw & hm) == (pre[w] & hm)) atomicAdd(&hist[(kw >> shift) & 255u], 1);
+    }
+    __syncthreads();
+    if (wave == 0) {
+      uint32_t pfx = 0u;
+      int rem = remaining;
+      wave_radix_digit(hist, shift, pfx, rem);
+      if (tid == 0) {
+        sdig[0] = pfx;
+        sdig[1] = (uint32_t)(remaining - rem);
+      }
+    }
+    __syncthreads();
+    pre[w] |= sdig[0];
+    remaining -= (int)sdig[1];
+    __syncthreads();
+  }
+  // the K entries with key <= the K-th key, in list order, then sorted
+  int n = 0;
+  for (int base = 0; base < m; base += ST) {
+    const int i = base + tid;
+    bool keep = false;
+    float h = 0.f, lw = 0.f;
+    int jv = 0;
+    if (i < m) {
+      h = gh[i];
+      lw = gl[i] + 0.f;
+      jv = gp[i];
+      const uint32_t k0 = f2ord(h), k1 = f2ord(lw), k2 = (uint32_t)jv;
+      keep = k0 < pre[0] || (k0 == pre[0] && (k1 < pre[1] || (k1 == pre[1] && k2 <= pre[2])));
+    }
+    int tc;
+    const int q = block_excl_scan(keep ? 1 : 0, ssh, &tc);
+    if (keep && n + q < 64) {
+      su[n + q] = h;
+      sl[n + q] = lw;
+      sj[n + q] = jv;
+    }
+    n += tc;
+  }
+  __syncthreads();
+  n = min(n, 64);                            // exactly K (positions are unique)
+  int n2 = 1;
+  while (n2 < n) n2 <<= 1;
+  for (int i = n + tid; i < n2; i += ST) {
+    su[i] = __int_as_float(0x7f800000);
+    sl[i] = 0.f;
+    sj[i] = 0x7fffffff;
+  }
+  __syncthreads();
+  block_bitonic(su, sl, sj, n2);
+  for (int q = tid; q < K; q += ST) {
+    idx[(size_t)gg * K + q] = sj[q];
+    dd[(size_t)gg * K + q] = su[q];
+  }
+}
+
+// Smallest value v (as ordered bits) of vals[0..m) with at least K values
+// <= v: the K-th smallest (requires m >= K).  Every thread calls it.
+__device__ float block_kth_by_bisection(const float* vals, int m, int K, int* ssh) {
+  uint32_t lo = 0u, hi = 0xffffffffu;
+  while (lo < hi) {
+    const uint32_t mid = lo + ((hi - lo) >> 1);
+    int c = 0;
+    for (int i = threadIdx.x; i < m; i += ST) c += (f2ord(vals[i]) <= mid) ? 1 : 0;
+    c = block_sum_i(c, ssh);
+    if (c >= K) hi = mid; else lo = mid + 1;
+  }
+  return ord2f(lo);
+}
+
 // Flagged keys, one block per key (unflagged keys exit at once):
-//  flag 1: the margin set exceeds the wave buffer.  It is gathered into
-//          global scratch (up to mcap entries), rescored like the wave path,
-//          and the K smallest by (hi, lo, position) are found by a radix
-//          selection on the 96-bit key, then sorted in LDS;
-//  flag 2 (a range list overflowed) or a margin set above mcap: exact
-//          full-row path, every candidate rescored with compensated
-//          arithmetic and a running best list kept in LDS (flat images, where
-//          most distances lie within the error bound of each other).
-// With defer != 0 the full-row cases are left flagged for a later pass;
-// keys completed here get their flag cleared.
+//  flag 1: the margin set exceeds the wave buffer.  It is gathered from the
+//          range lists into global scratch (up to mcap entries) and handed
+//          to rescore_select_set;
+//  flag 2: a range list overflowed, so the lists do not hold the margin set.
+//          With the key's distance row still in the chunk (rb.dist), it is
+//          re-derived from the row: every candidate with L_j <= T', T' the
+//          bound the key's scan published (T' >= T, so the candidates with
+//          U_j <= T, hence the K smallest U, are all among them), is gathered
+//          with (U, L); T is their K-th smallest U and the margin set
+//          {L_j <= T} is compacted in place and handed to rescore_select_set;
+//  either set above mcap: exact full-row path, every candidate rescored with
+//          compensated arithmetic and a running best list kept in LDS (flat
+//          images, where most distances lie within the error bound of each
+//          other).
+// With defer != 0, flag-2 keys, and flag-1 keys whose set exceeds mcap, are
+// left flagged for a later pass; keys completed here get their flag cleared.
 template <int EM>
 __global__ void __launch_bounds__(ST)
 k_rescore_overflow(const float* __restrict__ xp, int H, int W, int P, int Cp, int D, int L,
@@ -615,7 +730,8 @@ k_rescore_overflow(const float* __restrict__ xp, int H, int W, int P, int Cp, in
                    const float* __restrict__ ll, const int32_t* __restrict__ lcnt,
                    int32_t* __restrict__ oflag, int32_t* __restrict__ gpos,
                    float* __restrict__ ghi, float* __restrict__ glo, int mcap,
-                   int32_t* __restrict__ idx, float* __restrict__ dd, DevStats* st) {
+                   int32_t* __restrict__ idx, float* __restrict__ dd, RowBound rb,
+                   DevStats* st) {
   __shared__ float su[UCAP];
   __shared__ float sl[UCAP];
   __shared__ int sj[UCAP];
@@ -624,6 +740,7 @@ k_rescore_overflow(const float* __restrict__ xp, int H, int W, int P, int Cp, in
   __shared__ float fh[ST], fl[ST];           // full-row path: staged distances
   __shared__ int hist[256];
   __shared__ uint32_t sdig[2];
+  __shared__ int sgat;
   const int g = blockIdx.x;
   const int flag = oflag[g];
   if (flag == 0 || (flag == 2 && defer)) return;   // block-uniform
@@ -632,9 +749,11 @@ k_rescore_overflow(const float* __restrict__ xp, int H, int W, int P, int Cp, in
   const int Wc = W - P + 1;
   const int wave = tid >> 6;
   const int cpi = 64 / L;
+  const size_t go = (size_t)g * mcap;
   KeySlice<EM> ks;
   key_slice_load(ks, A + (size_t)gg * D, D, P, H, W, L, (tid & 63) & (L - 1));
   if (tid < S) scnt[tid] = lcnt[g * S + tid];
+  if (tid == 0) sgat = 0;
   __syncthreads();
   if (flag == 1) {
     const size_t o0 = (size_t)g * S * CAP;
@@ -651,7 +770,6 @@ k_rescore_overflow(const float* __restrict__ xp, int H, int W, int P, int Cp, in
       if (c >= K) hi = mid; else lo = mid + 1;
     }
     const float T = ord2f(lo);
-    const size_t go = (size_t)g * mcap;
     int m = 0;
     for (int sp = 0; sp < S; ++sp) {
       const int csp = scnt[sp];
@@ -671,79 +789,8 @@ k_rescore_overflow(const float* __restrict__ xp, int H, int W, int P, int Cp, in
       if (defer) return;
       goto full_row;
     }
-    coop_rescore(ks, xp, [&](int i) { return gpos[go + i]; }, wave * 2 * cpi, m, 8 * cpi, Wc, W,
-                 L, ghi + go, glo + go);
-    __syncthreads();
-    // radix selection of the K-th smallest key (ord(hi), ord(lo + 0), position)
-    uint32_t pre[3] = {0u, 0u, 0u};
-    int remaining = K;
-    for (int p = 0; p < 12; ++p) {
-      const int w = p >> 2, shift = 24 - 8 * (p & 3);
-      const uint32_t hm = shift == 24 ? 0u : (0xffffffffu << (shift + 8));
-      hist[tid] = 0;
-      __syncthreads();
-      for (int i = tid; i < m; i += ST) {
-        const uint32_t k0 = f2ord(ghi[go + i]), k1 = f2ord(glo[go + i] + 0.f);
-        const uint32_t k2 = (uint32_t)gpos[go + i];
-        bool match = true;
-        if (w > 0) match = k0 == pre[0];
-        if (w > 1) match = match && k1 == pre[1];
-        const uint32_t kw = w == 0 ? k0 : (w == 1 ? k1 : k2);
-        if (match && (kw & hm) == (pre[w] & hm)) atomicAdd(&hist[(kw >> shift) & 255u], 1);
-      }
-      __syncthreads();
-      if (wave == 0) {
-        uint32_t pfx = 0u;
-        int rem = remaining;
-        wave_radix_digit(hist, shift, pfx, rem);
-        if (tid == 0) {
-          sdig[0] = pfx;
-          sdig[1] = (uint32_t)(remaining - rem);
-        }
-      }
-      __syncthreads();
-      pre[w] |= sdig[0];
-      remaining -= (int)sdig[1];
-      __syncthreads();
-    }
-    // the K entries with key <= the K-th key, in list order, then sorted
-    int n = 0;
-    for (int base = 0; base < m; base += ST) {
-      const int i = base + tid;
-      bool keep = false;
-      float h = 0.f, lw = 0.f;
-      int jv = 0;
-      if (i < m) {
-        h = ghi[go + i];
-        lw = glo[go + i] + 0.f;
-        jv = gpos[go + i];
-        const uint32_t k0 = f2ord(h), k1 = f2ord(lw), k2 = (uint32_t)jv;
-        keep = k0 < pre[0] || (k0 == pre[0] && (k1 < pre[1] || (k1 == pre[1] && k2 <= pre[2])));
-      }
-      int tc;
-      const int q = block_excl_scan(keep ? 1 : 0, ssh, &tc);
-      if (keep && n + q < 64) {
-        su[n + q] = h;
-        sl[n + q] = lw;
-        sj[n + q] = jv;
-      }
-      n += tc;
-    }
-    __syncthreads();
-    n = min(n, 64);                          // exactly K (positions are unique)
-    int n2 = 1;
-    while (n2 < n) n2 <<= 1;
-    for (int i = n + tid; i < n2; i += ST) {
-      su[i] = __int_as_float(0x7f800000);
-      sl[i] = 0.f;
-      sj[i] = 0x7fffffff;
-    }
-    __syncthreads();
-    block_bitonic(su, sl, sj, n2);
-    for (int q = tid; q < K; q += ST) {
-      idx[(size_t)gg * K + q] = sj[q];
-      dd[(size_t)gg * K + q] = su[q];
-    }
+    rescore_select_set(ks, xp, gpos + go, ghi + go, glo + go, m, K, Wc, W, L, gg, idx, dd, su,
+                       sl, sj, ssh, hist, sdig);
     if (tid == 0) {
       oflag[g] = 0;
       if (st) {
@@ -752,6 +799,97 @@ k_rescore_overflow(const float* __restrict__ xp, int H, int W, int P, int Cp, in
       }
     }
     return;
+  }
+  if (rb.dist) {
+    // flag 2: the margin set re-derived from the key's distance row
+    const float Tp = rb.tkey[g];
+    const float* drow = rb.dist + (size_t)g * rb.ldd;
+    const float4 kmv = reinterpret_cast<const float4*>(rb.km)[gg];
+    const float kr = kmv.w, kmu = kmv.y;
+    const int l = tid & 63;
+    for (int base = 0; base < Ncand; base += 4 * ST) {
+      const int j = base + 4 * tid;
+      float dv[4], pv[4], mv[4];
+      if (j + 3 < Ncand) {
+        const float4 a = *reinterpret_cast<const float4*>(drow + j);
+        const float4 b0 = *reinterpret_cast<const float4*>(rb.cm + 2 * (size_t)j);
+        const float4 b1 = *reinterpret_cast<const float4*>(rb.cm + 2 * (size_t)j + 4);
+        dv[0] = a.x; dv[1] = a.y; dv[2] = a.z; dv[3] = a.w;
+        mv[0] = b0.x; pv[0] = b0.y; mv[1] = b0.z; pv[1] = b0.w;
+        mv[2] = b1.x; pv[2] = b1.y; mv[3] = b1.z; pv[3] = b1.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const bool ok = j + e < Ncand;
+          dv[e] = ok ? drow[j + e] : 0.f;
+          mv[e] = ok ? rb.cm[2 * (size_t)(j + e)] : 0.f;
+          pv[e] = ok ? rb.cm[2 * (size_t)(j + e) + 1] : 0.f;
+        }
+      }
+      float Uv[4], Lv[4];
+      bool keep[4];
+      int nkeep = 0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float eps = margin_eps(dv[e], pv[e], mv[e], kr, kmu, rb.pc, rb.coef, rb.coef2,
+                                     rb.cz);
+        Uv[e] = dv[e] + eps;
+        Lv[e] = dv[e] - eps;
+        keep[e] = j + e < Ncand && Lv[e] <= Tp;
+        nkeep += keep[e] ? 1 : 0;
+      }
+      // a wave reserves room for its entries with one LDS atomic
+      const int incl = wave_incl_scan(nkeep);
+      const int wtot = __shfl(incl, 63, 64);
+      if (wtot == 0) continue;               // wave-uniform
+      int wbase = 0;
+      if (l == 63) wbase = atomicAdd(&sgat, wtot);
+      int p = __shfl(wbase, 63, 64) + incl - nkeep;
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (keep[e]) {
+          if (p < mcap) {
+            gpos[go + p] = j + e;
+            ghi[go + p] = Uv[e];
+            glo[go + p] = Lv[e];
+          }
+          ++p;
+        }
+    }
+    __syncthreads();
+    int m = sgat;
+    if (m <= mcap && m >= K) {               // block-uniform
+      // T = K-th smallest U of the gathered entries (they hold the row's K
+      // smallest U); keep {L <= T} in place, in gathered order
+      const float T = block_kth_by_bisection(ghi + go, m, K, ssh);
+      int n = 0;
+      for (int b0 = 0; b0 < m; b0 += ST) {
+        const int i = b0 + tid;
+        bool kp = false;
+        int jv = 0;
+        if (i < m) {
+          jv = gpos[go + i];
+          kp = glo[go + i] <= T;
+        }
+        int tc;
+        const int pre = block_excl_scan(kp ? 1 : 0, ssh, &tc);
+        if (kp) gpos[go + n + pre] = jv;
+        n += tc;
+      }
+      __syncthreads();
+      m = n;
+      rescore_select_set(ks, xp, gpos + go, ghi + go, glo + go, m, K, Wc, W, L, gg, idx, dd, su,
+                         sl, sj, ssh, hist, sdig);
+      if (tid == 0) {
+        oflag[g] = 0;
+        if (st) {
+          atomicAdd(&st->margin_sum, (unsigned long long)m);
+          atomicMax(&st->margin_max, m);
+          atomicAdd(&st->regather, 1);
+        }
+      }
+      return;
+    }
   }
 full_row:
   const int BEST = UCAP;
@@ -810,22 +948,28 @@ full_row:
 
 }  // namespace
 
+// The bound coefficients of margin_eps for the plan's two forms, rounded up
+// so that the float values are not below the bound.
+static void margin_coefs(const glr_plan* pl, int bf16, float* coef, float* coef2, float* cz) {
+  const double u = 5.9604644775390625e-08;      // 2^-24
+  const double b = 0.00390625;                  // 2^-8, BF16 unit round-off
+  *coef = 0.f;
+  if (bf16) {
+    *coef = std::nextafter((float)(4.0 * (2.0 * b + b * b)), 1.f);
+    *coef2 = std::nextafter((float)((3.0 * pl->D + 26.0) * u), 1.f);
+    *cz = std::nextafter((float)std::sqrt((double)pl->D), 1e9f);
+  } else {
+    *coef2 = std::nextafter((float)(2.02 * (pl->D + pl->Cp + 4.0) * u), 1.f);
+    *cz = std::nextafter((float)(8.02 * pl->P * u), 1.f);
+  }
+}
+
 void launch_topk_partial(const glr_plan* pl, const float* dist, const float* kmb,
                          const int32_t* kmap, int g0, const float* cm2, int nk, int bf16,
                          uint32_t* tsh, int32_t* lj, float* lu, float* ll, int32_t* lcnt,
                          hipStream_t s) {
-  const double u = 5.9604644775390625e-08;      // 2^-24
-  const double b = 0.00390625;                  // 2^-8, BF16 unit round-off
-  // coefficients rounded up so that the float values are not below the bound
-  float coef = 0.f, coef2, cz;
-  if (bf16) {
-    coef = std::nextafter((float)(4.0 * (2.0 * b + b * b)), 1.f);
-    coef2 = std::nextafter((float)((3.0 * pl->D + 26.0) * u), 1.f);
-    cz = std::nextafter((float)std::sqrt((double)pl->D), 1e9f);
-  } else {
-    coef2 = std::nextafter((float)(2.02 * (pl->D + pl->Cp + 4.0) * u), 1.f);
-    cz = std::nextafter((float)(8.02 * pl->P * u), 1.f);
-  }
+  float coef, coef2, cz;
+  margin_coefs(pl, bf16, &coef, &coef2, &cz);
   // tsh[0..nk) holds +inf here: set by the key gather at the start of every
   // match call and restored by the rescoring kernel after every scan
   // the FP32 form's margin sets stay far below the BF16 form's: a smaller
@@ -856,27 +1000,37 @@ static void launch_select_t(const glr_plan* pl, const float* xp, const float* A,
                             const int32_t* kmap, int g0, int nk, const int32_t* lj,
                             const float* lu, const float* ll, const int32_t* lcnt, int32_t* idx,
                             float* dd, int32_t* oflag, uint32_t* tsh, int defer,
-                            const BigMargin& bm, DevStats* st, int L, hipStream_t s) {
+                            const BigMargin& bm, const RowBound& rb, DevStats* st, int L,
+                            hipStream_t s) {
   hipLaunchKernelGGL(k_select_rescore<EM>, dim3((nk + 3) / 4), dim3(256), 0, s, xp, pl->H, pl->W,
                      pl->P, pl->Cp, pl->D, L, A, kmap, g0, nk, pl->n_split, pl->Ncand, pl->K, lj,
-                     lu, ll, lcnt, idx, dd, oflag, tsh, st);
+                     lu, ll, lcnt, idx, dd, oflag, tsh, rb.tkey, st);
   hipLaunchKernelGGL(k_rescore_overflow<EM>, dim3(nk), dim3(ST), 0, s, xp, pl->H, pl->W, pl->P,
                      pl->Cp, pl->D, L, A, kmap, g0, pl->n_split, pl->Ncand, pl->K, defer, lj, lu,
-                     ll, lcnt, oflag, bm.pos, bm.hi, bm.lo, bm.cap, idx, dd, st);
+                     ll, lcnt, oflag, bm.pos, bm.hi, bm.lo, bm.cap, idx, dd, rb, st);
 }
 
 void launch_select_rescore(const glr_plan* pl, const float* xp, const float* A,
                            const int32_t* kmap, int g0, int nk, const int32_t* lj,
                            const float* lu, const float* ll, const int32_t* lcnt, int32_t* idx,
                            float* dd, int32_t* oflag, uint32_t* tsh, int defer,
-                           const BigMargin& bm, DevStats* st, hipStream_t s) {
+                           const BigMargin& bm, const float* dist, const float* kmb,
+                           const float* cm2, int bf16, float* tkey, DevStats* st, hipStream_t s) {
+  RowBound rb;
+  rb.dist = dist;
+  rb.ldd = (size_t)pl->ldd;
+  rb.km = kmb;
+  rb.cm = cm2;
+  rb.pc = bf16 ? 0 : 1;
+  margin_coefs(pl, bf16, &rb.coef, &rb.coef2, &rb.cz);
+  rb.tkey = tkey;
   const int L = rescore_lanes(pl->D);
   if ((pl->D + L - 1) / L <= 32)
     launch_select_t<32>(pl, xp, A, kmap, g0, nk, lj, lu, ll, lcnt, idx, dd, oflag, tsh, defer, bm,
-                        st, L, s);
+                        rb, st, L, s);
   else
     launch_select_t<64>(pl, xp, A, kmap, g0, nk, lj, lu, ll, lcnt, idx, dd, oflag, tsh, defer, bm,
-                        st, L, s);
+                        rb, st, L, s);
 }
 
 // Append the chunk keys g0 + g with oflag[g] != 0 to klist at *kcount, in

@@ -51,7 +51,9 @@ class Stats(ctypes.Structure):
                 ("match_launches", ctypes.c_int64), ("jacobi_sweeps_sum", ctypes.c_int64),
                 ("rematch_keys", ctypes.c_int64), ("surrogate_steps", ctypes.c_int64),
                 ("fallback_steps", ctypes.c_int64), ("judge_delta_last", ctypes.c_float),
-                ("ms_cnn", ctypes.c_float), ("ms_judge", ctypes.c_float)]
+                ("ms_cnn", ctypes.c_float), ("ms_judge", ctypes.c_float),
+                ("regather_keys", ctypes.c_int64), ("ms_rematch", ctypes.c_float),
+                ("rematch_launches", ctypes.c_int64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

@@ -81,18 +81,28 @@ def test_bf16_small_chunks_and_splits():
     assert check_groups(x.astype(np.float64), P, keys, host(idx), ref) == 0
 
 
-def test_bf16_constant_image_exact_path():
+@pytest.mark.parametrize("H,W", [(40, 50), (200, 200)])
+def test_bf16_constant_image_exact_path(H, W):
     # every centred patch is zero, so every d~ and every bound is exactly 0:
-    # all candidates tie, the exact full-row path runs, lowest positions win
+    # all candidates tie, the range lists overflow and the keys are
+    # re-matched in FP32, where the margin set is re-derived from the
+    # distance row (40 x 50) or, above 32768 candidates, the exact full-row
+    # path runs (200 x 200); lowest positions win
     require_gpu()
-    C, H, W, P, N, K = 2, 40, 50, 4, 6, 10
+    C, P, N, K = 2, 4, 6, 10
     x = np.full((C, H, W), 0.3, dtype=np.float32)
-    keys = np.array([0, 5, 100, 500, 900, 1300])
+    n_cand = (H - P + 1) * (W - P + 1)
+    keys = np.linspace(0, n_cand - 1, N).astype(np.int64)
     plan = _plan(C, H, W, P, N, K, precision="bf16")
     idx, dist = plan.match_topk(gpu(x), gpu(keys.astype(np.int32)))
     np.testing.assert_array_equal(host(idx), np.tile(np.arange(K), (N, 1)))
     assert np.all(host(dist) == 0)
-    assert plan.read_stats()["overflow_keys"] == N
+    st = plan.read_stats()
+    assert st["rematch_keys"] == N
+    if n_cand <= 32768:
+        assert st["regather_keys"] == N and st["overflow_keys"] == 0
+    else:
+        assert st["overflow_keys"] == N
 
 
 def _gap_iterate(wl):

@@ -67,19 +67,55 @@ def test_match_topk_small_chunks_and_splits():
     assert check_groups(x.astype(np.float64), P, keys, host(idx), ref) == 0
 
 
-def test_match_topk_constant_image_exact_path():
-    # every distance is exactly 0: the certified margin holds every candidate,
-    # the exact full-row path runs and ties resolve to the lowest positions
+@pytest.mark.parametrize("H,W", [(40, 50), (200, 200)])
+def test_match_topk_constant_image_exact_path(H, W):
+    # every distance is exactly 0: the certified margin holds every candidate
+    # and the range lists overflow.  With at most 32768 candidates the margin
+    # set is re-derived from the distance row and rescored from global memory
+    # (40 x 50); above that the exact full-row path runs (200 x 200, 38809
+    # candidates).  Ties resolve to the lowest positions either way.
     require_gpu()
-    C, H, W, P, N, K = 2, 40, 50, 4, 6, 10
+    C, P, N, K = 2, 4, 6, 10
     x = np.full((C, H, W), 0.3, dtype=np.float32)
-    keys = np.array([0, 5, 100, 500, 900, 1300])
+    n_cand = (H - P + 1) * (W - P + 1)
+    keys = np.linspace(0, n_cand - 1, N).astype(np.int64)
     plan = _plan(C, H, W, P, N, K)
     idx, dist = plan.match_topk(gpu(x), gpu(keys.astype(np.int32)))
     st = plan.read_stats()
     np.testing.assert_array_equal(host(idx), np.tile(np.arange(K), (N, 1)))
     assert np.all(host(dist) == 0)
-    assert st["overflow_keys"] == N
+    if n_cand <= 32768:
+        assert st["regather_keys"] == N and st["overflow_keys"] == 0
+        assert st["margin_max"] == n_cand
+    else:
+        assert st["overflow_keys"] == N
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_match_topk_list_overflow_regather(precision):
+    # the top 16 rows are one constant value, the rest is random: keys up
+    # there see ~2000 exact ties, most of them in the first candidate range,
+    # whose list overflows; their margin sets are re-derived from the
+    # distance rows.  Keys below keep the ordinary paths.
+    require_gpu()
+    C, H, W, P, N, K = 2, 128, 192, 4, 24, 32
+    x = random_image(C, H, W, seed=77, kind="uniform")
+    x[:, :16, :] = np.float32(0.4)
+    Wc = W - P + 1
+    n_cand = (H - P + 1) * Wc
+    top = np.array([r * Wc + c for r in (0, 3, 7, 12) for c in (0, 50, 100)])
+    rest = np.random.default_rng(9).choice(np.arange(13 * Wc, n_cand), size=N - len(top),
+                                           replace=False)
+    keys = np.sort(np.concatenate([top, rest]))
+    plan = _plan(C, H, W, P, N, K, precision=precision)
+    idx, dist = plan.match_topk(gpu(x), gpu(keys.astype(np.int32)))
+    st = plan.read_stats()
+    print("regather", st["regather_keys"], "overflow", st["overflow_keys"], "margin max",
+          st["margin_max"], "rematch", st["rematch_keys"], flush=True)
+    ref_idx, ref_dist = om.topk_exact(x.astype(np.float64), P, keys, K)
+    np.testing.assert_array_equal(host(idx), ref_idx)
+    np.testing.assert_allclose(host(dist), ref_dist, rtol=1e-6, atol=1e-30)
+    assert st["regather_keys"] >= len(top) and st["overflow_keys"] == 0
 
 
 def test_detect_keys_real_vs_oracle():
