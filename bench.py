@@ -3,19 +3,25 @@
 
 A step is one outer iteration of the data-fidelity loop: the data step plus
 the whole GLR prior step (key detection, global matching, top-K grouping,
-WNNM shrinkage, aggregation).  The default workload is the synthetic
-single-coil MRI problem (256 x 256 complex64, 6 x 6 patches, 1024 keys,
-K = 45, 30 ADMM iterations); ``--workload`` selects another one (the
-1024 x 1024 x 24-frame CACTI problem with ``--precision bf16`` is the
-precision form at scale).  Inputs are resident in HBM before the timed
+WNNM shrinkage, aggregation).  The default workload is the precision form at
+scale: compressive temporal imaging of a 1024 x 1024 x 24-frame synthetic
+video (8 x 8 x 24 patches, 16384 keys, K = 64, 50 GAP iterations), matched
+in BF16 on MFMA with FP32 sums and the certified FP32 rescoring.
+``--workload`` selects another one (``mri_256``, ``msfa_512``,
+``cacti_128``, ``surrogate``).  Inputs are resident in HBM before the timed
 region starts.
 
-Prints one JSON line.  ``value`` is timed on a plan without per-stage
-events; a second plan with them repeats the same number of iterations from
-the same state, and ``roofline`` covers the dominant kernel of that pass
-(largest share), with its average launch duration taken from the HIP events
-the library records on the launch stream.  ``cpu_baseline`` is the FP64 CPU
-oracle on a bounded sample of the same workload.
+Prints one JSON line.  ``value`` is iterations/s over the timed steps
+(W untimed iterations from t = 0 first, then K timed ones continuing the
+same trajectory).  ``roofline`` covers the matcher kernel of the form, with
+its average launch duration from the HIP event pairs the library records
+on the launch stream; on the large workloads those events are recorded in
+the timed pass itself (their cost is far below 1 % of an iteration), on the
+small ones a second pass of the same length from the same state takes them.
+The line also carries the stage split, the full-length reconstruction (every
+iteration, timed, with its PSNR), the FP32 form on the same state, and
+``cpu_baseline``: the FP64 CPU oracle on a bounded sample of the same
+workload, with the parity of keys and sampled groups on the same iterate.
 """
 import argparse
 import json
@@ -28,7 +34,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "GLR iterations/sec + matching TFLOP/s (% MFMA peak) at fixed PSNR vs oracle"
-WORKLOAD = "mri_256"
+WORKLOAD = "cacti_1024"
 
 # MI355X published peaks
 PEAK_FP32_MFMA_TFLOPS = 157.3
@@ -40,12 +46,17 @@ PEAK_HBM_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=60, help="timed GLR iterations")
-    ap.add_argument("--warmup", type=int, default=30, help="untimed GLR iterations first")
+    ap.add_argument("--steps", type=int, default=20, help="timed GLR iterations")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed GLR iterations first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-quality", action="store_true",
                     help="skip the full-length reconstruction that reports PSNR")
-    ap.add_argument("--cpu-iters", type=int, default=16, help="oracle iterations in the CPU sample")
+    ap.add_argument("--no-fp32-form", action="store_true",
+                    help="skip the FP32-form comparison of the BF16 workload")
+    ap.add_argument("--cpu-iters", type=int, default=16,
+                    help="oracle iterations in the CPU sample (small workloads)")
+    ap.add_argument("--cpu-keys", type=int, default=1536,
+                    help="sampled keys of the oracle's top-K timing (1024^2 workload)")
     ap.add_argument("--workload", default=WORKLOAD, choices=["mri_256", "cacti_1024", "msfa_512",
                                                               "cacti_128", "surrogate"])
     ap.add_argument("--precision", default=None, choices=["fp32", "bf16"],
@@ -72,6 +83,9 @@ CONFIG_TEXT = {
     "cacti_128": {"image": "128x128, 8 frames per snapshot", "solver": "GAP",
                   "mask": "Bernoulli(0.5) binary coded apertures"},
 }
+# workloads whose iterations are long enough that the stage events ride in
+# the timed pass
+LONG_STEPS = ("cacti_1024", "msfa_512")
 
 
 def traffic_file(workload):
@@ -93,6 +107,158 @@ def measured_traffic(kernel, workload):
         return None
 
 
+def wnnm_flop(n_groups, D, K, sweeps_mean):
+    """Algorithmic WNNM work per prior step: per group a QR preconditioning
+    (2 D K^2), one-sided Jacobi on the K x K factor (K(K-1)/2 column pairs
+    per sweep, 10 K flop per pair for the three dot products and the
+    rotation) at the mean sweep count, the rank update (2 D K^2)."""
+    return n_groups * (2.0 * D * K * K + sweeps_mean * (K * (K - 1) / 2.0) * 10.0 * K
+                       + 2.0 * D * K * K)
+
+
+def stage_split(st, n):
+    return {k[3:]: st[k] / n for k in ("ms_detect", "ms_norms", "ms_match", "ms_rematch",
+                                        "ms_topk", "ms_select", "ms_lowrank", "ms_aggregate",
+                                        "ms_data")}
+
+
+def kernel_rooflines(wl, prec, st, n_iter):
+    """Rooflines of the step's kernels from the per-stage event times of
+    ``n_iter`` iterations (algorithmic work only)."""
+    P, P2 = wl.patch, wl.patch + (wl.patch & 1)
+    Cp = wl.dim // (P * P)
+    small = Cp * P * P2 <= 72 and Cp <= 4
+    f32_kernel = "k_match_f32_slab" if small else "k_match_f32"
+    out = {}
+    launches = st["match_launches"]
+    if launches:
+        ms = st["ms_match"] / launches
+        flop = 2.0 * wl.n_keys * wl.n_cand * wl.dim * n_iter / launches
+        name = "k_match_bf16" if prec == "bf16" else f32_kernel
+        peak = PEAK_BF16_MFMA_TFLOPS if prec == "bf16" else PEAK_FP32_MFMA_TFLOPS
+        ach = flop / (ms * 1e-3) / 1e12
+        out[name] = {"bound": "mfma", "achieved": round(ach, 3), "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(ach / peak, 4),
+                     "launch_ms": round(ms, 4), "launches_per_step": launches / n_iter,
+                     "traffic": measured_traffic(name, wl.name)}
+    if st["rematch_launches"]:
+        # FP32 re-match of the BF16 form's overflowing keys: 2 D N_cand flop per key
+        ms = st["ms_rematch"] / st["rematch_launches"]
+        keys = st["rematch_keys"] / st["rematch_launches"]
+        ach = 2.0 * keys * wl.n_cand * wl.dim / (ms * 1e-3) / 1e12
+        out[f32_kernel + " (re-match)"] = {
+            "bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_FP32_MFMA_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_MFMA_TFLOPS, 4),
+            "launch_ms": round(ms, 4), "keys_per_launch": round(keys, 1)}
+    if st["ms_lowrank"] > 0:
+        sweeps = st["jacobi_sweeps_sum"] / max(wl.n_keys * n_iter, 1)
+        flop = wnnm_flop(wl.n_keys, wl.dim, wl.k, sweeps) * n_iter
+        ach = flop / (st["ms_lowrank"] * 1e-3) / 1e12
+        out["k_wnnm"] = {"bound": "alu", "achieved": round(ach, 3),
+                         "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(ach / PEAK_FP32_VALU_TFLOPS, 4),
+                         "launch_ms": round(st["ms_lowrank"] / n_iter, 4),
+                         "sweeps_mean": round(sweeps, 3),
+                         "traffic": measured_traffic("k_wnnm", wl.name)}
+    if st["ms_topk"] > 0:
+        # d~ read once per key and candidate (FP32), BF16 and FP32 passes alike
+        keys = wl.n_keys * n_iter + st["rematch_keys"]
+        gbs = 4.0 * keys * wl.n_cand / (st["ms_topk"] * 1e-3) / 1e9
+        out["k_topk_partial"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                                 "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                                 "traffic": measured_traffic("k_topk_partial", wl.name)}
+    return out
+
+
+def cpu_baseline_cacti_1024(wl, inst, xbar32, keys_gpu, idx_gpu, n_keys_sample):
+    """The oracle on a bounded sample of iteration 0 of the same input.
+
+    Timed: the GAP data step (FP64, from the oracle's own initial estimate),
+    key detection on the full iterate, the oracle's top-K grouping called
+    for one key (its fixed cost: patch matrix, candidate norms) and for
+    ``n_keys_sample`` keys (every (N / n)-th detected key), the WNNM
+    shrinkage and the aggregation of 64 of those groups.  One iteration is
+    extrapolated as data + detect + t_topk(1) + (t_topk(n) - t_topk(1)) *
+    (N - 1) / (n - 1) + (t_wnnm + t_aggregate) * N / 64.  The detector and
+    top-K run on the GPU's own FP32 pre-prior iterate (upcast exactly), so
+    their results are compared with the GPU's: keys over the whole image,
+    groups of the sampled keys."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    from oracle import operators as ops, detector as odet, matching as om
+    from oracle import lowrank as olr, aggregate as oag
+    m = inst["mask"]
+    N, P, K = wl.n_keys, wl.patch, wl.k
+    y = ops.cacti_forward(inst["x_true"].astype(np.float64), m)     # the input, not timed
+    R = ops.cacti_mask_sum(m)
+    x0 = ops.cacti_adjoint(y / np.where(R == 0, 1.0, R), m)
+    tm = {}
+    t0 = time.perf_counter()
+    ops.gap_update(x0, y, lambda v: ops.cacti_forward(v, m), lambda r: ops.cacti_adjoint(r, m), R)
+    tm["data"] = time.perf_counter() - t0
+    del x0, y
+    xb = xbar32.astype(np.float64)
+    t0 = time.perf_counter()
+    keys = odet.detect_keys(xb, P, N)
+    tm["detect"] = time.perf_counter() - t0
+    keys_equal = bool(np.array_equal(keys, keys_gpu))
+    step = max(N // n_keys_sample, 1)
+    sel = np.arange(0, N, step)[:n_keys_sample]
+    t0 = time.perf_counter()
+    om.topk_exact(xb, P, keys_gpu[sel[:1]], K)
+    tm["topk_1"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    idx, _ = om.topk_exact(xb, P, keys_gpu[sel], K)
+    tm["topk_n"] = time.perf_counter() - t0
+    groups_equal = int(np.sum(np.all(idx == idx_gpu[sel], axis=1)))
+    sub = idx[:64]
+    t0 = time.perf_counter()
+    Xh, _ = olr.shrink_groups(xb, P, sub, 0.5, wl.wnnm_c, wl.wnnm_eps)
+    tm["wnnm_64"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oag.aggregate(xb, P, sub, Xh)
+    tm["aggregate_64"] = time.perf_counter() - t0
+    n = len(sel)
+    per_key = max(tm["topk_n"] - tm["topk_1"], 0.0) / max(n - 1, 1)
+    t_iter = (tm["data"] + tm["detect"] + tm["topk_1"] + per_key * (N - 1)
+              + (tm["wnnm_64"] + tm["aggregate_64"]) * N / 64.0)
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    cpu = {"value": round(1.0 / t_iter, 6), "unit": "iterations/s", "cores": threads,
+           "kind": "oracle",
+           "sample": (f"iteration 0 of {wl.name}: GAP data step and key detection on the whole "
+                      f"iterate, top-K for 1 and for {n} sampled keys (every {step}th), WNNM and "
+                      f"aggregation for 64 groups; extrapolated to {N} keys "
+                      f"({sum(tm.values()):.1f} s of CPU work on {os.cpu_count()} host CPUs)"),
+           "seconds_per_iteration": round(t_iter, 2),
+           "timed_s": {k: round(v, 3) for k, v in tm.items()},
+           "parity_on_gpu_iterate": {"keys_equal": keys_equal,
+                                     "groups_equal": f"{groups_equal}/{n}"}}
+    return cpu
+
+
+def cpu_small_single_thread(log):
+    """The oracle's whole 5-iteration run of the 128 x 128 x 8 CACTI workload
+    on one thread, median of five runs."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    import synth
+    from oracle import reconstruct as orc
+    wl = synth.WORKLOADS["cacti_128"]
+    inst = synth.make_instance(wl)
+    y = orc.measure(wl, inst["x_true"], inst["mask"])
+    sig = synth.sigma_schedule(wl).astype(np.float64)
+    times = []
+    with threadpool_limits(1):
+        for _ in range(5):
+            t0 = time.perf_counter()
+            orc.reconstruct(wl, y, inst["mask"], sig)
+            times.append(time.perf_counter() - t0)
+    med = float(np.median(times))
+    log(f"cacti_128 oracle single thread: {med:.2f} s per run")
+    return {"workload": "cacti_128", "iters": wl.iters, "runs": 5, "cores": 1,
+            "median_s": round(med, 3), "iterations_per_s": round(wl.iters / med, 3)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -104,6 +270,9 @@ def main():
     import paper_2301_03047_amd as glr
     import synth
 
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.calibrate_copy:
         src = torch.ones(256 << 20, dtype=torch.float32, device="cuda")
@@ -114,7 +283,7 @@ def main():
     wname = args.workload
     if wname == "surrogate":
         from paper_2301_03047_amd import eval_surrogate
-        res = eval_surrogate.run(log=lambda m: print(m, file=sys.stderr, flush=True))
+        res = eval_surrogate.run(log=log)
         v = res["variants"]
         print(json.dumps({
             "metric": "CNN-surrogate form: wall time and PSNR on 16 MRI 256^2 + 16 CACTI "
@@ -131,98 +300,151 @@ def main():
     T = wl.iters
     mask = torch.from_numpy(inst["mask"]).cuda() if inst["mask"] is not None else None
     x_true = torch.from_numpy(inst["x_true"]).cuda()
-    def make_plan(timing):
-        return glr.Plan(wl.modality, wl.H, wl.W, wl.C, wl.patch, wl.n_keys, wl.k, iters=T,
-                        sigma=sig, mask=mask, timing=timing, precision=prec)
+    one_pass = wname in LONG_STEPS
 
-    # `value` comes from a plan without per-stage events; a second plan with
-    # them repeats the same number of iterations (continuing from the same
-    # state) for the stage split and the roofline of the dominant kernel
-    plan = make_plan(False)
+    def make_plan(timing, precision=prec):
+        return glr.Plan(wl.modality, wl.H, wl.W, wl.C, wl.patch, wl.n_keys, wl.k, iters=T,
+                        sigma=sig, mask=mask, timing=timing, precision=precision)
+
+    plan = make_plan(one_pass)
     y = plan.forward(x_true)                       # measurement synthesised on the GPU
     state = plan.new_state()
     out = torch.empty_like(x_true)
 
-    def run(p, n, t0):
+    def run(p, n, t0, st_buf):
         t = t0
         for _ in range(n):
-            p.reconstruct(y, t, t + 1, state=state, out=out)
+            p.reconstruct(y, t, t + 1, state=st_buf, out=out)
             t = (t + 1) % T
         return t
 
-    t = run(plan, args.warmup, 0)
+    log(f"{wname}: warmup {args.warmup}, timed {args.steps} iterations ({prec} matcher)")
+    t = run(plan, args.warmup, 0, state)
     torch.cuda.synchronize()
+    state_at_timed = state.clone()
+    t_timed = t
+    plan.read_stats(reset=True)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    t = run(plan, args.steps, t)
+    t = run(plan, args.steps, t, state)
     e1.record()
     torch.cuda.synchronize()
     ms_total = e0.elapsed_time(e1)
     ms_per_step = ms_total / args.steps
     value = 1000.0 / ms_per_step
-    plan_t = make_plan(True)
-    plan_t.read_stats(reset=True)                  # stage timers cover the second pass only
-    run(plan_t, args.steps, t)
-    torch.cuda.synchronize()
-    st = plan_t.read_stats(reset=True)
-    del plan_t
-
-    stages = {k[3:]: st[k] / args.steps for k in
-              ("ms_detect", "ms_norms", "ms_match", "ms_topk", "ms_select", "ms_lowrank",
-               "ms_aggregate", "ms_data")}
-    match_ms = st["ms_match"] / max(st["match_launches"], 1)
-    flop_per_launch = 2.0 * wl.n_keys * wl.n_cand * wl.dim / max(st["match_launches"] / args.steps, 1)
-    match_tflops = flop_per_launch / (match_ms * 1e-3) / 1e12
-    dominant = max(stages, key=stages.get)
-
-    # roofline of the dominant kernel
-    # the FP32 form runs its small-patch variant when a key tile's padded
-    # slab (Cp P P2 <= 72 values per key, Cp <= 4) fits in LDS
-    P, P2 = wl.patch, wl.patch + (wl.patch & 1)
-    Cp = wl.dim // (P * P)
-    small = Cp * P * P2 <= 72 and Cp <= 4
-    match_kernel = "k_match_bf16" if prec == "bf16" else (
-        "k_match_f32_slab" if small else "k_match_f32")
-    match_peak = PEAK_BF16_MFMA_TFLOPS if prec == "bf16" else PEAK_FP32_MFMA_TFLOPS
-    if dominant == "match":
-        roof = {"kernel": match_kernel, "bound": "mfma", "achieved": round(match_tflops, 3),
-                "peak": match_peak, "unit": "TFLOP/s",
-                "frac": round(match_tflops / match_peak, 4),
-                "traffic": measured_traffic(match_kernel, wname)}
-    elif dominant == "lowrank":
-        # WNNM per group: streamed Householder QR (2 D K^2), Jacobi sweeps on the
-        # K x K factor (6 K flop per pair per sweep for the three dots plus 12 K
-        # for the two rotations), W = V diag V^T (2 K^3) and the residual Y_c W
-        # (2 D K^2, FP64); counted at the measured sweep count
-        K, D = wl.k, wl.dim
-        sweeps = max(st["jacobi_sweeps_max"], 1)
-        flop = wl.n_keys * (2 * D * K * K + sweeps * (K * (K - 1) / 2) * 18 * K + 2 * K ** 3 + 2 * D * K * K)
-        ach = flop / (stages["lowrank"] * 1e-3) / 1e12
-        roof = {"kernel": "k_wnnm", "bound": "alu", "achieved": round(ach, 4),
-                "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(ach / PEAK_FP32_VALU_TFLOPS, 5),
-                "traffic": measured_traffic("k_wnnm", wname),
-                "note": "upper-bound flop count at the worst group's sweep count"}
-    elif dominant == "topk":
-        gbs = 4.0 * wl.n_keys * wl.n_cand / (stages["topk"] * 1e-3) / 1e9
-        roof = {"kernel": "k_topk_partial", "bound": "hbm", "achieved": round(gbs, 1),
-                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
-                "traffic": measured_traffic("k_topk_partial", wname)}
+    if one_pass:
+        st = plan.read_stats(reset=True)
     else:
-        roof = {"kernel": dominant, "bound": "latency", "achieved": None, "peak": None,
-                "unit": None, "frac": None, "traffic": None}
+        plan_t = make_plan(True)
+        plan_t.read_stats(reset=True)
+        run(plan_t, args.steps, t, state)
+        torch.cuda.synchronize()
+        st = plan_t.read_stats(reset=True)
+        del plan_t
+    log(f"timed: {ms_per_step:.2f} ms per iteration")
+    stages = stage_split(st, args.steps)
+    kernels = kernel_rooflines(wl, prec, st, args.steps)
+    match_name = next(k for k in kernels if k.startswith("k_match"))
+    mk = kernels[match_name]
+    roof = {"kernel": match_name, "bound": "mfma", "achieved": mk["achieved"],
+            "peak": mk["peak"], "unit": "TFLOP/s", "frac": mk["frac"],
+            "traffic": mk["traffic"],
+            "work": f"2*n_keys*N_cand*D = {2.0 * wl.n_keys * wl.n_cand * wl.dim:.4g} flop per "
+                    f"iteration over {mk['launches_per_step']:g} launches"}
+    rec = {
+        "metric": METRIC, "value": round(value, 4), "unit": "iterations/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16+f32" if prec == "bf16" else "f32",
+        "data": "synthetic",
+        "config": dict({"workload": wname, "patch": wl.patch, "keys": wl.n_keys, "K": wl.k,
+                        "iters": T, "matcher": prec,
+                        "timed_iterations": f"t = {t_timed}..{t_timed + args.steps - 1} "
+                                            f"(mod {T}) after {args.warmup} warm-up"},
+                       **CONFIG_TEXT[wname]),
+        "roofline": roof,
+        "cpu_baseline": None,
+        "matching_tflops": mk["achieved"],
+        "matching_frac_mfma_peak": mk["frac"],
+        "kernels": kernels,
+        "stages_ms_per_step": {k: round(v, 4) for k, v in stages.items()},
+        "margin_mean": round(st["margin_sum"] / max(wl.n_keys * args.steps, 1), 2),
+        "margin_max": st["margin_max"], "overflow_keys": st["overflow_keys"],
+        "regather_keys": st["regather_keys"], "rematch_keys": st["rematch_keys"],
+        "jacobi_sweeps_max": st["jacobi_sweeps_max"],
+    }
 
-    # quality: a fresh full reconstruction, and the first iterations vs the oracle
+    # quality: a fresh full-length reconstruction, timed as a whole
     from paper_2301_03047_amd.surrogate import psnr
     xt = inst["x_true"]
-    psnr_full = None
     if not args.no_quality:
-        fresh, _ = plan.reconstruct(y, 0, T)
-        psnr_full = psnr(fresh.cpu().numpy(), xt)
+        plan.read_stats(reset=True)
+        fs = plan.new_state()
+        e0.record()
+        fresh, _ = plan.reconstruct(y, 0, T, state=fs)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_full = e0.elapsed_time(e1)
+        sf = plan.read_stats(reset=True)
+        rec["full_run"] = {"iters": T, "seconds": round(ms_full / 1e3, 3),
+                           "iterations_per_s": round(T * 1e3 / ms_full, 4),
+                           "psnr_db": round(psnr(fresh.cpu().numpy(), xt), 4),
+                           "rematch_keys": sf["rematch_keys"],
+                           "regather_keys": sf["regather_keys"],
+                           "overflow_keys": sf["overflow_keys"],
+                           "margin_mean": round(sf["margin_sum"] / (wl.n_keys * T), 2)}
+        log(f"full run: {ms_full / 1e3:.2f} s, PSNR {rec['full_run']['psnr_db']} dB")
+        del fs
 
-    cpu = None
-    psnr_cmp = None
-    if not args.no_cpu_baseline and wname == "mri_256":
+    if prec == "bf16" and not args.no_fp32_form:
+        # the FP32 form on the same state: its speed, and bitwise-equal groups
+        # and prior-step output on the pre-prior iterate of the first timed step
+        pf = make_plan(False, "fp32")
+        n_f = args.steps
+        sf_buf = state_at_timed.clone()
+        run(pf, 1, t_timed, sf_buf)                      # warm-up of the FP32 plan
+        sf_buf.copy_(state_at_timed)
+        e0.record()
+        run(pf, n_f, t_timed, sf_buf)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_f = e0.elapsed_time(e1) / n_f
+        x_state = state_at_timed[:wl.C * wl.H * wl.W * 4].view(torch.float32).view(
+            wl.C, wl.H, wl.W)
+        xbar = plan.data_step(y, x=x_state.contiguous())
+        keys = plan.detect_keys(xbar)
+        ib, db = plan.match_topk(xbar, keys)
+        i32, d32 = pf.match_topk(xbar, keys)
+        ob = plan.prior_step(xbar, float(sig[t_timed]))
+        of = pf.prior_step(xbar, float(sig[t_timed]))
+        torch.cuda.synchronize()
+        rec["fp32_form"] = {
+            "iterations": f"t = {t_timed}..{t_timed + n_f - 1} from the same state",
+            "ms_per_step": round(ms_f, 3), "iterations_per_s": round(1e3 / ms_f, 4),
+            "bf16_speedup": round(ms_f / ms_per_step, 3),
+            "groups_equal": bool(torch.equal(ib, i32) and torch.equal(db, d32)),
+            "prior_output_equal": bool(torch.equal(ob, of))}
+        log(f"fp32 form: {ms_f:.1f} ms per iteration; groups equal "
+            f"{rec['fp32_form']['groups_equal']}")
+        del pf, sf_buf
+
+    if not args.no_cpu_baseline and wname == "cacti_1024":
+        # the pre-prior iterate of iteration 0 on the GPU, its keys and groups
+        s0 = plan.new_state()
+        x0, _ = plan.reconstruct(y, 0, 0, state=s0)
+        xbar = plan.data_step(y, x=x0)
+        keys = plan.detect_keys(xbar)
+        idx, _ = plan.match_topk(xbar, keys)
+        torch.cuda.synchronize()
+        xb_h, keys_h, idx_h = xbar.cpu().numpy(), keys.cpu().numpy(), idx.cpu().numpy()
+        del plan, s0, xbar
+        torch.cuda.empty_cache()
+        log("cpu baseline (oracle sample) ...")
+        cpu = cpu_baseline_cacti_1024(wl, inst, xb_h, keys_h, idx_h, args.cpu_keys)
+        cpu["small_single_thread"] = cpu_small_single_thread(log)
+        rec["cpu_baseline"] = cpu
+        log(f"cpu baseline: {cpu['seconds_per_iteration']} s per iteration (extrapolated)")
+    elif not args.no_cpu_baseline and wname == "mri_256":
         from threadpoolctl import threadpool_info
         from oracle import reconstruct as orc, metrics as om_metrics
         n_it = args.cpu_iters
@@ -231,8 +453,8 @@ def main():
         n_cmp = min(5, n_it)                         # tight comparison point
         early = {}
 
-        def keep(t, _v, z):
-            if t + 1 == n_cmp:
+        def keep(tt, _v, z):
+            if tt + 1 == n_cmp:
                 early["z"] = z.copy()
 
         t0 = time.perf_counter()
@@ -240,41 +462,23 @@ def main():
                               callback=keep)
         dt = time.perf_counter() - t0
         threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-        cpu = {"value": round(n_it / dt, 4), "unit": "iterations/s", "cores": threads,
-               "kind": "oracle",
-               "sample": f"first {n_it} of {T} ADMM iterations of {wname} (same input), "
-                         f"{dt:.1f} s on {os.cpu_count()} host CPUs"}
+        rec["cpu_baseline"] = {
+            "value": round(n_it / dt, 4), "unit": "iterations/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {n_it} of {T} ADMM iterations of {wname} (same input), "
+                      f"{dt:.1f} s on {os.cpu_count()} host CPUs"}
         # the first n_cmp iterations agree to FP32 rounding; later ones drift
         # apart once a rounding difference flips a discrete choice (a key or
         # a group member), which the per-iteration parity tests allow for
-        psnr_cmp = {}
+        cmp = {}
         for name, n, r in (("first", n_cmp, early["z"]), ("sample", n_it, ref)):
             g, _ = plan.reconstruct(y, 0, n)
             g = g.cpu().numpy()
             pg, pr = om_metrics.psnr(g, xt), om_metrics.psnr(r, xt)
-            psnr_cmp[name] = {"iters": n, "gpu_db": round(pg, 4), "oracle_db": round(pr, 4),
-                              "delta_db": round(pg - pr, 5),
-                              "rel_l2_vs_oracle": float(f"{om_metrics.rel_l2(g, r):.3e}")}
-
-    rec = {
-        "metric": METRIC, "value": round(value, 3), "unit": "iterations/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16+f32" if prec == "bf16" else "f32",
-        "data": "synthetic",
-        "config": dict({"workload": wname, "patch": wl.patch, "keys": wl.n_keys, "K": wl.k,
-                        "iters": T, "matcher": prec}, **CONFIG_TEXT[wname]),
-        "roofline": roof,
-        "cpu_baseline": cpu,
-        "matching_tflops": round(match_tflops, 3),
-        "matching_frac_mfma_peak": round(match_tflops / match_peak, 4),
-        "stages_ms_per_step": {k: round(v, 4) for k, v in stages.items()},
-        "psnr_full_db": None if psnr_full is None else round(psnr_full, 4),
-        "psnr_vs_oracle": psnr_cmp,
-        "margin_mean": round(st["margin_sum"] / max(wl.n_keys * args.steps, 1), 2),
-        "margin_max": st["margin_max"], "overflow_keys": st["overflow_keys"],
-        "jacobi_sweeps_max": st["jacobi_sweeps_max"],
-    }
+            cmp[name] = {"iters": n, "gpu_db": round(pg, 4), "oracle_db": round(pr, 4),
+                         "delta_db": round(pg - pr, 5),
+                         "rel_l2_vs_oracle": float(f"{om_metrics.rel_l2(g, r):.3e}")}
+        rec["psnr_vs_oracle"] = cmp
     print(json.dumps(rec), flush=True)
 
 
