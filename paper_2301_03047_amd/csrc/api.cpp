@@ -119,6 +119,8 @@ glr_status match_stage(glr_plan* pl, const float* xp, const int32_t* keys, int32
   float* kmb = (float*)(ws + pl->ws.kmb);
   float* cmeta = (float*)(ws + pl->ws.cmeta);
   float* cm2 = (float*)(ws + pl->ws.cm2);
+  float* kre = (float*)(ws + pl->ws.kre);
+  float* cre = (float*)(ws + pl->ws.cre);
   uint16_t* Ab = (uint16_t*)(ws + pl->ws.Ab);
   float* Ac = (float*)(ws + pl->ws.Ac);
   float* kn = (float*)(ws + pl->ws.kn);
@@ -144,8 +146,8 @@ glr_status match_stage(glr_plan* pl, const float* xp, const int32_t* keys, int32
     StageTimer t(pl, s, T_NORMS);
     launch_gather_keys(pl, xp, keys, A, tsh, s);
     if (bf) {
-      launch_key_meta(pl, A, Ab, kmb, s);
-      launch_cand_meta(pl, xp, cmeta, cm2, s);
+      launch_key_meta(pl, A, Ab, kmb, kre, s);
+      launch_cand_meta(pl, xp, cmeta, cm2, cre, s);
     } else {
       launch_key_meta_pc(pl, A, Ac, kn, kc, s);
       launch_cand_meta_pc(pl, xp, pn, pc, pq, s);
@@ -163,12 +165,13 @@ glr_status match_stage(glr_plan* pl, const float* xp, const int32_t* keys, int32
       }
       {
         StageTimer t(pl, s, T_TOPK);
-        launch_topk_partial(pl, dist, kn, kmap, g0, pq, nk, 0, tsh, lj, lu, ll, lcnt, s);
+        launch_topk_partial(pl, dist, kn, nullptr, kmap, g0, pq, nullptr, nk, 0, tsh, lj, lu,
+                            ll, lcnt, s);
       }
       {
         StageTimer t(pl, s, T_SELECT);
         launch_select_rescore(pl, xp, A, kmap, g0, nk, lj, lu, ll, lcnt, idx_out, dd_out, oflag,
-                              tsh, 0, bm, dist, kn, pq, 0, tkey, st, s);
+                              tsh, 0, bm, dist, kn, nullptr, pq, nullptr, 0, tkey, st, s);
       }
     }
   };
@@ -189,12 +192,13 @@ glr_status match_stage(glr_plan* pl, const float* xp, const int32_t* keys, int32
     }
     {
       StageTimer t(pl, s, T_TOPK);
-      launch_topk_partial(pl, dist, kmb, nullptr, g0, cm2, nk, 1, tsh, lj, lu, ll, lcnt, s);
+      launch_topk_partial(pl, dist, kmb, kre, nullptr, g0, cm2, cre, nk, 1, tsh, lj, lu, ll,
+                          lcnt, s);
     }
     {
       StageTimer t(pl, s, T_SELECT);
       launch_select_rescore(pl, xp, A, nullptr, g0, nk, lj, lu, ll, lcnt, idx_out, dd_out, oflag,
-                            tsh, 1, bm, dist, kmb, cm2, 1, tkey, st, s);
+                            tsh, 1, bm, dist, kmb, kre, cm2, cre, 1, tkey, st, s);
       launch_collect_flags(oflag, g0, nk, klist, kcount, st, s);
     }
   }
@@ -527,6 +531,8 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
   L.kmb = c.take(bf ? (size_t)pl->N * 16 : 0);
   L.cmeta = c.take(bf ? (size_t)Ncand * 16 : 0);
   L.cm2 = c.take(bf ? (size_t)Ncand * 8 : 0);
+  L.kre = c.take(bf ? (size_t)pl->N * 4 : 0);
+  L.cre = c.take(bf ? (size_t)Ncand * 4 : 0);
   L.Ac = c.take((size_t)pl->N * D * 4);
   L.kn = c.take((size_t)pl->N * 16);
   L.kc = c.take((size_t)pl->N * Cp * 4);

@@ -31,6 +31,7 @@ struct WsLayout {
   size_t keys;                   // detected keys [N]
   size_t A;                      // key matrix [N][D] f32
   size_t kmb, cmeta, cm2;        // BF16 form: centred key / candidate metadata (one mean)
+  size_t kre, cre;               // BF16 form: key / candidate BF16 rounding residual norms
   size_t Ac, kn, kc, pn, pc, pq; // FP32 form: channel-centred keys and metadata
   size_t Ab;                     // BF16 form: centred keys in the BF16 slice layout
   size_t tsh;                    // per-key shared threshold bound [n_chunk]
@@ -129,10 +130,13 @@ void launch_detect(const glr_plan* pl, const float* xp, char* ws, int32_t* keys,
 void launch_gather_keys(const glr_plan* pl, const float* xp, const int32_t* keys, float* A,
                         uint32_t* tsh, hipStream_t s);
 int bf16_key_row(int P);     // bf16 values per key and channel in the BF16 key layout
-// kmb[N] float4 (||a||^2, mu_k, sum a, ||a||); Ab (BF16 key slices) may be null
-void launch_key_meta(const glr_plan* pl, const float* A, uint16_t* Ab, float* kmb, hipStream_t s);
-// cmeta[Ncand] float4 (mu, ||pbar||^2, ||pbar||, sum pbar); cm2[Ncand] float2 (mu, ||pbar||)
-void launch_cand_meta(const glr_plan* pl, const float* xp, float* cmeta, float* cm2,
+// kmb[N] float4 (||a||^2, mu_k, sum a, ||a||), kre[N] ||a - bf16(a)||; Ab
+// (BF16 key slices) may be null
+void launch_key_meta(const glr_plan* pl, const float* A, uint16_t* Ab, float* kmb, float* kre,
+                     hipStream_t s);
+// cmeta[Ncand] float4 (mu, ||pbar||^2, ||pbar||, sum pbar); cm2[Ncand] float2
+// (mu, ||pbar||); cre[Ncand] ||pbar - bf16(pbar)||
+void launch_cand_meta(const glr_plan* pl, const float* xp, float* cmeta, float* cm2, float* cre,
                       hipStream_t s);
 // FP32 form, channel-centred: Ac[N][D] (a~), kn[N] float4 (||a~||^2, h_k, 0, ||a~||),
 // kc[N][Cp] (fl(P mu_kc)); pn[Ncand] (||p~||^2), pc[Cp][Ncand] float2
@@ -149,12 +153,13 @@ void launch_match_bf16(const glr_plan* pl, const float* xp, const uint16_t* Ab, 
                        const float* cmeta, int g0, int nk, float* dist, hipStream_t s);
 
 // topk.hip
-// bf16 = 1: BF16 form (kmb/cm2 of launch_key_meta/launch_cand_meta); 0: the
-// channel-centred FP32 form (kn/pq of launch_key_meta_pc/launch_cand_meta_pc)
+// bf16 = 1: BF16 form (kmb/cm2 and the residual norms kre/cre of
+// launch_key_meta/launch_cand_meta); 0: the channel-centred FP32 form
+// (kn/pq of launch_key_meta_pc/launch_cand_meta_pc; kre, cre null)
 void launch_topk_partial(const glr_plan* pl, const float* dist, const float* kmb,
-                         const int32_t* kmap, int g0, const float* cm2, int nk, int bf16,
-                         uint32_t* tsh, int32_t* lj, float* lu, float* ll, int32_t* lcnt,
-                         hipStream_t s);
+                         const float* kre, const int32_t* kmap, int g0, const float* cm2,
+                         const float* cre, int nk, int bf16, uint32_t* tsh, int32_t* lj,
+                         float* lu, float* ll, int32_t* lcnt, hipStream_t s);
 // Global scratch of the large-margin path: per chunk key, cap entries of
 // position, rescored hi and lo.
 struct BigMargin {
@@ -172,7 +177,9 @@ struct RowBound {
   const float* dist;
   size_t ldd;
   const float* km;
+  const float* kre;
   const float* cm;
+  const float* cre;
   int pc;
   float coef, coef2, cz;
   float* tkey;
@@ -182,7 +189,8 @@ void launch_select_rescore(const glr_plan* pl, const float* xp, const float* A,
                            const float* lu, const float* ll, const int32_t* lcnt, int32_t* idx,
                            float* dd, int32_t* oflag, uint32_t* tsh, int defer,
                            const BigMargin& bm, const float* dist, const float* kmb,
-                           const float* cm2, int bf16, float* tkey, DevStats* st, hipStream_t s);
+                           const float* kre, const float* cm2, const float* cre, int bf16,
+                           float* tkey, DevStats* st, hipStream_t s);
 void launch_collect_flags(const int32_t* oflag, int g0, int nk, int32_t* klist, int32_t* kcount,
                           DevStats* st, hipStream_t s);
 

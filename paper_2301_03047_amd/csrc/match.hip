@@ -628,11 +628,17 @@ __host__ __device__ constexpr int bf16_slices(int P) {
   return P <= 8 ? P + (P & 1) : (P <= 12 ? 24 : 32);
 }
 
+// BF16 value of f (round to nearest even) as a float
+__device__ __forceinline__ float bf16_val(float f) { return __uint_as_float(bf16_rne(f) << 16); }
+
 // Per key: kmb[g] = (||a||^2, mu_k, sum a, ||a||) with a = k - mu_k (FP32,
-// the values both matchers use); with Ab, also Ab[g][c][t][0..8) = bf16(a)
-// in the BF16 slice layout (padding zero).  One wave per key.
+// the values both matchers use) and kre[g] = ||a - bf16(a)|| (the BF16
+// operand's rounding residual, for the error bound); with Ab, also
+// Ab[g][c][t][0..8) = bf16(a) in the BF16 slice layout (padding zero).  One
+// wave per key.
 __global__ void k_key_meta(const float* __restrict__ A, int D, int P, int Cp, int NS, int XS,
-                           int N, uint16_t* __restrict__ Ab, float4* __restrict__ kmb) {
+                           int N, uint16_t* __restrict__ Ab, float4* __restrict__ kmb,
+                           float* __restrict__ kre) {
   const int g = blockIdx.x;
   if (g >= N) return;
   const float* k = A + (size_t)g * D;
@@ -641,17 +647,23 @@ __global__ void k_key_meta(const float* __restrict__ A, int D, int P, int Cp, in
   for (int d = l; d < D; d += 64) s += k[d];
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
   const float mu = s / (float)D;
-  float an = 0.f, sa = 0.f;
+  float an = 0.f, sa = 0.f, en = 0.f;
   for (int d = l; d < D; d += 64) {
     const float a = k[d] - mu;
+    const float e = a - bf16_val(a);        // exact
     an = fmaf(a, a, an);
     sa += a;
+    en = fmaf(e, e, en);
   }
   for (int o = 32; o > 0; o >>= 1) {
     an += __shfl_xor(an, o, 64);
     sa += __shfl_xor(sa, o, 64);
+    en += __shfl_xor(en, o, 64);
   }
-  if (l == 0) kmb[g] = make_float4(an, mu, sa, sqrtf(an));
+  if (l == 0) {
+    kmb[g] = make_float4(an, mu, sa, sqrtf(an));
+    kre[g] = sqrtf(en);
+  }
   if (!Ab) return;
   const int row = NS * 8;
   for (int e = l; e < Cp * row; e += 64) {
@@ -664,9 +676,12 @@ __global__ void k_key_meta(const float* __restrict__ A, int D, int P, int Cp, in
 
 // Per candidate: cmeta[j] = (mu_p, ||pbar||^2, ||pbar||, sum pbar) with
 // pbar = p - mu_p computed in FP32 exactly as the matcher forms its operand;
-// cm2[j] = (mu_p, ||pbar||) for the error bound of the top-K pass.
+// cm2[j] = (mu_p, ||pbar||) and cre[j] = ||pbar - bf16(pbar)|| (the residual
+// of the matcher's round-to-nearest-even BF16 operand) for the error bound
+// of the top-K pass.
 __global__ void k_cand_meta(const float* __restrict__ xp, int Cp, int H, int W, int P,
-                            float4* __restrict__ cmeta, float2* __restrict__ cm2) {
+                            float4* __restrict__ cmeta, float2* __restrict__ cm2,
+                            float* __restrict__ cre) {
   const int Wc = W - P + 1, Hc = H - P + 1;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= Hc * Wc) return;
@@ -679,19 +694,22 @@ __global__ void k_cand_meta(const float* __restrict__ xp, int Cp, int H, int W, 
       for (int dx = 0; dx < P; ++dx) s += row[dx];
     }
   const float mu = s / (float)D;
-  float pn = 0.f, sp = 0.f;
+  float pn = 0.f, sp = 0.f, en = 0.f;
   for (int ch = 0; ch < Cp; ++ch)
     for (int dy = 0; dy < P; ++dy) {
       const float* row = xp + ((size_t)ch * H + r + dy) * W + c;
       for (int dx = 0; dx < P; ++dx) {
         const float v = row[dx] - mu;
+        const float e = v - bf16_val(v);    // exact
         pn = fmaf(v, v, pn);
         sp += v;
+        en = fmaf(e, e, en);
       }
     }
   const float pr = sqrtf(pn);
   cmeta[j] = make_float4(mu, pn, pr, sp);
   cm2[j] = make_float2(mu, pr);
+  cre[j] = sqrtf(en);
 }
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -892,17 +910,18 @@ void launch_gather_keys(const glr_plan* pl, const float* xp, const int32_t* keys
 
 int bf16_key_row(int P) { return bf16_slices(P) * 8; }
 
-void launch_key_meta(const glr_plan* pl, const float* A, uint16_t* Ab, float* kmb, hipStream_t s) {
+void launch_key_meta(const glr_plan* pl, const float* A, uint16_t* Ab, float* kmb, float* kre,
+                     hipStream_t s) {
   const int NS = bf16_slices(pl->P);
   hipLaunchKernelGGL(k_key_meta, dim3(pl->N), dim3(64), 0, s, A, pl->D, pl->P, pl->Cp, NS,
-                     NS > 8 ? 2 : 1, pl->N, Ab, (float4*)kmb);
+                     NS > 8 ? 2 : 1, pl->N, Ab, (float4*)kmb, kre);
 }
 
-void launch_cand_meta(const glr_plan* pl, const float* xp, float* cmeta, float* cm2,
+void launch_cand_meta(const glr_plan* pl, const float* xp, float* cmeta, float* cm2, float* cre,
                       hipStream_t s) {
   const int n = pl->Ncand;
   hipLaunchKernelGGL(k_cand_meta, dim3((n + 255) / 256), dim3(256), 0, s, xp, pl->Cp, pl->H,
-                     pl->W, pl->P, (float4*)cmeta, (float2*)cm2);
+                     pl->W, pl->P, (float4*)cmeta, (float2*)cm2, cre);
 }
 
 void launch_key_meta_pc(const glr_plan* pl, const float* A, float* Ac, float* kn, float* kc,

@@ -1,16 +1,23 @@
 // Top-K grouping (eq. 1 with KNN grouping, searched over the whole image).
 //
-// The matcher's d~ (centred form) carries a rounding error bounded by
-//     eps_j = c1 ||a|| ||pbar_j|| + c2 R_j^2,
+// The matcher's d~ (BF16 form: one mean per patch) carries a rounding error
+// bounded by
+//     eps_j = c2 R_j^2 + c1 (||a|| ||e_j|| + ||e_a|| (||pbar_j|| + ||e_j||)),
 //     R_j = ||a|| + ||pbar_j|| + sqrt(D) |mu_k - mu_j|,
-// with a, pbar_j the centred key and candidate, u = 2^-24 (FP32 unit
-// round-off), b = 2^-8 (BF16 round-to-nearest-even unit round-off: 8
-// significant bits) and
-//     c2 = (3 D + 26) u       (FP32 dot-product sums, centring, epilogue),
-//     c1 = 4 (2 b + b^2)      (BF16 operand rounding of both factors, whose
-//                              worst case is 2 (2 b + b^2) ||a|| ||pbar||
-//                              on -2 S; 0 for the FP32 form),
-// each with a safety factor of two.  With U_j = d~_j + eps_j and
+// with a, pbar_j the centred key and candidate (FP32), e_a = a - bf16(a) and
+// e_j = pbar_j - bf16(pbar_j) the exact residuals of the BF16 operands (their
+// norms computed by the metadata kernels), u = 2^-24 (FP32 unit round-off)
+// and
+//     c2 = (3 D + 26) u       (FP32 dot-product sums, centring, epilogue;
+//                              a safety factor of two),
+//     c1 = 2 (1 + 2^-8)       (the BF16 operands: <a, pbar> - <bf16(a),
+//                              bf16(pbar)> = <a, e_j> + <e_a, bf16(pbar)>
+//                              exactly, at most ||a|| ||e_j|| + ||e_a||
+//                              (||pbar|| + ||e_j||) by Cauchy-Schwarz, twice
+//                              on -2 S; the factor 1 + 2^-8 covers the FP32
+//                              roundings of the norms and products).
+// The FP32 form's bound (channel-centred) is described at k_topk_partial.
+// With U_j = d~_j + eps_j and
 // L_j = d~_j - eps_j, let T be the K-th smallest U_j of a key: every member
 // of the exact top-K has L_j <= d_j <= T, so the margin set {j : L_j <= T}
 // contains the exact answer.  Stage 1 finds, per (key, candidate range), the
@@ -138,9 +145,11 @@ __device__ int wave_compact(int* bj, float* bu, float* bl, int n, float T) {
 
 // Error bound eps of one candidate's d~ (see k_topk_partial for the two
 // forms); d: d~, p: the candidate's centred norm, m: its mean (BF16 form) or
-// channel-mean term h_j (FP32 form); kr, kmu: the key's.
-__device__ __forceinline__ float margin_eps(float d, float p, float m, float kr, float kmu, int pc,
-                                            float coef, float coef2, float cz) {
+// channel-mean term h_j (FP32 form), ep: its BF16 residual norm (BF16 form);
+// kr, kmu, ek: the key's.
+__device__ __forceinline__ float margin_eps(float d, float p, float m, float ep, float kr,
+                                            float kmu, float ek, int pc, float coef,
+                                            float coef2, float cz) {
   if (pc) {
     const float w = cz * (kmu + m);
     // hardware square root (within 1 ulp; the bound's slack covers it)
@@ -149,12 +158,13 @@ __device__ __forceinline__ float margin_eps(float d, float p, float m, float kr,
     return fmaf(y, fmaf(coef2, y, w), w * w);
   }
   const float R = (kr + p) + cz * fabsf(kmu - m);
-  return coef * (kr * p) + coef2 * (R * R);
+  return coef * (kr * ep + ek * (p + ep)) + coef2 * (R * R);
 }
 
 // Error bound of d~ per candidate (key row kmap[g0+g] or g0+g):
 //  pc == 0 (BF16 form, one mean per patch): km = (||a||^2, mu_k, sum a, ||a||),
-//    cm = (mu_j, ||pbar_j||); eps = coef ||a|| ||pbar|| + coef2 R^2 with
+//    ke = ||e_a||, cm = (mu_j, ||pbar_j||), ce = ||e_j||; eps = coef (||a||
+//    ||e_j|| + ||e_a|| (||pbar_j|| + ||e_j||)) + coef2 R^2 with
 //    R = ||a|| + ||pbar|| + cz |mu_k - mu_j|, cz = sqrt(D);
 //  pc == 1 (channel-centred FP32 form): km = (||a~||^2, h_k, 0, ||a~||),
 //    cm = (h_j, ||p~_j||); with w = cz (h_k + h_j) (the centring residues)
@@ -163,10 +173,11 @@ __device__ __forceinline__ float margin_eps(float d, float p, float m, float kr,
 //    distance.
 // tsh[g]: the key's shared bound of T (ordered bits, +inf at launch), lowered
 // with atomicMin by every range.
-template <int U4, int WCAP>
-__global__ void __launch_bounds__(256)
+template <int U4, int WCAP, int MINW, bool PF>
+__global__ void __launch_bounds__(256, MINW)
 k_topk_partial(const float* __restrict__ dist, size_t ldd, const float4* __restrict__ km,
-               const int32_t* __restrict__ kmap, int g0, const float* __restrict__ cm, int Ncand,
+               const float* __restrict__ ke, const int32_t* __restrict__ kmap, int g0,
+               const float* __restrict__ cm, const float* __restrict__ ce, int Ncand,
                int split_len, int S, int nk, int K, int pc, float coef, float coef2, float cz,
                uint32_t* __restrict__ tsh, int32_t* __restrict__ lj, float* __restrict__ lu,
                float* __restrict__ ll, int32_t* __restrict__ lcnt) {
@@ -189,8 +200,10 @@ k_topk_partial(const float* __restrict__ dist, size_t ldd, const float4* __restr
   int* hist = shist[wave];
   const int j0 = sp * split_len;
   const int j1 = min(Ncand, j0 + split_len);
-  const float4 kmv = km[kmap ? kmap[g0 + g] : g0 + g];
+  const int gk = kmap ? kmap[g0 + g] : g0 + g;
+  const float4 kmv = km[gk];
   const float kr = kmv.w, kmu = kmv.y;
+  const float ek = pc ? 0.f : ke[gk];
   // publish T to the key's shared bound and take the bound back
   auto share = [&](float Tl) {
     uint32_t old = 0u;
@@ -209,8 +222,25 @@ k_topk_partial(const float* __restrict__ dist, size_t ldd, const float4* __restr
   // buffer: the first chunk's first WCAP candidates seed T.
   constexpr int CH = 256 * U4;
   constexpr int SU = WCAP / 256 < U4 ? WCAP / 256 : U4;   // chunk blocks that seed T
-  // pv: ||pbar_j||; mv: mu_j
+  // pv: ||pbar_j||; mv: mu_j; ev: ||e_j|| (BF16 form)
+  // ev: the BF16 form's residual norms, loaded with the next chunk (PF) or
+  // at the start of each chunk (fewer registers; the other waves of the
+  // SIMD cover the latency)
   float dv[U4][4], pv[U4][4], mv[U4][4], dn[U4][4], pn[U4][4], mn[U4][4];
+  float ev[U4][4], en[U4][4];
+  auto load_ev = [&](int base, float (&ee)[U4][4]) {
+#pragma unroll
+    for (int u = 0; u < U4; ++u) {
+      const int j = base + u * 256 + 4 * l;
+      if (!pc && j + 3 < j1) {
+        const float4 c4 = *reinterpret_cast<const float4*>(ce + j);
+        ee[u][0] = c4.x; ee[u][1] = c4.y; ee[u][2] = c4.z; ee[u][3] = c4.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) ee[u][e] = (!pc && j + e < j1) ? ce[j + e] : 0.f;
+      }
+    }
+  };
   auto load = [&](int base, float (&d)[U4][4], float (&p)[U4][4], float (&m)[U4][4]) {
 #pragma unroll
     for (int u = 0; u < U4; ++u) {
@@ -234,8 +264,13 @@ k_topk_partial(const float* __restrict__ dist, size_t ldd, const float4* __restr
     }
   };
   load(j0, dv, pv, mv);
+  if constexpr (PF) load_ev(j0, ev);
   for (int base = j0; base < j1; base += CH) {
-    if (base + CH < j1) load(base + CH, dn, pn, mn);
+    if (base + CH < j1) {
+      load(base + CH, dn, pn, mn);
+      if constexpr (PF) load_ev(base + CH, en);
+    }
+    if constexpr (!PF) load_ev(base, ev);
     // positions past the end of the range are never admitted (explicit
     // validity: an infinite L would still pass L <= T while T is +inf)
     float Lv[U4][4], Uv[U4][4];
@@ -245,8 +280,8 @@ k_topk_partial(const float* __restrict__ dist, size_t ldd, const float4* __restr
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int j = base + u * 256 + 4 * l + e;
-        const float eps =
-            margin_eps(dv[u][e], pv[u][e], mv[u][e], kr, kmu, pc, coef, coef2, cz);
+        const float eps = margin_eps(dv[u][e], pv[u][e], mv[u][e], ev[u][e], kr, kmu, ek, pc,
+                                     coef, coef2, cz);
         ok[u][e] = j < j1;
         Uv[u][e] = dv[u][e] + eps;
         Lv[u][e] = dv[u][e] - eps;
@@ -303,6 +338,7 @@ k_topk_partial(const float* __restrict__ dist, size_t ldd, const float4* __restr
         dv[u][e] = dn[u][e];
         pv[u][e] = pn[u][e];
         mv[u][e] = mn[u][e];
+        if constexpr (PF) ev[u][e] = en[u][e];
       }
   }
   if (!ovf) {
@@ -806,10 +842,11 @@ k_rescore_overflow(const float* __restrict__ xp, int H, int W, int P, int Cp, in
     const float* drow = rb.dist + (size_t)g * rb.ldd;
     const float4 kmv = reinterpret_cast<const float4*>(rb.km)[gg];
     const float kr = kmv.w, kmu = kmv.y;
+    const float ek = rb.pc ? 0.f : rb.kre[gg];
     const int l = tid & 63;
     for (int base = 0; base < Ncand; base += 4 * ST) {
       const int j = base + 4 * tid;
-      float dv[4], pv[4], mv[4];
+      float dv[4], pv[4], mv[4], ev[4];
       if (j + 3 < Ncand) {
         const float4 a = *reinterpret_cast<const float4*>(drow + j);
         const float4 b0 = *reinterpret_cast<const float4*>(rb.cm + 2 * (size_t)j);
@@ -817,6 +854,12 @@ k_rescore_overflow(const float* __restrict__ xp, int H, int W, int P, int Cp, in
         dv[0] = a.x; dv[1] = a.y; dv[2] = a.z; dv[3] = a.w;
         mv[0] = b0.x; pv[0] = b0.y; mv[1] = b0.z; pv[1] = b0.w;
         mv[2] = b1.x; pv[2] = b1.y; mv[3] = b1.z; pv[3] = b1.w;
+        if (!rb.pc) {
+          const float4 c4 = *reinterpret_cast<const float4*>(rb.cre + j);
+          ev[0] = c4.x; ev[1] = c4.y; ev[2] = c4.z; ev[3] = c4.w;
+        } else {
+          ev[0] = ev[1] = ev[2] = ev[3] = 0.f;
+        }
       } else {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -824,6 +867,7 @@ k_rescore_overflow(const float* __restrict__ xp, int H, int W, int P, int Cp, in
           dv[e] = ok ? drow[j + e] : 0.f;
           mv[e] = ok ? rb.cm[2 * (size_t)(j + e)] : 0.f;
           pv[e] = ok ? rb.cm[2 * (size_t)(j + e) + 1] : 0.f;
+          ev[e] = (ok && !rb.pc) ? rb.cre[j + e] : 0.f;
         }
       }
       float Uv[4], Lv[4];
@@ -831,8 +875,8 @@ k_rescore_overflow(const float* __restrict__ xp, int H, int W, int P, int Cp, in
       int nkeep = 0;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const float eps = margin_eps(dv[e], pv[e], mv[e], kr, kmu, rb.pc, rb.coef, rb.coef2,
-                                     rb.cz);
+        const float eps = margin_eps(dv[e], pv[e], mv[e], ev[e], kr, kmu, ek, rb.pc, rb.coef,
+                                     rb.coef2, rb.cz);
         Uv[e] = dv[e] + eps;
         Lv[e] = dv[e] - eps;
         keep[e] = j + e < Ncand && Lv[e] <= Tp;
@@ -952,10 +996,10 @@ full_row:
 // so that the float values are not below the bound.
 static void margin_coefs(const glr_plan* pl, int bf16, float* coef, float* coef2, float* cz) {
   const double u = 5.9604644775390625e-08;      // 2^-24
-  const double b = 0.00390625;                  // 2^-8, BF16 unit round-off
+  const double b = 0.00390625;                  // 2^-8: slack of the BF16 residual term
   *coef = 0.f;
   if (bf16) {
-    *coef = std::nextafter((float)(4.0 * (2.0 * b + b * b)), 1.f);
+    *coef = std::nextafter((float)(2.0 * (1.0 + b)), 1e9f);
     *coef2 = std::nextafter((float)((3.0 * pl->D + 26.0) * u), 1.f);
     *cz = std::nextafter((float)std::sqrt((double)pl->D), 1e9f);
   } else {
@@ -965,26 +1009,29 @@ static void margin_coefs(const glr_plan* pl, int bf16, float* coef, float* coef2
 }
 
 void launch_topk_partial(const glr_plan* pl, const float* dist, const float* kmb,
-                         const int32_t* kmap, int g0, const float* cm2, int nk, int bf16,
-                         uint32_t* tsh, int32_t* lj, float* lu, float* ll, int32_t* lcnt,
-                         hipStream_t s) {
+                         const float* kre, const int32_t* kmap, int g0, const float* cm2,
+                         const float* cre, int nk, int bf16, uint32_t* tsh, int32_t* lj,
+                         float* lu, float* ll, int32_t* lcnt, hipStream_t s) {
   float coef, coef2, cz;
   margin_coefs(pl, bf16, &coef, &coef2, &cz);
   // tsh[0..nk) holds +inf here: set by the key gather at the start of every
   // match call and restored by the rescoring kernel after every scan
   // the FP32 form's margin sets stay far below the BF16 form's: a smaller
-  // wave buffer and 768-candidate steps (fewer registers) fit four waves per
-  // SIMD instead of three
+  // wave buffer (28 KB of LDS per block) and no residual norms to prefetch
+  // fit four waves per SIMD; the BF16 form's 1024-entry buffers (53 KB) fit
+  // three, and its 768-candidate steps (12 bytes of bound terms per
+  // candidate, all prefetched one step ahead) keep the registers within them
   const dim3 grid((nk + 3) / 4 * pl->n_split);
   if (bf16)
-    hipLaunchKernelGGL((k_topk_partial<4, CAP>), grid, dim3(256), 0, s, dist, (size_t)pl->ldd,
-                       (const float4*)kmb, kmap, g0, cm2, pl->Ncand, pl->split_len, pl->n_split,
-                       nk, pl->K, 0, coef, coef2, cz, tsh, lj, lu, ll, lcnt);
+    hipLaunchKernelGGL((k_topk_partial<3, CAP, 3, true>), grid, dim3(256), 0, s, dist,
+                       (size_t)pl->ldd, (const float4*)kmb, kre, kmap, g0, cm2, cre, pl->Ncand,
+                       pl->split_len, pl->n_split, nk, pl->K, 0, coef, coef2, cz, tsh, lj, lu, ll,
+                       lcnt);
   else
-    hipLaunchKernelGGL((k_topk_partial<3, 512>), grid,
-                       dim3(256), 0, s, dist, (size_t)pl->ldd, (const float4*)kmb, kmap, g0, cm2,
-                       pl->Ncand, pl->split_len, pl->n_split, nk, pl->K, 1, coef, coef2, cz, tsh,
-                       lj, lu, ll, lcnt);
+    hipLaunchKernelGGL((k_topk_partial<3, 512, 4, false>), grid,
+                       dim3(256), 0, s, dist, (size_t)pl->ldd, (const float4*)kmb, kre, kmap, g0,
+                       cm2, cre, pl->Ncand, pl->split_len, pl->n_split, nk, pl->K, 1, coef, coef2,
+                       cz, tsh, lj, lu, ll, lcnt);
 }
 
 // Lanes per candidate of the exact rescoring: the fewest (>= 8) that keep
@@ -1015,12 +1062,15 @@ void launch_select_rescore(const glr_plan* pl, const float* xp, const float* A,
                            const float* lu, const float* ll, const int32_t* lcnt, int32_t* idx,
                            float* dd, int32_t* oflag, uint32_t* tsh, int defer,
                            const BigMargin& bm, const float* dist, const float* kmb,
-                           const float* cm2, int bf16, float* tkey, DevStats* st, hipStream_t s) {
+                           const float* kre, const float* cm2, const float* cre, int bf16,
+                           float* tkey, DevStats* st, hipStream_t s) {
   RowBound rb;
   rb.dist = dist;
   rb.ldd = (size_t)pl->ldd;
   rb.km = kmb;
+  rb.kre = kre;
   rb.cm = cm2;
+  rb.cre = cre;
   rb.pc = bf16 ? 0 : 1;
   margin_coefs(pl, bf16, &rb.coef, &rb.coef2, &rb.cz);
   rb.tkey = tkey;

@@ -30,6 +30,7 @@ BF16_CASES = [
     (1, 40, 40, 16, 20, 8, "smooth"),
     (4, 24, 24, 4, 30, 11, "dup"),
     (24, 48, 160, 8, 150, 64, "smooth"),
+    (40, 36, 44, 4, 30, 16, "smooth"),
 ]
 
 

@@ -35,6 +35,9 @@ MATCH_CASES = [
     (2, 40, 60, 9, 40, 10, "smooth"),
     (1, 40, 40, 11, 30, 8, "uniform"),
     (1, 45, 140, 7, 70, 12, "smooth"),
+    # more than 32 channels: the epilogue's channel-mean term in two passes
+    (40, 36, 44, 4, 30, 16, "smooth"),
+    (40, 30, 30, 3, 25, 9, "uniform"),
 ]
 
 
@@ -148,7 +151,9 @@ def test_detect_keys_complex_vs_oracle():
 
 @pytest.mark.parametrize("shape", [(8, 40, 40, 6, 60, 32), (2, 30, 33, 5, 40, 45),
                                    (16, 32, 32, 6, 20, 64), (1, 20, 20, 3, 10, 1),
-                                   (1, 24, 24, 3, 12, 16)])
+                                   (1, 24, 24, 3, 12, 16),
+                                   # the 1024^2 x 24 CACTI group shape: D = 1536, K = 64
+                                   (24, 64, 64, 8, 40, 64)])
 def test_lowrank_aggregate_vs_oracle(shape):
     require_gpu()
     C, H, W, P, N, K = shape
@@ -260,6 +265,39 @@ def test_prior_step_deterministic():
     a = host(plan.prior_step(gpu(x), 0.04))
     b = host(plan.prior_step(gpu(x), 0.04))
     np.testing.assert_array_equal(a, b)
+
+
+def test_msfa_512_full_size_prior_step_vs_oracle():
+    # the 512 x 512 x 16-band MSFA workload at its real size (4096 keys over
+    # 507^2 candidates, FP32 matcher), first GAP iterate: keys bit-exact,
+    # every group equal to the oracle's exact top-K except rows whose
+    # differing members tie within 1e-9 of the row's distances (the GPU's
+    # compensated FP32 sums and the oracle's FP64 sums order such near-ties
+    # by their own roundings; check_groups verifies those rows' distance
+    # profiles), the whole prior step within rel-L2 1e-5 of the oracle's
+    require_gpu()
+    from oracle import operators as ops
+    wl = synth.WORKLOADS["msfa_512"]
+    inst = synth.make_instance(wl)
+    y = ops.msfa_forward(inst["x_true"].astype(np.float64))
+    x0 = ops.msfa_init(y, wl.C)
+    xb = ops.gap_update(x0, y, ops.msfa_forward, lambda r: ops.msfa_adjoint(r, wl.C),
+                        np.ones_like(y)).astype(np.float32)
+    sigma = float(synth.sigma_schedule(wl)[0])
+    plan = glr.Plan("msfa", wl.H, wl.W, wl.C, wl.patch, wl.n_keys, wl.k)
+    xg = gpu(xb)
+    keys = host(plan.detect_keys(xg))
+    idx = host(plan.match_topk(xg, gpu(keys))[0])
+    out = host(plan.prior_step(xg, sigma))
+    print("oracle prior step of msfa_512 ...", flush=True)
+    ref = opr.prior_step(xb.astype(np.float64), wl.patch, wl.n_keys, wl.k, sigma, WNNM_C, WNNM_EPS)
+    np.testing.assert_array_equal(keys, ref["keys"])
+    ties = check_groups(xb.astype(np.float64), wl.patch, keys, idx, ref["idx"])
+    err = metrics.rel_l2(out, ref["x_out"])
+    print(f"msfa_512: {ties} numerical-tie rows of {wl.n_keys}, prior step rel-L2 {err:.3e}",
+          flush=True)
+    assert ties <= wl.n_keys // 100, ties
+    assert err <= 1e-5, err
 
 
 def test_msfa_512_full_size_sampled_keys():
