@@ -248,6 +248,16 @@ GLR_API glr_status glr_state_bytes(const glr_plan* plan, size_t* bytes);
 GLR_API glr_status glr_reconstruct(glr_plan* plan, const void* y, void* state, int32_t t_begin,
                            int32_t t_end, void* x_out, void* ws, void* stream);
 
+/* The pre-prior iterate of the next iteration, from a loop state (as left by
+ * glr_reconstruct, or initialised by it with t_begin = t_end = 0): the image
+ * the prior step of that iteration receives.  CACTI/MSFA: the GAP data step
+ * x + Phi^T((y - Phi x) / R~) of the state's iterate; MRI: v = x + u with
+ * x = F^H((M y + rho F(z - u)) / (M + rho)) from the state's z and u.
+ * v_out in the image layout, not aliasing the state; the state is not
+ * changed. */
+GLR_API glr_status glr_pre_prior(glr_plan* plan, const void* y, const void* state, void* v_out,
+                                 void* ws, void* stream);
+
 /* Synchronise the plan's last stream and copy the counters; reset != 0 zeroes
  * them afterwards. */
 GLR_API glr_status glr_read_stats(glr_plan* plan, glr_stats* host_out, int32_t reset);

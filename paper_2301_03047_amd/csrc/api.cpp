@@ -226,7 +226,8 @@ glr_status lowrank_stage(glr_plan* pl, const float* xp, const int32_t* idx, floa
     StageTimer t(pl, s, T_LOWRANK);
     int zn = 0;
     int32_t* z = agg_zero_range(pl, (int32_t*)(ws + pl->ws.pairs), &zn);
-    launch_wnnm(pl, xp, idx, sigma, xhat, sv, st, z, zn, count_step ? 1 : 0, s);
+    launch_wnnm(pl, xp, idx, sigma, xhat, sv, st, z, zn, count_step ? 1 : 0,
+                (float*)(ws + pl->ws.xi), s);
   }
   {
     StageTimer t(pl, s, T_AGG);
@@ -517,6 +518,7 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
   WsLayout& L = pl->ws;
   L.xp = c.take(HW * Cp * 4);
   L.xo = c.take(HW * Cp * 4);
+  L.xi = c.take(HW * Cp * 4);
   L.q = c.take(HW);
   L.gxx = c.take(HW * 4);
   L.gyy = c.take(HW * 4);
@@ -827,6 +829,32 @@ glr_status glr_reconstruct(glr_plan* pl, const void* y, void* state, int32_t t_b
     }
     hipMemcpyAsync(x_out, z, (size_t)HW * 8, hipMemcpyDeviceToDevice, s);
   }
+  return check_hip(__func__);
+}
+
+glr_status glr_pre_prior(glr_plan* pl, const void* y, const void* state, void* v_out, void* ws,
+                         void* stream) {
+  glr_status e = check_plan_ws(pl, ws, __func__);
+  if (e) return e;
+  REQUIRE_PTR(y);
+  REQUIRE_PTR(state);
+  REQUIRE_PTR(v_out);
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  ensure_stats(pl, w, s);
+  const int HW = pl->H * pl->W;
+  if (!pl->is_complex) {
+    if (v_out == state) return fail(GLR_ERR_INVALID_ARG, "v_out must not alias the state");
+    return data_step_impl(pl, y, state, nullptr, nullptr, v_out, w, s);
+  }
+  // ADMM: x = F^H((M y + rho F(z - u)) / (M + rho)) into the complex scratch,
+  // v = x + u in planar form (the prior's input), then interleaved into v_out
+  const float2* st = (const float2*)state;
+  float2* xs = (float2*)(w + pl->ws.cplx_b);
+  float* vp = (float*)(w + pl->ws.xp);
+  e = data_step_impl(pl, y, nullptr, st + HW, st + 2 * (size_t)HW, xs, w, s, vp);
+  if (e) return e;
+  launch_from_planar(vp, (float2*)v_out, HW, s);
   return check_hip(__func__);
 }
 

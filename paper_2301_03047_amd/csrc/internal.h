@@ -26,6 +26,7 @@ struct DevStats {
 // Byte offsets of the workspace buffers (all 256-aligned).
 struct WsLayout {
   size_t xp, xo;                 // planar copies of input / output (complex data)
+  size_t xi;                     // channel-interleaved copy [H][W][Cp] for the group loads
   size_t q, gxx, gyy, gxy, r25;  // detector
   size_t cflag, slist, sval;     // detector candidate flags / survivor list, scores
   size_t keys;                   // detected keys [N]
@@ -196,9 +197,10 @@ void launch_collect_flags(const int32_t* oflag, int g0, int nk, int32_t* klist, 
 
 // lowrank.hip
 // zbuf[0..zn) is set to zero (nullable); bump != 0 counts a prior step
+// xi: scratch [H][W][Cp] for the channel-interleaved copy of xp
 void launch_wnnm(const glr_plan* pl, const float* xp, const int32_t* idx, float sigma,
                  float* xhat, float* sv, DevStats* st, int32_t* zbuf, int zn, int bump,
-                 hipStream_t s);
+                 float* xi, hipStream_t s);
 
 // aggregate.hip
 // sortbuf: aggregation sort scratch (agg_sort_ints(pl) int32); offs [Ncand + 1];

@@ -20,6 +20,11 @@
 //  4. X = Y - Yc W, W = V diag(w) V^T: the residual sum_i (s_i - s'_i) u_i v_i^T
 //     accumulated in FP64 (sigma = 0 gives w = 0, W = 0, X = Y exactly).
 // Data and the SVD are FP32; only the angles and the residual use FP64.
+// The group rows are read from a channel-interleaved copy of the iterate,
+// xi[(r*W + c)*Cp + ch], made once per step, and taken in the output order
+// e = (dy*P + dx)*Cp + ch (the row order does not change the factorisation):
+// one member's patch row over all channels is then one contiguous run, and a
+// 64-row chunk of one member is 256 consecutive bytes.
 // Estimates are written per member patch in (dy, dx, channel) order:
 // xhat[(g*K + j)*D + (dy*P + dx)*Cp + c], staged through LDS.
 #include "common.h"
@@ -32,35 +37,35 @@ namespace {
 constexpr int LS = 65;           // LDS stride (conflict-free column/row access)
 constexpr int BR = 64;           // rows per streamed chunk
 
-__device__ __forceinline__ size_t elem_off(int d, int P, int W, size_t HW) {
-  const int PP = P * P;
-  const int ch = d / PP;
-  const int rem = d - ch * PP;
-  const int dy = rem / P, dx = rem - dy * P;
-  return (size_t)ch * HW + (size_t)dy * W + dx;
+// xi[(p)*Cp + c] = xp[c*HW + p]: the channel-interleaved copy the group
+// loads read (one thread per output element: coalesced writes; the reads of
+// a block touch Cp short runs that the next blocks reuse from L2)
+__global__ void k_interleave(const float* __restrict__ xp, int Cp, size_t HW,
+                             float* __restrict__ xi) {
+  const size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= HW * Cp) return;
+  const size_t p = o / Cp;
+  const int c = (int)(o - p * Cp);
+  xi[o] = xp[(size_t)c * HW + p];
 }
 
 __device__ __forceinline__ float bcast(float v, int lane) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
 }
 
-// Lane i < nb loads row d0+i of Y into B[i][0..K) (raw values) and its mean.
-// With Cp > 0 the rows are taken in the output order e = (dy P + dx) Cp + c
-// instead of d = (c P + dy) P + dx.
+// Lane i < nb loads row e = d0+i (output order (dy P + dx) Cp + c) of Y from
+// the interleaved copy xi into B[i][0..K) (raw values) and its mean; spos
+// holds the members' top-left pixels r W + c.
 // Row stride RS (LS by default); with kpad > K the entries K..kpad-1 of a
 // row are zeroed.
-__device__ __forceinline__ void load_rows(const float* __restrict__ xp, const int* spos, int d0,
-                                          int nb, int K, int P, int W, size_t HW, float* B,
-                                          float* smu, int Cp = 0, int RS = LS, int kpad = 0) {
+__device__ __forceinline__ void load_rows(const float* __restrict__ xi, const int* spos, int d0,
+                                          int nb, int K, int P, int W, int Cp, float* B,
+                                          float* smu, int RS = LS, int kpad = 0) {
   const int i = threadIdx.x;
   if (i < nb) {
-    size_t o;
-    if (Cp > 0) {
-      const int e = d0 + i, c = e % Cp, pix = e / Cp;
-      o = (size_t)c * HW + (size_t)(pix / P) * W + pix % P;
-    } else {
-      o = elem_off(d0 + i, P, W, HW);
-    }
+    const int e = d0 + i, pix = e / Cp, c = e - pix * Cp;
+    const int dy = pix / P;
+    const size_t o = ((size_t)dy * W + (pix - dy * P)) * Cp + c;
     // all of a row's loads in flight at once: the 64 member positions come
     // in 16-byte LDS reads (entries past K repeat the last member; their
     // values are not stored); the sum runs in member order
@@ -72,7 +77,7 @@ __device__ __forceinline__ void load_rows(const float* __restrict__ xp, const in
     }
     float v[64];
 #pragma unroll
-    for (int u = 0; u < 64; ++u) v[u] = xp[o + sp[u]];
+    for (int u = 0; u < 64; ++u) v[u] = xi[o + (size_t)sp[u] * Cp];
     float s = 0.f;
 #pragma unroll
     for (int u = 0; u < 64; ++u)
@@ -236,7 +241,7 @@ __device__ __forceinline__ void qr_chunk(float* Rl, const float* Bl, const float
 
 template <int KP>
 __global__ void __launch_bounds__(64)
-k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* __restrict__ idx,
+k_wnnm(const float* __restrict__ xi, int H, int W, int P, int D, const int32_t* __restrict__ idx,
        int K, float sigma, float wc, float weps, int max_sweeps, float* __restrict__ xhat,
        float* __restrict__ sv, DevStats* st, int32_t* __restrict__ zbuf, int zn, int bump) {
   constexpr int XS = KP + 4;       // row stride of the column-exchange buffer (16-byte rows)
@@ -253,7 +258,7 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
   const int g = blockIdx.x;
   const int lane = threadIdx.x;
   const int Wc = W - P + 1;
-  const size_t HW = (size_t)H * W;
+  const int Cp = D / (P * P);
   // side duties of the step, folded in to save launches: clear the
   // aggregation's counters (read only by the kernels after this one) and
   // count the prior step
@@ -278,7 +283,7 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
   bool fset = false;
   for (int d0 = 0; d0 < D; d0 += BR) {
     const int nb = min(BR, D - d0);
-    load_rows(xp, spos, d0, nb, K, P, W, HW, Bl, smu);
+    load_rows(xi, spos, d0, nb, K, P, W, Cp, Bl, smu);
     if (nb > 32) qr_chunk<64>(Rl, Bl, smu, Cb, nb, K, lane, fe, fset);
     else if (nb > 16) qr_chunk<32>(Rl, Bl, smu, Cb, nb, K, lane, fe, fset);
     else if (nb > 8) qr_chunk<16>(Rl, Bl, smu, Cb, nb, K, lane, fe, fset);
@@ -468,13 +473,12 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
   // of the order, so the chunks are written out as contiguous runs
   // sum_a (y_a - mu) w_a = sum_a y_a w_a - mu sum_a w_a (FP64); rows staged
   // with a 16-byte stride and zero padding so the inner loop is branch-free
-  const int Cp = D / (P * P);
   double wsum = 0.0;
 #pragma unroll
   for (int a = 0; a < KP; ++a) wsum += wcol[a];
   for (int d0 = 0; d0 < D; d0 += BR) {
     const int nb = min(BR, D - d0);
-    load_rows(xp, spos, d0, nb, K, P, W, HW, Bl, smu, Cp, XS, KP);
+    load_rows(xi, spos, d0, nb, K, P, W, Cp, Bl, smu, XS, KP);
     if (lane < K) {
       for (int i = 0; i < nb; ++i) {
         float row[KP];
@@ -502,15 +506,18 @@ k_wnnm(const float* __restrict__ xp, int H, int W, int P, int D, const int32_t* 
 
 void launch_wnnm(const glr_plan* pl, const float* xp, const int32_t* idx, float sigma,
                  float* xhat, float* sv, DevStats* st, int32_t* zbuf, int zn, int bump,
-                 hipStream_t s) {
+                 float* xi, hipStream_t s) {
   const int K = pl->K;
+  const size_t HW = (size_t)pl->H * pl->W, n = HW * pl->Cp;
+  hipLaunchKernelGGL(k_interleave, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, xp, pl->Cp,
+                     HW, xi);
   if (K <= 32)
-    hipLaunchKernelGGL(k_wnnm<32>, dim3(pl->N), dim3(64), 0, s, xp, pl->H, pl->W, pl->P, pl->D,
+    hipLaunchKernelGGL(k_wnnm<32>, dim3(pl->N), dim3(64), 0, s, xi, pl->H, pl->W, pl->P, pl->D,
                        idx, K, sigma, pl->wnnm_c, pl->wnnm_eps, 30, xhat, sv, st, zbuf, zn, bump);
   else if (K <= 48)
-    hipLaunchKernelGGL(k_wnnm<48>, dim3(pl->N), dim3(64), 0, s, xp, pl->H, pl->W, pl->P, pl->D,
+    hipLaunchKernelGGL(k_wnnm<48>, dim3(pl->N), dim3(64), 0, s, xi, pl->H, pl->W, pl->P, pl->D,
                        idx, K, sigma, pl->wnnm_c, pl->wnnm_eps, 30, xhat, sv, st, zbuf, zn, bump);
   else
-    hipLaunchKernelGGL(k_wnnm<64>, dim3(pl->N), dim3(64), 0, s, xp, pl->H, pl->W, pl->P, pl->D,
+    hipLaunchKernelGGL(k_wnnm<64>, dim3(pl->N), dim3(64), 0, s, xi, pl->H, pl->W, pl->P, pl->D,
                        idx, K, sigma, pl->wnnm_c, pl->wnnm_eps, 30, xhat, sv, st, zbuf, zn, bump);
 }

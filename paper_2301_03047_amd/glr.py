@@ -102,6 +102,7 @@ def lib():
         "glr_prior_step_static": (st, [_vp, _vp, ctypes.c_float, _vp, _vp]),
         "glr_state_bytes": (st, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
         "glr_reconstruct": (st, [_vp, _vp, _vp, _c_i32, _c_i32, _vp, _vp, _vp]),
+        "glr_pre_prior": (st, [_vp, _vp, _vp, _vp, _vp, _vp]),
         "glr_read_stats": (st, [_vp, ctypes.POINTER(Stats), _c_i32]),
         "glr_cnn_param_count": (_c_i32, []),
         "glr_cnn_packed_bytes": (ctypes.c_size_t, []),
@@ -318,6 +319,14 @@ class Plan:
         _check(lib().glr_reconstruct(self._h, _ptr(y), _ptr(state), int(t_begin), int(t_end),
                                      _ptr(out), _ptr(self.ws), self._stream()))
         return out, state
+
+    def pre_prior(self, y, state, out=None):
+        """The image the next iteration's prior step receives, from ``state``."""
+        self._meas(y)
+        out = self._empty_image() if out is None else out
+        _check(lib().glr_pre_prior(self._h, _ptr(y), _ptr(state), _ptr(out), _ptr(self.ws),
+                                   self._stream()))
+        return out
 
     def read_stats(self, reset=False):
         s = Stats()

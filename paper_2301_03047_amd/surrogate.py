@@ -20,22 +20,17 @@ def glr_pairs(plan: Plan, y, iters=None):
     T = plan.iters if iters is None else iters
     H, W = plan.H, plan.W
     state = plan.new_state()
+    plan.reconstruct(y, 0, 0, state=state)              # initial estimate only
     out = []
     for t in range(T):
+        pre = plan.pre_prior(y, state)                  # what iteration t's prior receives
+        plan.reconstruct(y, t, t + 1, state=state)
         if plan.modality == MRI:
-            plan.reconstruct(y, t, t + 1, state=state)
-            st = state[: 3 * H * W * 8].view(torch.complex64)
-            z, u = st[H * W:2 * H * W].view(H, W), st[2 * H * W:].view(H, W)
-            v = u + z                               # pre-prior iterate x_t + u_{t-1}
-            pre = torch.stack([v.real, v.imag]).contiguous()
+            z = state[: 3 * H * W * 8].view(torch.complex64)[H * W:2 * H * W].view(H, W)
+            pre = torch.stack([pre.real, pre.imag]).contiguous()
             post = torch.stack([z.real, z.imag]).contiguous()
         else:
-            x_t = state[: plan.C * H * W * 4].view(torch.float32).view(plan.C, H, W)
-            if t == 0:
-                plan.reconstruct(y, 0, 0, state=state)   # initial estimate only
-            pre = plan.data_step(y, x=x_t.contiguous()).clone()
-            plan.reconstruct(y, t, t + 1, state=state)
-            post = x_t.clone()
+            post = state[: plan.C * H * W * 4].view(torch.float32).view(plan.C, H, W).clone()
         out.append((pre, post, float(plan._sigma[t])))
     return out
 

@@ -47,6 +47,42 @@ def test_mri_forward_adjoint_data_step():
     assert metrics.rel_l2(xn, ref) <= 2e-6
 
 
+def test_pre_prior_iterate():
+    # the image the next prior step receives, from a loop state: the ADMM
+    # x-update plus u (MRI), the GAP data step (CACTI); against the oracle's
+    # operators on the state's own values
+    require_gpu()
+    wl = small(synth.WORKLOADS["mri_256"], H=64, W=64, n_keys=64, k=16, iters=3)
+    inst = synth.make_instance(synth.WORKLOADS["mri_256"])
+    x = inst["x_true"][96:160, 96:160].copy()
+    m = synth.mri_line_mask(64, 5)
+    sig = synth.sigma_schedule(wl)
+    plan = glr.Plan("mri", wl.H, wl.W, 1, wl.patch, wl.n_keys, wl.k, iters=wl.iters, sigma=sig,
+                    mask=gpu(m))
+    y = plan.forward(gpu(x.astype(np.complex64)))
+    state = plan.new_state()
+    plan.reconstruct(y, 0, 2, state=state)
+    v = host(plan.pre_prior(y, state))
+    st = host(state)[: 3 * 64 * 64 * 8].view(np.complex64)
+    z, u = st[4096:8192].reshape(64, 64), st[8192:].reshape(64, 64)
+    xr = ops.admm_x_update(host(y).astype(np.complex128), z.astype(np.complex128),
+                           u.astype(np.complex128), m, 1.0)
+    assert metrics.rel_l2(v, xr + u) <= 2e-6
+    F, H, W = 8, 48, 40
+    mc = synth.cacti_masks(F, H, W, 2)
+    xc = synth.workloads.random_image(F, H, W, seed=3)
+    pc = glr.Plan("cacti", H, W, F, 4, 8, 4, iters=2, sigma=np.full(2, 0.05, np.float32),
+                  mask=gpu(mc))
+    yc = pc.forward(gpu(xc))
+    sc = pc.new_state()
+    pc.reconstruct(yc, 0, 1, state=sc)
+    vc = host(pc.pre_prior(yc, sc))
+    x1 = host(sc)[: F * H * W * 4].view(np.float32).reshape(F, H, W).astype(np.float64)
+    ref = ops.gap_update(x1, host(yc).astype(np.float64), lambda q: ops.cacti_forward(q, mc),
+                         lambda r: ops.cacti_adjoint(r, mc), ops.cacti_mask_sum(mc))
+    assert np.abs(vc - ref).max() <= 1e-5
+
+
 def test_gap_steps():
     require_gpu()
     F, H, W = 8, 48, 40
