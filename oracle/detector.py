@@ -147,3 +147,34 @@ def detect_keys(x, patch, n_keys, is_complex=False):
             if need == 0:
                 break
     return np.nonzero(chosen)[0].astype(np.int64)
+
+
+def uniform_keys(Hc, Wc, step):
+    """Exemplars of classic block matching: a uniform grid of top-left
+    positions (r, c) = (step a, step b) with r < Hc, c < Wc (the paper's
+    "traditional uniform selection", Method section), ascending index
+    r*Wc + c."""
+    rr = np.arange(0, Hc, step, dtype=np.int64)
+    cc = np.arange(0, Wc, step, dtype=np.int64)
+    return (rr[:, None] * Wc + cc[None, :]).reshape(-1)
+
+
+def exemplar_keys(x, patch, n_keys, mode, step, is_complex=False):
+    """Exemplar keys for one prior step.
+
+    mode "corner": the N corner keys of ``detect_keys``; "uniform": the
+    uniform grid of ``step``; "corner_uniform": the corner keys followed by a
+    uniform grid whose interval is three times ``step`` (the corner-based
+    block matching of the CACTI experiment, Results section, which adds a
+    modest number of uniformly selected exemplars at three times the vanilla
+    interval).  A grid position that is also a corner is kept twice."""
+    _, H, W = np.asarray(x).shape
+    Hc, Wc = H - patch + 1, W - patch + 1
+    if mode == "corner":
+        return detect_keys(x, patch, n_keys, is_complex=is_complex)
+    if mode == "uniform":
+        return uniform_keys(Hc, Wc, step)
+    if mode == "corner_uniform":
+        return np.concatenate([detect_keys(x, patch, n_keys, is_complex=is_complex),
+                               uniform_keys(Hc, Wc, 3 * step)])
+    raise ValueError(mode)

@@ -126,3 +126,33 @@ def topk_bruteforce(x, patch, keys, K):
         idx[a] = order
         dist[a] = d[order]
     return idx, dist
+
+
+def window_topk(x, patch, keys, K, radius):
+    """Block matching in a local window (eq. 1 with KNN grouping, the
+    vanilla BM the paper compares against): for the key at (r_g, c_g) the
+    candidates are the positions (r, c) of the top-left grid with
+    |r - r_g| <= radius and |c - c_g| <= radius; the group is their first K
+    by (d, j) ascending, d the direct squared distance (FP64).  Returns
+    ``idx`` int64 ``[N][K]`` and ``dist`` ``[N][K]``."""
+    x = np.asarray(x, dtype=np.float64)
+    C, H, W = x.shape
+    P = patch
+    Hc, Wc = H - P + 1, W - P + 1
+    pm = patch_matrix(x, P)
+    keys = np.asarray(keys, dtype=np.int64)
+    idx = np.empty((keys.shape[0], K), dtype=np.int64)
+    dist = np.empty((keys.shape[0], K))
+    for a, g in enumerate(keys):
+        rg, cg = divmod(int(g), Wc)
+        rr = np.arange(max(rg - radius, 0), min(rg + radius, Hc - 1) + 1)
+        cc = np.arange(max(cg - radius, 0), min(cg + radius, Wc - 1) + 1)
+        cand = (rr[:, None] * Wc + cc[None, :]).reshape(-1)
+        if cand.size < K:
+            raise ValueError("window holds fewer than K candidates")
+        diff = pm[cand] - pm[g][None, :]
+        d = np.sum(diff * diff, axis=1)
+        order = np.lexsort((cand, d))[:K]
+        idx[a] = cand[order]
+        dist[a] = d[order]
+    return idx, dist

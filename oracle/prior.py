@@ -3,20 +3,29 @@ shrink each group by WNNM, aggregate (Method section, eq. 1, eq. 8 sizes,
 the low-rank objective and WNNM)."""
 import numpy as np
 
-from .detector import detect_keys
-from .matching import topk_exact
+from .detector import exemplar_keys
+from .matching import topk_exact, window_topk
 from .lowrank import shrink_groups
 from .aggregate import aggregate
 
 
-def prior_step(x, patch, n_keys, K, sigma, c, eps, is_complex=False, keys=None):
+def prior_step(x, patch, n_keys, K, sigma, c, eps, is_complex=False, keys=None,
+               exemplars="corner", step=4, search="global", radius=20):
     """Apply the prior to iterate ``x`` (planar real ``[C'][H][W]``; complex
     data as ``[2][H][W]`` = (Re, Im)).  ``keys`` may be supplied to bypass the
-    detector.  Returns a dict with keys, idx, dist, Xhat, sv, x_out."""
+    detector.  ``exemplars`` ("corner", "uniform", "corner_uniform", with the
+    uniform interval ``step``) and ``search`` ("global", or "window" of half
+    width ``radius``: the block-matching baselines) select the variant.
+    Returns a dict with keys, idx, dist, Xhat, sv, x_out."""
     x = np.asarray(x, dtype=np.float64)
     if keys is None:
-        keys = detect_keys(x, patch, n_keys, is_complex=is_complex)
-    idx, dist = topk_exact(x, patch, keys, K)
+        keys = exemplar_keys(x, patch, n_keys, exemplars, step, is_complex=is_complex)
+    if search == "global":
+        idx, dist = topk_exact(x, patch, keys, K)
+    elif search == "window":
+        idx, dist = window_topk(x, patch, keys, K, radius)
+    else:
+        raise ValueError(search)
     Xhat, sv = shrink_groups(x, patch, idx, sigma, c, eps)
     x_out, cnt = aggregate(x, patch, idx, Xhat)
     return {"keys": keys, "idx": idx, "dist": dist, "Xhat": Xhat, "sv": sv,

@@ -17,7 +17,11 @@ from .prior import prior_step, to_planar, from_planar
 
 def _prior(xp, wl, sigma, is_complex):
     return prior_step(xp, wl.patch, wl.n_keys, wl.k, float(sigma), wl.wnnm_c,
-                      wl.wnnm_eps, is_complex=is_complex)["x_out"]
+                      wl.wnnm_eps, is_complex=is_complex,
+                      exemplars=getattr(wl, "exemplars", "corner"),
+                      step=getattr(wl, "uniform_step", 4),
+                      search=getattr(wl, "search", "global"),
+                      radius=getattr(wl, "window", 20))["x_out"]
 
 
 def reconstruct(wl, y, mask, sigmas, iters=None, callback=None):

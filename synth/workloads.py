@@ -31,6 +31,14 @@ class Workload:
     rho: float = 1.0       # ADMM penalty (mri)
     precision: str = "fp32"
     seed: int = 0          # scene seed; the mask seed is seed + 1
+    # exemplar selection ("corner", "uniform", "corner_uniform"; uniform grid
+    # interval, three times it for corner_uniform) and search region
+    # ("global", or a local "window" of half width `window`)
+    exemplars: str = "corner"
+    uniform_step: int = 4
+    search: str = "global"
+    window: int = 20
+    gap_acc: bool = False  # accelerated GAP (measurement residual accumulated)
 
     @property
     def real_channels(self):
@@ -43,6 +51,19 @@ class Workload:
     @property
     def dim(self):
         return self.real_channels * self.patch * self.patch
+
+    @property
+    def keys_total(self):
+        """Exemplars per prior step: n_keys corners, the uniform grid, or both."""
+        Hc, Wc = self.H - self.patch + 1, self.W - self.patch + 1
+
+        def grid(s):
+            return (-(-Hc // s)) * (-(-Wc // s))
+        if self.exemplars == "uniform":
+            return grid(self.uniform_step)
+        if self.exemplars == "corner_uniform":
+            return self.n_keys + grid(3 * self.uniform_step)
+        return self.n_keys
 
 
 # Noise schedules: the first level is of the order of the initial estimate's
@@ -58,6 +79,20 @@ WORKLOADS = {
                           seed=4200),
     "cacti_1024": Workload("cacti_1024", "cacti", 1024, 1024, 24, 8, 16384, 64, 50, 1.0, 0.05,
                            precision="bf16", seed=3000),
+    # the paper's CACTI shape (8 frames of 256 x 256) for the matching
+    # ablation: global matching from corner exemplars against block matching
+    # in a 41 x 41 window from a uniform grid (interval 4), from corners, and
+    # from corners plus a grid of three times the interval
+    "cacti_256": Workload("cacti_256", "cacti", 256, 256, 8, 6, 512, 32, 20, 1.0, 0.05,
+                          seed=5000),
+}
+
+
+ABLATION = {
+    "gm_corner": dict(exemplars="corner", search="global"),
+    "bm_uniform": dict(exemplars="uniform", search="window"),
+    "bm_corner": dict(exemplars="corner", search="window"),
+    "bm_corner_uniform": dict(exemplars="corner_uniform", search="window"),
 }
 
 

@@ -186,3 +186,23 @@ def test_quantise_complex_by_hand():
     re3 = np.array([[3, 1, 0]], dtype=f32)          # m = 9, 1, 0
     im3 = np.zeros_like(re3)
     assert det.quantise_complex(re3, im3).tolist() == [[255, 28, 0]]
+
+
+def test_uniform_exemplar_grid():
+    from oracle import detector as dt
+    # rows {0, 3}, columns {0, 3, 6} of a 5 x 7 grid
+    np.testing.assert_array_equal(dt.uniform_keys(5, 7, 3), [0, 3, 6, 21, 24, 27])
+    np.testing.assert_array_equal(dt.uniform_keys(4, 4, 1), np.arange(16))
+    assert dt.uniform_keys(10, 10, 20).tolist() == [0]
+
+
+def test_corner_uniform_exemplars_concatenate_the_coarse_grid():
+    from oracle import detector as dt
+    x = synth.workloads.random_image(2, 30, 34, seed=3)
+    P, N, s = 5, 12, 2
+    k = dt.exemplar_keys(x, P, N, "corner_uniform", s)
+    corners = dt.detect_keys(x, P, N)
+    grid = dt.uniform_keys(30 - P + 1, 34 - P + 1, 3 * s)
+    np.testing.assert_array_equal(k, np.concatenate([corners, grid]))
+    np.testing.assert_array_equal(dt.exemplar_keys(x, P, N, "uniform", s),
+                                  dt.uniform_keys(26, 30, s))

@@ -114,3 +114,60 @@ def test_single_key_distance_map_equals_exact_rational_bruteforce(kind):
         np.testing.assert_allclose(full, mt.direct_distances(x, P, g, np.arange(full.size)),
                                    rtol=1e-13, atol=1e-300)
         assert nxt >= dist[-1]
+
+
+def _bf_window_exact(x, P, keys, K, radius):
+    """Pure-Python exact arithmetic over the key's window only."""
+    C, H, W = x.shape
+    Hc, Wc = H - P + 1, W - P + 1
+    xf = [[[Fraction(float(x[c, r, q])) for q in range(W)] for r in range(H)] for c in range(C)]
+    out = []
+    for g in keys:
+        gr, gc = divmod(int(g), Wc)
+        ds = []
+        for jr in range(Hc):
+            for jc in range(Wc):
+                if abs(jr - gr) > radius or abs(jc - gc) > radius:
+                    continue
+                d = Fraction(0)
+                for c in range(C):
+                    for dy in range(P):
+                        for dx in range(P):
+                            e = xf[c][gr + dy][gc + dx] - xf[c][jr + dy][jc + dx]
+                            d += e * e
+                ds.append((d, jr * Wc + jc))
+        ds.sort()
+        out.append([j for _, j in ds[:K]])
+    return out
+
+
+@pytest.mark.parametrize("kind", ["uniform", "dup"])
+def test_window_topk_equals_exact_rational_bruteforce(kind):
+    x = synth.workloads.random_image(2, 14, 13, seed=6, kind=kind)
+    P, K, R = 3, 6, 3
+    Wc = 13 - P + 1
+    keys = [0, 5, 3 * Wc + 4, 11 * Wc + 10, 7 * Wc]
+    idx, dist = mt.window_topk(x.astype(np.float64), P, keys, K, R)
+    assert idx.tolist() == _bf_window_exact(x, P, keys, K, R)
+    # members lie in the key's window
+    for a, g in enumerate(keys):
+        gr, gc = divmod(g, Wc)
+        rr, cc = np.divmod(idx[a], Wc)
+        assert np.all(np.abs(rr - gr) <= R) and np.all(np.abs(cc - gc) <= R)
+        assert np.all(np.diff(dist[a]) >= 0)
+
+
+def test_window_covering_the_grid_is_global_matching():
+    x = synth.workloads.random_image(3, 16, 18, seed=7, kind="smooth")
+    P, K = 4, 9
+    keys = np.array([0, 40, 77, 160, 194])
+    a, da = mt.window_topk(x.astype(np.float64), P, keys, K, radius=20)
+    b, db = mt.topk_bruteforce(x.astype(np.float64), P, keys, K)
+    np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(da, db)
+
+
+def test_window_too_small_for_k_is_refused():
+    x = synth.workloads.random_image(1, 10, 10, seed=8)
+    with pytest.raises(ValueError):
+        mt.window_topk(x.astype(np.float64), 3, [0], 10, radius=2)   # 3 x 3 corner window
