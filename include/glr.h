@@ -63,6 +63,13 @@ enum {
 enum { GLR_CACTI = 0, GLR_MRI = 1, GLR_MSFA = 2 };   /* eq. 2, eq. 3, eq. 4-5 */
 enum { GLR_SOLVER_GAP = 0, GLR_SOLVER_ADMM = 1 };
 enum { GLR_PREC_FP32 = 0, GLR_PREC_BF16_RESCORE = 1 };
+/* Exemplar selection (Method section: corners of the edge map instead of the
+ * traditional uniform grid; Results, CACTI: corners plus a modest uniform
+ * grid at three times the vanilla interval). */
+enum { GLR_EXEMPLAR_CORNER = 0, GLR_EXEMPLAR_UNIFORM = 1, GLR_EXEMPLAR_CORNER_UNIFORM = 2 };
+/* Search region: global matching over the whole candidate grid (eq. 8), or
+ * block matching in a local window around each key (eq. 1, vanilla BM). */
+enum { GLR_SEARCH_GLOBAL = 0, GLR_SEARCH_WINDOW = 1 };
 
 /* Sensing problem (eq. 2-5). */
 typedef struct glr_problem {
@@ -111,6 +118,18 @@ typedef struct glr_params {
   int32_t judge_stride;  /* default 8                                            */
   float judge_delta_max; /* default 0.02                                         */
   const void* cnn_packed; /* device, glr_cnn_packed_bytes(), from glr_cnn_pack()  */
+  /* Block-matching baselines (the paper's comparison).  exemplars: CORNER
+   * takes the n_keys corner keys; UNIFORM the grid of top-left positions
+   * (s a, s b), s = uniform_step (n_keys is then ignored); CORNER_UNIFORM the
+   * n_keys corners followed by the grid of interval 3 s.  The plan's key
+   * count N is reported by glr_plan_keys() (at most 16384).  search: GLOBAL
+   * (every candidate) or WINDOW (candidates within `window` rows and columns
+   * of the key; (window + 1)^2 >= K required).  The groups are exact either
+   * way: the window's distances are all computed with compensated sums. */
+  int32_t exemplars;      /* default GLR_EXEMPLAR_CORNER                         */
+  int32_t uniform_step;   /* default 4                                           */
+  int32_t search;         /* default GLR_SEARCH_GLOBAL                           */
+  int32_t window;         /* default 20 (a 41 x 41 window)                        */
 } glr_params;
 
 /* Counters of the last prior steps, read by glr_read_stats(). */
@@ -162,6 +181,9 @@ GLR_API glr_status glr_plan_create(glr_plan** out, const glr_problem* problem,
                            const glr_params* params, size_t* workspace_bytes);
 GLR_API glr_status glr_plan_destroy(glr_plan* plan);
 GLR_API glr_status glr_workspace_size(const glr_plan* plan, size_t* bytes);
+/* Exemplar keys per prior step (the length of keys, idx and dist): n_keys
+ * for CORNER, the uniform grid's size for UNIFORM, both for CORNER_UNIFORM. */
+GLR_API glr_status glr_plan_keys(const glr_plan* plan, int32_t* n_keys);
 
 /* --------------------------------------------------------------- operators
  * y = Phi x (eq. 2, eq. 3, eq. 4).  x in the image layout; y: CACTI/MSFA
@@ -185,7 +207,9 @@ GLR_API glr_status glr_data_step(glr_plan* plan, const void* y, const void* x, c
  * Key detection (corner exemplars, Method section / Fig. 1a): keys[N] int32,
  * ascending top-left positions.  Reading: integer Harris on a u8 detection
  * image, 3x3 non-maximum suppression, best N by score, uniform raster fill
- * when fewer corners exist. */
+ * when fewer corners exist.  With params.exemplars UNIFORM the keys are the
+ * uniform grid; with CORNER_UNIFORM the n_keys corners followed by the grid
+ * of three times the interval (N = glr_plan_keys()). */
 GLR_API glr_status glr_detect_keys(glr_plan* plan, const void* x, int32_t* keys, void* ws,
                            void* stream);
 /* Global matching and grouping (eq. 1 made global; eq. 8 candidate grid):
@@ -194,7 +218,9 @@ GLR_API glr_status glr_detect_keys(glr_plan* plan, const void* x, int32_t* keys,
  * dist[g][q] those distances (float32).  keys: device int32 [N] (any order,
  * each < N_cand).  The distance contraction runs on MFMA; candidates within a
  * certified error margin of the K-th distance are rescored with compensated
- * (double-float32) arithmetic so that the selection equals the exact one. */
+ * (double-float32) arithmetic so that the selection equals the exact one.
+ * With params.search WINDOW the candidates are those of the key's window
+ * (block matching), all scored with compensated arithmetic. */
 GLR_API glr_status glr_match_topk(glr_plan* plan, const void* x, const int32_t* keys,
                           int32_t* idx, float* dist, void* ws, void* stream);
 /* Low-rank step and aggregation (WNNM on each group, the low-rank objective

@@ -111,6 +111,16 @@ enum { T_DETECT = 0, T_MATCH, T_TOPK, T_SELECT, T_LOWRANK, T_AGG, T_DATA, T_NORM
 static_assert(T_COUNT <= GLR_STAGE_SLOTS, "stage timer slots");
 
 // ---------------------------------------------------------------- prior step
+// The N exemplar keys of one prior step (corner detection, the uniform grid,
+// or corners followed by the grid of three times the interval).
+void launch_exemplars(const glr_plan* pl, const float* xp, char* ws, int32_t* keys,
+                      hipStream_t s) {
+  if (pl->exemplars != GLR_EXEMPLAR_UNIFORM) launch_detect(pl, xp, ws, keys, pl->n_corner, s);
+  if (pl->exemplars == GLR_EXEMPLAR_UNIFORM) launch_uniform_keys(pl, keys, pl->uniform_step, s);
+  if (pl->exemplars == GLR_EXEMPLAR_CORNER_UNIFORM)
+    launch_uniform_keys(pl, keys + pl->n_corner, 3 * pl->uniform_step, s);
+}
+
 // xp: planar [Cp][H][W]; xo: planar output; keys_in: optional caller keys.
 // idx_out/dd_out: where groups go (may be the workspace buffers).
 glr_status match_stage(glr_plan* pl, const float* xp, const int32_t* keys, int32_t* idx_out,
@@ -142,6 +152,15 @@ glr_status match_stage(glr_plan* pl, const float* xp, const int32_t* keys, int32
   const bool bf = pl->precision == GLR_PREC_BF16_RESCORE;
   const BigMargin bm = {(int32_t*)(ws + pl->ws.bpos), (float*)(ws + pl->ws.bhi),
                         (float*)(ws + pl->ws.blo), pl->mcap};
+  if (pl->search == GLR_SEARCH_WINDOW) {
+    {
+      StageTimer t(pl, s, T_NORMS);
+      launch_gather_keys(pl, xp, keys, A, tsh, s);
+    }
+    StageTimer t(pl, s, T_MATCH);
+    launch_window_topk(pl, xp, A, keys, idx_out, dd_out, s);
+    return check_hip("glr_match_topk");
+  }
   {
     StageTimer t(pl, s, T_NORMS);
     launch_gather_keys(pl, xp, keys, A, tsh, s);
@@ -244,7 +263,7 @@ glr_status prior_planar(glr_plan* pl, const float* xp, float sigma, float* xo, c
   float* dd = (float*)(ws + pl->ws.dd);
   {
     StageTimer t(pl, s, T_DETECT);
-    launch_detect(pl, xp, ws, keys, s);
+    launch_exemplars(pl, xp, ws, keys, s);
   }
   glr_status e = check_hip("detect");
   if (e) return e;
@@ -286,7 +305,7 @@ glr_status surrogate_prior(glr_plan* pl, const float* xp, float sigma, float* xo
     const int ns = (N + pl->judge_stride - 1) / pl->judge_stride;
     {
       StageTimer t(pl, s, T_DETECT);
-      launch_detect(pl, xp, ws, keys, s);
+      launch_exemplars(pl, xp, ws, keys, s);
       launch_stride_keys(keys, N, pl->judge_stride, sub, s);
     }
     // the subset step reuses the plan's buffers with N = ns keys
@@ -400,6 +419,10 @@ void glr_params_default(glr_params* p) {
   p->judge_stride = 8;
   p->judge_delta_max = 0.02f;
   p->cnn_packed = nullptr;
+  p->exemplars = GLR_EXEMPLAR_CORNER;
+  p->uniform_step = 4;
+  p->search = GLR_SEARCH_GLOBAL;
+  p->window = 20;
 }
 
 glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_params* pr,
@@ -424,13 +447,35 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
   const long long Ncand = (long long)Hc * Wc;
   if (pr->k < 1 || pr->k > Ncand) return fail(GLR_ERR_SHAPE, "K=%d must be in [1, N_cand=%lld]", pr->k, Ncand);
   if (pr->k > 64) return fail(GLR_ERR_UNSUPPORTED, "K=%d > 64", pr->k);
-  if (pr->n_keys < 1 || pr->n_keys > Ncand)
+  if (pr->exemplars < GLR_EXEMPLAR_CORNER || pr->exemplars > GLR_EXEMPLAR_CORNER_UNIFORM)
+    return fail(GLR_ERR_INVALID_ARG, "unknown exemplar selection %d", pr->exemplars);
+  if (pr->search != GLR_SEARCH_GLOBAL && pr->search != GLR_SEARCH_WINDOW)
+    return fail(GLR_ERR_INVALID_ARG, "unknown search %d", pr->search);
+  const bool corners = pr->exemplars != GLR_EXEMPLAR_UNIFORM;
+  if (corners && (pr->n_keys < 1 || pr->n_keys > Ncand))
     return fail(GLR_ERR_SHAPE, "n_keys=%d must be in [1, N_cand=%lld]", pr->n_keys, Ncand);
-  if (pr->n_keys > 16384)
-    return fail(GLR_ERR_UNSUPPORTED, "n_keys=%d above 16384", pr->n_keys);
+  long long n_total = corners ? pr->n_keys : 0;
+  if (pr->exemplars != GLR_EXEMPLAR_CORNER) {
+    if (pr->uniform_step < 1) return fail(GLR_ERR_INVALID_ARG, "uniform_step must be >= 1");
+    const long long st = pr->exemplars == GLR_EXEMPLAR_UNIFORM ? pr->uniform_step
+                                                                : 3LL * pr->uniform_step;
+    n_total += ((Hc + st - 1) / st) * ((Wc + st - 1) / st);
+  }
+  // (a candidate's aggregation bucket holds one entry per group: at most N)
+  if (n_total > 16384)
+    return fail(GLR_ERR_UNSUPPORTED, "%lld exemplar keys above 16384", n_total);
+  if (pr->search == GLR_SEARCH_WINDOW) {
+    if (pr->window < 1 || pr->window > 4096)
+      return fail(GLR_ERR_INVALID_ARG, "window must be in [1, 4096]");
+    const long long corner_win =
+        (long long)std::min(pr->window + 1, Hc) * std::min(pr->window + 1, Wc);
+    if (corner_win < pr->k)
+      return fail(GLR_ERR_SHAPE, "a window of %d at a grid corner holds %lld < K=%d candidates",
+                  pr->window, corner_win, pr->k);
+  }
   if (Ncand + 1 > 4096LL * 4096LL)
     return fail(GLR_ERR_UNSUPPORTED, "N_cand=%lld above 4096^2 - 1", Ncand);
-  if ((long long)pr->n_keys * pr->k > (1LL << 30))
+  if (n_total * pr->k > (1LL << 30))
     return fail(GLR_ERR_UNSUPPORTED, "n_keys*K too large");
   if (pr->iters < 0) return fail(GLR_ERR_INVALID_ARG, "iters < 0");
   if (pr->iters > 0 && !pr->sigma) return fail(GLR_ERR_INVALID_ARG, "sigma is NULL");
@@ -473,7 +518,12 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
   pl->is_complex = pb->modality == GLR_MRI;
   pl->mask = pb->mask;
   pl->P = P;
-  pl->N = pr->n_keys;
+  pl->N = (int)n_total;
+  pl->n_corner = corners ? pr->n_keys : 0;
+  pl->exemplars = pr->exemplars;
+  pl->uniform_step = pr->uniform_step;
+  pl->search = pr->search;
+  pl->window = pr->window;
   pl->K = pr->k;
   pl->T = pr->iters;
   pl->solver = pr->solver;
@@ -500,6 +550,8 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
   if (nch < 1) nch = 1;
   if (nch >= 128) nch = nch / 128 * 128;
   pl->n_chunk = (int)std::min<long long>(nch, pl->N);
+  // window search needs no distance chunks or candidate-range lists
+  if (pl->search == GLR_SEARCH_WINDOW) pl->n_chunk = 1;
   // ranges per key: enough waves to fill the chip; more for the BF16 form,
   // whose larger margin sets need the combined capacity of more range lists
   const int target = pr->precision == GLR_PREC_BF16_RESCORE ? 32768 : 8192;
@@ -599,6 +651,12 @@ glr_status glr_plan_destroy(glr_plan* pl) {
   return GLR_OK;
 }
 
+glr_status glr_plan_keys(const glr_plan* pl, int32_t* n_keys) {
+  if (!pl || !n_keys) return fail(GLR_ERR_INVALID_ARG, "glr_plan_keys: NULL argument");
+  *n_keys = pl->N;
+  return GLR_OK;
+}
+
 glr_status glr_workspace_size(const glr_plan* pl, size_t* bytes) {
   if (!pl || !bytes) return fail(GLR_ERR_INVALID_ARG, "glr_workspace_size: NULL argument");
   *bytes = pl->ws.total;
@@ -685,7 +743,7 @@ glr_status glr_detect_keys(glr_plan* pl, const void* x, int32_t* keys, void* ws,
   const float* xp = planar_in(pl, x, w, s);
   {
     StageTimer t(pl, s, T_DETECT);
-    launch_detect(pl, xp, w, keys, s);
+    launch_exemplars(pl, xp, w, keys, s);
   }
   return check_hip(__func__);
 }

@@ -383,7 +383,24 @@ __global__ void __launch_bounds__(SEL_T) k_select(uint8_t* __restrict__ flag,
 
 }  // namespace
 
-void launch_detect(const glr_plan* pl, const float* xp, char* ws, int32_t* keys, hipStream_t s) {
+// keys[i] = (step (i / nc)) Wc + step (i % nc), nc = ceil(Wc / step): the
+// uniform exemplar grid, ascending
+__global__ void k_uniform_keys(int32_t* __restrict__ keys, int n, int Wc, int step, int nc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int a = i / nc, b = i - a * nc;
+  keys[i] = a * step * Wc + b * step;
+}
+
+void launch_uniform_keys(const glr_plan* pl, int32_t* keys, int step, hipStream_t s) {
+  const int nr = (pl->Hc + step - 1) / step, nc = (pl->Wc + step - 1) / step;
+  const int n = nr * nc;
+  hipLaunchKernelGGL(k_uniform_keys, dim3((n + 255) / 256), dim3(256), 0, s, keys, n, pl->Wc,
+                     step, nc);
+}
+
+void launch_detect(const glr_plan* pl, const float* xp, char* ws, int32_t* keys, int n_sel,
+                   hipStream_t s) {
   const int H = pl->H, W = pl->W, HW = H * W;
   uint8_t* q = (uint8_t*)(ws + pl->ws.q);
   int* gxx = (int*)(ws + pl->ws.gxx);
@@ -405,6 +422,6 @@ void launch_detect(const glr_plan* pl, const float* xp, char* ws, int32_t* keys,
   hipLaunchKernelGGL(k_sobel, dim3(nblk(HW)), dim3(TPB), 0, s, q, H, W, gxx, gyy, gxy);
   hipLaunchKernelGGL(k_harris, dim3(nblk(HW)), dim3(TPB), 0, s, gxx, gyy, gxy, H, W, r25);
   hipLaunchKernelGGL(k_nms, dim3(nblk((size_t)pl->Ncand)), dim3(TPB), 0, s, r25, H, W, pl->P, flag);
-  hipLaunchKernelGGL(k_select, dim3(1), dim3(SEL_T), 0, s, flag, r25, H, W, pl->P, pl->N, slist,
+  hipLaunchKernelGGL(k_select, dim3(1), dim3(SEL_T), 0, s, flag, r25, H, W, pl->P, n_sel, slist,
                      sval, keys, st);
 }

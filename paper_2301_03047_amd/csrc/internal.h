@@ -55,6 +55,8 @@ struct glr_plan {
   int modality, H, W, C, Cp, is_complex;
   const uint8_t* mask;
   int P, N, K, T, solver, precision, timing;
+  int n_corner;                   // corner exemplars (N counts the uniform grid too)
+  int exemplars, uniform_step, search, window;
   float rho, wnnm_c, wnnm_eps;
   std::vector<float> sigma;
   // derived sizes
@@ -124,7 +126,11 @@ void launch_to_planar(const float2* z, float* p, int n, hipStream_t s);
 void launch_from_planar(const float* p, float2* z, int n, hipStream_t s);
 
 // detect.hip
-void launch_detect(const glr_plan* pl, const float* xp, char* ws, int32_t* keys, hipStream_t s);
+// the n_sel best corner keys (n_sel <= N_cand)
+void launch_detect(const glr_plan* pl, const float* xp, char* ws, int32_t* keys, int n_sel,
+                   hipStream_t s);
+// the uniform exemplar grid of interval step (ceil(Hc/step) ceil(Wc/step) keys)
+void launch_uniform_keys(const glr_plan* pl, int32_t* keys, int step, hipStream_t s);
 
 // match.hip
 // also resets the top-K scan's per-key bounds tsh[0..min(n_chunk, N)) to +inf
@@ -194,6 +200,10 @@ void launch_select_rescore(const glr_plan* pl, const float* xp, const float* A,
                            float* tkey, DevStats* st, hipStream_t s);
 void launch_collect_flags(const int32_t* oflag, int g0, int nk, int32_t* klist, int32_t* kcount,
                           DevStats* st, hipStream_t s);
+// block matching in a (2 window + 1)^2 window around each key: exact groups
+// (compensated distances, (distance, position) order) for keys[0..N)
+void launch_window_topk(const glr_plan* pl, const float* xp, const float* A, const int32_t* keys,
+                        int32_t* idx, float* dd, hipStream_t s);
 
 // lowrank.hip
 // zbuf[0..zn) is set to zero (nullable); bump != 0 counts a prior step

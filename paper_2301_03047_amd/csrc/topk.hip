@@ -990,6 +990,93 @@ full_row:
   }
 }
 
+// Block matching in a local window (eq. 1 with KNN grouping, the vanilla
+// BM the paper compares global matching against): one block per key; the
+// candidates are the grid positions within `win` rows and columns of the
+// key (clipped to the grid), every one rescored with the compensated
+// arithmetic of the margin sets, and a running best list kept in LDS gives
+// the first K by (distance, position).  No contraction form and no margin:
+// the window is small enough to score directly.
+template <int EM>
+__global__ void __launch_bounds__(ST)
+k_window_topk(const float* __restrict__ xp, int H, int W, int P, int D, int L,
+              const float* __restrict__ A, const int32_t* __restrict__ keys, int N, int K,
+              int win, int32_t* __restrict__ idx, float* __restrict__ dd) {
+  __shared__ float su[UCAP];
+  __shared__ float sl[UCAP];
+  __shared__ int sj[UCAP];
+  __shared__ int ssh[ST / 64 + 1];
+  __shared__ float fh[ST], fl[ST];
+  const int g = blockIdx.x;
+  if (g >= N) return;                        // block-uniform
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int cpi = 64 / L;
+  const int Hc = H - P + 1, Wc = W - P + 1;
+  const int t = keys[g];
+  const int gr = t / Wc, gc = t - gr * Wc;
+  const int r0 = max(gr - win, 0), r1 = min(gr + win, Hc - 1);
+  const int c0 = max(gc - win, 0), c1 = min(gc + win, Wc - 1);
+  const int ww = c1 - c0 + 1;
+  const int n = (r1 - r0 + 1) * ww;
+  KeySlice<EM> ks;
+  key_slice_load(ks, A + (size_t)g * D, D, P, H, W, L, (tid & 63) & (L - 1));
+  auto pos = [&](int i) {
+    const int a = i / ww;
+    return (r0 + a) * Wc + c0 + (i - a * ww);
+  };
+  const int BEST = UCAP;
+  int cur = 0;
+  float th = __int_as_float(0x7f800000), tl = 0.f;
+  int tj = 0x7fffffff;
+  for (int base = 0; base < n; base += ST) {
+    coop_rescore(ks, xp, [&](int i) { return pos(base + i); }, wave * 2 * cpi, min(ST, n - base),
+                 8 * cpi, Wc, W, L, fh, fl);
+    __syncthreads();
+    const int i = base + tid;
+    df32 v = {0.f, 0.f};
+    bool adm = false;
+    int j = 0;
+    if (i < n) {
+      j = pos(i);
+      v.hi = fh[tid];
+      v.lo = fl[tid];
+      adm = cur < K || df_less(v.hi, v.lo, j, th, tl, tj);
+    }
+    int tc;
+    const int pre = block_excl_scan(adm ? 1 : 0, ssh, &tc);
+    if (adm) {
+      su[cur + pre] = v.hi;
+      sl[cur + pre] = v.lo;
+      sj[cur + pre] = j;
+    }
+    cur += tc;
+    __syncthreads();
+    if (cur > BEST - ST || base + ST >= n) {
+      int n2 = 1;
+      while (n2 < cur) n2 <<= 1;
+      for (int q = cur + tid; q < n2; q += ST) {
+        su[q] = __int_as_float(0x7f800000);
+        sl[q] = 0.f;
+        sj[q] = 0x7fffffff;
+      }
+      __syncthreads();
+      block_bitonic(su, sl, sj, n2);
+      cur = cur < K ? cur : K;
+      if (cur >= K) {
+        th = su[K - 1];
+        tl = sl[K - 1];
+        tj = sj[K - 1];
+      }
+      __syncthreads();
+    }
+  }
+  for (int q = tid; q < K; q += ST) {
+    idx[(size_t)g * K + q] = sj[q];
+    dd[(size_t)g * K + q] = su[q];
+  }
+}
+
 }  // namespace
 
 // The bound coefficients of margin_eps for the plan's two forms, rounded up
@@ -1108,4 +1195,15 @@ k_collect_flags(const int32_t* __restrict__ oflag, int g0, int nk, int32_t* __re
 void launch_collect_flags(const int32_t* oflag, int g0, int nk, int32_t* klist, int32_t* kcount,
                           DevStats* st, hipStream_t s) {
   hipLaunchKernelGGL(k_collect_flags, dim3(1), dim3(1024), 0, s, oflag, g0, nk, klist, kcount, st);
+}
+
+void launch_window_topk(const glr_plan* pl, const float* xp, const float* A, const int32_t* keys,
+                        int32_t* idx, float* dd, hipStream_t s) {
+  const int L = rescore_lanes(pl->D);
+  if ((pl->D + L - 1) / L <= 32)
+    hipLaunchKernelGGL(k_window_topk<32>, dim3(pl->N), dim3(ST), 0, s, xp, pl->H, pl->W, pl->P,
+                       pl->D, L, A, keys, pl->N, pl->K, pl->window, idx, dd);
+  else
+    hipLaunchKernelGGL(k_window_topk<64>, dim3(pl->N), dim3(ST), 0, s, xp, pl->H, pl->W, pl->P,
+                       pl->D, L, A, keys, pl->N, pl->K, pl->window, idx, dd);
 }

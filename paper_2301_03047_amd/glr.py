@@ -18,6 +18,8 @@ STATUS_NAMES = {0: "GLR_OK", 1: "GLR_ERR_INVALID_ARG", 2: "GLR_ERR_SHAPE",
                 3: "GLR_ERR_ALIGNMENT", 4: "GLR_ERR_UNSUPPORTED",
                 5: "GLR_ERR_WORKSPACE_TOO_SMALL", 6: "GLR_ERR_HIP"}
 _MODALITY = {"cacti": CACTI, "mri": MRI, "msfa": MSFA}
+EXEMPLARS = {"corner": 0, "uniform": 1, "corner_uniform": 2}
+SEARCH = {"global": 0, "window": 1}
 STATIC_SCRATCH_BYTES = 64 << 20          # GLR_STATIC_SCRATCH_BYTES
 
 _c_i32 = ctypes.c_int32
@@ -37,7 +39,8 @@ class Params(ctypes.Structure):
                 ("precision", _c_i32), ("dist_chunk_mb", _c_i32), ("timing", _c_i32),
                 ("surrogate", _c_i32), ("surrogate_frac", ctypes.c_float),
                 ("judge_stride", _c_i32), ("judge_delta_max", ctypes.c_float),
-                ("cnn_packed", _vp)]
+                ("cnn_packed", _vp), ("exemplars", _c_i32), ("uniform_step", _c_i32),
+                ("search", _c_i32), ("window", _c_i32)]
 
 
 class Stats(ctypes.Structure):
@@ -91,6 +94,7 @@ def lib():
                                  ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)]),
         "glr_plan_destroy": (st, [_vp]),
         "glr_workspace_size": (st, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+        "glr_plan_keys": (st, [_vp, ctypes.POINTER(_c_i32)]),
         "glr_forward": (st, [_vp, _vp, _vp, _vp, _vp]),
         "glr_adjoint": (st, [_vp, _vp, _vp, _vp, _vp]),
         "glr_fft2d": (st, [_vp, _vp, _vp, _c_i32, _vp, _vp]),
@@ -138,7 +142,8 @@ class Plan:
     def __init__(self, modality, H, W, C, patch, n_keys, k, iters=0, sigma=None, mask=None,
                  rho=1.0, wnnm_c=None, wnnm_eps=None, precision="fp32", dist_chunk_mb=8192,
                  timing=False, device="cuda", allocate=True, cnn=None, surrogate_frac=0.6,
-                 judge_stride=8, judge_delta_max=0.02):
+                 judge_stride=8, judge_delta_max=0.02, exemplars="corner", uniform_step=4,
+                 search="global", window=20):
         import torch
         L = lib()
         self.modality = _MODALITY[modality] if isinstance(modality, str) else int(modality)
@@ -161,6 +166,10 @@ class Plan:
         par.precision = PREC[precision]
         par.dist_chunk_mb = int(dist_chunk_mb)
         par.timing = 1 if timing else 0
+        par.exemplars = EXEMPLARS[exemplars]
+        par.uniform_step = int(uniform_step)
+        par.search = SEARCH[search]
+        par.window = int(window)
         self.cnn = cnn                      # keeps the packed weights alive
         if cnn is not None:
             par.surrogate = 1
@@ -179,12 +188,25 @@ class Plan:
         _check(L.glr_plan_create(ctypes.byref(h), ctypes.byref(prob), ctypes.byref(par),
                                  ctypes.byref(wsb)))
         self._h = h
+        nk = _c_i32()
+        _check(L.glr_plan_keys(h, ctypes.byref(nk)))
+        self.n_keys = int(nk.value)          # exemplar keys per prior step (N)
         self.workspace_bytes = int(wsb.value)
         self.ws = None
         if allocate:
             self.ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=device)
 
     # ------------------------------------------------------------ helpers
+    @classmethod
+    def for_workload(cls, wl, mask=None, **kw):
+        """A plan with the shapes and method parameters of a ``synth`` workload."""
+        import synth
+        args = dict(iters=wl.iters, sigma=synth.sigma_schedule(wl), mask=mask,
+                    precision=wl.precision, exemplars=wl.exemplars,
+                    uniform_step=wl.uniform_step, search=wl.search, window=wl.window)
+        args.update(kw)
+        return cls(wl.modality, wl.H, wl.W, wl.C, wl.patch, wl.n_keys, wl.k, **args)
+
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value and _LIB is not None:

@@ -142,3 +142,38 @@ def test_static_prior_step_refuses_on_the_host():
     finally:
         L.glr_plan_destroy(h)
     assert L.glr_prior_step_static(None, fake, ctypes.c_float(0.05), fake, None) == 1
+
+
+def _keys_of(**kw):
+    L = glr.lib()
+    prob = Problem(glr.CACTI, kw.pop("H"), kw.pop("W"), kw.pop("C"), FAKE_MASK)
+    par = Params()
+    L.glr_params_default(ctypes.byref(par))
+    par.patch, par.n_keys, par.k = kw.pop("P"), kw.pop("N"), kw.pop("K")
+    for k, v in kw.items():
+        setattr(par, k, v)
+    h = ctypes.c_void_p()
+    ws = ctypes.c_size_t()
+    st = L.glr_plan_create(ctypes.byref(h), ctypes.byref(prob), ctypes.byref(par), ctypes.byref(ws))
+    if st:
+        return st, None
+    n = ctypes.c_int32()
+    assert L.glr_plan_keys(h, ctypes.byref(n)) == 0
+    L.glr_plan_destroy(h)
+    return 0, n.value
+
+
+def test_exemplar_counts_and_window_limits():
+    # 256 x 256, P = 6: a 251 x 251 grid; interval 4 -> 63^2, interval 12 -> 21^2
+    assert _keys_of(H=256, W=256, C=8, P=6, N=512, K=32) == (0, 512)
+    assert _keys_of(H=256, W=256, C=8, P=6, N=512, K=32, exemplars=1, uniform_step=4) == (0, 3969)
+    assert _keys_of(H=256, W=256, C=8, P=6, N=512, K=32, exemplars=2, uniform_step=4) == (0, 953)
+    assert _keys_of(H=256, W=256, C=8, P=6, N=512, K=32, search=1, window=20) == (0, 512)
+    # a 5 x 5 corner window holds 25 < K = 32 candidates
+    assert _keys_of(H=64, W=64, C=2, P=4, N=8, K=32, search=1, window=4)[0] == 2
+    assert _keys_of(H=64, W=64, C=2, P=4, N=8, K=32, search=1, window=0)[0] == 1
+    assert _keys_of(H=64, W=64, C=2, P=4, N=8, K=8, exemplars=3)[0] == 1
+    assert _keys_of(H=64, W=64, C=2, P=4, N=8, K=8, search=2)[0] == 1
+    assert _keys_of(H=64, W=64, C=2, P=4, N=8, K=8, exemplars=1, uniform_step=0)[0] == 1
+    # more than 16384 exemplars: 1019^2 positions at interval 4 -> 255^2
+    assert _keys_of(H=1024, W=1024, C=1, P=6, N=8, K=8, exemplars=1, uniform_step=4)[0] == 4
