@@ -270,7 +270,7 @@ def run_ablation(log):
     import torch
     import paper_2301_03047_amd as glr
     import synth
-    from paper_2301_03047_amd.surrogate import psnr
+    from paper_2301_03047_amd.metrics import psnr, ssim
     base = synth.WORKLOADS["cacti_256"]
     inst = synth.make_instance(base)
     mask = torch.from_numpy(inst["mask"]).cuda()
@@ -300,7 +300,8 @@ def run_ablation(log):
                                                       + st["ms_select"]) / T, 3),
                      "lowrank_ms_per_iteration": round((st["ms_lowrank"] + st["ms_aggregate"]) / T, 3),
                      "detect_ms_per_iteration": round(st["ms_detect"] / T, 3),
-                     "psnr_db": round(psnr(out.cpu().numpy(), inst["x_true"]), 3)}
+                     "psnr_db": round(psnr(out.cpu().numpy(), inst["x_true"]), 3),
+                     "ssim": round(ssim(out.cpu().numpy(), inst["x_true"]), 4)}
         log(f"{name}: {res[name]}")
         del plan, pt
     gm, bm = res["gm_corner"], res["bm_uniform"]
@@ -439,7 +440,7 @@ def main():
     }
 
     # quality: a fresh full-length reconstruction, timed as a whole
-    from paper_2301_03047_amd.surrogate import psnr
+    from paper_2301_03047_amd.metrics import psnr, ssim
     xt = inst["x_true"]
     if not args.no_quality:
         plan.read_stats(reset=True)
@@ -453,6 +454,7 @@ def main():
         rec["full_run"] = {"iters": T, "seconds": round(ms_full / 1e3, 3),
                            "iterations_per_s": round(T * 1e3 / ms_full, 4),
                            "psnr_db": round(psnr(fresh.cpu().numpy(), xt), 4),
+                           "ssim": round(ssim(fresh.cpu().numpy(), xt), 4),
                            "rematch_keys": sf["rematch_keys"],
                            "regather_keys": sf["regather_keys"],
                            "overflow_keys": sf["overflow_keys"],

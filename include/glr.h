@@ -61,7 +61,10 @@ enum {
 };
 
 enum { GLR_CACTI = 0, GLR_MRI = 1, GLR_MSFA = 2 };   /* eq. 2, eq. 3, eq. 4-5 */
-enum { GLR_SOLVER_GAP = 0, GLR_SOLVER_ADMM = 1 };
+/* GAP_ACC: accelerated GAP, the measurement replaced by an accumulated one,
+ * y_acc <- y_acc + (y - Phi x) (y_acc = y at the start), before each
+ * projection (a reading: the paper names GAP without the variant). */
+enum { GLR_SOLVER_GAP = 0, GLR_SOLVER_ADMM = 1, GLR_SOLVER_GAP_ACC = 2 };
 enum { GLR_PREC_FP32 = 0, GLR_PREC_BF16_RESCORE = 1 };
 /* Exemplar selection (Method section: corners of the edge map instead of the
  * traditional uniform grid; Results, CACTI: corners plus a modest uniform
@@ -89,7 +92,7 @@ typedef struct glr_params {
   int32_t n_keys;        /* N, exemplar (key) patches per prior step            */
   int32_t k;             /* K, group size (K nearest patches), 1..64            */
   int32_t iters;         /* T, outer iterations of glr_reconstruct              */
-  int32_t solver;        /* GAP for CACTI/MSFA, ADMM for MRI                    */
+  int32_t solver;        /* GAP or GAP_ACC for CACTI/MSFA, ADMM for MRI         */
   float rho;             /* ADMM penalty                                        */
   const float* sigma;    /* host [iters]: noise level per iteration (copied)    */
   float wnnm_c;          /* WNNM weight constant c (default 2*sqrt(2))          */
@@ -199,7 +202,9 @@ GLR_API glr_status glr_fft2d(glr_plan* plan, const void* in, void* out, int32_t 
 /* Data step.  GAP (CACTI, MSFA): x_out = x + Phi^T((y - Phi x) / R~) with
  * R = diag(Phi Phi^T) and zeros of R replaced by 1.  ADMM (MRI): x_out =
  * F^H((M y + rho F(z - u)) / (M + rho)); z and u are complex64 [H][W] and
- * ignored for GAP (may be NULL).  In-place (x_out == x) allowed. */
+ * ignored for GAP (may be NULL).  In-place (x_out == x) allowed.  (Always
+ * the plain GAP step: the accelerated one needs the loop state's
+ * accumulated measurement, see glr_reconstruct / glr_pre_prior.) */
 GLR_API glr_status glr_data_step(glr_plan* plan, const void* y, const void* x, const void* z,
                          const void* u, void* x_out, void* ws, void* stream);
 
@@ -264,9 +269,10 @@ GLR_API glr_status glr_prior_step_static(glr_plan* plan, const void* x_in, float
 /* --------------------------------------------------------------- loop
  * Run outer iterations t_begin .. t_end-1 of the GAP/ADMM loop with the GLR
  * prior (sigma[t] per iteration).  state: device buffer of
- * glr_state_bytes() holding the loop state (iterate; MRI: x, z, u); when
+ * glr_state_bytes() holding the loop state (iterate; MRI: x, z, u;
+ * GAP_ACC: then the accumulated measurement [H][W]); when
  * t_begin == 0 it is initialised from y (CACTI: Phi^T(y / R~); MSFA: 4x4
- * cell replication; MRI: x = z = F^H(M y), u = 0), otherwise it must hold
+ * cell replication; MRI: x = z = F^H(M y), u = 0; y_acc = y), otherwise it must hold
  * the state left by a previous call, so a run may be split and resumed.
  * x_out receives the current estimate (CACTI/MSFA: the last prior output;
  * MRI: z). */

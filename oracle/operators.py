@@ -98,6 +98,16 @@ def gap_update(x, y, forward, adjoint, R):
     return x + adjoint((y - forward(x)) / Rt)
 
 
+def gap_acc_update(x, y, y_acc, forward, adjoint, R):
+    """Accelerated GAP step (reading: the measurement replaced by an
+    accumulated one): y_acc' = y_acc + (y - Phi x), then
+    x_bar = x + Phi^T((y_acc' - Phi x) / R~).  Returns (x_bar, y_acc')."""
+    Rt = np.where(R == 0, 1.0, R)
+    r = forward(x)
+    y_acc = y_acc + (y - r)
+    return x + adjoint((y_acc - r) / Rt), y_acc
+
+
 def admm_x_update(y, z, u, line_mask, rho):
     """Closed-form ADMM data step for eq. 3:
     x = F^H((M*y + rho*F(z - u)) / (M + rho))."""

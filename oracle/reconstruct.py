@@ -32,23 +32,24 @@ def reconstruct(wl, y, mask, sigmas, iters=None, callback=None):
     ``callback(t, pre_prior, post_prior)`` is called each iteration.
     Returns the final estimate (real ``[C][H][W]`` or complex ``[H][W]``)."""
     T = wl.iters if iters is None else iters
-    if wl.modality == "cacti":
-        R = ops.cacti_mask_sum(mask)
-        Rt = np.where(R == 0, 1.0, R)
-        x = ops.cacti_adjoint(y / Rt, mask)
+    acc = getattr(wl, "gap_acc", False)
+    if wl.modality in ("cacti", "msfa"):
+        if wl.modality == "cacti":
+            R = ops.cacti_mask_sum(mask)
+            x = ops.cacti_adjoint(y / np.where(R == 0, 1.0, R), mask)
+            fwd = lambda v: ops.cacti_forward(v, mask)
+            adj = lambda r: ops.cacti_adjoint(r, mask)
+        else:
+            R = np.ones_like(y)
+            x = ops.msfa_init(y, wl.C)
+            fwd = ops.msfa_forward
+            adj = lambda r: ops.msfa_adjoint(r, wl.C)
+        y_acc = np.array(y, dtype=np.float64)
         for t in range(T):
-            xb = ops.gap_update(x, y, lambda v: ops.cacti_forward(v, mask),
-                                lambda r: ops.cacti_adjoint(r, mask), R)
-            x = _prior(xb, wl, sigmas[t], False)
-            if callback:
-                callback(t, xb, x)
-        return x
-    if wl.modality == "msfa":
-        B = wl.C
-        x = ops.msfa_init(y, B)
-        for t in range(T):
-            xb = ops.gap_update(x, y, ops.msfa_forward,
-                                lambda r: ops.msfa_adjoint(r, B), np.ones_like(y))
+            if acc:
+                xb, y_acc = ops.gap_acc_update(x, y, y_acc, fwd, adj, R)
+            else:
+                xb = ops.gap_update(x, y, fwd, adj, R)
             x = _prior(xb, wl, sigmas[t], False)
             if callback:
                 callback(t, xb, x)

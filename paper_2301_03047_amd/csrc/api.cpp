@@ -348,15 +348,18 @@ const float* planar_in(glr_plan* pl, const void* x, char* ws, hipStream_t s) {
 }
 
 // For MRI with vp, also vp = planar form of x_out + u (the prior's input).
+// yacc: accelerated GAP's accumulated measurement (null: plain GAP), updated
+// when wacc != 0.
 glr_status data_step_impl(glr_plan* pl, const void* y, const void* x, const void* z,
                           const void* u, void* x_out, char* ws, hipStream_t s,
-                          float* vp = nullptr) {
+                          float* vp = nullptr, float* yacc = nullptr, int wacc = 0) {
   StageTimer t(pl, s, T_DATA);
   const int H = pl->H, W = pl->W, HW = H * W;
   if (pl->modality == GLR_CACTI) {
-    launch_cacti_gap((const float*)x, (const float*)y, pl->mask, (float*)x_out, pl->C, HW, s);
+    launch_cacti_gap((const float*)x, (const float*)y, pl->mask, (float*)x_out, pl->C, HW, yacc,
+                     wacc, s);
   } else if (pl->modality == GLR_MSFA) {
-    launch_msfa_gap((const float*)x, (const float*)y, (float*)x_out, H, W, s);
+    launch_msfa_gap((const float*)x, (const float*)y, (float*)x_out, H, W, yacc, wacc, s);
   } else {
     // F(z - u) with the k-space update fused into the transform's passes
     float2* a = (float2*)(ws + pl->ws.cplx_a);
@@ -497,8 +500,8 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
     if (!pow2(pb->H) || !pow2(pb->W) || pb->H < 4 || pb->W < 4 || pb->H > 2048 || pb->W > 2048)
       return fail(GLR_ERR_UNSUPPORTED, "MRI needs H, W powers of two in [4, 2048]");
     if (pr->solver != GLR_SOLVER_ADMM) return fail(GLR_ERR_INVALID_ARG, "MRI uses the ADMM solver");
-  } else if (pr->solver != GLR_SOLVER_GAP) {
-    return fail(GLR_ERR_INVALID_ARG, "CACTI/MSFA use the GAP solver");
+  } else if (pr->solver != GLR_SOLVER_GAP && pr->solver != GLR_SOLVER_GAP_ACC) {
+    return fail(GLR_ERR_INVALID_ARG, "CACTI/MSFA use the GAP or accelerated GAP solver");
   }
   if (pb->modality == GLR_MSFA) {
     if (pb->C != 16) return fail(GLR_ERR_UNSUPPORTED, "MSFA needs 16 bands");
@@ -803,10 +806,20 @@ glr_status glr_prior_step(glr_plan* pl, const void* x_in, float sigma, void* x_o
   return check_hip(__func__);
 }
 
+// Loop state: the iterate (MRI: x, z, u), accelerated GAP's accumulated
+// measurement [H][W], then the surrogate-active flag (int32).
+size_t state_yacc_offset(const glr_plan* pl) {
+  const size_t HW = (size_t)pl->H * pl->W;
+  return pl->is_complex ? 3 * HW * 8 : (size_t)pl->C * HW * 4;
+}
+size_t state_flag_offset(const glr_plan* pl) {
+  const size_t HW = (size_t)pl->H * pl->W;
+  return state_yacc_offset(pl) + (pl->solver == GLR_SOLVER_GAP_ACC ? HW * 4 : 0);
+}
+
 glr_status glr_state_bytes(const glr_plan* pl, size_t* bytes) {
   if (!pl || !bytes) return fail(GLR_ERR_INVALID_ARG, "glr_state_bytes: NULL argument");
-  const size_t HW = (size_t)pl->H * pl->W;
-  *bytes = pl->is_complex ? 3 * HW * 8 : (size_t)pl->C * HW * 4;
+  *bytes = state_flag_offset(pl);
   if (pl->surrogate) *bytes += 256;              // surrogate-active flag (int32)
   return GLR_OK;
 }
@@ -825,8 +838,9 @@ glr_status glr_reconstruct(glr_plan* pl, const void* y, void* state, int32_t t_b
   ensure_stats(pl, w, s);
   const int H = pl->H, W = pl->W, HW = H * W;
   // surrogate-active flag in the state tail
-  int32_t* flag = (int32_t*)((char*)state + (pl->is_complex ? 3 * (size_t)HW * 8
-                                                              : (size_t)pl->C * HW * 4));
+  int32_t* flag = (int32_t*)((char*)state + state_flag_offset(pl));
+  float* yacc = pl->solver == GLR_SOLVER_GAP_ACC ? (float*)((char*)state + state_yacc_offset(pl))
+                                                 : nullptr;
   int active = 0;
   // ceil(frac * T) with frac taken to 6 decimals (0.6f must give 3 of 5, not 4)
   const long long fr = std::llround((double)pl->surrogate_frac * 1e6);
@@ -857,9 +871,10 @@ glr_status glr_reconstruct(glr_plan* pl, const void* y, void* state, int32_t t_b
     if (t_begin == 0) {
       if (pl->modality == GLR_CACTI) launch_cacti_init((const float*)y, pl->mask, x, pl->C, HW, s);
       else launch_msfa_init((const float*)y, x, H, W, s);
+      if (yacc) hipMemcpyAsync(yacc, y, (size_t)HW * 4, hipMemcpyDeviceToDevice, s);
     }
     for (int t = t_begin; t < t_end; ++t) {
-      e = data_step_impl(pl, y, x, nullptr, nullptr, xb, w, s);
+      e = data_step_impl(pl, y, x, nullptr, nullptr, xb, w, s, nullptr, yacc, 1);
       if (e) return e;
       e = prior(t, xb, x);
       if (e) return e;
@@ -903,7 +918,10 @@ glr_status glr_pre_prior(glr_plan* pl, const void* y, const void* state, void* v
   const int HW = pl->H * pl->W;
   if (!pl->is_complex) {
     if (v_out == state) return fail(GLR_ERR_INVALID_ARG, "v_out must not alias the state");
-    return data_step_impl(pl, y, state, nullptr, nullptr, v_out, w, s);
+    float* yacc = pl->solver == GLR_SOLVER_GAP_ACC
+                      ? (float*)((char*)state + state_yacc_offset(pl)) : nullptr;
+    // the accumulated measurement is read, not advanced
+    return data_step_impl(pl, y, state, nullptr, nullptr, v_out, w, s, nullptr, yacc, 0);
   }
   // ADMM: x = F^H((M y + rho F(z - u)) / (M + rho)) into the complex scratch,
   // v = x + u in planar form (the prior's input), then interleaved into v_out

@@ -95,12 +95,14 @@ void launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
 void launch_cacti_forward(const float* x, const uint8_t* m, float* y, int F, int HW, hipStream_t s);
 void launch_cacti_adjoint(const float* y, const uint8_t* m, float* x, int F, int HW, hipStream_t s);
 void launch_cacti_init(const float* y, const uint8_t* m, float* x, int F, int HW, hipStream_t s);
+// yacc (nullable): accelerated GAP's accumulated measurement, updated when wacc
 void launch_cacti_gap(const float* x, const float* y, const uint8_t* m, float* xo, int F, int HW,
-                      hipStream_t s);
+                      float* yacc, int wacc, hipStream_t s);
 void launch_msfa_forward(const float* x, float* y, int H, int W, hipStream_t s);
 void launch_msfa_adjoint(const float* y, float* x, int H, int W, hipStream_t s);
 void launch_msfa_init(const float* y, float* x, int H, int W, hipStream_t s);
-void launch_msfa_gap(const float* x, const float* y, float* xo, int H, int W, hipStream_t s);
+void launch_msfa_gap(const float* x, const float* y, float* xo, int H, int W, float* yacc,
+                     int wacc, hipStream_t s);
 // Optional fusions of the 2-D FFT (see k_fft_rows / k_fft_cols): the rows pass
 // transforms in + beta in2; the columns pass applies the ADMM k-space update
 // (ky, lines, rho) and/or writes vp = planar(result + pu).

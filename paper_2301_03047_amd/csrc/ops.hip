@@ -47,8 +47,19 @@ __global__ void k_cacti_init(const float* __restrict__ y, const uint8_t* __restr
 }
 
 // GAP: x_bar = x + Phi^T((y - Phi x) / R~).  In-place safe.
+// Accelerated GAP (yacc non-null): the measurement is replaced by the
+// accumulated one, ya = yacc + (y - Phi x), x_bar = x + Phi^T((ya - Phi x) / R~);
+// ya is written back when wacc != 0.
+__device__ __forceinline__ float gap_target(float yv, float phi, float* yacc, int p, int wacc) {
+  if (!yacc) return yv;
+  const float ya = yacc[p] + (yv - phi);
+  if (wacc) yacc[p] = ya;
+  return ya;
+}
+
 __global__ void k_cacti_gap(const float* x, const float* __restrict__ y,
-                            const uint8_t* __restrict__ m, float* xo, int F, int HW) {
+                            const uint8_t* __restrict__ m, float* xo, int F, int HW, float* yacc,
+                            int wacc) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= HW) return;
   float phi = 0.f;
@@ -58,7 +69,8 @@ __global__ void k_cacti_gap(const float* x, const float* __restrict__ y,
       phi += x[(size_t)t * HW + p];
       ++R;
     }
-  float upd = (y[p] - phi) / (float)(R ? R : 1);
+  const float yt = gap_target(y[p], phi, yacc, p, wacc);
+  float upd = (yt - phi) / (float)(R ? R : 1);
   for (int t = 0; t < F; ++t) {
     size_t i = (size_t)t * HW + p;
     xo[i] = x[i] + (m[i] ? upd : 0.f);
@@ -94,15 +106,17 @@ __global__ void k_msfa_init(const float* __restrict__ y, float* __restrict__ x, 
 }
 
 // GAP with Phi Phi^T = I: only the measured band of each pixel moves.
-__global__ void k_msfa_gap(const float* x, const float* __restrict__ y, float* xo, int H, int W) {
+__global__ void k_msfa_gap(const float* x, const float* __restrict__ y, float* xo, int H, int W,
+                           float* yacc, int wacc) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= H * W) return;
   int r = p / W, c = p - r * W;
   int b = msfa_band(r, c);
+  const float yt = gap_target(y[p], x[(size_t)b * H * W + p], yacc, p, wacc);
   for (int k = 0; k < 16; ++k) {
     size_t i = (size_t)k * H * W + p;
     float v = x[i];
-    xo[i] = (k == b) ? v + (y[p] - v) : v;
+    xo[i] = (k == b) ? v + (yt - v) : v;
   }
 }
 
@@ -272,8 +286,9 @@ void launch_cacti_init(const float* y, const uint8_t* m, float* x, int F, int HW
   hipLaunchKernelGGL(k_cacti_init, dim3(nblk(HW)), dim3(TPB), 0, s, y, m, x, F, HW);
 }
 void launch_cacti_gap(const float* x, const float* y, const uint8_t* m, float* xo, int F, int HW,
-                      hipStream_t s) {
-  hipLaunchKernelGGL(k_cacti_gap, dim3(nblk(HW)), dim3(TPB), 0, s, x, y, m, xo, F, HW);
+                      float* yacc, int wacc, hipStream_t s) {
+  hipLaunchKernelGGL(k_cacti_gap, dim3(nblk(HW)), dim3(TPB), 0, s, x, y, m, xo, F, HW, yacc,
+                     wacc);
 }
 void launch_msfa_forward(const float* x, float* y, int H, int W, hipStream_t s) {
   hipLaunchKernelGGL(k_msfa_forward, dim3(nblk((size_t)H * W)), dim3(TPB), 0, s, x, y, H, W);
@@ -284,8 +299,10 @@ void launch_msfa_adjoint(const float* y, float* x, int H, int W, hipStream_t s) 
 void launch_msfa_init(const float* y, float* x, int H, int W, hipStream_t s) {
   hipLaunchKernelGGL(k_msfa_init, dim3(nblk((size_t)H * W)), dim3(TPB), 0, s, y, x, H, W);
 }
-void launch_msfa_gap(const float* x, const float* y, float* xo, int H, int W, hipStream_t s) {
-  hipLaunchKernelGGL(k_msfa_gap, dim3(nblk((size_t)H * W)), dim3(TPB), 0, s, x, y, xo, H, W);
+void launch_msfa_gap(const float* x, const float* y, float* xo, int H, int W, float* yacc,
+                     int wacc, hipStream_t s) {
+  hipLaunchKernelGGL(k_msfa_gap, dim3(nblk((size_t)H * W)), dim3(TPB), 0, s, x, y, xo, H, W, yacc,
+                     wacc);
 }
 
 // Orthonormal 2-D DFT: rows then columns, each scaled by 1/sqrt(length).

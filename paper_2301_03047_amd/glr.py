@@ -12,7 +12,7 @@ import os
 import numpy as np
 
 CACTI, MRI, MSFA = 0, 1, 2
-SOLVER_GAP, SOLVER_ADMM = 0, 1
+SOLVER_GAP, SOLVER_ADMM, SOLVER_GAP_ACC = 0, 1, 2
 PREC = {"fp32": 0, "bf16": 1}
 STATUS_NAMES = {0: "GLR_OK", 1: "GLR_ERR_INVALID_ARG", 2: "GLR_ERR_SHAPE",
                 3: "GLR_ERR_ALIGNMENT", 4: "GLR_ERR_UNSUPPORTED",
@@ -143,7 +143,7 @@ class Plan:
                  rho=1.0, wnnm_c=None, wnnm_eps=None, precision="fp32", dist_chunk_mb=8192,
                  timing=False, device="cuda", allocate=True, cnn=None, surrogate_frac=0.6,
                  judge_stride=8, judge_delta_max=0.02, exemplars="corner", uniform_step=4,
-                 search="global", window=20):
+                 search="global", window=20, gap_acc=False):
         import torch
         L = lib()
         self.modality = _MODALITY[modality] if isinstance(modality, str) else int(modality)
@@ -157,7 +157,8 @@ class Plan:
         par = Params()
         L.glr_params_default(ctypes.byref(par))
         par.patch, par.n_keys, par.k, par.iters = self.patch, self.n_keys, self.k, self.iters
-        par.solver = SOLVER_ADMM if self.modality == MRI else SOLVER_GAP
+        par.solver = SOLVER_ADMM if self.modality == MRI else (
+            SOLVER_GAP_ACC if gap_acc else SOLVER_GAP)
         par.rho = float(rho)
         if wnnm_c is not None:
             par.wnnm_c = float(wnnm_c)
@@ -203,7 +204,8 @@ class Plan:
         import synth
         args = dict(iters=wl.iters, sigma=synth.sigma_schedule(wl), mask=mask,
                     precision=wl.precision, exemplars=wl.exemplars,
-                    uniform_step=wl.uniform_step, search=wl.search, window=wl.window)
+                    uniform_step=wl.uniform_step, search=wl.search, window=wl.window,
+                    gap_acc=wl.gap_acc)
         args.update(kw)
         return cls(wl.modality, wl.H, wl.W, wl.C, wl.patch, wl.n_keys, wl.k, **args)
 

@@ -215,3 +215,48 @@ def test_reconstruct_mri_per_iteration_parity_and_resume():
     a, st = plan.reconstruct(yg, 0, 2)
     b, _ = plan.reconstruct(yg, 2, wl.iters, state=st)
     np.testing.assert_array_equal(host(b), out)
+
+
+@pytest.mark.parametrize("modality", ["cacti", "msfa"])
+def test_accelerated_gap_loop_vs_oracle(modality):
+    # accelerated GAP: every pre-prior iterate against the oracle's step on
+    # the GPU's own state, and a three-iteration loop against the oracle's
+    require_gpu()
+    if modality == "cacti":
+        wl = small(synth.WORKLOADS["cacti_128"], H=48, W=56, n_keys=24, k=16, iters=3,
+                   gap_acc=True)
+        x_true = synth.cacti_video(wl.C, wl.H, wl.W, 7)
+        m = synth.cacti_masks(wl.C, wl.H, wl.W, 8)
+        fwd = lambda v: ops.cacti_forward(v, m)
+        adj = lambda r: ops.cacti_adjoint(r, m)
+        R = ops.cacti_mask_sum(m)
+        mask = gpu(m)
+    else:
+        wl = small(synth.WORKLOADS["msfa_512"], H=48, W=48, n_keys=24, k=16, iters=3,
+                   gap_acc=True)
+        x_true = synth.msfa_cube(wl.C, wl.H, wl.W, 9)
+        m = None
+        fwd = ops.msfa_forward
+        adj = lambda r: ops.msfa_adjoint(r, wl.C)
+        R = np.ones((wl.H, wl.W))
+        mask = None
+    plan = glr.Plan.for_workload(wl, mask=mask)
+    y = plan.forward(gpu(x_true))
+    y64 = host(y).astype(np.float64)
+    state = plan.new_state()
+    plan.reconstruct(y, 0, 0, state=state)
+    n = wl.C * wl.H * wl.W
+    for t in range(wl.iters):
+        st = host(state)
+        x = st[: 4 * n].view(np.float32).reshape(wl.C, wl.H, wl.W).astype(np.float64)
+        ya = st[4 * n: 4 * n + 4 * wl.H * wl.W].view(np.float32).reshape(wl.H, wl.W)
+        xb_ref, _ = ops.gap_acc_update(x, y64, ya.astype(np.float64), fwd, adj, R)
+        xb = host(plan.pre_prior(y, state))
+        assert np.abs(xb - xb_ref).max() <= 1e-5, (modality, t)
+        plan.reconstruct(y, t, t + 1, state=state)
+    out, _ = plan.reconstruct(y, 0, wl.iters)
+    ref = orc.reconstruct(small(wl, wnnm_c=WNNM_C), y64, m,
+                          synth.sigma_schedule(wl).astype(np.float64))
+    err = metrics.rel_l2(host(out), ref)
+    print(modality, "accelerated GAP loop rel-L2", err, flush=True)
+    assert err <= 1e-3

@@ -134,3 +134,39 @@ def test_admm_x_update_solves_its_subproblem():
     M = ops.mri_mask2d(m, W)
     grad = ops.ifft2c(M * (M * ops.fft2c(x) - y)) + rho * (x - (z - u))
     assert np.abs(grad).max() < 1e-12
+
+
+def test_accelerated_gap_makes_a_linear_shrink_consistent():
+    # with the prior x -> x / 2 the accelerated iteration's fixed point has
+    # Phi x = y (the accumulated residual undoes the shrink); plain GAP keeps
+    # a residual of the order of the shrink
+    import synth
+    F, H, W = 4, 12, 10
+    m = synth.cacti_masks(F, H, W, 3)
+    rng = np.random.default_rng(4)
+    y = ops.cacti_forward(rng.uniform(size=(F, H, W)), m)
+    R = ops.cacti_mask_sum(m)
+    fwd = lambda v: ops.cacti_forward(v, m)
+    adj = lambda r: ops.cacti_adjoint(r, m)
+    x = ops.cacti_adjoint(y / np.where(R == 0, 1.0, R), m)
+    xa, ya = x.copy(), y.copy()
+    for _ in range(400):
+        xb, ya = ops.gap_acc_update(xa, y, ya, fwd, adj, R)
+        xa = 0.5 * xb
+        x = 0.5 * ops.gap_update(x, y, fwd, adj, R)
+    ok = R > 0
+    assert np.abs(fwd(xa) - y)[ok].max() <= 1e-9 * np.abs(y).max()
+    assert np.abs(fwd(x) - y)[ok].max() >= 0.1 * np.abs(y)[ok].min()
+
+
+def test_accelerated_gap_step_by_hand():
+    # one pixel, two frames, both masks open: Phi x = x0 + x1, R = 2
+    m = np.ones((2, 1, 1), np.uint8)
+    x = np.array([[[0.25]], [[0.5]]])
+    y = np.array([[1.5]])
+    y_acc = np.array([[1.5]])
+    xb, ya = ops.gap_acc_update(x, y, y_acc, lambda v: ops.cacti_forward(v, m),
+                                lambda r: ops.cacti_adjoint(r, m), ops.cacti_mask_sum(m))
+    # y_acc' = 1.5 + (1.5 - 0.75) = 2.25; update (2.25 - 0.75) / 2 = 0.75 per frame
+    assert ya[0, 0] == 2.25
+    np.testing.assert_array_equal(xb[:, 0, 0], [1.0, 1.25])
