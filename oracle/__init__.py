@@ -10,7 +10,7 @@ docstring; where the paper is silent the reading taken is stated there too.
 Arithmetic is NumPy FP64 unless a step fixes another precision (the detector
 quantiser works in IEEE FP32, emulated exactly with ``np.float32``).
 """
-from . import operators, detector, matching, lowrank, aggregate, prior, reconstruct, metrics
+from . import operators, detector, matching, lowrank, aggregate, prior, reconstruct, metrics, edges
 
 __all__ = ["operators", "detector", "matching", "lowrank", "aggregate", "prior",
-           "reconstruct", "metrics"]
+           "reconstruct", "metrics", "edges"]

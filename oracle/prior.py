@@ -10,17 +10,22 @@ from .aggregate import aggregate
 
 
 def prior_step(x, patch, n_keys, K, sigma, c, eps, is_complex=False, keys=None,
-               exemplars="corner", step=4, search="global", radius=20):
+               exemplars="corner", step=4, search="global", radius=20, score="l2"):
     """Apply the prior to iterate ``x`` (planar real ``[C'][H][W]``; complex
     data as ``[2][H][W]`` = (Re, Im)).  ``keys`` may be supplied to bypass the
     detector.  ``exemplars`` ("corner", "uniform", "corner_uniform", with the
     uniform interval ``step``) and ``search`` ("global", or "window" of half
-    width ``radius``: the block-matching baselines) select the variant.
+    width ``radius``: the block-matching baselines) select the variant;
+    ``score`` "edge" groups by the edge-map heat map of eq. 6-8 instead of
+    the squared distance (``dist`` then holds the heat values).
     Returns a dict with keys, idx, dist, Xhat, sv, x_out."""
     x = np.asarray(x, dtype=np.float64)
     if keys is None:
         keys = exemplar_keys(x, patch, n_keys, exemplars, step, is_complex=is_complex)
-    if search == "global":
+    if score == "edge":
+        from .edges import topk_edge
+        idx, dist = topk_edge(x, patch, keys, K, is_complex=is_complex)
+    elif search == "global":
         idx, dist = topk_exact(x, patch, keys, K)
     elif search == "window":
         idx, dist = window_topk(x, patch, keys, K, radius)

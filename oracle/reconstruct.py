@@ -21,7 +21,8 @@ def _prior(xp, wl, sigma, is_complex):
                       exemplars=getattr(wl, "exemplars", "corner"),
                       step=getattr(wl, "uniform_step", 4),
                       search=getattr(wl, "search", "global"),
-                      radius=getattr(wl, "window", 20))["x_out"]
+                      radius=getattr(wl, "window", 20),
+                      score=getattr(wl, "score", "l2"))["x_out"]
 
 
 def reconstruct(wl, y, mask, sigmas, iters=None, callback=None):
