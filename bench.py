@@ -295,6 +295,7 @@ def run_ablation(log):
         st = pt.read_stats(reset=True)
         T = wl.iters
         res[name] = {"keys": plan.n_keys, "exemplars": wl.exemplars, "search": wl.search,
+                     "score": wl.score,
                      "ms_per_iteration": round(ms / T, 3),
                      "match_ms_per_iteration": round((st["ms_norms"] + st["ms_match"] + st["ms_topk"]
                                                       + st["ms_select"]) / T, 3),

@@ -73,6 +73,12 @@ enum { GLR_EXEMPLAR_CORNER = 0, GLR_EXEMPLAR_UNIFORM = 1, GLR_EXEMPLAR_CORNER_UN
 /* Search region: global matching over the whole candidate grid (eq. 8), or
  * block matching in a local window around each key (eq. 1, vanilla BM). */
 enum { GLR_SEARCH_GLOBAL = 0, GLR_SEARCH_WINDOW = 1 };
+/* Matching score: the squared L2 distance of the patches (eq. 1, the reading
+ * the plan defaults to), or the paper's edge-map correlation (eq. 6-8): the
+ * heat value of key and candidate is the number of coinciding pixels of
+ * their binary rising/falling, horizontal/vertical Sobel edge patches
+ * (larger = more similar). */
+enum { GLR_SCORE_L2 = 0, GLR_SCORE_EDGE = 1 };
 
 /* Sensing problem (eq. 2-5). */
 typedef struct glr_problem {
@@ -133,6 +139,13 @@ typedef struct glr_params {
   int32_t uniform_step;   /* default 4                                           */
   int32_t search;         /* default GLR_SEARCH_GLOBAL                           */
   int32_t window;         /* default 20 (a 41 x 41 window)                        */
+  /* Matching score (default GLR_SCORE_L2).  GLR_SCORE_EDGE: edge maps per real
+   * channel of the quantised image (complex data: of the detection image),
+   * th = ceil(max |gradient| / 10); the heat values are exact integers (BF16
+   * MFMA on 0/1 operands), the group is the K largest, the lowest position
+   * winning ties, and glr_match_topk's dist holds the heat values.  Needs
+   * GLR_SEARCH_GLOBAL and 4 C'' P^2 <= 8192 (C'' = C' real, 1 complex). */
+  int32_t score;
 } glr_params;
 
 /* Counters of the last prior steps, read by glr_read_stats(). */

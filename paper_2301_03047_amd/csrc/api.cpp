@@ -152,6 +152,42 @@ glr_status match_stage(glr_plan* pl, const float* xp, const int32_t* keys, int32
   const bool bf = pl->precision == GLR_PREC_BF16_RESCORE;
   const BigMargin bm = {(int32_t*)(ws + pl->ws.bpos), (float*)(ws + pl->ws.bhi),
                         (float*)(ws + pl->ws.blo), pl->mcap};
+  if (pl->score == GLR_SCORE_EDGE) {
+    // the stacked binary maps are matched as an image of 4 Ce channels with
+    // the BF16 matcher in raw form (d = -2 H exactly), then grouped by the
+    // exact integer top-K of the heat values
+    float* E = (float*)(ws + pl->ws.E);
+    const int Cp0 = pl->Cp, D0 = pl->D;
+    const int De = 4 * pl->Ce * pl->P * pl->P;
+    auto as_maps = [&](bool on) {
+      pl->Cp = on ? 4 * pl->Ce : Cp0;
+      pl->D = on ? De : D0;
+    };
+    {
+      StageTimer t(pl, s, T_NORMS);
+      launch_edges(pl, xp, ws, E, s);
+      as_maps(true);
+      launch_gather_keys(pl, E, keys, A, tsh, s);
+      launch_key_meta(pl, A, Ab, kmb, kre, 1, s);
+      launch_cand_meta(pl, E, cmeta, cm2, cre, 1, s);
+      as_maps(false);
+    }
+    for (int g0 = 0; g0 < pl->N; g0 += pl->n_chunk) {
+      const int nk = std::min(pl->n_chunk, pl->N - g0);
+      {
+        StageTimer t(pl, s, T_MATCH);
+        as_maps(true);
+        launch_match_bf16(pl, E, Ab, kmb, cmeta, g0, nk, dist, s);
+        as_maps(false);
+        if (pl->timing) pl->match_launches++;
+      }
+      {
+        StageTimer t(pl, s, T_TOPK);
+        launch_topk_heat(pl, dist, g0, nk, De, idx_out, dd_out, s);
+      }
+    }
+    return check_hip("glr_match_topk");
+  }
   if (pl->search == GLR_SEARCH_WINDOW) {
     {
       StageTimer t(pl, s, T_NORMS);
@@ -165,8 +201,8 @@ glr_status match_stage(glr_plan* pl, const float* xp, const int32_t* keys, int32
     StageTimer t(pl, s, T_NORMS);
     launch_gather_keys(pl, xp, keys, A, tsh, s);
     if (bf) {
-      launch_key_meta(pl, A, Ab, kmb, kre, s);
-      launch_cand_meta(pl, xp, cmeta, cm2, cre, s);
+      launch_key_meta(pl, A, Ab, kmb, kre, 0, s);
+      launch_cand_meta(pl, xp, cmeta, cm2, cre, 0, s);
     } else {
       launch_key_meta_pc(pl, A, Ac, kn, kc, s);
       launch_cand_meta_pc(pl, xp, pn, pc, pq, s);
@@ -426,6 +462,7 @@ void glr_params_default(glr_params* p) {
   p->uniform_step = 4;
   p->search = GLR_SEARCH_GLOBAL;
   p->window = 20;
+  p->score = GLR_SCORE_L2;
 }
 
 glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_params* pr,
@@ -454,6 +491,15 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
     return fail(GLR_ERR_INVALID_ARG, "unknown exemplar selection %d", pr->exemplars);
   if (pr->search != GLR_SEARCH_GLOBAL && pr->search != GLR_SEARCH_WINDOW)
     return fail(GLR_ERR_INVALID_ARG, "unknown search %d", pr->search);
+  if (pr->score != GLR_SCORE_L2 && pr->score != GLR_SCORE_EDGE)
+    return fail(GLR_ERR_INVALID_ARG, "unknown score %d", pr->score);
+  const int Ce = pb->modality == GLR_MRI ? 1 : Cp;
+  if (pr->score == GLR_SCORE_EDGE) {
+    if (pr->search != GLR_SEARCH_GLOBAL)
+      return fail(GLR_ERR_UNSUPPORTED, "the edge-map score needs global search");
+    if (4LL * Ce * P * P > 8192)
+      return fail(GLR_ERR_UNSUPPORTED, "edge patch length 4*%d*%d^2 above 8192", Ce, P);
+  }
   const bool corners = pr->exemplars != GLR_EXEMPLAR_UNIFORM;
   if (corners && (pr->n_keys < 1 || pr->n_keys > Ncand))
     return fail(GLR_ERR_SHAPE, "n_keys=%d must be in [1, N_cand=%lld]", pr->n_keys, Ncand);
@@ -527,6 +573,8 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
   pl->uniform_step = pr->uniform_step;
   pl->search = pr->search;
   pl->window = pr->window;
+  pl->score = pr->score;
+  pl->Ce = Ce;
   pl->K = pr->k;
   pl->T = pr->iters;
   pl->solver = pr->solver;
@@ -583,20 +631,27 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
   L.slist = c.take((size_t)Ncand * 4);
   L.sval = c.take((size_t)Ncand * 8);
   L.keys = c.take((size_t)pl->N * 4);
-  L.A = c.take((size_t)pl->N * D * 4);
-  const bool bf = pr->precision == GLR_PREC_BF16_RESCORE;
+  const bool edge = pr->score == GLR_SCORE_EDGE;
+  const int De = 4 * Ce * P * P;                 // edge patch length
+  L.A = c.take((size_t)pl->N * (edge ? std::max(D, De) : D) * 4);
+  // the BF16 buffers serve the BF16 form and the edge score alike
+  const bool bf = pr->precision == GLR_PREC_BF16_RESCORE || edge;
   L.kmb = c.take(bf ? (size_t)pl->N * 16 : 0);
   L.cmeta = c.take(bf ? (size_t)Ncand * 16 : 0);
   L.cm2 = c.take(bf ? (size_t)Ncand * 8 : 0);
   L.kre = c.take(bf ? (size_t)pl->N * 4 : 0);
   L.cre = c.take(bf ? (size_t)Ncand * 4 : 0);
+  L.E = c.take(edge ? (size_t)4 * Ce * HW * 4 : 0);
+  L.eq = c.take(edge ? (size_t)Ce * HW : 0);
+  L.egx = c.take(edge ? (size_t)2 * Ce * HW * 2 : 0);
+  L.emax = c.take(edge ? 4 : 0);
   L.Ac = c.take((size_t)pl->N * D * 4);
   L.kn = c.take((size_t)pl->N * 16);
   L.kc = c.take((size_t)pl->N * Cp * 4);
   L.pn = c.take((size_t)Ncand * 4);
   L.pc = c.take((size_t)Cp * Ncand * 8);
   L.pq = c.take((size_t)Ncand * 8);
-  L.Ab = c.take(bf ? (size_t)pl->N * Cp * bf16_key_row(P) * 2 : 0);
+  L.Ab = c.take(bf ? (size_t)pl->N * (edge ? std::max(Cp, 4 * Ce) : Cp) * bf16_key_row(P) * 2 : 0);
   L.tsh = c.take((size_t)pl->n_chunk * 4);
   L.tkey = c.take((size_t)pl->n_chunk * 4);
   L.klist = c.take(bf ? (size_t)pl->N * 4 : 0);

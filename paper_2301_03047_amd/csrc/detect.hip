@@ -383,6 +383,65 @@ __global__ void __launch_bounds__(SEL_T) k_select(uint8_t* __restrict__ flag,
 
 }  // namespace
 
+// ---------------------------------------------------------------- edge maps
+// The paper's matching score (eq. 6-8) correlates binary edge maps.  Reading:
+// per real channel, the quantised channel image q_c = clamp(rint(255 x_c))
+// (complex data: the detector's single quantised squared-magnitude image),
+// the detector's integer Sobel (replicate borders), and rising and falling
+// edges thresholded at th = ceil(max |g| / 10) over the whole stack:
+// E[4c + 0] = [gx > th], E[4c + 1] = [-gx > th], E[4c + 2] = [gy > th],
+// E[4c + 3] = [-gy > th] (gx along columns, gy along rows).
+
+// per-channel quantisation q[p] = clamp(rint(255 x[p]), 0, 255) of n values
+__global__ void k_quant_chan(const float* __restrict__ x, size_t n, uint8_t* __restrict__ q) {
+  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  float v = rintf(255.0f * x[p]);
+  q[p] = (uint8_t)fminf(fmaxf(v, 0.0f), 255.0f);
+}
+
+// Sobel of every channel image of q [Ce][H][W]: gx, gy (|g| <= 1020) and the
+// largest |g| of the stack (one atomic per block; *gmax cleared before)
+__global__ void k_edge_grad(const uint8_t* __restrict__ q, int Ce, int H, int W,
+                            int16_t* __restrict__ gxo, int16_t* __restrict__ gyo,
+                            uint32_t* __restrict__ gmax) {
+  __shared__ uint32_t red[TPB / 64];
+  const size_t HW = (size_t)H * W;
+  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t m = 0;
+  if (p < HW * Ce) {
+    const int ch = (int)(p / HW);
+    const int pix = (int)(p - (size_t)ch * HW);
+    const int r = pix / W, c = pix - r * W;
+    const int rm = clampi(r - 1, 0, H - 1), rp = clampi(r + 1, 0, H - 1);
+    const int cm = clampi(c - 1, 0, W - 1), cp = clampi(c + 1, 0, W - 1);
+    const uint8_t* qc = q + (size_t)ch * HW;
+    auto Q = [&](int rr, int cc) { return (int)qc[rr * W + cc]; };
+    const int gx = (Q(rm, cp) + 2 * Q(r, cp) + Q(rp, cp)) - (Q(rm, cm) + 2 * Q(r, cm) + Q(rp, cm));
+    const int gy = (Q(rp, cm) + 2 * Q(rp, c) + Q(rp, cp)) - (Q(rm, cm) + 2 * Q(rm, c) + Q(rm, cp));
+    gxo[p] = (int16_t)gx;
+    gyo[p] = (int16_t)gy;
+    m = (uint32_t)max(abs(gx), abs(gy));
+  }
+  m = block_max_u32(m, red);
+  if (threadIdx.x == 0 && m > 0) atomicMax(gmax, m);
+}
+
+__global__ void k_edge_maps(const int16_t* __restrict__ gx, const int16_t* __restrict__ gy,
+                            int Ce, size_t HW, const uint32_t* __restrict__ gmax,
+                            float* __restrict__ E) {
+  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= HW * Ce) return;
+  const int th = (int)((gmax[0] + 9u) / 10u);
+  const size_t ch = p / HW, pix = p - ch * HW;
+  const int x = gx[p], y = gy[p];
+  float* e = E + 4 * ch * HW + pix;
+  e[0] = x > th ? 1.f : 0.f;
+  e[HW] = -x > th ? 1.f : 0.f;
+  e[2 * HW] = y > th ? 1.f : 0.f;
+  e[3 * HW] = -y > th ? 1.f : 0.f;
+}
+
 // keys[i] = (step (i / nc)) Wc + step (i % nc), nc = ceil(Wc / step): the
 // uniform exemplar grid, ascending
 __global__ void k_uniform_keys(int32_t* __restrict__ keys, int n, int Wc, int step, int nc) {
@@ -390,6 +449,27 @@ __global__ void k_uniform_keys(int32_t* __restrict__ keys, int n, int Wc, int st
   if (i >= n) return;
   const int a = i / nc, b = i - a * nc;
   keys[i] = a * step * Wc + b * step;
+}
+
+void launch_edges(const glr_plan* pl, const float* xp, char* ws, float* E, hipStream_t s) {
+  const int H = pl->H, W = pl->W;
+  const size_t HW = (size_t)H * W;
+  const int Ce = pl->is_complex ? 1 : pl->Cp;
+  uint8_t* q = (uint8_t*)(ws + pl->ws.eq);
+  int16_t* gx = (int16_t*)(ws + pl->ws.egx);
+  int16_t* gy = gx + (size_t)Ce * HW;
+  uint32_t* gmax = (uint32_t*)(ws + pl->ws.emax);
+  launch_fill_u32(gmax, 0u, 1, s);
+  if (pl->is_complex) {
+    uint32_t* part = (uint32_t*)(ws + pl->ws.red);
+    const int nb = std::min(nblk(HW), MAXB);
+    hipLaunchKernelGGL(k_mag2_max, dim3(nb), dim3(TPB), 0, s, xp, (int)HW, part);
+    hipLaunchKernelGGL(k_quant_cplx, dim3(nblk(HW)), dim3(TPB), 0, s, xp, (int)HW, part, nb, q);
+  } else {
+    hipLaunchKernelGGL(k_quant_chan, dim3(nblk(HW * Ce)), dim3(TPB), 0, s, xp, HW * Ce, q);
+  }
+  hipLaunchKernelGGL(k_edge_grad, dim3(nblk(HW * Ce)), dim3(TPB), 0, s, q, Ce, H, W, gx, gy, gmax);
+  hipLaunchKernelGGL(k_edge_maps, dim3(nblk(HW * Ce)), dim3(TPB), 0, s, gx, gy, Ce, HW, gmax, E);
 }
 
 void launch_uniform_keys(const glr_plan* pl, int32_t* keys, int step, hipStream_t s) {

@@ -33,6 +33,7 @@ struct WsLayout {
   size_t A;                      // key matrix [N][D] f32
   size_t kmb, cmeta, cm2;        // BF16 form: centred key / candidate metadata (one mean)
   size_t kre, cre;               // BF16 form: key / candidate BF16 rounding residual norms
+  size_t E, eq, egx, emax;       // edge-map score: maps, quantised channels, gradients, max
   size_t Ac, kn, kc, pn, pc, pq; // FP32 form: channel-centred keys and metadata
   size_t Ab;                     // BF16 form: centred keys in the BF16 slice layout
   size_t tsh;                    // per-key shared threshold bound [n_chunk]
@@ -57,6 +58,8 @@ struct glr_plan {
   int P, N, K, T, solver, precision, timing;
   int n_corner;                   // corner exemplars (N counts the uniform grid too)
   int exemplars, uniform_step, search, window;
+  int score;                      // GLR_SCORE_L2 | GLR_SCORE_EDGE
+  int Ce;                         // edge-map channels per real channel group (score EDGE)
   float rho, wnnm_c, wnnm_eps;
   std::vector<float> sigma;
   // derived sizes
@@ -131,6 +134,9 @@ void launch_from_planar(const float* p, float2* z, int n, hipStream_t s);
 // the n_sel best corner keys (n_sel <= N_cand)
 void launch_detect(const glr_plan* pl, const float* xp, char* ws, int32_t* keys, int n_sel,
                    hipStream_t s);
+// binary edge maps E [4 Ce][H][W] (0/1 floats) of the matching score of
+// eq. 6-8, Ce = C' for real data, 1 for complex data
+void launch_edges(const glr_plan* pl, const float* xp, char* ws, float* E, hipStream_t s);
 // the uniform exemplar grid of interval step (ceil(Hc/step) ceil(Wc/step) keys)
 void launch_uniform_keys(const glr_plan* pl, int32_t* keys, int step, hipStream_t s);
 
@@ -140,13 +146,14 @@ void launch_gather_keys(const glr_plan* pl, const float* xp, const int32_t* keys
                         uint32_t* tsh, hipStream_t s);
 int bf16_key_row(int P);     // bf16 values per key and channel in the BF16 key layout
 // kmb[N] float4 (||a||^2, mu_k, sum a, ||a||), kre[N] ||a - bf16(a)||; Ab
-// (BF16 key slices) may be null
+// (BF16 key slices) may be null.  raw != 0: no centring and zero norm terms
+// (the BF16 matcher then returns -2 <k, p>: the edge-map score)
 void launch_key_meta(const glr_plan* pl, const float* A, uint16_t* Ab, float* kmb, float* kre,
-                     hipStream_t s);
+                     int raw, hipStream_t s);
 // cmeta[Ncand] float4 (mu, ||pbar||^2, ||pbar||, sum pbar); cm2[Ncand] float2
-// (mu, ||pbar||); cre[Ncand] ||pbar - bf16(pbar)||
+// (mu, ||pbar||); cre[Ncand] ||pbar - bf16(pbar)||; raw as above
 void launch_cand_meta(const glr_plan* pl, const float* xp, float* cmeta, float* cm2, float* cre,
-                      hipStream_t s);
+                      int raw, hipStream_t s);
 // FP32 form, channel-centred: Ac[N][D] (a~), kn[N] float4 (||a~||^2, h_k, 0, ||a~||),
 // kc[N][Cp] (fl(P mu_kc)); pn[Ncand] (||p~||^2), pc[Cp][Ncand] float2
 // (mu_pc, fl(P mu_pc)), pq[Ncand] float2 (h_p, ||p~||)
@@ -202,6 +209,10 @@ void launch_select_rescore(const glr_plan* pl, const float* xp, const float* A,
                            float* tkey, DevStats* st, hipStream_t s);
 void launch_collect_flags(const int32_t* oflag, int g0, int nk, int32_t* klist, int32_t* kcount,
                           DevStats* st, hipStream_t s);
+// groups of the edge heat map from a chunk of d = -2 H (H <= hmax <= 8192):
+// the K largest H per key, lowest position first among ties
+void launch_topk_heat(const glr_plan* pl, const float* dist, int g0, int nk, int hmax,
+                      int32_t* idx, float* dd, hipStream_t s);
 // block matching in a (2 window + 1)^2 window around each key: exact groups
 // (compensated distances, (distance, position) order) for keys[0..N)
 void launch_window_topk(const glr_plan* pl, const float* xp, const float* A, const int32_t* keys,

@@ -636,9 +636,12 @@ __device__ __forceinline__ float bf16_val(float f) { return __uint_as_float(bf16
 // operand's rounding residual, for the error bound); with Ab, also
 // Ab[g][c][t][0..8) = bf16(a) in the BF16 slice layout (padding zero).  One
 // wave per key.
+// raw != 0 (the edge-map score): no centring (mu = 0) and kmb = (0, 0, 0,
+// ||k||), so the BF16 matcher's epilogue returns -2 <k, p> exactly for 0/1
+// vectors.
 __global__ void k_key_meta(const float* __restrict__ A, int D, int P, int Cp, int NS, int XS,
                            int N, uint16_t* __restrict__ Ab, float4* __restrict__ kmb,
-                           float* __restrict__ kre) {
+                           float* __restrict__ kre, int raw) {
   const int g = blockIdx.x;
   if (g >= N) return;
   const float* k = A + (size_t)g * D;
@@ -646,7 +649,7 @@ __global__ void k_key_meta(const float* __restrict__ A, int D, int P, int Cp, in
   float s = 0.f;
   for (int d = l; d < D; d += 64) s += k[d];
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-  const float mu = s / (float)D;
+  const float mu = raw ? 0.f : s / (float)D;
   float an = 0.f, sa = 0.f, en = 0.f;
   for (int d = l; d < D; d += 64) {
     const float a = k[d] - mu;
@@ -661,7 +664,7 @@ __global__ void k_key_meta(const float* __restrict__ A, int D, int P, int Cp, in
     en += __shfl_xor(en, o, 64);
   }
   if (l == 0) {
-    kmb[g] = make_float4(an, mu, sa, sqrtf(an));
+    kmb[g] = raw ? make_float4(0.f, 0.f, 0.f, sqrtf(an)) : make_float4(an, mu, sa, sqrtf(an));
     kre[g] = sqrtf(en);
   }
   if (!Ab) return;
@@ -681,7 +684,7 @@ __global__ void k_key_meta(const float* __restrict__ A, int D, int P, int Cp, in
 // of the top-K pass.
 __global__ void k_cand_meta(const float* __restrict__ xp, int Cp, int H, int W, int P,
                             float4* __restrict__ cmeta, float2* __restrict__ cm2,
-                            float* __restrict__ cre) {
+                            float* __restrict__ cre, int raw) {
   const int Wc = W - P + 1, Hc = H - P + 1;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= Hc * Wc) return;
@@ -693,7 +696,7 @@ __global__ void k_cand_meta(const float* __restrict__ xp, int Cp, int H, int W, 
       const float* row = xp + ((size_t)ch * H + r + dy) * W + c;
       for (int dx = 0; dx < P; ++dx) s += row[dx];
     }
-  const float mu = s / (float)D;
+  const float mu = raw ? 0.f : s / (float)D;
   float pn = 0.f, sp = 0.f, en = 0.f;
   for (int ch = 0; ch < Cp; ++ch)
     for (int dy = 0; dy < P; ++dy) {
@@ -707,7 +710,7 @@ __global__ void k_cand_meta(const float* __restrict__ xp, int Cp, int H, int W, 
       }
     }
   const float pr = sqrtf(pn);
-  cmeta[j] = make_float4(mu, pn, pr, sp);
+  cmeta[j] = raw ? make_float4(0.f, 0.f, pr, 0.f) : make_float4(mu, pn, pr, sp);
   cm2[j] = make_float2(mu, pr);
   cre[j] = sqrtf(en);
 }
@@ -911,17 +914,17 @@ void launch_gather_keys(const glr_plan* pl, const float* xp, const int32_t* keys
 int bf16_key_row(int P) { return bf16_slices(P) * 8; }
 
 void launch_key_meta(const glr_plan* pl, const float* A, uint16_t* Ab, float* kmb, float* kre,
-                     hipStream_t s) {
+                     int raw, hipStream_t s) {
   const int NS = bf16_slices(pl->P);
   hipLaunchKernelGGL(k_key_meta, dim3(pl->N), dim3(64), 0, s, A, pl->D, pl->P, pl->Cp, NS,
-                     NS > 8 ? 2 : 1, pl->N, Ab, (float4*)kmb, kre);
+                     NS > 8 ? 2 : 1, pl->N, Ab, (float4*)kmb, kre, raw);
 }
 
 void launch_cand_meta(const glr_plan* pl, const float* xp, float* cmeta, float* cm2, float* cre,
-                      hipStream_t s) {
+                      int raw, hipStream_t s) {
   const int n = pl->Ncand;
   hipLaunchKernelGGL(k_cand_meta, dim3((n + 255) / 256), dim3(256), 0, s, xp, pl->Cp, pl->H,
-                     pl->W, pl->P, (float4*)cmeta, (float2*)cm2, cre);
+                     pl->W, pl->P, (float4*)cmeta, (float2*)cm2, cre, raw);
 }
 
 void launch_key_meta_pc(const glr_plan* pl, const float* A, float* Ac, float* kn, float* kc,

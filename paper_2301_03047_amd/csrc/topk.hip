@@ -1077,6 +1077,102 @@ k_window_topk(const float* __restrict__ xp, int H, int W, int P, int D, int L,
   }
 }
 
+// Groups by the edge heat map (eq. 8; larger = more similar): the matcher
+// wrote d = -2 H for the chunk's keys, H an exact integer in [0, hmax].
+// One block per key: a histogram of H over the row (LDS), the threshold
+// value H* with at least K candidates at or above it, then every wave scans
+// its quarter of the row in order and keeps the candidates above H* and the
+// ties at H* whose rank in position order (the ties of the lower quarters
+// first) is below the number still needed; the K kept entries are sorted by
+// (H desc, position asc).  Integer values: no margin, no rescoring.
+constexpr int HEAT_BINS = 8193;
+__global__ void __launch_bounds__(ST)
+k_topk_heat(const float* __restrict__ dist, size_t ldd, int Ncand, int nk, int K, int hmax,
+            const int32_t* __restrict__ kmap, int g0, int32_t* __restrict__ idx,
+            float* __restrict__ dd) {
+  __shared__ int hist[HEAT_BINS];
+  __shared__ int seg[ST];
+  __shared__ int wties[ST / 64];
+  __shared__ int sth[2];
+  __shared__ int sh_h[64], sh_j[64];
+  __shared__ int scount;
+  const int g = blockIdx.x;
+  if (g >= nk) return;                       // block-uniform
+  const int tid = threadIdx.x, l = lane_id(), wave = tid >> 6;
+  const float* drow = dist + (size_t)g * ldd;
+  auto heat = [&](int j) { return min(max((int)(-0.5f * drow[j]), 0), hmax); };
+  for (int i = tid; i <= hmax; i += ST) hist[i] = 0;
+  if (tid == 0) scount = 0;
+  __syncthreads();
+  for (int j = tid; j < Ncand; j += ST) atomicAdd(&hist[heat(j)], 1);
+  __syncthreads();
+  const int B = (hmax + 1 + ST - 1) / ST;
+  {
+    int sum = 0;
+    for (int v = tid * B; v < min((tid + 1) * B, hmax + 1); ++v) sum += hist[v];
+    seg[tid] = sum;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int run = 0, t = ST - 1;
+    for (; t > 0 && run + seg[t] < K; --t) run += seg[t];
+    int v = min((t + 1) * B, hmax + 1) - 1;
+    for (; v > t * B && run + hist[v] < K; --v) run += hist[v];
+    sth[0] = v;                              // H*
+    sth[1] = K - run;                        // ties at H* still needed
+  }
+  __syncthreads();
+  const int hs = sth[0], need = sth[1];
+  // each wave: a contiguous quarter of the row, in position order
+  const int q4 = ((Ncand + 4 * 64 - 1) / (4 * 64)) * 64;
+  const int ja = wave * q4, jb = min(Ncand, ja + q4);
+  int nt = 0;
+  for (int b = ja; b < jb; b += 64) {
+    const int j = b + l;
+    nt += __popcll(__ballot(j < jb && heat(j) == hs));
+  }
+  if (l == 0) wties[wave] = nt;
+  __syncthreads();
+  int seen = 0;
+  for (int w = 0; w < wave; ++w) seen += wties[w];
+  for (int b = ja; b < jb; b += 64) {
+    const int j = b + l;
+    const int h = j < jb ? heat(j) : -1;
+    const uint64_t tie = __ballot(h == hs);
+    const bool take = h > hs || (h == hs && seen + lanes_below(tie) < need);
+    seen += __popcll(tie);
+    if (take) {
+      const int p = atomicAdd(&scount, 1);
+      if (p < 64) {
+        sh_h[p] = h;
+        sh_j[p] = j;
+      }
+    }
+  }
+  __syncthreads();
+  // K entries (the positions are distinct): sort by (H desc, j asc)
+  if (wave == 0) {
+    const int n = min(scount, 64);
+    int hh = l < n ? sh_h[l] : -1, jj = l < n ? sh_j[l] : 0x7fffffff;
+    for (int k = 2; k <= 64; k <<= 1)
+      for (int s2 = k >> 1; s2 > 0; s2 >>= 1) {
+        const int ho = __shfl_xor(hh, s2, 64), jo = __shfl_xor(jj, s2, 64);
+        const bool before = hh > ho || (hh == ho && jj < jo);   // this entry first
+        const bool up = (l & k) == 0, lower = (l & s2) == 0;
+        const bool keep = (lower == up) ? before : !before;
+        if (!keep) {
+          hh = ho;
+          jj = jo;
+        }
+      }
+    const int gg = kmap ? kmap[g0 + g] : g0 + g;
+    if (l < K) {
+      idx[(size_t)gg * K + l] = jj;
+      dd[(size_t)gg * K + l] = (float)hh;
+    }
+  }
+}
+
 }  // namespace
 
 // The bound coefficients of margin_eps for the plan's two forms, rounded up
@@ -1206,4 +1302,10 @@ void launch_window_topk(const glr_plan* pl, const float* xp, const float* A, con
   else
     hipLaunchKernelGGL(k_window_topk<64>, dim3(pl->N), dim3(ST), 0, s, xp, pl->H, pl->W, pl->P,
                        pl->D, L, A, keys, pl->N, pl->K, pl->window, idx, dd);
+}
+
+void launch_topk_heat(const glr_plan* pl, const float* dist, int g0, int nk, int hmax,
+                      int32_t* idx, float* dd, hipStream_t s) {
+  hipLaunchKernelGGL(k_topk_heat, dim3(nk), dim3(ST), 0, s, dist, (size_t)pl->ldd, pl->Ncand, nk,
+                     pl->K, hmax, nullptr, g0, idx, dd);
 }

@@ -39,6 +39,7 @@ class Workload:
     search: str = "global"
     window: int = 20
     gap_acc: bool = False  # accelerated GAP (measurement residual accumulated)
+    score: str = "l2"      # matching score: "l2" distance or the "edge"-map correlation
 
     @property
     def real_channels(self):
@@ -90,6 +91,7 @@ WORKLOADS = {
 
 ABLATION = {
     "gm_corner": dict(exemplars="corner", search="global"),
+    "gm_corner_edge": dict(exemplars="corner", search="global", score="edge"),
     "bm_uniform": dict(exemplars="uniform", search="window"),
     "bm_corner": dict(exemplars="corner", search="window"),
     "bm_corner_uniform": dict(exemplars="corner_uniform", search="window"),
