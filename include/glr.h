@@ -79,6 +79,7 @@ enum { GLR_SEARCH_GLOBAL = 0, GLR_SEARCH_WINDOW = 1 };
  * their binary rising/falling, horizontal/vertical Sobel edge patches
  * (larger = more similar). */
 enum { GLR_SCORE_L2 = 0, GLR_SCORE_EDGE = 1 };
+enum { GLR_AGG_UNIFORM = 0, GLR_AGG_RANK = 1 };
 
 /* Sensing problem (eq. 2-5). */
 typedef struct glr_problem {
@@ -146,6 +147,12 @@ typedef struct glr_params {
    * winning ties, and glr_match_topk's dist holds the heat values.  Needs
    * GLR_SEARCH_GLOBAL and 4 C'' P^2 <= 8192 (C'' = C' real, 1 complex). */
   int32_t score;
+  /* Aggregation weights (default GLR_AGG_UNIFORM: every member estimate
+   * weighs 1, a pixel is the mean of its covering estimates).  GLR_AGG_RANK:
+   * every estimate of group g weighs 1 / max(r_g, 1), r_g the number of
+   * singular values the WNNM shrinkage keeps non-zero, and a pixel is the
+   * weighted mean (a variant of the aggregation of the Method section). */
+  int32_t agg_weights;
 } glr_params;
 
 /* Counters of the last prior steps, read by glr_read_stats(). */

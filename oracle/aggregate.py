@@ -7,9 +7,11 @@ member covers keep the pre-prior value.
 import numpy as np
 
 
-def aggregate(xbar, patch, idx, Xhat):
+def aggregate(xbar, patch, idx, Xhat, weights=None):
     """x_out from x_bar ``[C][H][W]``, member positions ``idx [N][K]`` (top-left
-    grid indices) and estimates ``Xhat [N][K][D]``."""
+    grid indices) and estimates ``Xhat [N][K][D]``.  With ``weights`` ``[N]``
+    every estimate of group g weighs weights[g] and a pixel is the weighted
+    mean of its covering estimates (the per-group weighting variant)."""
     xbar = np.asarray(xbar, dtype=np.float64)
     C, H, W = xbar.shape
     P = patch
@@ -18,14 +20,17 @@ def aggregate(xbar, patch, idx, Xhat):
     cnt = np.zeros((H, W))
     flat_idx = np.asarray(idx).reshape(-1)
     est = np.asarray(Xhat, dtype=np.float64).reshape(flat_idx.shape[0], C, P, P)
+    K = np.asarray(idx).shape[1]
+    w = np.ones(flat_idx.shape[0]) if weights is None else np.repeat(
+        np.asarray(weights, dtype=np.float64), K)
     r0, c0 = np.divmod(flat_idx, Wc)
     for dy in range(P):
         for dx in range(P):
             rr = r0 + dy
             cc = c0 + dx
-            np.add.at(cnt, (rr, cc), 1.0)
+            np.add.at(cnt, (rr, cc), w)
             for ch in range(C):
-                np.add.at(num[ch], (rr, cc), est[:, ch, dy, dx])
+                np.add.at(num[ch], (rr, cc), w * est[:, ch, dy, dx])
     out = xbar.copy()
     m = cnt > 0
     out[:, m] = num[:, m] / cnt[m][None]

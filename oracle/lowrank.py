@@ -51,3 +51,12 @@ def shrink_groups(x, patch, idx, sigma, c, eps):
         out[g] = X.T
         sv[g] = s
     return out, sv
+
+
+def group_weights(sv, K, sigma, c, eps):
+    """Per-group aggregation weights (variant; reading: the inverse of the
+    shrunk group's rank, 1 / max(r, 1) with r the number of singular values
+    WNNM keeps non-zero, so groups the low-rank model describes with fewer
+    components weigh more).  ``sv`` ``[N][min(D, K)]``."""
+    r = np.sum(wnnm_weights(np.asarray(sv, dtype=np.float64), K, sigma, c, eps) > 0, axis=1)
+    return 1.0 / np.maximum(r, 1)

@@ -5,20 +5,23 @@ import numpy as np
 
 from .detector import exemplar_keys
 from .matching import topk_exact, window_topk
-from .lowrank import shrink_groups
+from .lowrank import shrink_groups, group_weights
 from .aggregate import aggregate
 
 
 def prior_step(x, patch, n_keys, K, sigma, c, eps, is_complex=False, keys=None,
-               exemplars="corner", step=4, search="global", radius=20, score="l2"):
+               exemplars="corner", step=4, search="global", radius=20, score="l2",
+               agg_weights="uniform"):
     """Apply the prior to iterate ``x`` (planar real ``[C'][H][W]``; complex
     data as ``[2][H][W]`` = (Re, Im)).  ``keys`` may be supplied to bypass the
     detector.  ``exemplars`` ("corner", "uniform", "corner_uniform", with the
     uniform interval ``step``) and ``search`` ("global", or "window" of half
     width ``radius``: the block-matching baselines) select the variant;
     ``score`` "edge" groups by the edge-map heat map of eq. 6-8 instead of
-    the squared distance (``dist`` then holds the heat values).
-    Returns a dict with keys, idx, dist, Xhat, sv, x_out."""
+    the squared distance (``dist`` then holds the heat values);
+    ``agg_weights`` "rank" weighs each group's estimates by 1 / (its kept
+    WNNM rank) in the aggregation (``weights`` then holds them).
+    Returns a dict with keys, idx, dist, Xhat, sv, weights, x_out, count."""
     x = np.asarray(x, dtype=np.float64)
     if keys is None:
         keys = exemplar_keys(x, patch, n_keys, exemplars, step, is_complex=is_complex)
@@ -32,9 +35,14 @@ def prior_step(x, patch, n_keys, K, sigma, c, eps, is_complex=False, keys=None,
     else:
         raise ValueError(search)
     Xhat, sv = shrink_groups(x, patch, idx, sigma, c, eps)
-    x_out, cnt = aggregate(x, patch, idx, Xhat)
+    wts = None
+    if agg_weights == "rank":
+        wts = group_weights(sv, K, sigma, c, eps)
+    elif agg_weights != "uniform":
+        raise ValueError(agg_weights)
+    x_out, cnt = aggregate(x, patch, idx, Xhat, weights=wts)
     return {"keys": keys, "idx": idx, "dist": dist, "Xhat": Xhat, "sv": sv,
-            "x_out": x_out, "count": cnt}
+            "weights": wts, "x_out": x_out, "count": cnt}
 
 
 def to_planar(z):

@@ -22,7 +22,8 @@ def _prior(xp, wl, sigma, is_complex):
                       step=getattr(wl, "uniform_step", 4),
                       search=getattr(wl, "search", "global"),
                       radius=getattr(wl, "window", 20),
-                      score=getattr(wl, "score", "l2"))["x_out"]
+                      score=getattr(wl, "score", "l2"),
+                      agg_weights=getattr(wl, "agg_weights", "uniform"))["x_out"]
 
 
 def reconstruct(wl, y, mask, sigmas, iters=None, callback=None):

@@ -153,15 +153,19 @@ constexpr int UB = 4;             // 16-byte staging loads in flight per thread
 // fixed order (dy, position, entry) ascending: the covering entries of a
 // pixel are one contiguous run of the staged list, whose column is kept per
 // entry.  Lanes run over the channels of a pixel, which all have the same
-// trip counts.
+// trip counts.  WG: entry e weighs gw[e / K] (its group's weight) and the
+// pixel is the weighted mean; otherwise every entry weighs 1.
+template <bool WG>
 __global__ void __launch_bounds__(GT)
 k_gather(const float* __restrict__ xbar, const float* __restrict__ xhat,
          const int32_t* __restrict__ ent, const int32_t* __restrict__ offs, int Cp, int H, int W,
-         int P, int D, float* __restrict__ out, int32_t* __restrict__ cover) {
+         int P, int D, const float* __restrict__ gw, int K, float* __restrict__ out,
+         int32_t* __restrict__ cover) {
   __shared__ __align__(16) float lds[LDS_FLOATS];
   __shared__ int spos[GX + 17];             // window bucket starts (P <= 16), + end
   __shared__ int sent[LDS_FLOATS / 4];      // entry ids of the staged chunk
   __shared__ int scol[LDS_FLOATS / 4];      // their top-left columns
+  __shared__ float swt[WG ? LDS_FLOATS / 4 : 1];   // their weights
   const int r = blockIdx.y;
   const int c0 = blockIdx.x * GX;
   const int cg0 = blockIdx.z * CG;
@@ -171,10 +175,12 @@ k_gather(const float* __restrict__ xbar, const float* __restrict__ xhat,
   const int npair = GX * ncg;
   constexpr int NPT = GX * CG / GT;         // pairs per thread (max)
   float acc[NPT];
+  float wsum[NPT];
   int cnt[NPT];
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     acc[k] = 0.f;
+    wsum[k] = 0.f;
     cnt[k] = 0;
   }
   const int rowlen = ncg * P;               // floats staged per entry
@@ -206,7 +212,11 @@ k_gather(const float* __restrict__ xbar, const float* __restrict__ xhat,
       const int ib = min(eb, ia + cap);
       const int nrow = ib - ia;
       __syncthreads();
-      for (int i = tid; i < nrow; i += GT) sent[i] = ent[ia + i];
+      for (int i = tid; i < nrow; i += GT) {
+        const int e = ent[ia + i];
+        sent[i] = e;
+        if (WG) swt[i] = gw[e / K];
+      }
       for (int k = tid; k < nwin; k += GT) {
         const int i0 = max(spos[k], ia), i1 = min(spos[k + 1], ib);
         for (int i = i0; i < i1; ++i) scol[i - ia] = tc0 + k;
@@ -262,8 +272,18 @@ k_gather(const float* __restrict__ xbar, const float* __restrict__ xhat,
           if (c < W && lo <= hi) {
             const int b0 = max(spos[lo - tc0], ia), b1 = min(spos[hi - tc0 + 1], ib);
             float a = acc[k];
-            for (int i = b0; i < b1; ++i)
-              a += lds[(i - ia) * rowlen + (c - scol[i - ia]) * ncg + ch];
+            if (WG) {
+              float ws = wsum[k];
+              for (int i = b0; i < b1; ++i) {
+                const float w = swt[i - ia];
+                a = fmaf(w, lds[(i - ia) * rowlen + (c - scol[i - ia]) * ncg + ch], a);
+                ws += w;
+              }
+              wsum[k] = ws;
+            } else {
+              for (int i = b0; i < b1; ++i)
+                a += lds[(i - ia) * rowlen + (c - scol[i - ia]) * ncg + ch];
+            }
             acc[k] = a;
           }
         }
@@ -281,7 +301,7 @@ k_gather(const float* __restrict__ xbar, const float* __restrict__ xhat,
         const int n = cnt[k];
         if (cover && cg0 == 0 && ch == 0) cover[(size_t)r * W + c] = n;
         const size_t o = (size_t)(cg0 + ch) * HW + (size_t)r * W + c;
-        out[o] = n ? acc[k] / (float)n : xbar[o];
+        out[o] = n ? acc[k] / (WG ? wsum[k] : (float)n) : xbar[o];
       }
     }
   }
@@ -290,8 +310,8 @@ k_gather(const float* __restrict__ xbar, const float* __restrict__ xhat,
 }  // namespace
 
 void launch_aggregate(const glr_plan* pl, const float* xbar, const int32_t* idx,
-                      const float* xhat, int32_t* sortbuf, int32_t* offs, float* out,
-                      int32_t* cover, hipStream_t s) {
+                      const float* xhat, const float* gw, int32_t* sortbuf, int32_t* offs,
+                      float* out, int32_t* cover, hipStream_t s) {
   const int M = pl->M, n = pl->Ncand + 1;
   int32_t* ent = sortbuf;                       // [M]
   int32_t* cnt = sortbuf + pl->M2;              // [Ncand + 1], later the scatter cursor
@@ -308,6 +328,10 @@ void launch_aggregate(const glr_plan* pl, const float* xbar, const int32_t* idx,
                      pl->Ncand, ent, big, nbig);
   hipLaunchKernelGGL(k_bucket_sort_large, dim3(256), dim3(1024), 0, s, offs, ent, big, nbig);
   dim3 grid((pl->W + GX - 1) / GX, pl->H, (pl->Cp + CG - 1) / CG);
-  hipLaunchKernelGGL(k_gather, grid, dim3(GT), 0, s, xbar, xhat, ent, offs, pl->Cp, pl->H, pl->W,
-                     pl->P, pl->D, out, cover);
+  if (gw)
+    hipLaunchKernelGGL(k_gather<true>, grid, dim3(GT), 0, s, xbar, xhat, ent, offs, pl->Cp, pl->H,
+                       pl->W, pl->P, pl->D, gw, pl->K, out, cover);
+  else
+    hipLaunchKernelGGL(k_gather<false>, grid, dim3(GT), 0, s, xbar, xhat, ent, offs, pl->Cp, pl->H,
+                       pl->W, pl->P, pl->D, gw, pl->K, out, cover);
 }

@@ -277,16 +277,17 @@ glr_status lowrank_stage(glr_plan* pl, const float* xp, const int32_t* idx, floa
                          bool count_step = false) {
   float* xhat = (float*)(ws + pl->ws.xhat);
   DevStats* st = (DevStats*)(ws + pl->ws.stats);
+  float* gw = pl->agg_weights == GLR_AGG_RANK ? (float*)(ws + pl->ws.gw) : nullptr;
   {
     StageTimer t(pl, s, T_LOWRANK);
     int zn = 0;
     int32_t* z = agg_zero_range(pl, (int32_t*)(ws + pl->ws.pairs), &zn);
     launch_wnnm(pl, xp, idx, sigma, xhat, sv, st, z, zn, count_step ? 1 : 0,
-                (float*)(ws + pl->ws.xi), s);
+                (float*)(ws + pl->ws.xi), gw, s);
   }
   {
     StageTimer t(pl, s, T_AGG);
-    launch_aggregate(pl, xp, idx, xhat, (int32_t*)(ws + pl->ws.pairs),
+    launch_aggregate(pl, xp, idx, xhat, gw, (int32_t*)(ws + pl->ws.pairs),
                      (int32_t*)(ws + pl->ws.offs), xo, cover, s);
   }
   return check_hip("glr_lowrank_aggregate");
@@ -463,6 +464,7 @@ void glr_params_default(glr_params* p) {
   p->search = GLR_SEARCH_GLOBAL;
   p->window = 20;
   p->score = GLR_SCORE_L2;
+  p->agg_weights = GLR_AGG_UNIFORM;
 }
 
 glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_params* pr,
@@ -493,6 +495,8 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
     return fail(GLR_ERR_INVALID_ARG, "unknown search %d", pr->search);
   if (pr->score != GLR_SCORE_L2 && pr->score != GLR_SCORE_EDGE)
     return fail(GLR_ERR_INVALID_ARG, "unknown score %d", pr->score);
+  if (pr->agg_weights != GLR_AGG_UNIFORM && pr->agg_weights != GLR_AGG_RANK)
+    return fail(GLR_ERR_INVALID_ARG, "unknown aggregation weights %d", pr->agg_weights);
   const int Ce = pb->modality == GLR_MRI ? 1 : Cp;
   if (pr->score == GLR_SCORE_EDGE) {
     if (pr->search != GLR_SEARCH_GLOBAL)
@@ -574,6 +578,7 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
   pl->search = pr->search;
   pl->window = pr->window;
   pl->score = pr->score;
+  pl->agg_weights = pr->agg_weights;
   pl->Ce = Ce;
   pl->K = pr->k;
   pl->T = pr->iters;
@@ -671,6 +676,7 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
   L.dd = c.take((size_t)pl->M * 4);
   L.xhat = c.take((size_t)pl->M * D * 4);
   L.sv = c.take((size_t)pl->M * 4);
+  L.gw = c.take(pr->agg_weights == GLR_AGG_RANK ? (size_t)pl->N * 4 : 0);
   L.pairs = c.take(agg_sort_ints(pl) * 4);
   L.offs = c.take(((size_t)Ncand + 1) * 4);
   L.cplx_a = c.take(pl->is_complex ? HW * 8 : 0);

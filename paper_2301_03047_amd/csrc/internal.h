@@ -45,6 +45,7 @@ struct WsLayout {
   size_t lj, lu, ll, lcnt, oflag; // partial top-K lists, per-key overflow flags
   size_t idx, dd;                // groups [N][K], distances [N][K]
   size_t xhat, sv;               // group estimates [N][D][K]; singular values
+  size_t gw;                     // per-group aggregation weights [N] (GLR_AGG_RANK)
   size_t pairs, offs;            // aggregation sort keys, CSR offsets
   size_t cplx_a, cplx_b;         // complex scratch (FFT / ADMM)
   size_t red;                    // small reduction scratch
@@ -59,6 +60,7 @@ struct glr_plan {
   int n_corner;                   // corner exemplars (N counts the uniform grid too)
   int exemplars, uniform_step, search, window;
   int score;                      // GLR_SCORE_L2 | GLR_SCORE_EDGE
+  int agg_weights;                // GLR_AGG_UNIFORM | GLR_AGG_RANK
   int Ce;                         // edge-map channels per real channel group (score EDGE)
   float rho, wnnm_c, wnnm_eps;
   std::vector<float> sigma;
@@ -223,15 +225,16 @@ void launch_window_topk(const glr_plan* pl, const float* xp, const float* A, con
 // xi: scratch [H][W][Cp] for the channel-interleaved copy of xp
 void launch_wnnm(const glr_plan* pl, const float* xp, const int32_t* idx, float sigma,
                  float* xhat, float* sv, DevStats* st, int32_t* zbuf, int zn, int bump,
-                 float* xi, hipStream_t s);
+                 float* xi, float* gw, hipStream_t s);
 
 // aggregate.hip
 // sortbuf: aggregation sort scratch (agg_sort_ints(pl) int32); offs [Ncand + 1];
 // cover (nullable): per-pixel count of covering estimates [H][W]
 // The counters at agg_zero_range(pl, sortbuf) must be zero on entry.
+// gw: per-group weights [N] (weighted mean), or null (plain mean)
 void launch_aggregate(const glr_plan* pl, const float* xbar, const int32_t* idx,
-                      const float* xhat, int32_t* sortbuf, int32_t* offs, float* out,
-                      int32_t* cover, hipStream_t s);
+                      const float* xhat, const float* gw, int32_t* sortbuf, int32_t* offs,
+                      float* out, int32_t* cover, hipStream_t s);
 // counts, block sums and queue length of the aggregation sort: one contiguous
 // range of sortbuf (returns its start; *n its length)
 inline int32_t* agg_zero_range(const glr_plan* pl, int32_t* sortbuf, int* n) {

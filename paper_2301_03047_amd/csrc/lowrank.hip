@@ -16,7 +16,8 @@
 //     without accumulating rotations;
 //  3. WNNM: sigma_hat = sqrt(max(s^2 - K sigma^2, 0)),
 //     tau = c sqrt(K) sigma^2 / (sigma_hat + eps), s' = max(s - tau, 0),
-//     w = (s - s') / s;
+//     w = (s - s') / s; for weighted aggregation the group's weight
+//     1 / max(r, 1), r the number of s' > 0;
 //  4. X = Y - Yc W, W = V diag(w) V^T: the residual sum_i (s_i - s'_i) u_i v_i^T
 //     accumulated in FP64 (sigma = 0 gives w = 0, W = 0, X = Y exactly).
 // Data and the SVD are FP32; only the angles and the residual use FP64.
@@ -243,7 +244,8 @@ template <int KP>
 __global__ void __launch_bounds__(64)
 k_wnnm(const float* __restrict__ xi, int H, int W, int P, int D, const int32_t* __restrict__ idx,
        int K, float sigma, float wc, float weps, int max_sweeps, float* __restrict__ xhat,
-       float* __restrict__ sv, DevStats* st, int32_t* __restrict__ zbuf, int zn, int bump) {
+       float* __restrict__ sv, DevStats* st, int32_t* __restrict__ zbuf, int zn, int bump,
+       float* __restrict__ gw) {
   constexpr int XS = KP + 4;       // row stride of the column-exchange buffer (16-byte rows)
   constexpr int BLN = 64 * (XS > LS ? XS : LS);
   __shared__ __align__(16) float Rl[BLN];   // R columns (Rl[j*LS + i]); exchange rows; W columns
@@ -416,13 +418,18 @@ k_wnnm(const float* __restrict__ xi, int H, int W, int P, int D, const int32_t* 
   // the columns sit in lanes 0..Kp-1 in some order; for odd K one of them
   // is the zero padding column (cid == K), whose w is 0 and which is left
   // out of the singular-value list
+  bool kept = false;
   if (lane < Kp) {
     const float shat = sqrtf(fmaxf(s * s - (float)K * sigma * sigma, 0.f));
     const float tau = wc * sqrtf((float)K) * sigma * sigma / (shat + weps);
     const float sn = fmaxf(s - tau, 0.f);
     ssig[lane] = cid < K ? ss : -1.f;
     sw[lane] = s > 0.f ? (s - sn) / s : 0.f;
+    kept = cid < K && sn > 0.f;
   }
+  // aggregation weight of the group: 1 / max(r, 1), r = singular values kept
+  const int rk = __popcll(__ballot(kept));
+  if (gw && lane == 0) gw[g] = 1.0f / (float)(rk > 0 ? rk : 1);
   // V rows and columns past K (past Kp) are written as zeros: the products
   // below run over all KP entries, and 0 times stale LDS contents could be NaN
   if (lane < KP) {
@@ -506,18 +513,18 @@ k_wnnm(const float* __restrict__ xi, int H, int W, int P, int D, const int32_t* 
 
 void launch_wnnm(const glr_plan* pl, const float* xp, const int32_t* idx, float sigma,
                  float* xhat, float* sv, DevStats* st, int32_t* zbuf, int zn, int bump,
-                 float* xi, hipStream_t s) {
+                 float* xi, float* gw, hipStream_t s) {
   const int K = pl->K;
   const size_t HW = (size_t)pl->H * pl->W, n = HW * pl->Cp;
   hipLaunchKernelGGL(k_interleave, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, xp, pl->Cp,
                      HW, xi);
   if (K <= 32)
     hipLaunchKernelGGL(k_wnnm<32>, dim3(pl->N), dim3(64), 0, s, xi, pl->H, pl->W, pl->P, pl->D,
-                       idx, K, sigma, pl->wnnm_c, pl->wnnm_eps, 30, xhat, sv, st, zbuf, zn, bump);
+                       idx, K, sigma, pl->wnnm_c, pl->wnnm_eps, 30, xhat, sv, st, zbuf, zn, bump, gw);
   else if (K <= 48)
     hipLaunchKernelGGL(k_wnnm<48>, dim3(pl->N), dim3(64), 0, s, xi, pl->H, pl->W, pl->P, pl->D,
-                       idx, K, sigma, pl->wnnm_c, pl->wnnm_eps, 30, xhat, sv, st, zbuf, zn, bump);
+                       idx, K, sigma, pl->wnnm_c, pl->wnnm_eps, 30, xhat, sv, st, zbuf, zn, bump, gw);
   else
     hipLaunchKernelGGL(k_wnnm<64>, dim3(pl->N), dim3(64), 0, s, xi, pl->H, pl->W, pl->P, pl->D,
-                       idx, K, sigma, pl->wnnm_c, pl->wnnm_eps, 30, xhat, sv, st, zbuf, zn, bump);
+                       idx, K, sigma, pl->wnnm_c, pl->wnnm_eps, 30, xhat, sv, st, zbuf, zn, bump, gw);
 }

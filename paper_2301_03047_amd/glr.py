@@ -21,6 +21,7 @@ _MODALITY = {"cacti": CACTI, "mri": MRI, "msfa": MSFA}
 EXEMPLARS = {"corner": 0, "uniform": 1, "corner_uniform": 2}
 SEARCH = {"global": 0, "window": 1}
 SCORE = {"l2": 0, "edge": 1}
+AGG_WEIGHTS = {"uniform": 0, "rank": 1}
 STATIC_SCRATCH_BYTES = 64 << 20          # GLR_STATIC_SCRATCH_BYTES
 
 _c_i32 = ctypes.c_int32
@@ -41,7 +42,8 @@ class Params(ctypes.Structure):
                 ("surrogate", _c_i32), ("surrogate_frac", ctypes.c_float),
                 ("judge_stride", _c_i32), ("judge_delta_max", ctypes.c_float),
                 ("cnn_packed", _vp), ("exemplars", _c_i32), ("uniform_step", _c_i32),
-                ("search", _c_i32), ("window", _c_i32), ("score", _c_i32)]
+                ("search", _c_i32), ("window", _c_i32), ("score", _c_i32),
+                ("agg_weights", _c_i32)]
 
 
 class Stats(ctypes.Structure):
@@ -144,7 +146,8 @@ class Plan:
                  rho=1.0, wnnm_c=None, wnnm_eps=None, precision="fp32", dist_chunk_mb=8192,
                  timing=False, device="cuda", allocate=True, cnn=None, surrogate_frac=0.6,
                  judge_stride=8, judge_delta_max=0.02, exemplars="corner", uniform_step=4,
-                 search="global", window=20, gap_acc=False, score="l2"):
+                 search="global", window=20, gap_acc=False, score="l2",
+                 agg_weights="uniform"):
         import torch
         L = lib()
         self.modality = _MODALITY[modality] if isinstance(modality, str) else int(modality)
@@ -173,6 +176,7 @@ class Plan:
         par.search = SEARCH[search]
         par.window = int(window)
         par.score = SCORE[score]
+        par.agg_weights = AGG_WEIGHTS[agg_weights]
         self.cnn = cnn                      # keeps the packed weights alive
         if cnn is not None:
             par.surrogate = 1
@@ -207,7 +211,7 @@ class Plan:
         args = dict(iters=wl.iters, sigma=synth.sigma_schedule(wl), mask=mask,
                     precision=wl.precision, exemplars=wl.exemplars,
                     uniform_step=wl.uniform_step, search=wl.search, window=wl.window,
-                    gap_acc=wl.gap_acc, score=wl.score)
+                    gap_acc=wl.gap_acc, score=wl.score, agg_weights=wl.agg_weights)
         args.update(kw)
         return cls(wl.modality, wl.H, wl.W, wl.C, wl.patch, wl.n_keys, wl.k, **args)
 

@@ -40,6 +40,7 @@ class Workload:
     window: int = 20
     gap_acc: bool = False  # accelerated GAP (measurement residual accumulated)
     score: str = "l2"      # matching score: "l2" distance or the "edge"-map correlation
+    agg_weights: str = "uniform"   # aggregation: "uniform", or "rank" (1 / kept rank per group)
 
     @property
     def real_channels(self):

@@ -70,7 +70,7 @@ def test_valid_plans_report_workspace():
     (dict(N=0), 2), (dict(N=10 ** 6), 2), (dict(H=8, W=8, P=6, N=9, K=10), 2),
     (dict(C=128, P=6), 4), (dict(mask=0), 1), (dict(mask=FAKE_MASK + 1), 3),
     (dict(modality=7), 1), (dict(precision=5), 1), (dict(solver=1), 1),
-    (dict(iters=3), 1), (dict(wnnm_eps=0.0), 1),
+    (dict(iters=3), 1), (dict(wnnm_eps=0.0), 1), (dict(agg_weights=2), 1),
 ])
 def test_invalid_plans(kw, code):
     st, _, msg = _create(**kw)

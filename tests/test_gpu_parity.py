@@ -201,6 +201,53 @@ def test_lowrank_tiny_scale_image(shape):
     assert err <= 1e-5 and sv_err <= 1e-3
 
 
+@pytest.mark.parametrize("shape", [(8, 40, 40, 6, 60, 32), (2, 30, 33, 5, 40, 45),
+                                   (24, 64, 64, 8, 40, 64)])
+def test_rank_weighted_aggregation_vs_oracle(shape):
+    # per-group weights 1 / (kept WNNM rank): the GPU takes the kept/not
+    # decision in FP32 on its own singular values, so the seeded inputs are
+    # checked to hold no value near its threshold (the oracle's decisions do
+    # not move under a 1e-4 change of sigma)
+    require_gpu()
+    C, H, W, P, N, K = shape
+    print("rank weights", shape, flush=True)
+    x = random_image(C, H, W, seed=C + H + 1, kind="smooth")
+    x64 = x.astype(np.float64)
+    keys = odet.detect_keys(x, P, N)
+    idx, _ = om.topk_exact(x64, P, keys, K)
+    sigma = 0.05
+    Xhat, sv_ref = olr.shrink_groups(x64, P, idx, sigma, WNNM_C, WNNM_EPS)
+    w = olr.group_weights(sv_ref, K, sigma, WNNM_C, WNNM_EPS)
+    for f in (1 - 1e-4, 1 + 1e-4):
+        np.testing.assert_array_equal(w, olr.group_weights(sv_ref, K, sigma * f, WNNM_C, WNNM_EPS))
+    assert len(np.unique(w)) > 1
+    plan = _plan(C, H, W, P, N, K, agg_weights="rank")
+    out = host(plan.lowrank_aggregate(gpu(x), gpu(idx.astype(np.int32)), sigma))
+    ref, _ = oag.aggregate(x64, P, idx, Xhat, weights=w)
+    uni, _ = oag.aggregate(x64, P, idx, Xhat)
+    err = metrics.rel_l2(out, ref)
+    print(f"  rel-L2 {err:.2e} (uniform vs weighted {metrics.rel_l2(uni, ref):.2e})", flush=True)
+    assert err <= 1e-5
+    assert metrics.rel_l2(uni, ref) > 100 * max(err, 1e-8)
+
+
+def test_rank_weighted_prior_step_vs_oracle():
+    require_gpu()
+    C, H, W, P, N, K = 8, 64, 72, 6, 80, 32
+    x = random_image(C, H, W, seed=77, kind="smooth")
+    sigma = 0.04
+    plan = _plan(C, H, W, P, N, K, agg_weights="rank")
+    out = host(plan.prior_step(gpu(x), sigma))
+    ref = opr.prior_step(x.astype(np.float64), P, N, K, sigma, WNNM_C, WNNM_EPS,
+                         agg_weights="rank")
+    for f in (1 - 1e-4, 1 + 1e-4):       # no kept/not decision near its threshold
+        np.testing.assert_array_equal(
+            ref["weights"], olr.group_weights(ref["sv"], K, sigma * f, WNNM_C, WNNM_EPS))
+    err = metrics.rel_l2(out, ref["x_out"])
+    print("rank-weighted prior step rel-L2", err, flush=True)
+    assert err <= 1e-5
+
+
 def test_identity_shrink_returns_input_exactly():
     require_gpu()
     C, H, W, P, N, K = 3, 30, 30, 4, 40, 12

@@ -166,3 +166,33 @@ def test_gather_groups_loop_by_loop():
                 for dy in range(P):
                     for dx in range(P):
                         assert G[g, j, (ch * P + dy) * P + dx] == x[ch, r + dy, c0 + dx]
+
+
+def test_weighted_aggregation_by_hand_and_uniform_limit():
+    from oracle import aggregate as oag
+    # two one-pixel patches (P = 1) on the same pixel: (1 * 2 + 3 / 3) / (1 + 1 / 3)
+    xbar = np.zeros((1, 2, 2))
+    idx = np.array([[0], [0]])
+    Xhat = np.array([[[2.0]], [[3.0]]])
+    out, cnt = oag.aggregate(xbar, 1, idx, Xhat, weights=[1.0, 1.0 / 3.0])
+    assert out[0, 0, 0] == (2.0 + 1.0) / (1.0 + 1.0 / 3.0)
+    assert cnt[0, 0] == 1.0 + 1.0 / 3.0 and out[0, 1, 1] == 0.0
+    # equal weights reduce to the uniform mean
+    rng = np.random.default_rng(2)
+    x = rng.uniform(size=(2, 9, 9))
+    idx = rng.integers(0, 49, size=(5, 4))
+    Xh = rng.uniform(size=(5, 4, 2 * 9))
+    a, _ = oag.aggregate(x, 3, idx, Xh)
+    b, _ = oag.aggregate(x, 3, idx, Xh, weights=np.full(5, 0.25))
+    np.testing.assert_allclose(a, b, rtol=1e-14)
+
+
+def test_group_weights_count_the_kept_components():
+    from oracle import lowrank as olr
+    # K = 4, sigma = 0.5: a singular value is kept iff s - tau > 0; with
+    # s^2 = K sigma^2 + shat^2, s = 3 keeps (tau = c sqrt(K) sigma^2 / shat)
+    c, eps, K, sig = 2 * np.sqrt(2), 1e-16, 4, 0.5
+    sv = np.array([[3.0, 0.2, 0.0, 0.0], [3.0, 2.5, 0.1, 0.0], [0.1, 0.05, 0.0, 0.0]])
+    kept = (olr.wnnm_weights(sv, K, sig, c, eps) > 0).sum(axis=1)
+    assert kept.tolist() == [1, 2, 0]
+    np.testing.assert_array_equal(olr.group_weights(sv, K, sig, c, eps), [1.0, 0.5, 1.0])
