@@ -153,6 +153,18 @@ typedef struct glr_params {
    * singular values the WNNM shrinkage keeps non-zero, and a pixel is the
    * weighted mean (a variant of the aggregation of the Method section). */
   int32_t agg_weights;
+  /* Inner WNNM iterations per prior step (default 1: one shrinkage).  With
+   * wnnm_iters = J > 1 the groups of the step's one matching are shrunk J
+   * times (the iterative regularisation of WNNM [Gu et al. 2014]):
+   *   y1 = xbar, yk = x(k-1) + wnnm_delta (xbar - y(k-1)),
+   *   sigma1 = sigma, sigmak = wnnm_lambda sqrt(max(sigma^2 - mean((xbar - yk)^2), 0)),
+   *   xk = aggregation of the WNNM estimates of the groups of yk at sigmak
+   * (uncovered pixels keep yk); the step returns xJ.  1 <= J <= 16;
+   * wnnm_delta in [0, 1] (default 0.1), wnnm_lambda > 0 (default 0.54).
+   * Not combined with the surrogate. */
+  int32_t wnnm_iters;
+  float wnnm_delta;
+  float wnnm_lambda;
 } glr_params;
 
 /* Counters of the last prior steps, read by glr_read_stats(). */
@@ -253,8 +265,10 @@ GLR_API glr_status glr_match_topk(glr_plan* plan, const void* x, const int32_t* 
  * mean-centred, decomposed by a one-sided Jacobi SVD (QR-preconditioned),
  * its singular values shrunk by the WNNM weights for noise level sigma, and
  * the member estimates averaged back per pixel; pixels no member covers keep
- * x_in.  sv: optional device float32 [N][K], singular values descending
- * (NULL to skip).  x_out must not alias x_in. */
+ * x_in (weighted per group with params.agg_weights RANK).  One shrinkage:
+ * params.wnnm_iters applies to glr_prior_step and glr_reconstruct only.
+ * sv: optional device float32 [N][K], singular values descending (NULL to
+ * skip).  x_out must not alias x_in. */
 GLR_API glr_status glr_lowrank_aggregate(glr_plan* plan, const void* x_in, const int32_t* idx,
                                  float sigma, void* x_out, float* sv, void* ws,
                                  void* stream);

@@ -23,7 +23,10 @@ def _prior(xp, wl, sigma, is_complex):
                       search=getattr(wl, "search", "global"),
                       radius=getattr(wl, "window", 20),
                       score=getattr(wl, "score", "l2"),
-                      agg_weights=getattr(wl, "agg_weights", "uniform"))["x_out"]
+                      agg_weights=getattr(wl, "agg_weights", "uniform"),
+                      inner=getattr(wl, "wnnm_iters", 1),
+                      delta=getattr(wl, "wnnm_delta", 0.1),
+                      lam=getattr(wl, "wnnm_lambda", 0.54))["x_out"]
 
 
 def reconstruct(wl, y, mask, sigmas, iters=None, callback=None):

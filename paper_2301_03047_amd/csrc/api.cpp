@@ -274,7 +274,7 @@ glr_status match_stage(glr_plan* pl, const float* xp, const int32_t* keys, int32
 
 glr_status lowrank_stage(glr_plan* pl, const float* xp, const int32_t* idx, float sigma, float* xo,
                          float* sv, char* ws, hipStream_t s, int32_t* cover = nullptr,
-                         bool count_step = false) {
+                         bool count_step = false, const float* sigp = nullptr) {
   float* xhat = (float*)(ws + pl->ws.xhat);
   DevStats* st = (DevStats*)(ws + pl->ws.stats);
   float* gw = pl->agg_weights == GLR_AGG_RANK ? (float*)(ws + pl->ws.gw) : nullptr;
@@ -283,7 +283,7 @@ glr_status lowrank_stage(glr_plan* pl, const float* xp, const int32_t* idx, floa
     int zn = 0;
     int32_t* z = agg_zero_range(pl, (int32_t*)(ws + pl->ws.pairs), &zn);
     launch_wnnm(pl, xp, idx, sigma, xhat, sv, st, z, zn, count_step ? 1 : 0,
-                (float*)(ws + pl->ws.xi), gw, s);
+                (float*)(ws + pl->ws.xi), gw, sigp, s);
   }
   {
     StageTimer t(pl, s, T_AGG);
@@ -307,6 +307,21 @@ glr_status prior_planar(glr_plan* pl, const float* xp, float sigma, float* xo, c
   e = match_stage(pl, xp, keys, idx, dd, ws, s);
   if (e) return e;
   e = lowrank_stage(pl, xp, idx, sigma, xo, (float*)(ws + pl->ws.sv), ws, s, nullptr, true);
+  // inner WNNM iterations on the same groups: y^(k) = x^(k-1) + delta (xbar -
+  // y^(k-1)) with y^(1) = xbar, the noise level re-estimated on the device
+  // (no host read), x^(k) the shrinkage and aggregation of y^(k)
+  float* yk = (float*)(ws + pl->ws.yk);
+  float* sigk = (float*)(ws + pl->ws.isig);
+  for (int k = 2; k <= pl->wnnm_iters && !e; ++k) {
+    {
+      StageTimer t(pl, s, T_LOWRANK);
+      launch_inner_update(xp, xo, k == 2 ? xp : yk, yk, (size_t)pl->Cp * pl->H * pl->W,
+                          pl->wnnm_delta, sigma, pl->wnnm_lambda, (double*)(ws + pl->ws.ipart),
+                          sigk, s);
+    }
+    e = lowrank_stage(pl, yk, idx, sigma, xo, (float*)(ws + pl->ws.sv), ws, s, nullptr, false,
+                      sigk);
+  }
   if (e) return e;
   return check_hip("prior step");
 }
@@ -465,6 +480,9 @@ void glr_params_default(glr_params* p) {
   p->window = 20;
   p->score = GLR_SCORE_L2;
   p->agg_weights = GLR_AGG_UNIFORM;
+  p->wnnm_iters = 1;
+  p->wnnm_delta = 0.1f;
+  p->wnnm_lambda = 0.54f;
 }
 
 glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_params* pr,
@@ -497,6 +515,14 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
     return fail(GLR_ERR_INVALID_ARG, "unknown score %d", pr->score);
   if (pr->agg_weights != GLR_AGG_UNIFORM && pr->agg_weights != GLR_AGG_RANK)
     return fail(GLR_ERR_INVALID_ARG, "unknown aggregation weights %d", pr->agg_weights);
+  if (pr->wnnm_iters < 1 || pr->wnnm_iters > 16)
+    return fail(GLR_ERR_INVALID_ARG, "wnnm_iters %d not in [1, 16]", pr->wnnm_iters);
+  if (pr->wnnm_iters > 1 &&
+      !(pr->wnnm_delta >= 0.f && pr->wnnm_delta <= 1.f && pr->wnnm_lambda > 0.f &&
+        std::isfinite(pr->wnnm_lambda)))
+    return fail(GLR_ERR_INVALID_ARG, "wnnm_delta must lie in [0, 1] and wnnm_lambda be positive");
+  if (pr->wnnm_iters > 1 && pr->surrogate)
+    return fail(GLR_ERR_UNSUPPORTED, "inner WNNM iterations are not combined with the surrogate");
   const int Ce = pb->modality == GLR_MRI ? 1 : Cp;
   if (pr->score == GLR_SCORE_EDGE) {
     if (pr->search != GLR_SEARCH_GLOBAL)
@@ -579,6 +605,9 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
   pl->window = pr->window;
   pl->score = pr->score;
   pl->agg_weights = pr->agg_weights;
+  pl->wnnm_iters = pr->wnnm_iters;
+  pl->wnnm_delta = pr->wnnm_delta;
+  pl->wnnm_lambda = pr->wnnm_lambda;
   pl->Ce = Ce;
   pl->K = pr->k;
   pl->T = pr->iters;
@@ -677,6 +706,10 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
   L.xhat = c.take((size_t)pl->M * D * 4);
   L.sv = c.take((size_t)pl->M * 4);
   L.gw = c.take(pr->agg_weights == GLR_AGG_RANK ? (size_t)pl->N * 4 : 0);
+  const bool inner = pr->wnnm_iters > 1;
+  L.yk = c.take(inner ? HW * Cp * 4 : 0);
+  L.ipart = c.take(inner ? 1024 * 8 : 0);
+  L.isig = c.take(inner ? 4 : 0);
   L.pairs = c.take(agg_sort_ints(pl) * 4);
   L.offs = c.take(((size_t)Ncand + 1) * 4);
   L.cplx_a = c.take(pl->is_complex ? HW * 8 : 0);

@@ -46,6 +46,7 @@ struct WsLayout {
   size_t idx, dd;                // groups [N][K], distances [N][K]
   size_t xhat, sv;               // group estimates [N][D][K]; singular values
   size_t gw;                     // per-group aggregation weights [N] (GLR_AGG_RANK)
+  size_t yk, ipart, isig;        // inner WNNM iterations: y^(k), partial sums, sigma_k
   size_t pairs, offs;            // aggregation sort keys, CSR offsets
   size_t cplx_a, cplx_b;         // complex scratch (FFT / ADMM)
   size_t red;                    // small reduction scratch
@@ -61,6 +62,8 @@ struct glr_plan {
   int exemplars, uniform_step, search, window;
   int score;                      // GLR_SCORE_L2 | GLR_SCORE_EDGE
   int agg_weights;                // GLR_AGG_UNIFORM | GLR_AGG_RANK
+  int wnnm_iters;                 // inner WNNM iterations per prior step (1: one shrinkage)
+  float wnnm_delta, wnnm_lambda;  // their regularisation step and noise re-estimate factor
   int Ce;                         // edge-map channels per real channel group (score EDGE)
   float rho, wnnm_c, wnnm_eps;
   std::vector<float> sigma;
@@ -225,7 +228,13 @@ void launch_window_topk(const glr_plan* pl, const float* xp, const float* A, con
 // xi: scratch [H][W][Cp] for the channel-interleaved copy of xp
 void launch_wnnm(const glr_plan* pl, const float* xp, const int32_t* idx, float sigma,
                  float* xhat, float* sv, DevStats* st, int32_t* zbuf, int zn, int bump,
-                 float* xi, float* gw, hipStream_t s);
+                 float* xi, float* gw, const float* sigp, hipStream_t s);
+// one inner WNNM iteration's regularisation: ynew = x + delta (xbar - yprev)
+// (ynew may be yprev), and sig_out = lambda sqrt(max(sigma^2 - mean((xbar -
+// ynew)^2), 0)) on the device; part holds 1024 doubles
+void launch_inner_update(const float* xbar, const float* x, const float* yprev, float* ynew,
+                         size_t n, float delta, float sigma, float lambda, double* part,
+                         float* sig_out, hipStream_t s);
 
 // aggregate.hip
 // sortbuf: aggregation sort scratch (agg_sort_ints(pl) int32); offs [Ncand + 1];

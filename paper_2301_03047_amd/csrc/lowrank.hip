@@ -243,7 +243,8 @@ __device__ __forceinline__ void qr_chunk(float* Rl, const float* Bl, const float
 template <int KP>
 __global__ void __launch_bounds__(64)
 k_wnnm(const float* __restrict__ xi, int H, int W, int P, int D, const int32_t* __restrict__ idx,
-       int K, float sigma, float wc, float weps, int max_sweeps, float* __restrict__ xhat,
+       int K, float sigma_h, const float* __restrict__ sigp, float wc, float weps,
+       int max_sweeps, float* __restrict__ xhat,
        float* __restrict__ sv, DevStats* st, int32_t* __restrict__ zbuf, int zn, int bump,
        float* __restrict__ gw) {
   constexpr int XS = KP + 4;       // row stride of the column-exchange buffer (16-byte rows)
@@ -407,6 +408,8 @@ k_wnnm(const float* __restrict__ xi, int H, int W, int P, int D, const int32_t* 
   __syncthreads();
 
   // ---- 3. singular values, WNNM factors, V into LDS (V[k][i] = column i / sigma_i)
+  // (the noise level comes from the device when an inner iteration estimated it)
+  const float sigma = sigp ? sigp[0] : sigma_h;
   float s2a = 0.f, s2b = 0.f;
 #pragma unroll
   for (int k = 0; k < KP; k += 2) {
@@ -509,22 +512,77 @@ k_wnnm(const float* __restrict__ xi, int H, int W, int P, int D, const int32_t* 
   }
 }
 
+// Iterative regularisation between inner WNNM iterations:
+// y_new = x + delta (xbar - y_prev) elementwise (FP32), and per block the
+// FP64 sum of (xbar - y_new)^2 in a fixed order (grid-stride per thread,
+// then a fixed tree over the block).
+constexpr int IB = 256, IG = 1024;     // threads per block, blocks (fixed: the sum's order)
+__global__ void __launch_bounds__(IB)
+k_inner_update(const float* __restrict__ xbar, const float* __restrict__ x,
+               const float* yprev, float* ynew, size_t n, float delta,
+               double* __restrict__ part) {
+  __shared__ double red[IB];
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * IB + threadIdx.x; i < n; i += (size_t)IG * IB) {
+    const float xb = xbar[i];
+    const float y = fmaf(delta, xb - yprev[i], x[i]);
+    ynew[i] = y;
+    const double d = (double)xb - (double)y;
+    acc = fma(d, d, acc);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = IB / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// sigma_k = lambda sqrt(max(sigma^2 - S / n, 0)), S the sum of the partials
+__global__ void __launch_bounds__(IG)
+k_inner_sigma(const double* __restrict__ part, size_t n, float sigma, float lambda,
+              float* __restrict__ sig_out) {
+  __shared__ double red[IG];
+  red[threadIdx.x] = part[threadIdx.x];
+  __syncthreads();
+  for (int h = IG / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double s2 = (double)sigma * (double)sigma - red[0] / (double)n;
+    sig_out[0] = (float)((double)lambda * sqrt(s2 > 0.0 ? s2 : 0.0));
+  }
+}
+
 }  // namespace
+
+void launch_inner_update(const float* xbar, const float* x, const float* yprev, float* ynew,
+                         size_t n, float delta, float sigma, float lambda, double* part,
+                         float* sig_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_inner_update, dim3(IG), dim3(IB), 0, s, xbar, x, yprev, ynew, n, delta,
+                     part);
+  hipLaunchKernelGGL(k_inner_sigma, dim3(1), dim3(IG), 0, s, part, n, sigma, lambda, sig_out);
+}
 
 void launch_wnnm(const glr_plan* pl, const float* xp, const int32_t* idx, float sigma,
                  float* xhat, float* sv, DevStats* st, int32_t* zbuf, int zn, int bump,
-                 float* xi, float* gw, hipStream_t s) {
+                 float* xi, float* gw, const float* sigp, hipStream_t s) {
   const int K = pl->K;
   const size_t HW = (size_t)pl->H * pl->W, n = HW * pl->Cp;
   hipLaunchKernelGGL(k_interleave, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, xp, pl->Cp,
                      HW, xi);
   if (K <= 32)
     hipLaunchKernelGGL(k_wnnm<32>, dim3(pl->N), dim3(64), 0, s, xi, pl->H, pl->W, pl->P, pl->D,
-                       idx, K, sigma, pl->wnnm_c, pl->wnnm_eps, 30, xhat, sv, st, zbuf, zn, bump, gw);
+                       idx, K, sigma, sigp, pl->wnnm_c, pl->wnnm_eps, 30, xhat, sv, st, zbuf, zn, bump,
+                       gw);
   else if (K <= 48)
     hipLaunchKernelGGL(k_wnnm<48>, dim3(pl->N), dim3(64), 0, s, xi, pl->H, pl->W, pl->P, pl->D,
-                       idx, K, sigma, pl->wnnm_c, pl->wnnm_eps, 30, xhat, sv, st, zbuf, zn, bump, gw);
+                       idx, K, sigma, sigp, pl->wnnm_c, pl->wnnm_eps, 30, xhat, sv, st, zbuf, zn, bump,
+                       gw);
   else
     hipLaunchKernelGGL(k_wnnm<64>, dim3(pl->N), dim3(64), 0, s, xi, pl->H, pl->W, pl->P, pl->D,
-                       idx, K, sigma, pl->wnnm_c, pl->wnnm_eps, 30, xhat, sv, st, zbuf, zn, bump, gw);
+                       idx, K, sigma, sigp, pl->wnnm_c, pl->wnnm_eps, 30, xhat, sv, st, zbuf, zn, bump,
+                       gw);
 }

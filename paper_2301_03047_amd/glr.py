@@ -43,7 +43,8 @@ class Params(ctypes.Structure):
                 ("judge_stride", _c_i32), ("judge_delta_max", ctypes.c_float),
                 ("cnn_packed", _vp), ("exemplars", _c_i32), ("uniform_step", _c_i32),
                 ("search", _c_i32), ("window", _c_i32), ("score", _c_i32),
-                ("agg_weights", _c_i32)]
+                ("agg_weights", _c_i32), ("wnnm_iters", _c_i32),
+                ("wnnm_delta", ctypes.c_float), ("wnnm_lambda", ctypes.c_float)]
 
 
 class Stats(ctypes.Structure):
@@ -147,7 +148,7 @@ class Plan:
                  timing=False, device="cuda", allocate=True, cnn=None, surrogate_frac=0.6,
                  judge_stride=8, judge_delta_max=0.02, exemplars="corner", uniform_step=4,
                  search="global", window=20, gap_acc=False, score="l2",
-                 agg_weights="uniform"):
+                 agg_weights="uniform", wnnm_iters=1, wnnm_delta=None, wnnm_lambda=None):
         import torch
         L = lib()
         self.modality = _MODALITY[modality] if isinstance(modality, str) else int(modality)
@@ -177,6 +178,11 @@ class Plan:
         par.window = int(window)
         par.score = SCORE[score]
         par.agg_weights = AGG_WEIGHTS[agg_weights]
+        par.wnnm_iters = int(wnnm_iters)
+        if wnnm_delta is not None:
+            par.wnnm_delta = float(wnnm_delta)
+        if wnnm_lambda is not None:
+            par.wnnm_lambda = float(wnnm_lambda)
         self.cnn = cnn                      # keeps the packed weights alive
         if cnn is not None:
             par.surrogate = 1
@@ -211,7 +217,9 @@ class Plan:
         args = dict(iters=wl.iters, sigma=synth.sigma_schedule(wl), mask=mask,
                     precision=wl.precision, exemplars=wl.exemplars,
                     uniform_step=wl.uniform_step, search=wl.search, window=wl.window,
-                    gap_acc=wl.gap_acc, score=wl.score, agg_weights=wl.agg_weights)
+                    gap_acc=wl.gap_acc, score=wl.score, agg_weights=wl.agg_weights,
+                    wnnm_iters=wl.wnnm_iters, wnnm_delta=wl.wnnm_delta,
+                    wnnm_lambda=wl.wnnm_lambda)
         args.update(kw)
         return cls(wl.modality, wl.H, wl.W, wl.C, wl.patch, wl.n_keys, wl.k, **args)
 

@@ -41,6 +41,11 @@ class Workload:
     gap_acc: bool = False  # accelerated GAP (measurement residual accumulated)
     score: str = "l2"      # matching score: "l2" distance or the "edge"-map correlation
     agg_weights: str = "uniform"   # aggregation: "uniform", or "rank" (1 / kept rank per group)
+    # inner WNNM iterations per prior step (iterative regularisation step
+    # delta, noise re-estimate factor lambda)
+    wnnm_iters: int = 1
+    wnnm_delta: float = 0.1
+    wnnm_lambda: float = 0.54
 
     @property
     def real_channels(self):

@@ -71,6 +71,8 @@ def test_valid_plans_report_workspace():
     (dict(C=128, P=6), 4), (dict(mask=0), 1), (dict(mask=FAKE_MASK + 1), 3),
     (dict(modality=7), 1), (dict(precision=5), 1), (dict(solver=1), 1),
     (dict(iters=3), 1), (dict(wnnm_eps=0.0), 1), (dict(agg_weights=2), 1),
+    (dict(wnnm_iters=0), 1), (dict(wnnm_iters=17), 1), (dict(wnnm_iters=2, wnnm_delta=2.0), 1),
+    (dict(wnnm_iters=2, wnnm_lambda=0.0), 1),
 ])
 def test_invalid_plans(kw, code):
     st, _, msg = _create(**kw)

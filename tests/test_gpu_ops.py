@@ -260,3 +260,35 @@ def test_accelerated_gap_loop_vs_oracle(modality):
     err = metrics.rel_l2(host(out), ref)
     print(modality, "accelerated GAP loop rel-L2", err, flush=True)
     assert err <= 1e-3
+
+
+@pytest.mark.parametrize("modality", ["cacti", "mri"])
+def test_inner_wnnm_iterations_loop_vs_oracle(modality):
+    # three outer iterations with two inner WNNM iterations per prior step
+    # (MRI: the complex iterate's planar form) against the oracle's loop
+    require_gpu()
+    if modality == "cacti":
+        wl = small(synth.WORKLOADS["cacti_128"], H=48, W=56, n_keys=24, k=16, iters=3,
+                   wnnm_iters=2)
+        x_true = synth.cacti_video(wl.C, wl.H, wl.W, 21)
+        m = synth.cacti_masks(wl.C, wl.H, wl.W, 22)
+    else:
+        wl = small(synth.WORKLOADS["mri_256"], H=64, W=64, n_keys=64, k=16, iters=3,
+                   wnnm_iters=2)
+        x_true = synth.mri_phantom(wl.H, wl.W, 23)
+        m = synth.mri_line_mask(wl.H, 24)
+    plan = glr.Plan.for_workload(wl, mask=gpu(m))
+    y = plan.forward(gpu(x_true))
+    out, _ = plan.reconstruct(y, 0, wl.iters)
+    out = host(out)
+    yh = host(y).astype(np.complex128 if modality == "mri" else np.float64)
+    ref = orc.reconstruct(small(wl, wnnm_c=WNNM_C), yh, m,
+                          synth.sigma_schedule(wl).astype(np.float64))
+    one = orc.reconstruct(small(wl, wnnm_c=WNNM_C, wnnm_iters=1), yh, m,
+                          synth.sigma_schedule(wl).astype(np.float64))
+    err = metrics.rel_l2(out, ref)
+    dp = metrics.psnr(out, x_true) - metrics.psnr(ref, x_true)
+    print(f"{modality} inner x2 loop rel-L2 {err:.2e} dPSNR {dp:.4f}; "
+          f"vs one shrinkage {metrics.rel_l2(one, ref):.2e}", flush=True)
+    assert err <= 1e-3 and abs(dp) <= 0.01
+    assert metrics.rel_l2(one, ref) > 10 * err

@@ -248,6 +248,26 @@ def test_rank_weighted_prior_step_vs_oracle():
     assert err <= 1e-5
 
 
+@pytest.mark.parametrize("J", [2, 3])
+def test_inner_wnnm_iterations_prior_step_vs_oracle(J):
+    # the same groups shrunk J times with iterative regularisation; the noise
+    # level of iterations 2..J is estimated on the device
+    require_gpu()
+    C, H, W, P, N, K = 8, 56, 60, 6, 60, 32
+    print("inner iterations", J, flush=True)
+    x = random_image(C, H, W, seed=91, kind="smooth")
+    sigma = 0.05
+    plan = _plan(C, H, W, P, N, K, wnnm_iters=J)
+    out = host(plan.prior_step(gpu(x), sigma))
+    ref = opr.prior_step(x.astype(np.float64), P, N, K, sigma, WNNM_C, WNNM_EPS, inner=J)
+    one = opr.prior_step(x.astype(np.float64), P, N, K, sigma, WNNM_C, WNNM_EPS)
+    err = metrics.rel_l2(out, ref["x_out"])
+    print(f"  rel-L2 {err:.2e}, sigmas {ref['sigmas']}, "
+          f"vs one shrinkage {metrics.rel_l2(one['x_out'], ref['x_out']):.2e}", flush=True)
+    assert err <= 1e-5
+    assert metrics.rel_l2(one["x_out"], ref["x_out"]) > 100 * max(err, 1e-8)
+
+
 def test_identity_shrink_returns_input_exactly():
     require_gpu()
     C, H, W, P, N, K = 3, 30, 30, 4, 40, 12

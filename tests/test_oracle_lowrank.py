@@ -196,3 +196,50 @@ def test_group_weights_count_the_kept_components():
     kept = (olr.wnnm_weights(sv, K, sig, c, eps) > 0).sum(axis=1)
     assert kept.tolist() == [1, 2, 0]
     np.testing.assert_array_equal(olr.group_weights(sv, K, sig, c, eps), [1.0, 0.5, 1.0])
+
+
+def test_inner_iterations_worked_by_hand():
+    # the recursion with a stand-in step x = y / 2 (any shrink-and-aggregate
+    # map can be passed in): xbar = 1, x1 = 1/2, delta = 0.1, lam = 0.5, sigma = 2
+    #   y2 = 0.5 + 0.1 (1 - 1)   = 0.5,   sigma2 = 0.5 sqrt(4 - 0.25)   = 0.5 sqrt(3.75)
+    #   x2 = 0.25
+    #   y3 = 0.25 + 0.1 (1 - 0.5) = 0.3,  sigma3 = 0.5 sqrt(4 - 0.49)   = 0.5 sqrt(3.51)
+    #   x3 = 0.15
+    from oracle.prior import inner_iterations
+    seen = []
+
+    def step(y, s):
+        seen.append((float(y[0]), s))
+        return None, None, None, y / 2, None
+    x, sig, _ = inner_iterations(np.ones(1), np.full(1, 0.5), 2.0, 3, 0.1, 0.5, step)
+    assert abs(x[0] - 0.15) < 1e-15
+    np.testing.assert_allclose(sig, [2.0, 0.5 * np.sqrt(3.75), 0.5 * np.sqrt(3.51)], rtol=1e-15)
+    np.testing.assert_allclose([v for v, _ in seen], [0.5, 0.3], rtol=1e-15)
+
+
+def test_inner_iterations_special_cases():
+    from oracle import prior as opr
+    from synth.workloads import random_image
+    C, H, W, P, N, K = 3, 24, 26, 4, 12, 8
+    x = random_image(C, H, W, seed=9).astype(np.float64)
+    c, eps = 2 * np.sqrt(2), 1e-16
+    # sigma = 0: every shrinkage is the identity, so every iteration returns xbar
+    r = opr.prior_step(x, P, N, K, 0.0, c, eps, inner=4)
+    np.testing.assert_allclose(r["x_out"], x, rtol=0, atol=1e-12)
+    assert r["sigmas"] == [0.0, 0.0, 0.0, 0.0]
+    # one iteration is the plain step; the second sees a smaller noise level
+    one = opr.prior_step(x, P, N, K, 0.05, c, eps)
+    two = opr.prior_step(x, P, N, K, 0.05, c, eps, inner=2)
+    assert len(one["sigmas"]) == 1 and 0 < two["sigmas"][1] < 0.54 * 0.05
+    np.testing.assert_array_equal(one["idx"], two["idx"])
+    assert np.abs(two["x_out"] - one["x_out"]).max() > 1e-6
+    # delta = 0 and lam chosen so sigma_2 = sigma: the second shrinkage acts on x^(1)
+    # (y2 = x1) with the first sigma, i.e. two plain steps on fixed groups
+    d = np.mean((x - one["x_out"]) ** 2)
+    lam = 0.05 / np.sqrt(0.05 ** 2 - d)
+    two0 = opr.prior_step(x, P, N, K, 0.05, c, eps, inner=2, delta=0.0, lam=lam)
+    from oracle import aggregate as oag
+    Xh, _ = lr.shrink_groups(one["x_out"], P, one["idx"], 0.05, c, eps)
+    again, _ = oag.aggregate(one["x_out"], P, one["idx"], Xh)
+    np.testing.assert_allclose(two0["sigmas"][1], 0.05, rtol=1e-12)
+    np.testing.assert_allclose(two0["x_out"], again, rtol=1e-12, atol=1e-14)
