@@ -891,6 +891,271 @@ k_match_bf16(const float* __restrict__ xp, int H, int W, int P, int Cp,
   }
 }
 
+// Double-buffered BF16 matcher for patch sides up to 8 (NS <= 8 slices per
+// channel): 256 keys x 256 candidates per block, eight waves, each a 64 x 128
+// tile (2 x 4 MFMA 32 x 32 tiles).  Per channel the key slab (As) and the
+// candidate operand (Bs) are staged in one of two LDS buffers while the MFMAs
+// read the other, with one barrier per channel.  The candidate operand is
+// built from registers: wave t (t < NS) builds slice t (patch row t) of the
+// 256 candidates, lane l the four candidates 4l..4l+3 from three 16-byte
+// reads of image row r + t (columns c0 + 4l .. c0 + 4l + 11; the eight-value
+// windows of the four candidates overlap).  The loads for channel ch + 2 are
+// issued once channel ch + 1 is staged, a whole channel of MFMAs ahead of
+// their use.  The channel loop is unrolled by two so both buffers have static
+// addresses and the staging of one buffer can be scheduled between the MFMAs
+// that read the other.  Same operand layout, slice order and epilogue as
+// k_match_bf16 (the same MFMA sequence per output).
+constexpr int DBM = 256;                  // keys per block (double-buffered form)
+constexpr int DBN = 256;                  // candidates per block
+
+// Instruction order of one channel step (LDS reads of the first two
+// k-steps, then per k-step its eight MFMAs with the next k-step's reads and a
+// share of the staging work between them), so the staging of the other
+// buffer runs in the shadow of the MFMAs and at most two k-steps of operands
+// are live.
+template <int NS>
+__device__ __forceinline__ void sched_db_step() {
+  constexpr int KS = NS / 2;
+  __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);          // DS reads, k-step 0
+  if (KS > 1) __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
+#pragma unroll
+  for (int kk = 0; kk < KS; ++kk) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);      // MFMA
+      __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);      // VALU (operand build)
+      if (i == 3 && kk + 2 < KS) __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
+      if (i & 1) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);   // DS write
+      if (kk == KS - 1 && (i & 1) == 0) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+    }
+  }
+}
+
+template <int NS, bool VEC4>
+__global__ void __launch_bounds__(512, 1)
+k_match_bf16_db(const float* __restrict__ xp, int H, int W, int P, int Cp,
+                const uint16_t* __restrict__ Ab, const float4* __restrict__ kmb,
+                const float4* __restrict__ cmeta, int g0, int nk, float* __restrict__ dist,
+                size_t ldd) {
+  static_assert(NS <= 8 && (NS & 1) == 0, "double-buffered matcher: P <= 8");
+  constexpr int NT = 4;                     // 32-candidate tiles per wave
+  constexpr int ROWB = NS * 8;              // bf16 per key and channel
+  constexpr int AST = ROWB + 8;             // LDS row stride of the key slab (bf16)
+  constexpr int NAU = NS / 2;               // uint4 per thread of the key slab (2 threads/key)
+  constexpr int ASZ = DBM * AST;
+  constexpr int BSZ = NS * DBN * 8 + NS * DBN / 2;
+  __shared__ __align__(16) uint16_t As0[ASZ];
+  __shared__ __align__(16) uint16_t As1[ASZ];
+  __shared__ __align__(16) uint16_t Bs0[BSZ];
+  __shared__ __align__(16) uint16_t Bs1[BSZ];
+  __shared__ float4 skm[DBM];
+
+  const int Hc = H - P + 1, Wc = W - P + 1;
+  const int ntc = (Wc + DBN - 1) / DBN;
+  int b = blockIdx.x;
+  const int ct = b % ntc;
+  b /= ntc;
+  const int r = b % Hc;
+  const int kt = b / Hc;
+  const int c0 = ct * DBN;
+  const int kbase = kt * DBM;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int l32 = lane & 31, lhi = lane >> 5;
+  const int D = Cp * P * P;
+
+  if (tid < DBM) {
+    const int g = kbase + tid;
+    skm[tid] = g < nk ? kmb[g0 + g] : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  // the builder's four candidates and their means (constant over channels)
+  const int cb = c0 + 4 * lane;
+  float mu[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) mu[u] = cb + u < Wc ? cmeta[(size_t)r * Wc + cb + u].x : 0.f;
+  const bool builder = NS == 8 || wave < NS;   // all eight waves build when NS = 8
+  const bool row_ok = wave < P;             // padding rows (P odd) are zeros
+  const int akey = tid >> 1, ahalf = tid & 1;
+  const bool key_ok = kbase + akey < nk;
+  const uint16_t* asrc = Ab + (size_t)(g0 + (key_ok ? kbase + akey : 0)) * Cp * ROWB +
+                         ahalf * (ROWB / 2);
+  const size_t HW = (size_t)H * W;
+  const float* bsrc = xp + (size_t)(r + (row_ok ? wave : 0)) * W;
+
+  // Loads are always issued in bounds; what must read as zero (keys past
+  // nk, columns past W, padding rows, channels past Cp: an odd Cp is rounded
+  // up to even) is cleared by bit masks when staged, so the loads have no
+  // consumer before the next staging and every step stays one block.
+  uint4 ra[NAU];
+  float4 rb[3];
+  uint32_t km, rm[3];
+  const uint32_t kmask = key_ok ? 0xffffffffu : 0u;
+  const uint32_t rmask = row_ok ? 0xffffffffu : 0u;
+  auto load = [&](int ch) {
+    const uint32_t cm_ok = ch < Cp ? 0xffffffffu : 0u;
+    km = kmask & cm_ok;
+    ch = min(ch, Cp - 1);
+#pragma unroll
+    for (int u = 0; u < NAU; ++u)
+      ra[u] = *reinterpret_cast<const uint4*>(asrc + (size_t)ch * ROWB + u * 8);
+    if (builder) {
+      const float* row = bsrc + (size_t)ch * HW;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        const int cm = cb + 4 * m;
+        if (VEC4) {
+          // W % 4 == 0 and cm % 4 == 0: the group is wholly inside the row
+          // or wholly past its end (then read in bounds and cleared)
+          rb[m] = *reinterpret_cast<const float4*>(row + min(cm, W - 4));
+          rm[m] = cm < W ? rmask & cm_ok : 0u;
+        } else {
+          // columns past W read the row's last value; the builder's
+          // candidates that use them lie past Wc and are never stored
+          rb[m] = make_float4(row[min(cm, W - 1)], row[min(cm + 1, W - 1)],
+                              row[min(cm + 2, W - 1)], row[min(cm + 3, W - 1)]);
+          rm[m] = rmask & cm_ok;
+        }
+      }
+    }
+  };
+  // LDS byte offsets: one per-lane base per operand, the rest immediates.
+  // Candidate row q of slice t sits at 16 (q' + q' / 16), q' = t DBN + q.
+  const int a_st = (akey * AST + ahalf * (ROWB / 2)) * 2;
+  const int bq = wave * DBN + 4 * lane;                 // builder: rows bq .. bq + 3
+  const int b_st = 16 * (bq + (bq >> 4));
+  const int a_rd = ((wm * 64 + l32) * AST + lhi * 8) * 2;
+  const int bl = lhi * DBN + wn * (32 * NT) + l32;     // fragment row of t = lhi, nt = 0
+  const int b_rd = 16 * (bl + (bl >> 4));
+  auto stage = [&](uint16_t* As, uint16_t* Bs) {
+    char* Ab8 = reinterpret_cast<char*>(As) + a_st;
+    char* Bb8 = reinterpret_cast<char*>(Bs) + b_st;
+#pragma unroll
+    for (int u = 0; u < NAU; ++u)
+      *reinterpret_cast<uint4*>(Ab8 + 16 * u) =
+          make_uint4(ra[u].x & km, ra[u].y & km, ra[u].z & km, ra[u].w & km);
+    if (builder) {
+      auto cl = [](float v, uint32_t m) { return __uint_as_float(__float_as_uint(v) & m); };
+      const float f[12] = {cl(rb[0].x, rm[0]), cl(rb[0].y, rm[0]), cl(rb[0].z, rm[0]),
+                           cl(rb[0].w, rm[0]), cl(rb[1].x, rm[1]), cl(rb[1].y, rm[1]),
+                           cl(rb[1].z, rm[1]), cl(rb[1].w, rm[1]), cl(rb[2].x, rm[2]),
+                           cl(rb[2].y, rm[2]), cl(rb[2].z, rm[2]), cl(rb[2].w, rm[2])};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        uint32_t wd[4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h)
+          wd[h] = __builtin_bit_cast(uint32_t, __builtin_convertvector(
+                      (f32x2){f[u + 2 * h] - mu[u], f[u + 2 * h + 1] - mu[u]},
+                      bf16x2));   // round to nearest even
+        // rows bq + u share bq's 16-row group (bq is a multiple of 4)
+        *reinterpret_cast<uint4*>(Bb8 + 16 * u) = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+      }
+    }
+  };
+
+  f32x16 acc[2][NT];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[i][j][q] = 0.f;
+
+  auto mfma = [&](const uint16_t* As, const uint16_t* Bs) {
+    const char* Ar8 = reinterpret_cast<const char*>(As) + a_rd;
+    const char* Br8 = reinterpret_cast<const char*>(Bs) + b_rd;
+#pragma unroll
+    for (int kk = 0; kk < NS / 2; ++kk) {
+      bf16x8 a[2], bb[NT];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+        a[mt] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(
+                    Ar8 + 2 * (mt * 32 * AST + 2 * kk * 8)));
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)   // slice 2 kk + lhi, rows + 2 kk DBN + 32 nt
+        bb[nt] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(
+                     Br8 + 16 * ((2 * kk * DBN + nt * 32) + (2 * kk * DBN + nt * 32) / 16)));
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+          acc[mt][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mt], bb[nt], acc[mt][nt], 0, 0, 0);
+    }
+  };
+
+  // channel ch is read from buffer ch & 1; the loop runs over an even
+  // channel count (a zero channel pads an odd Cp) so that each iteration is
+  // one straight-line block and the accumulators stay in place
+  const int Cp2 = Cp + (Cp & 1);
+  load(0);
+  stage(As0, Bs0);
+  load(1);
+  __syncthreads();
+  for (int ch = 0; ch < Cp2; ch += 2) {
+    mfma(As0, Bs0);
+    stage(As1, Bs1);
+    load(ch + 2);
+    sched_db_step<NS>();
+    __syncthreads();
+    mfma(As1, Bs1);
+    stage(As0, Bs0);
+    load(ch + 3);
+    sched_db_step<NS>();
+    __syncthreads();
+  }
+
+  // epilogue: d~ = ||a||^2 + ||pbar||^2 - 2 S + D dmu^2 + 2 dmu (sum a - sum pbar)
+  // (the arithmetic of centred_dist).  Key terms are read once per output
+  // row, candidate terms once per column; each row's four 32-candidate runs
+  // are stored from one row pointer.
+  const int colb = c0 + wn * (32 * NT) + l32;
+  float4 cmv[NT];
+  bool cok[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    const int col = colb + nt * 32;
+    cok[nt] = col < Wc;
+    cmv[nt] = cmeta[(size_t)r * Wc + (cok[nt] ? col : 0)];
+  }
+  float* dbase = dist + (size_t)r * Wc + colb;
+  const int nrow = min(DBM, nk - kbase);     // rows of this key tile that exist
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int i = wm * 64 + mt * 32 + 8 * (q >> 2) + 4 * lhi + (q & 3);
+      if (i >= nrow) continue;
+      const float4 km = skm[i];
+      float* drow = dbase + (size_t)(kbase + i) * ldd;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const float4 cm = cmv[nt];
+        const float dmu = km.y - cm.x;
+        const float base = (km.x + cm.y) - 2.0f * acc[mt][nt][q];
+        const float d = (base + ((float)D * dmu) * dmu) + 2.0f * dmu * (km.z - cm.w);
+        if (cok[nt]) drow[nt * 32] = d;
+      }
+    }
+}
+
+template <int NS>
+void launch_match_bf16_db(const glr_plan* pl, const float* xp, const uint16_t* Ab,
+                          const float* kmb, const float* cmeta, int g0, int nk, float* dist,
+                          hipStream_t s) {
+  const int ntc = (pl->Wc + DBN - 1) / DBN;
+  const int nkt = (nk + DBM - 1) / DBM;
+  const size_t blocks = (size_t)nkt * pl->Hc * ntc;
+  if ((pl->W & 3) == 0)
+    hipLaunchKernelGGL((k_match_bf16_db<NS, true>), dim3((unsigned)blocks), dim3(512), 0, s, xp,
+                       pl->H, pl->W, pl->P, pl->Cp, Ab, (const float4*)kmb, (const float4*)cmeta,
+                       g0, nk, dist, (size_t)pl->ldd);
+  else
+    hipLaunchKernelGGL((k_match_bf16_db<NS, false>), dim3((unsigned)blocks), dim3(512), 0, s, xp,
+                       pl->H, pl->W, pl->P, pl->Cp, Ab, (const float4*)kmb, (const float4*)cmeta,
+                       g0, nk, dist, (size_t)pl->ldd);
+}
+
 template <int NS>
 void launch_match_bf16_t(const glr_plan* pl, const float* xp, const uint16_t* Ab,
                          const float* kmb, const float* cmeta, int g0, int nk, float* dist,
@@ -961,10 +1226,10 @@ void launch_match_f32(const glr_plan* pl, const float* xp, const float* Ac, cons
 void launch_match_bf16(const glr_plan* pl, const float* xp, const uint16_t* Ab, const float* kmb,
                        const float* cmeta, int g0, int nk, float* dist, hipStream_t s) {
   switch (bf16_slices(pl->P)) {
-    case 2: launch_match_bf16_t<2>(pl, xp, Ab, kmb, cmeta, g0, nk, dist, s); break;
-    case 4: launch_match_bf16_t<4>(pl, xp, Ab, kmb, cmeta, g0, nk, dist, s); break;
-    case 6: launch_match_bf16_t<6>(pl, xp, Ab, kmb, cmeta, g0, nk, dist, s); break;
-    case 8: launch_match_bf16_t<8>(pl, xp, Ab, kmb, cmeta, g0, nk, dist, s); break;
+    case 2: launch_match_bf16_db<2>(pl, xp, Ab, kmb, cmeta, g0, nk, dist, s); break;
+    case 4: launch_match_bf16_db<4>(pl, xp, Ab, kmb, cmeta, g0, nk, dist, s); break;
+    case 6: launch_match_bf16_db<6>(pl, xp, Ab, kmb, cmeta, g0, nk, dist, s); break;
+    case 8: launch_match_bf16_db<8>(pl, xp, Ab, kmb, cmeta, g0, nk, dist, s); break;
     case 24: launch_match_bf16_t<24>(pl, xp, Ab, kmb, cmeta, g0, nk, dist, s); break;
     default: launch_match_bf16_t<32>(pl, xp, Ab, kmb, cmeta, g0, nk, dist, s); break;
   }
