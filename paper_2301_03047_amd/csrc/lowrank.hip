@@ -5,10 +5,9 @@
 // One wave per group Y (D x K, column j = member patch j); lane j owns
 // column j and keeps it in registers:
 //  1. rows are streamed in chunks of up to 64 (each lane loads one row and
-//     removes its mean, Yc = Y - mu 1^T); the chunk is folded into the
-//     running triangular factor R by Householder reflections on [R; chunk];
-//     the reflector's column is broadcast through LDS, its scalars by lane
-//     reads;
+//     its mean; Yc = Y - mu 1^T in FP32); the Gram matrix G = Yc^T Yc is
+//     accumulated in FP64 (lane (bi, bj) owns an 8 x 8 block) and factored by
+//     an FP64 Cholesky, R^T R = G: R is the QR factor of Yc up to row signs;
 //  2. one-sided Jacobi on the columns of R^T (odd-even transposition
 //     ordering, partner columns moved between lanes by DPP, rotation angles
 //     computed in FP64); the converged columns are sigma_i v_i with v_i the
@@ -20,7 +19,8 @@
 //     1 / max(r, 1), r the number of s' > 0;
 //  4. X = Y - Yc W, W = V diag(w) V^T: the residual sum_i (s_i - s'_i) u_i v_i^T
 //     accumulated in FP64 (sigma = 0 gives w = 0, W = 0, X = Y exactly).
-// Data and the SVD are FP32; only the angles and the residual use FP64.
+// The Gram matrix, its factor, the rotation angles and the residual use
+// FP64; the data and the Jacobi iteration FP32.
 // The group rows are read from a channel-interleaved copy of the iterate,
 // xi[(r*W + c)*Cp + ch], made once per step, and taken in the output order
 // e = (dy*P + dx)*Cp + ch (the row order does not change the factorisation):
@@ -50,18 +50,17 @@ __global__ void k_interleave(const float* __restrict__ xp, int Cp, size_t HW,
   xi[o] = xp[(size_t)c * HW + p];
 }
 
-__device__ __forceinline__ float bcast(float v, int lane) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
-}
 
 // Lane i < nb loads row e = d0+i (output order (dy P + dx) Cp + c) of Y from
 // the interleaved copy xi into B[i][0..K) (raw values) and its mean; spos
 // holds the members' top-left pixels r W + c.
 // Row stride RS (LS by default); with kpad > K the entries K..kpad-1 of a
-// row are zeroed.
+// row are zeroed.  With tr, the chunk is stored transposed, B[u*RS + i]
+// (member-major).
 __device__ __forceinline__ void load_rows(const float* __restrict__ xi, const int* spos, int d0,
                                           int nb, int K, int P, int W, int Cp, float* B,
-                                          float* smu, int RS = LS, int kpad = 0) {
+                                          float* smu, int RS = LS, int kpad = 0,
+                                          bool tr = false) {
   const int i = threadIdx.x;
   if (i < nb) {
     const int e = d0 + i, pix = e / Cp, c = e - pix * Cp;
@@ -83,10 +82,10 @@ __device__ __forceinline__ void load_rows(const float* __restrict__ xi, const in
 #pragma unroll
     for (int u = 0; u < 64; ++u)
       if (u < K) {
-        B[i * RS + u] = v[u];
+        B[tr ? u * RS + i : i * RS + u] = v[u];
         s += v[u];
       }
-    for (int j = K; j < kpad; ++j) B[i * RS + j] = 0.f;
+    for (int j = K; j < kpad; ++j) B[tr ? j * RS + i : i * RS + j] = 0.f;
     smu[i] = s / (float)K;
   }
   __syncthreads();
@@ -125,6 +124,14 @@ __device__ __forceinline__ double jacobi_angle(float a1, float a2, float ga, flo
   return t;
 }
 
+// A double held by lane k (uniform k), read as two 32-bit halves.
+__device__ __forceinline__ double bcast64(double v, int k) {
+  const long long x = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffll), k);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), k);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
 // The value held by lane ^ 1 (a DPP quad permutation: no LDS traffic).
 __device__ __forceinline__ float lane_xor1(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, true));
@@ -146,11 +153,6 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  return v;
-}
 
 template <int N>
 __device__ __forceinline__ void store_vec(float* dst, const float (&v)[N]) {
@@ -167,79 +169,6 @@ __device__ __forceinline__ void load_vec(float (&v)[N], const float* src) {
   }
 }
 
-// Folds one streamed chunk of nb <= NB rows (in Bl, row means in smu) into
-// the running triangular factor R (Rl[j*LS + i] = R[i][j]) by K Householder
-// reflections on [R; chunk].  NB is the chunk height rounded up to a power
-// of two, so a short last chunk does not run the full-height loops (the
-// padding rows are zero and would not change any sum).
-template <int NB>
-__device__ __forceinline__ void qr_chunk(float* Rl, const float* Bl, const float* smu, float* Cb,
-                                         int nb, int K, int lane, int& fe, bool& fset) {
-  float b[NB];
-#pragma unroll
-  for (int i = 0; i < NB; ++i) b[i] = (i < nb && lane < K) ? Bl[i * LS + lane] - smu[i] : 0.f;
-  if (!fset) {
-    float mx = 0.f;
-#pragma unroll
-    for (int i = 0; i < NB; ++i) mx = fmaxf(mx, fabsf(b[i]));
-    mx = wave_max(mx);
-    if (mx > 0.f) {
-      int e;
-      frexpf(mx, &e);                       // mx = f 2^e, f in [0.5, 1)
-      fe = min(1 - e, 126);
-      fset = true;
-    }
-  }
-  const float fs = ldexpf(1.f, fe);
-#pragma unroll
-  for (int i = 0; i < NB; ++i) b[i] *= fs;
-  for (int k = 0; k < K; ++k) {
-    // lane k's chunk column goes to LDS for every lane; each lane's dot
-    // product with it is, in lane k, the squared norm of that column below
-    // R[k][k].  Lane k then builds the reflector that zeroes the column,
-    // normalised to a unit leading entry (v = (x0 - alpha, b) / v0, scale
-    // tau = |v0| / ||v|| in [1, 2]) so that no step overflows however small
-    // the column's residual is; its 1 / v0 and tau reach the other lanes as
-    // scalars
-    if (lane == k) store_vec(Cb, b);
-    wave_sync();
-    float bk[NB];
-    load_vec(bk, Cb);
-    float w[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};   // short dependency chains
-#pragma unroll
-    for (int i = 0; i < NB; ++i) w[i & 7] = fmaf(bk[i], b[i], w[i & 7]);
-    const float dot = ((w[0] + w[1]) + (w[2] + w[3])) + ((w[4] + w[5]) + (w[6] + w[7]));
-    float rv = 0.f, tau = 0.f;
-    if (lane == k) {
-      const float x0 = Rl[k * LS + k];
-      // hardware square root and reciprocals (within 1 ulp): the
-      // reflector stays orthogonal to working precision
-      const float nrm = __builtin_amdgcn_sqrtf(fmaf(x0, x0, dot));
-      float alpha = x0;
-      if (dot > 0.f && nrm > 0.f) {
-        alpha = x0 >= 0.f ? -nrm : nrm;
-        const float v0 = x0 - alpha;          // |v0| = |x0| + nrm >= nrm
-        rv = __builtin_amdgcn_rcpf(v0);
-        tau = fabsf(v0) * __builtin_amdgcn_rcpf(nrm);
-      }
-      Rl[k * LS + k] = alpha;
-    }
-    rv = bcast(rv, k);
-    tau = bcast(tau, k);
-    // column j: R[k][j] -= sc, chunk column -= sc rv b_k with
-    // sc = tau (R[k][j] + rv (b_k . b_j))
-    if (tau > 0.f && lane > k && lane < K) {
-      const float rk = Rl[lane * LS + k];
-      const float sc = tau * fmaf(rv, dot, rk);
-      const float f = -sc * rv;
-#pragma unroll
-      for (int i = 0; i < NB; ++i) b[i] = fmaf(f, bk[i], b[i]);
-      Rl[lane * LS + k] = rk - sc;
-    }
-    wave_sync();
-  }
-}
-
 template <int KP>
 __global__ void __launch_bounds__(64)
 k_wnnm(const float* __restrict__ xi, int H, int W, int P, int D, const int32_t* __restrict__ idx,
@@ -248,11 +177,17 @@ k_wnnm(const float* __restrict__ xi, int H, int W, int P, int D, const int32_t* 
        float* __restrict__ sv, DevStats* st, int32_t* __restrict__ zbuf, int zn, int bump,
        float* __restrict__ gw) {
   constexpr int XS = KP + 4;       // row stride of the column-exchange buffer (16-byte rows)
+  constexpr int TS = 68;           // row stride of W and of the member-major chunk (64 + 4)
   constexpr int BLN = 64 * (XS > LS ? XS : LS);
-  __shared__ __align__(16) float Rl[BLN];   // R columns (Rl[j*LS + i]); exchange rows; W columns
-  // chunk rows Bl[i*LS + j]; then exchange rows and V rows with stride XS
-  __shared__ __align__(16) float Bl[BLN];
-  __shared__ __align__(16) float Cb[BR + 4];    // broadcast reflector u, its scale tau at [BR]
+  static_assert(KP * TS <= BLN, "W and the member-major chunk fit a buffer");
+  static_assert(2 * BLN * 4 >= 64 * 64 * 8, "the Gram matrix fits the two buffers");
+  // Rl: R columns (Rl[j*LS + i]); exchange rows; W columns.  Bl: chunk rows
+  // (stride XS); then exchange rows and V rows with stride XS.  Both together
+  // first hold the FP64 Gram matrix.
+  __shared__ __align__(16) float RB[2 * BLN];
+  float* const Rl = RB;
+  float* const Bl = RB + BLN;
+  __shared__ __align__(16) double srow[64];     // one row of the Cholesky factor
   __shared__ float smu[64];
   __shared__ __align__(16) int spos[64];
   __shared__ float sw[64];
@@ -277,22 +212,96 @@ k_wnnm(const float* __restrict__ xi, int H, int W, int P, int D, const int32_t* 
   for (int i = 0; i < 64; ++i) Rl[lane * LS + i] = 0.f;
   __syncthreads();
 
-  // ---- 1. streamed Householder QR of Yc, scaled by the power of two 2^fe
-  // that brings the first non-zero chunk's largest entry into [1, 2): exact,
-  // and it keeps squares and inner products of tiny groups out of the FP32
-  // subnormal range (phases 1-3 work on the scaled group; the singular values
-  // are scaled back before the shrinkage, and phase 4 reads the raw rows)
+  // ---- 1. Gram matrix G = Yc^T Yc in FP64 over the streamed rows (lane
+  // (bi, bj) accumulates the 8 x 8 block G[8 bi ..][8 bj ..]; the FP32
+  // centred values and their products are exact in FP64), then its Cholesky
+  // factor R (R^T R = G, upper triangular, column j in lane j; a pivot <= 0,
+  // which only a numerically dependent column gives, leaves a zero row).  R
+  // equals the QR factor of Yc up to the signs of its rows, so it has the
+  // same singular values and right singular vectors.  R is handed to the
+  // Jacobi phase in FP32, scaled by the power of two 2^fe that brings its
+  // largest entry into [1, 2) (phases 2-3 work on the scaled factor; the
+  // singular values are scaled back before the shrinkage, and phase 4 reads
+  // the raw rows).
   int fe = 0;
-  bool fset = false;
-  for (int d0 = 0; d0 < D; d0 += BR) {
-    const int nb = min(BR, D - d0);
-    load_rows(xi, spos, d0, nb, K, P, W, Cp, Bl, smu);
-    if (nb > 32) qr_chunk<64>(Rl, Bl, smu, Cb, nb, K, lane, fe, fset);
-    else if (nb > 16) qr_chunk<32>(Rl, Bl, smu, Cb, nb, K, lane, fe, fset);
-    else if (nb > 8) qr_chunk<16>(Rl, Bl, smu, Cb, nb, K, lane, fe, fset);
-    else qr_chunk<8>(Rl, Bl, smu, Cb, nb, K, lane, fe, fset);
-    __syncthreads();
+  {
+    const int bi = lane >> 3, bj = lane & 7;
+    double acc[8][8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[p][q] = 0.0;
+    for (int d0 = 0; d0 < D; d0 += BR) {
+      const int nb = min(BR, D - d0);
+      load_rows(xi, spos, d0, nb, K, P, W, Cp, Bl, smu, XS);
+      // centre the chunk in place (lane i: row i), once for all lanes
+      if (lane < nb) {
+        const float mu = smu[lane];
+        for (int u = 0; u < K; ++u) Bl[lane * XS + u] -= mu;
+      }
+      __syncthreads();
+#pragma unroll 2
+      for (int i = 0; i < nb; ++i) {
+        float a[8], b[8];
+        load_vec(a, Bl + i * XS + 8 * bi);
+        load_vec(b, Bl + i * XS + 8 * bj);
+        double ya[8], yb[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          ya[t] = 8 * bi + t < K ? (double)a[t] : 0.0;
+          yb[t] = 8 * bj + t < K ? (double)b[t] : 0.0;
+        }
+#pragma unroll
+        for (int p = 0; p < 8; ++p)
+#pragma unroll
+          for (int q = 0; q < 8; ++q) acc[p][q] = fma(ya[p], yb[q], acc[p][q]);
+      }
+      __syncthreads();
+    }
+    double* G = reinterpret_cast<double*>(RB);
+#pragma unroll
+    for (int p = 0; p < 8; ++p)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) G[(8 * bi + p) * 64 + 8 * bj + q] = acc[p][q];
   }
+  __syncthreads();
+  {
+    const double* G = reinterpret_cast<const double*>(RB);
+    double cj[KP];
+#pragma unroll
+    for (int i = 0; i < KP; ++i) cj[i] = G[i * 64 + lane];
+    __syncthreads();                             // RB is rewritten below
+    // columns k >= K are zero (G is zero there): their steps change nothing
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const double dkk = bcast64(cj[k], k);
+      const double rkk = dkk > 0.0 ? sqrt(dkk) : 0.0;
+      const double inv = rkk > 0.0 ? 1.0 / rkk : 0.0;
+      cj[k] = lane == k ? rkk : cj[k] * inv;     // row k of R (lanes > k), its pivot
+      srow[lane] = cj[k];
+      wave_sync();
+      // Schur update of the trailing entries; entries below a lane's
+      // diagonal are left as they fall and cleared below
+#pragma unroll
+      for (int i = k + 1; i < KP; ++i) cj[i] = fma(-srow[i], cj[k], cj[i]);
+      wave_sync();
+    }
+    double mx = 0.0;
+#pragma unroll
+    for (int i = 0; i < KP; ++i) {
+      if (i > lane || lane >= K) cj[i] = 0.0;
+      mx = fmax(mx, fabs(cj[i]));
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+    if (mx > 0.0) {
+      int e;
+      frexp(mx, &e);                             // mx = f 2^e, f in [0.5, 1)
+      fe = max(min(1 - e, 126), -126);
+    }
+    for (int i = 0; i < 64; ++i) Rl[lane * LS + i] = i < KP ? (float)ldexp(cj[i], fe) : 0.f;
+  }
+  __syncthreads();
 
   // ---- 2. one-sided Jacobi on the columns of M = R^T: lane i holds row i of R
   float m[KP];
@@ -451,7 +460,7 @@ k_wnnm(const float* __restrict__ xi, int H, int W, int P, int D, const int32_t* 
     atomicAdd(&st->sweeps_sum, (unsigned long long)sweeps);
   }
   // W[a][b] = sum_i w_i V[a][i] V[b][i]; lane b holds w_i V[b][i] and builds
-  // column b of W into Rl[b*LS + a]
+  // column b of W into Rl[a*TS + b] (W row-major, 16-byte rows of 64)
   {
     float vb[KP];
     load_vec(vb, Bl + lane * XS);
@@ -469,46 +478,71 @@ k_wnnm(const float* __restrict__ xi, int H, int W, int P, int D, const int32_t* 
           c2 = fmaf(va[i + 2], vb[i + 2], c2);
           c3 = fmaf(va[i + 3], vb[i + 3], c3);
         }
-        Rl[lane * LS + a] = (c0 + c1) + (c2 + c3);
+        Rl[a * TS + lane] = (c0 + c1) + (c2 + c3);
       }
+    // rows and columns of W past K are zero
+    for (int a = K; a < KP; ++a) Rl[a * TS + lane] = 0.f;
+    if (lane >= K)
+      for (int a = 0; a < K; ++a) Rl[a * TS + lane] = 0.f;
   }
   __syncthreads();
-  double wcol[KP];
-#pragma unroll
-  for (int a = 0; a < KP; ++a) wcol[a] = (lane < K && a < K) ? (double)Rl[lane * LS + a] : 0.0;
+  {
+    double ws = 0.0;
+    for (int a = 0; a < K; ++a) ws += (double)Rl[a * TS + lane];
+    srow[lane] = ws;                           // column sums of W (FP64)
+  }
+  __syncthreads();
 
-  // ---- 4. X = Y - Yc W (residual in FP64); the chunk's results go to Rl
-  // (free once W is in registers) as [j][i], then out as contiguous rows
-  // rows in the output order (dy, dx, c); each row's result is independent
-  // of the order, so the chunks are written out as contiguous runs
-  // sum_a (y_a - mu) w_a = sum_a y_a w_a - mu sum_a w_a (FP64); rows staged
-  // with a 16-byte stride and zero padding so the inner loop is branch-free
-  double wsum = 0.0;
+  // ---- 4. X = Y - Yc W (residual in FP64), per streamed chunk of rows held
+  // member-major (Bl[u*TS + i] = Y[i][u]): lane (bi, bj) computes the 8 x 8
+  // block of rows 8 bi .. and members 8 bj .., with
+  // sum_a (y_a - mu) w_a = sum_a y_a w_a - mu sum_a w_a (FP64; W and the
+  // chunk are zero past K), and writes each member's eight rows
+  {
+    const int bi = lane >> 3, bj = lane & 7;
+    double wsj[8];
 #pragma unroll
-  for (int a = 0; a < KP; ++a) wsum += wcol[a];
-  for (int d0 = 0; d0 < D; d0 += BR) {
-    const int nb = min(BR, D - d0);
-    load_rows(xi, spos, d0, nb, K, P, W, Cp, Bl, smu, XS, KP);
-    if (lane < K) {
-      for (int i = 0; i < nb; ++i) {
-        float row[KP];
-        load_vec(row, Bl + i * XS);
-        double r0 = 0.0, r1 = 0.0;
+    for (int q = 0; q < 8; ++q) wsj[q] = srow[8 * bj + q];
+    for (int d0 = 0; d0 < D; d0 += BR) {
+      const int nb = min(BR, D - d0);
+      load_rows(xi, spos, d0, nb, K, P, W, Cp, Bl, smu, TS, KP, true);
+      double acc[8][8];
 #pragma unroll
-        for (int a = 0; a < KP; a += 2) {
-          r0 = fma((double)row[a], wcol[a], r0);
-          r1 = fma((double)row[a + 1], wcol[a + 1], r1);
+      for (int p = 0; p < 8; ++p)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[p][q] = 0.0;
+#pragma unroll 2
+      for (int a = 0; a < KP; ++a) {
+        float yv[8], wv[8];
+        load_vec(yv, Bl + a * TS + 8 * bi);
+        load_vec(wv, Rl + a * TS + 8 * bj);
+        double yd[8], wd[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          yd[t] = (double)yv[t];
+          wd[t] = (double)wv[t];
         }
-        const double r = (r0 + r1) - (double)smu[i] * wsum;
-        Rl[lane * LS + i] = (float)((double)Bl[i * XS + lane] - r);
+#pragma unroll
+        for (int p = 0; p < 8; ++p)
+#pragma unroll
+          for (int q = 0; q < 8; ++q) acc[p][q] = fma(yd[p], wd[q], acc[p][q]);
       }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int j = 8 * bj + q;
+        if (j >= K) continue;
+        float* outp = xhat + ((size_t)g * K + j) * D + d0;
+        float yv[8];
+        load_vec(yv, Bl + j * TS + 8 * bi);
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+          const int i = 8 * bi + p;
+          const double r = acc[p][q] - (double)smu[i] * wsj[q];
+          if (i < nb) outp[i] = (float)((double)yv[p] - r);
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    if (lane < nb) {
-      float* outp = xhat + (size_t)g * K * D + d0 + lane;
-      for (int j = 0; j < K; ++j) outp[(size_t)j * D] = Rl[j * LS + lane];
-    }
-    __syncthreads();
   }
 }
 
