@@ -188,18 +188,22 @@ glr_status match_stage(glr_plan* pl, const float* xp, const int32_t* keys, int32
     }
     return check_hip("glr_match_topk");
   }
+  // the exact rescoring reads the channel-interleaved copy of the image
+  float* xi = (float*)(ws + pl->ws.xi);
   if (pl->search == GLR_SEARCH_WINDOW) {
     {
       StageTimer t(pl, s, T_NORMS);
       launch_gather_keys(pl, xp, keys, A, tsh, s);
+      launch_interleave(pl, xp, xi, s);
     }
     StageTimer t(pl, s, T_MATCH);
-    launch_window_topk(pl, xp, A, keys, idx_out, dd_out, s);
+    launch_window_topk(pl, xi, A, keys, idx_out, dd_out, s);
     return check_hip("glr_match_topk");
   }
   {
     StageTimer t(pl, s, T_NORMS);
     launch_gather_keys(pl, xp, keys, A, tsh, s);
+    launch_interleave(pl, xp, xi, s);
     if (bf) {
       launch_key_meta(pl, A, Ab, kmb, kre, 0, s);
       launch_cand_meta(pl, xp, cmeta, cm2, cre, 0, s);
@@ -225,7 +229,7 @@ glr_status match_stage(glr_plan* pl, const float* xp, const int32_t* keys, int32
       }
       {
         StageTimer t(pl, s, T_SELECT);
-        launch_select_rescore(pl, xp, A, kmap, g0, nk, lj, lu, ll, lcnt, idx_out, dd_out, oflag,
+        launch_select_rescore(pl, xi, A, kmap, g0, nk, lj, lu, ll, lcnt, idx_out, dd_out, oflag,
                               tsh, 0, bm, dist, kn, nullptr, pq, nullptr, 0, tkey, st, s);
       }
     }
@@ -252,7 +256,7 @@ glr_status match_stage(glr_plan* pl, const float* xp, const int32_t* keys, int32
     }
     {
       StageTimer t(pl, s, T_SELECT);
-      launch_select_rescore(pl, xp, A, nullptr, g0, nk, lj, lu, ll, lcnt, idx_out, dd_out, oflag,
+      launch_select_rescore(pl, xi, A, nullptr, g0, nk, lj, lu, ll, lcnt, idx_out, dd_out, oflag,
                             tsh, 1, bm, dist, kmb, kre, cm2, cre, 1, tkey, st, s);
       launch_collect_flags(oflag, g0, nk, klist, kcount, st, s);
     }
@@ -282,8 +286,9 @@ glr_status lowrank_stage(glr_plan* pl, const float* xp, const int32_t* idx, floa
     StageTimer t(pl, s, T_LOWRANK);
     int zn = 0;
     int32_t* z = agg_zero_range(pl, (int32_t*)(ws + pl->ws.pairs), &zn);
-    launch_wnnm(pl, xp, idx, sigma, xhat, sv, st, z, zn, count_step ? 1 : 0,
-                (float*)(ws + pl->ws.xi), gw, sigp, s);
+    float* xi = (float*)(ws + pl->ws.xi);
+    launch_interleave(pl, xp, xi, s);
+    launch_wnnm(pl, xi, idx, sigma, xhat, sv, st, z, zn, count_step ? 1 : 0, gw, sigp, s);
   }
   {
     StageTimer t(pl, s, T_AGG);

@@ -205,7 +205,8 @@ struct RowBound {
   float coef, coef2, cz;
   float* tkey;
 };
-void launch_select_rescore(const glr_plan* pl, const float* xp, const float* A,
+// xi: the channel-interleaved copy of the image (launch_interleave)
+void launch_select_rescore(const glr_plan* pl, const float* xi, const float* A,
                            const int32_t* kmap, int g0, int nk, const int32_t* lj,
                            const float* lu, const float* ll, const int32_t* lcnt, int32_t* idx,
                            float* dd, int32_t* oflag, uint32_t* tsh, int defer,
@@ -220,15 +221,20 @@ void launch_topk_heat(const glr_plan* pl, const float* dist, int g0, int nk, int
                       int32_t* idx, float* dd, hipStream_t s);
 // block matching in a (2 window + 1)^2 window around each key: exact groups
 // (compensated distances, (distance, position) order) for keys[0..N)
-void launch_window_topk(const glr_plan* pl, const float* xp, const float* A, const int32_t* keys,
+// xi: the channel-interleaved copy of the image (launch_interleave)
+void launch_window_topk(const glr_plan* pl, const float* xi, const float* A, const int32_t* keys,
                         int32_t* idx, float* dd, hipStream_t s);
 
 // lowrank.hip
 // zbuf[0..zn) is set to zero (nullable); bump != 0 counts a prior step
 // xi: scratch [H][W][Cp] for the channel-interleaved copy of xp
-void launch_wnnm(const glr_plan* pl, const float* xp, const int32_t* idx, float sigma,
+// xi[(r*W + c)*Cp + ch] = xp[ch*H*W + r*W + c]: the channel-interleaved copy
+// of a planar image that the low-rank step and the exact rescoring read
+void launch_interleave(const glr_plan* pl, const float* xp, float* xi, hipStream_t s);
+// xi: the image's channel-interleaved copy (launch_interleave), made by the caller
+void launch_wnnm(const glr_plan* pl, const float* xi, const int32_t* idx, float sigma,
                  float* xhat, float* sv, DevStats* st, int32_t* zbuf, int zn, int bump,
-                 float* xi, float* gw, const float* sigp, hipStream_t s);
+                 float* gw, const float* sigp, hipStream_t s);
 // one inner WNNM iteration's regularisation: ynew = x + delta (xbar - yprev)
 // (ynew may be yprev), and sig_out = lambda sqrt(max(sigma^2 - mean((xbar -
 // ynew)^2), 0)) on the device; part holds 1024 doubles

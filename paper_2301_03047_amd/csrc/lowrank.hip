@@ -600,13 +600,16 @@ void launch_inner_update(const float* xbar, const float* x, const float* yprev, 
   hipLaunchKernelGGL(k_inner_sigma, dim3(1), dim3(IG), 0, s, part, n, sigma, lambda, sig_out);
 }
 
-void launch_wnnm(const glr_plan* pl, const float* xp, const int32_t* idx, float sigma,
-                 float* xhat, float* sv, DevStats* st, int32_t* zbuf, int zn, int bump,
-                 float* xi, float* gw, const float* sigp, hipStream_t s) {
-  const int K = pl->K;
+void launch_interleave(const glr_plan* pl, const float* xp, float* xi, hipStream_t s) {
   const size_t HW = (size_t)pl->H * pl->W, n = HW * pl->Cp;
   hipLaunchKernelGGL(k_interleave, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, xp, pl->Cp,
                      HW, xi);
+}
+
+void launch_wnnm(const glr_plan* pl, const float* xi, const int32_t* idx, float sigma,
+                 float* xhat, float* sv, DevStats* st, int32_t* zbuf, int zn, int bump,
+                 float* gw, const float* sigp, hipStream_t s) {
+  const int K = pl->K;
   if (K <= 32)
     hipLaunchKernelGGL(k_wnnm<32>, dim3(pl->N), dim3(64), 0, s, xi, pl->H, pl->W, pl->P, pl->D,
                        idx, K, sigma, sigp, pl->wnnm_c, pl->wnnm_eps, 30, xhat, sv, st, zbuf, zn, bump,

@@ -372,16 +372,19 @@ __device__ int block_sum_i(int v, int* sh) {
 // ---------------------------------------------------------------- exact rescoring
 // The compensated (double-float32) distance of one candidate is computed by
 // L lanes together (L = 8..64, a power of two fixed by D): lane s of the
-// group owns the patch elements d = s + e L, holds the key's values and the
-// elements' image offsets in registers, accumulates its squared differences
-// with TwoSum/TwoProd, and the group combines its partial sums with a
-// butterfly of compensated additions (every lane of the group ends with the
-// same value).  Candidate rows are read as P-float segments, so a wave's
-// loads are coalesced, and the key is read once per key.
+// group owns the patch elements t = s + e L in the channel-interleaved order
+// t = (dy P + dx) Cp + c, holds the key's values and the elements' offsets
+// in registers, accumulates its squared differences with TwoSum/TwoProd, and
+// the group combines its partial sums with a butterfly of compensated
+// additions (every lane of the group ends with the same value).  Candidates
+// are read from the channel-interleaved copy of the image, xi[(r W + c) Cp +
+// ch]: a patch row over all channels is one contiguous run of P Cp floats,
+// so consecutive lanes read consecutive addresses and a patch spans P runs
+// (P Cp / 32 cache lines each) instead of Cp P segments of P floats.
 template <int EM>
 struct KeySlice {
   float kv[EM];
-  int off[EM];       // image offset of element d relative to the patch's top-left
+  int off[EM];       // offset of element t in xi relative to the patch's top-left
 };
 
 // Elements past D get offset 0 and are masked to a zero difference, so every
@@ -389,14 +392,15 @@ struct KeySlice {
 template <int EM>
 __device__ __forceinline__ void key_slice_load(KeySlice<EM>& ks, const float* __restrict__ kvec,
                                                int D, int P, int H, int W, int L, int s) {
+  const int Cp = D / (P * P);
 #pragma unroll
   for (int e = 0; e < EM; ++e) {
-    const int d = s + e * L;
-    if (d < D) {
-      const int c = d / (P * P), rem = d - c * (P * P);
-      const int dy = rem / P, dx = rem - dy * P;
-      ks.kv[e] = kvec[d];
-      ks.off[e] = (c * H + dy) * W + dx;
+    const int t = s + e * L;
+    if (t < D) {
+      const int pix = t / Cp, c = t - pix * Cp;
+      const int dy = pix / P, dx = pix - dy * P;
+      ks.kv[e] = kvec[(c * P + dy) * P + dx];    // the key vector is in (c, dy, dx) order
+      ks.off[e] = (dy * W + dx) * Cp + c;
     } else {
       ks.kv[e] = 0.f;
       ks.off[e] = -1;
@@ -404,18 +408,20 @@ __device__ __forceinline__ void key_slice_load(KeySlice<EM>& ks, const float* __
   }
 }
 
-// Compensated distances of two candidates (image offsets b0, b1 of their
+// Compensated distances of two candidates (xi offsets b0, b1 of their
 // top-left pixels; both valid positions) by the L-lane group; every lane of
 // the group returns the group's sums.
 template <int EM>
-__device__ __forceinline__ void coop_dist2(const KeySlice<EM>& ks, const float* __restrict__ xp,
-                                           int b0, int b1, int L, df32& r0, df32& r1) {
+__device__ __forceinline__ void coop_dist2(const KeySlice<EM>& ks, const float* __restrict__ xi,
+                                           size_t b0, size_t b1, int L, df32& r0, df32& r1) {
   float p0[EM], p1[EM];
+  const float* x0 = xi + b0;
+  const float* x1 = xi + b1;
 #pragma unroll
   for (int e = 0; e < EM; ++e) {
     const int o = ks.off[e] < 0 ? 0 : ks.off[e];
-    p0[e] = xp[b0 + o];
-    p1[e] = xp[b1 + o];
+    p0[e] = x0[o];
+    p1[e] = x1[o];
   }
   df32 a0 = {0.f, 0.f}, a1 = {0.f, 0.f};
 #pragma unroll
@@ -440,9 +446,9 @@ __device__ __forceinline__ void coop_dist2(const KeySlice<EM>& ks, const float* 
 // groups take two entries each.  Invalid slots read position 0 and are not
 // written.
 template <int EM, typename PosF>
-__device__ __forceinline__ void coop_rescore(const KeySlice<EM>& ks, const float* __restrict__ xp,
+__device__ __forceinline__ void coop_rescore(const KeySlice<EM>& ks, const float* __restrict__ xi,
                                              PosF pos, int first, int m, int stride, int Wc,
-                                             int W, int L, float* hh, float* ll) {
+                                             int W, int Cp, int L, float* hh, float* ll) {
   const int l = lane_id();
   const int s = l & (L - 1), grp = l / L, cpi = 64 / L;
   for (int i0 = first; i0 < m; i0 += stride) {
@@ -451,7 +457,8 @@ __device__ __forceinline__ void coop_rescore(const KeySlice<EM>& ks, const float
     const int ja = va ? pos(ia) : 0, jb = vb ? pos(ib) : 0;
     const int ra = ja / Wc, rb = jb / Wc;
     df32 da, db;
-    coop_dist2(ks, xp, ra * W + (ja - ra * Wc), rb * W + (jb - rb * Wc), L, da, db);
+    coop_dist2(ks, xi, (size_t)(ra * W + (ja - ra * Wc)) * Cp,
+               (size_t)(rb * W + (jb - rb * Wc)) * Cp, L, da, db);
     if (s == 0) {
       if (va) { hh[ia] = da.hi; ll[ia] = da.lo; }
       if (vb) { hh[ib] = db.hi; ll[ib] = db.lo; }
@@ -504,18 +511,22 @@ __device__ void wave_bitonic(float* h, float* lo, int* j, int n) {
     }
 }
 
-constexpr int UW = 1024;          // margin-set capacity per key (wave path)
+constexpr int UW = 1024;          // list entries staged per key (wave path)
+// Margin sets above MW go to the block path (four waves per key): the wave
+// path rescores two candidates at a time, so a launch would otherwise wait
+// on its keys with the largest sets.
+constexpr int MW = 256;
 
 // One wave per key: the key's threshold T (K-th smallest U over all range
 // lists) by a radix selection streamed over the lists, the margin set
 // {L <= T} gathered in list order, rescored with compensated arithmetic,
 // sorted by (distance, position); the first K are kept.  Only the margin set
 // is held in LDS, so the lists' union may be far larger than UW.  Keys
-// whose margin set exceeds UW, or whose range lists overflowed, are flagged
+// whose margin set exceeds MW, or whose range lists overflowed, are flagged
 // for the kernel below.
 template <int EM>
 __global__ void __launch_bounds__(256)
-k_select_rescore(const float* __restrict__ xp, int H, int W, int P, int Cp, int D, int L,
+k_select_rescore(const float* __restrict__ xi, int H, int W, int P, int Cp, int D, int L,
                  const float* __restrict__ A, const int32_t* __restrict__ kmap, int g0, int nk,
                  int S, int Ncand, int K,
                  const int32_t* __restrict__ lj, const float* __restrict__ lu,
@@ -606,8 +617,8 @@ k_select_rescore(const float* __restrict__ xp, int H, int W, int P, int Cp, int 
       }
     }
   }
-  if (m > UW || m < K) {                     // m < K cannot happen with valid lists
-    if (l == 0) oflag[g] = m > UW ? 1 : 2;
+  if (m > MW || m < K) {                     // m < K cannot happen with valid lists
+    if (l == 0) oflag[g] = m > MW ? 1 : 2;
     return;
   }
   if (l == 0) oflag[g] = 0;
@@ -616,7 +627,7 @@ k_select_rescore(const float* __restrict__ xp, int H, int W, int P, int Cp, int 
   {
     KeySlice<EM> ks;
     key_slice_load(ks, A + (size_t)gg * D, D, P, H, W, L, l & (L - 1));
-    coop_rescore(ks, xp, [&](int i) { return jj[i]; }, 0, m, 2 * (64 / L), Wc, W, L, u, lo);
+    coop_rescore(ks, xi, [&](int i) { return jj[i]; }, 0, m, 2 * (64 / L), Wc, W, Cp, L, u, lo);
   }
   wave_sync_lds();
   int n2 = 1;
@@ -644,15 +655,15 @@ k_select_rescore(const float* __restrict__ xp, int H, int W, int P, int Cp, int 
 // 96-bit key (ord(hi), ord(lo + 0), position), the K entries at or below it
 // gathered and sorted in LDS.  Every thread of the block calls it.
 template <int EM>
-__device__ void rescore_select_set(const KeySlice<EM>& ks, const float* __restrict__ xp,
+__device__ void rescore_select_set(const KeySlice<EM>& ks, const float* __restrict__ xi,
                                    const int32_t* gp, float* gh, float* gl, int m, int K, int Wc,
-                                   int W, int L, int gg, int32_t* __restrict__ idx,
+                                   int W, int Cp, int L, int gg, int32_t* __restrict__ idx,
                                    float* __restrict__ dd, float* su, float* sl, int* sj,
                                    int* ssh, int* hist, uint32_t* sdig) {
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
   const int cpi = 64 / L;
-  coop_rescore(ks, xp, [&](int i) { return gp[i]; }, wave * 2 * cpi, m, 8 * cpi, Wc, W, L, gh,
+  coop_rescore(ks, xi, [&](int i) { return gp[i]; }, wave * 2 * cpi, m, 8 * cpi, Wc, W, Cp, L, gh,
                gl);
   __syncthreads();
   uint32_t pre[3] = {0u, 0u, 0u};
@@ -759,7 +770,7 @@ __device__ float block_kth_by_bisection(const float* vals, int m, int K, int* ss
 // left flagged for a later pass; keys completed here get their flag cleared.
 template <int EM>
 __global__ void __launch_bounds__(ST)
-k_rescore_overflow(const float* __restrict__ xp, int H, int W, int P, int Cp, int D, int L,
+k_rescore_overflow(const float* __restrict__ xi, int H, int W, int P, int Cp, int D, int L,
                    const float* __restrict__ A, const int32_t* __restrict__ kmap, int g0, int S,
                    int Ncand, int K, int defer,
                    const int32_t* __restrict__ lj, const float* __restrict__ lu,
@@ -825,7 +836,7 @@ k_rescore_overflow(const float* __restrict__ xp, int H, int W, int P, int Cp, in
       if (defer) return;
       goto full_row;
     }
-    rescore_select_set(ks, xp, gpos + go, ghi + go, glo + go, m, K, Wc, W, L, gg, idx, dd, su,
+    rescore_select_set(ks, xi, gpos + go, ghi + go, glo + go, m, K, Wc, W, Cp, L, gg, idx, dd, su,
                        sl, sj, ssh, hist, sdig);
     if (tid == 0) {
       oflag[g] = 0;
@@ -922,7 +933,7 @@ k_rescore_overflow(const float* __restrict__ xp, int H, int W, int P, int Cp, in
       }
       __syncthreads();
       m = n;
-      rescore_select_set(ks, xp, gpos + go, ghi + go, glo + go, m, K, Wc, W, L, gg, idx, dd, su,
+      rescore_select_set(ks, xi, gpos + go, ghi + go, glo + go, m, K, Wc, W, Cp, L, gg, idx, dd, su,
                          sl, sj, ssh, hist, sdig);
       if (tid == 0) {
         oflag[g] = 0;
@@ -941,8 +952,8 @@ full_row:
   float th = __int_as_float(0x7f800000), tl = 0.f;
   int tj = 0x7fffffff;
   for (int base = 0; base < Ncand; base += ST) {
-    coop_rescore(ks, xp, [&](int i) { return base + i; }, wave * 2 * cpi, min(ST, Ncand - base),
-                 8 * cpi, Wc, W, L, fh, fl);
+    coop_rescore(ks, xi, [&](int i) { return base + i; }, wave * 2 * cpi, min(ST, Ncand - base),
+                 8 * cpi, Wc, W, Cp, L, fh, fl);
     __syncthreads();
     const int j = base + tid;
     df32 v = {0.f, 0.f};
@@ -999,7 +1010,7 @@ full_row:
 // the window is small enough to score directly.
 template <int EM>
 __global__ void __launch_bounds__(ST)
-k_window_topk(const float* __restrict__ xp, int H, int W, int P, int D, int L,
+k_window_topk(const float* __restrict__ xi, int H, int W, int P, int D, int L,
               const float* __restrict__ A, const int32_t* __restrict__ keys, int N, int K,
               int win, int32_t* __restrict__ idx, float* __restrict__ dd) {
   __shared__ float su[UCAP];
@@ -1030,8 +1041,8 @@ k_window_topk(const float* __restrict__ xp, int H, int W, int P, int D, int L,
   float th = __int_as_float(0x7f800000), tl = 0.f;
   int tj = 0x7fffffff;
   for (int base = 0; base < n; base += ST) {
-    coop_rescore(ks, xp, [&](int i) { return pos(base + i); }, wave * 2 * cpi, min(ST, n - base),
-                 8 * cpi, Wc, W, L, fh, fl);
+    coop_rescore(ks, xi, [&](int i) { return pos(base + i); }, wave * 2 * cpi, min(ST, n - base),
+                 8 * cpi, Wc, W, D / (P * P), L, fh, fl);
     __syncthreads();
     const int i = base + tid;
     df32 v = {0.f, 0.f};
@@ -1226,21 +1237,21 @@ static int rescore_lanes(int D) {
 }
 
 template <int EM>
-static void launch_select_t(const glr_plan* pl, const float* xp, const float* A,
+static void launch_select_t(const glr_plan* pl, const float* xi, const float* A,
                             const int32_t* kmap, int g0, int nk, const int32_t* lj,
                             const float* lu, const float* ll, const int32_t* lcnt, int32_t* idx,
                             float* dd, int32_t* oflag, uint32_t* tsh, int defer,
                             const BigMargin& bm, const RowBound& rb, DevStats* st, int L,
                             hipStream_t s) {
-  hipLaunchKernelGGL(k_select_rescore<EM>, dim3((nk + 3) / 4), dim3(256), 0, s, xp, pl->H, pl->W,
+  hipLaunchKernelGGL(k_select_rescore<EM>, dim3((nk + 3) / 4), dim3(256), 0, s, xi, pl->H, pl->W,
                      pl->P, pl->Cp, pl->D, L, A, kmap, g0, nk, pl->n_split, pl->Ncand, pl->K, lj,
                      lu, ll, lcnt, idx, dd, oflag, tsh, rb.tkey, st);
-  hipLaunchKernelGGL(k_rescore_overflow<EM>, dim3(nk), dim3(ST), 0, s, xp, pl->H, pl->W, pl->P,
+  hipLaunchKernelGGL(k_rescore_overflow<EM>, dim3(nk), dim3(ST), 0, s, xi, pl->H, pl->W, pl->P,
                      pl->Cp, pl->D, L, A, kmap, g0, pl->n_split, pl->Ncand, pl->K, defer, lj, lu,
                      ll, lcnt, oflag, bm.pos, bm.hi, bm.lo, bm.cap, idx, dd, rb, st);
 }
 
-void launch_select_rescore(const glr_plan* pl, const float* xp, const float* A,
+void launch_select_rescore(const glr_plan* pl, const float* xi, const float* A,
                            const int32_t* kmap, int g0, int nk, const int32_t* lj,
                            const float* lu, const float* ll, const int32_t* lcnt, int32_t* idx,
                            float* dd, int32_t* oflag, uint32_t* tsh, int defer,
@@ -1259,10 +1270,10 @@ void launch_select_rescore(const glr_plan* pl, const float* xp, const float* A,
   rb.tkey = tkey;
   const int L = rescore_lanes(pl->D);
   if ((pl->D + L - 1) / L <= 32)
-    launch_select_t<32>(pl, xp, A, kmap, g0, nk, lj, lu, ll, lcnt, idx, dd, oflag, tsh, defer, bm,
+    launch_select_t<32>(pl, xi, A, kmap, g0, nk, lj, lu, ll, lcnt, idx, dd, oflag, tsh, defer, bm,
                         rb, st, L, s);
   else
-    launch_select_t<64>(pl, xp, A, kmap, g0, nk, lj, lu, ll, lcnt, idx, dd, oflag, tsh, defer, bm,
+    launch_select_t<64>(pl, xi, A, kmap, g0, nk, lj, lu, ll, lcnt, idx, dd, oflag, tsh, defer, bm,
                         rb, st, L, s);
 }
 
@@ -1293,14 +1304,14 @@ void launch_collect_flags(const int32_t* oflag, int g0, int nk, int32_t* klist, 
   hipLaunchKernelGGL(k_collect_flags, dim3(1), dim3(1024), 0, s, oflag, g0, nk, klist, kcount, st);
 }
 
-void launch_window_topk(const glr_plan* pl, const float* xp, const float* A, const int32_t* keys,
+void launch_window_topk(const glr_plan* pl, const float* xi, const float* A, const int32_t* keys,
                         int32_t* idx, float* dd, hipStream_t s) {
   const int L = rescore_lanes(pl->D);
   if ((pl->D + L - 1) / L <= 32)
-    hipLaunchKernelGGL(k_window_topk<32>, dim3(pl->N), dim3(ST), 0, s, xp, pl->H, pl->W, pl->P,
+    hipLaunchKernelGGL(k_window_topk<32>, dim3(pl->N), dim3(ST), 0, s, xi, pl->H, pl->W, pl->P,
                        pl->D, L, A, keys, pl->N, pl->K, pl->window, idx, dd);
   else
-    hipLaunchKernelGGL(k_window_topk<64>, dim3(pl->N), dim3(ST), 0, s, xp, pl->H, pl->W, pl->P,
+    hipLaunchKernelGGL(k_window_topk<64>, dim3(pl->N), dim3(ST), 0, s, xi, pl->H, pl->W, pl->P,
                        pl->D, L, A, keys, pl->N, pl->K, pl->window, idx, dd);
 }
 
