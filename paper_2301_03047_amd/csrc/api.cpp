@@ -677,9 +677,11 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
   const bool bf = pr->precision == GLR_PREC_BF16_RESCORE || edge;
   L.kmb = c.take(bf ? (size_t)pl->N * 16 : 0);
   L.cmeta = c.take(bf ? (size_t)Ncand * 16 : 0);
-  L.cm2 = c.take(bf ? (size_t)Ncand * 8 : 0);
+  // arrays the top-K stage streams carry SPAD entries of padding, so its
+  // chunked loads stay in bounds without a ragged-edge path
+  L.cm2 = c.take(bf ? ((size_t)Ncand + SPAD) * 8 : 0);
   L.kre = c.take(bf ? (size_t)pl->N * 4 : 0);
-  L.cre = c.take(bf ? (size_t)Ncand * 4 : 0);
+  L.cre = c.take(bf ? ((size_t)Ncand + SPAD) * 4 : 0);
   L.E = c.take(edge ? (size_t)4 * Ce * HW * 4 : 0);
   L.eq = c.take(edge ? (size_t)Ce * HW : 0);
   L.egx = c.take(edge ? (size_t)2 * Ce * HW * 2 : 0);
@@ -689,7 +691,7 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
   L.kc = c.take((size_t)pl->N * Cp * 4);
   L.pn = c.take((size_t)Ncand * 4);
   L.pc = c.take((size_t)Cp * Ncand * 8);
-  L.pq = c.take((size_t)Ncand * 8);
+  L.pq = c.take(((size_t)Ncand + SPAD) * 8);
   L.Ab = c.take(bf ? (size_t)pl->N * (edge ? std::max(Cp, 4 * Ce) : Cp) * bf16_key_row(P) * 2 : 0);
   L.tsh = c.take((size_t)pl->n_chunk * 4);
   L.tkey = c.take((size_t)pl->n_chunk * 4);
@@ -699,7 +701,7 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
   L.bpos = c.take((size_t)pl->n_chunk * pl->mcap * 4);
   L.bhi = c.take((size_t)pl->n_chunk * pl->mcap * 4);
   L.blo = c.take((size_t)pl->n_chunk * pl->mcap * 4);
-  L.dist = c.take((size_t)pl->n_chunk * pl->ldd * 4);
+  L.dist = c.take(((size_t)pl->n_chunk * pl->ldd + SPAD) * 4);
   const size_t nlist = (size_t)pl->n_chunk * pl->n_split;
   L.lj = c.take(nlist * GLR_SPLIT_CAP * 4);
   L.lu = c.take(nlist * GLR_SPLIT_CAP * 4);

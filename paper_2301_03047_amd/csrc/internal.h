@@ -194,6 +194,10 @@ struct BigMargin {
 // and candidate bound terms the scan used (same arguments as
 // launch_topk_partial), and tkey, where the select kernel leaves the bound
 // each key's scan published.
+// Padding (entries) after the arrays the top-K stage streams in chunks:
+// the distance chunk, the candidate bound terms (cm2, cre, pq).  Its reads
+// reach at most two chunks (2 x 768 candidates) past a range's end.
+constexpr int SPAD = 2048;
 struct RowBound {
   const float* dist;
   size_t ldd;

@@ -173,12 +173,12 @@ __device__ __forceinline__ float margin_eps(float d, float p, float m, float ep,
 //    distance.
 // tsh[g]: the key's shared bound of T (ordered bits, +inf at launch), lowered
 // with atomicMin by every range.
-template <int U4, int WCAP, int MINW, bool PF>
+template <int U4, int WCAP, int MINW, bool PF, int pc>
 __global__ void __launch_bounds__(256, MINW)
 k_topk_partial(const float* __restrict__ dist, size_t ldd, const float4* __restrict__ km,
                const float* __restrict__ ke, const int32_t* __restrict__ kmap, int g0,
                const float* __restrict__ cm, const float* __restrict__ ce, int Ncand,
-               int split_len, int S, int nk, int K, int pc, float coef, float coef2, float cz,
+               int split_len, int S, int nk, int K, float coef, float coef2, float cz,
                uint32_t* __restrict__ tsh, int32_t* __restrict__ lj, float* __restrict__ lu,
                float* __restrict__ ll, int32_t* __restrict__ lcnt) {
   static_assert(WCAP >= 512 && WCAP <= CAP, "wave buffer size");
@@ -228,48 +228,38 @@ k_topk_partial(const float* __restrict__ dist, size_t ldd, const float4* __restr
   // SIMD cover the latency)
   float dv[U4][4], pv[U4][4], mv[U4][4], dn[U4][4], pn[U4][4], mn[U4][4];
   float ev[U4][4], en[U4][4];
+  // Every load is one unconditional 16-byte read, and the next chunk is
+  // always prefetched: a chunk starts at most one chunk past the range (j0
+  // and the chunk size are multiples of 4, so j is too) and the streamed
+  // arrays carry SPAD entries of padding, so reads past j1 stay in bounds;
+  // their values are never admitted (ok below).  No branch around a load,
+  // so the next chunk's loads stay in flight while this one is processed.
   auto load_ev = [&](int base, float (&ee)[U4][4]) {
 #pragma unroll
     for (int u = 0; u < U4; ++u) {
       const int j = base + u * 256 + 4 * l;
-      if (!pc && j + 3 < j1) {
-        const float4 c4 = *reinterpret_cast<const float4*>(ce + j);
-        ee[u][0] = c4.x; ee[u][1] = c4.y; ee[u][2] = c4.z; ee[u][3] = c4.w;
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) ee[u][e] = (!pc && j + e < j1) ? ce[j + e] : 0.f;
-      }
+      float4 c4 = make_float4(0.f, 0.f, 0.f, 0.f);
+      if constexpr (!pc) c4 = *reinterpret_cast<const float4*>(ce + j);   // pc: no residual norms
+      ee[u][0] = c4.x; ee[u][1] = c4.y; ee[u][2] = c4.z; ee[u][3] = c4.w;
     }
   };
   auto load = [&](int base, float (&d)[U4][4], float (&p)[U4][4], float (&m)[U4][4]) {
 #pragma unroll
     for (int u = 0; u < U4; ++u) {
       const int j = base + u * 256 + 4 * l;
-      if (j + 3 < j1) {
-        const float4 a = *reinterpret_cast<const float4*>(drow + j);
-        d[u][0] = a.x; d[u][1] = a.y; d[u][2] = a.z; d[u][3] = a.w;
-        const float4 b0 = *reinterpret_cast<const float4*>(cm + 2 * (size_t)j);
-        const float4 b1 = *reinterpret_cast<const float4*>(cm + 2 * (size_t)j + 4);
-        m[u][0] = b0.x; p[u][0] = b0.y; m[u][1] = b0.z; p[u][1] = b0.w;
-        m[u][2] = b1.x; p[u][2] = b1.y; m[u][3] = b1.z; p[u][3] = b1.w;
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const bool ok = j + e < j1;
-          d[u][e] = ok ? drow[j + e] : 0.f;
-          m[u][e] = ok ? cm[2 * (size_t)(j + e)] : 0.f;
-          p[u][e] = ok ? cm[2 * (size_t)(j + e) + 1] : 0.f;
-        }
-      }
+      const float4 a = *reinterpret_cast<const float4*>(drow + j);
+      d[u][0] = a.x; d[u][1] = a.y; d[u][2] = a.z; d[u][3] = a.w;
+      const float4 b0 = *reinterpret_cast<const float4*>(cm + 2 * (size_t)j);
+      const float4 b1 = *reinterpret_cast<const float4*>(cm + 2 * (size_t)j + 4);
+      m[u][0] = b0.x; p[u][0] = b0.y; m[u][1] = b0.z; p[u][1] = b0.w;
+      m[u][2] = b1.x; p[u][2] = b1.y; m[u][3] = b1.z; p[u][3] = b1.w;
     }
   };
   load(j0, dv, pv, mv);
   if constexpr (PF) load_ev(j0, ev);
   for (int base = j0; base < j1; base += CH) {
-    if (base + CH < j1) {
-      load(base + CH, dn, pn, mn);
-      if constexpr (PF) load_ev(base + CH, en);
-    }
+    load(base + CH, dn, pn, mn);
+    if constexpr (PF) load_ev(base + CH, en);
     if constexpr (!PF) load_ev(base, ev);
     // positions past the end of the range are never admitted (explicit
     // validity: an infinite L would still pass L <= T while T is +inf)
@@ -1212,19 +1202,19 @@ void launch_topk_partial(const glr_plan* pl, const float* dist, const float* kmb
   // match call and restored by the rescoring kernel after every scan
   // the FP32 form's margin sets stay far below the BF16 form's: a smaller
   // wave buffer (28 KB of LDS per block) and no residual norms to prefetch
-  // fit four waves per SIMD; the BF16 form's 1024-entry buffers (53 KB) fit
-  // three, and its 768-candidate steps (12 bytes of bound terms per
-  // candidate, all prefetched one step ahead) keep the registers within them
+  // fit three waves per SIMD; the BF16 form's 1024-entry buffers (53 KB) and
+  // its 768-candidate steps (16 bytes per candidate, always prefetched one
+  // step ahead) fit two.  Either way 8 to 12 KB per wave are in flight.
   const dim3 grid((nk + 3) / 4 * pl->n_split);
   if (bf16)
-    hipLaunchKernelGGL((k_topk_partial<3, CAP, 3, true>), grid, dim3(256), 0, s, dist,
+    hipLaunchKernelGGL((k_topk_partial<3, CAP, 2, true, 0>), grid, dim3(256), 0, s, dist,
                        (size_t)pl->ldd, (const float4*)kmb, kre, kmap, g0, cm2, cre, pl->Ncand,
-                       pl->split_len, pl->n_split, nk, pl->K, 0, coef, coef2, cz, tsh, lj, lu, ll,
+                       pl->split_len, pl->n_split, nk, pl->K, coef, coef2, cz, tsh, lj, lu, ll,
                        lcnt);
   else
-    hipLaunchKernelGGL((k_topk_partial<3, 512, 4, false>), grid,
+    hipLaunchKernelGGL((k_topk_partial<3, 512, 3, false, 1>), grid,
                        dim3(256), 0, s, dist, (size_t)pl->ldd, (const float4*)kmb, kre, kmap, g0,
-                       cm2, cre, pl->Ncand, pl->split_len, pl->n_split, nk, pl->K, 1, coef, coef2,
+                       cm2, cre, pl->Ncand, pl->split_len, pl->n_split, nk, pl->K, coef, coef2,
                        cz, tsh, lj, lu, ll, lcnt);
 }
 
