@@ -1258,8 +1258,17 @@ void launch_select_rescore(const glr_plan* pl, const float* xi, const float* A,
   rb.pc = bf16 ? 0 : 1;
   margin_coefs(pl, bf16, &rb.coef, &rb.coef2, &rb.cz);
   rb.tkey = tkey;
+  // the slice held per lane: the smallest instance that fits (registers,
+  // hence waves per SIMD, follow it)
   const int L = rescore_lanes(pl->D);
-  if ((pl->D + L - 1) / L <= 32)
+  const int em = (pl->D + L - 1) / L;
+  if (em <= 16)
+    launch_select_t<16>(pl, xi, A, kmap, g0, nk, lj, lu, ll, lcnt, idx, dd, oflag, tsh, defer, bm,
+                        rb, st, L, s);
+  else if (em <= 24)
+    launch_select_t<24>(pl, xi, A, kmap, g0, nk, lj, lu, ll, lcnt, idx, dd, oflag, tsh, defer, bm,
+                        rb, st, L, s);
+  else if (em <= 32)
     launch_select_t<32>(pl, xi, A, kmap, g0, nk, lj, lu, ll, lcnt, idx, dd, oflag, tsh, defer, bm,
                         rb, st, L, s);
   else
@@ -1297,7 +1306,14 @@ void launch_collect_flags(const int32_t* oflag, int g0, int nk, int32_t* klist, 
 void launch_window_topk(const glr_plan* pl, const float* xi, const float* A, const int32_t* keys,
                         int32_t* idx, float* dd, hipStream_t s) {
   const int L = rescore_lanes(pl->D);
-  if ((pl->D + L - 1) / L <= 32)
+  const int em = (pl->D + L - 1) / L;
+  if (em <= 16)
+    hipLaunchKernelGGL(k_window_topk<16>, dim3(pl->N), dim3(ST), 0, s, xi, pl->H, pl->W, pl->P,
+                       pl->D, L, A, keys, pl->N, pl->K, pl->window, idx, dd);
+  else if (em <= 24)
+    hipLaunchKernelGGL(k_window_topk<24>, dim3(pl->N), dim3(ST), 0, s, xi, pl->H, pl->W, pl->P,
+                       pl->D, L, A, keys, pl->N, pl->K, pl->window, idx, dd);
+  else if (em <= 32)
     hipLaunchKernelGGL(k_window_topk<32>, dim3(pl->N), dim3(ST), 0, s, xi, pl->H, pl->W, pl->P,
                        pl->D, L, A, keys, pl->N, pl->K, pl->window, idx, dd);
   else
