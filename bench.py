@@ -74,6 +74,7 @@ KERNEL_SOURCES = {
     "k_match_f32": "paper_2301_03047_amd/csrc/match.hip",
     "k_match_f32_slab": "paper_2301_03047_amd/csrc/match.hip",
     "k_match_bf16": "paper_2301_03047_amd/csrc/match.hip",
+    "k_match_bf16_db": "paper_2301_03047_amd/csrc/match.hip",
     "k_topk_partial": "paper_2301_03047_amd/csrc/topk.hip",
 }
 CONFIG_TEXT = {
@@ -139,7 +140,9 @@ def kernel_rooflines(wl, prec, st, n_iter):
     if launches:
         ms = st["ms_match"] / launches
         flop = 2.0 * wl.n_keys * wl.n_cand * wl.dim * n_iter / launches
-        name = "k_match_bf16" if prec == "bf16" else f32_kernel
+        # the double-buffered BF16 matcher serves patch sides up to 8
+        bf16_kernel = "k_match_bf16_db" if wl.patch <= 8 else "k_match_bf16"
+        name = bf16_kernel if prec == "bf16" else f32_kernel
         peak = PEAK_BF16_MFMA_TFLOPS if prec == "bf16" else PEAK_FP32_MFMA_TFLOPS
         ach = flop / (ms * 1e-3) / 1e12
         out[name] = {"bound": "mfma", "achieved": round(ach, 3), "peak": peak,

@@ -6,8 +6,9 @@
 // Deterministic: entries e = g*K + q are bucketed by position with a
 // counting sort (integer counts, an exclusive scan for the CSR offsets, a
 // scatter, then each bucket sorted by e), and each pixel gathers its
-// covering estimates in a fixed order (dy, dx, e ascending); no
-// floating-point atomics.
+// covering estimates in a fixed order (slice, then dy, dx, e ascending,
+// with the row segments' entry streams cut into equal slices for load
+// balance); no floating-point atomics.
 #include "common.h"
 #include "internal.h"
 
@@ -137,39 +138,90 @@ k_bucket_sort_large(const int32_t* __restrict__ offs, int32_t* __restrict__ ent,
   }
 }
 
-constexpr int GX = 64;            // pixels per block (one image row segment)
+constexpr int GX = 64;            // pixels per row segment
 constexpr int GT = 256;           // threads per block
-constexpr int CG = 32;            // channels per block (grid z covers the rest)
+constexpr int CG = 32;            // channels per block (grid y covers the rest)
 constexpr int LDS_FLOATS = 8192;  // staged estimate rows per chunk (32 KB)
 constexpr int UB = 4;             // 16-byte staging loads in flight per thread
+constexpr int EB = 1024;          // entries per gather slice (load balance)
 
-// One block per (image row r, 64-pixel segment, channel group).  Estimates
-// are stored per member patch as xhat[e][dy][dx][c], so the dy-row of an
-// entry is one contiguous run of P*Cp floats.  For each dy the entries of
-// the window of top-left positions (row r - dy, columns c0 - P + 1 ..
-// c0 + GX - 1) are contiguous in the CSR order; their dy-rows are staged in
-// LDS in chunks (all loads of a thread's batch issued before its stores)
-// and every (pixel, channel) of the block sums its covering values in the
+// The work of a row segment (image row r, 64 pixels from c0) is the stream
+// of entries that cover it: for dy = 0 .. P-1, the entries of the window of
+// top-left positions (row r - dy, columns c0 - P + 1 .. c0 + GX - 1), which
+// are contiguous in the CSR order.  Segments differ by orders of magnitude
+// (a candidate many groups chose makes its neighbourhood heavy), so the
+// stream is cut into slices of EB entries, one block each: a segment with
+// one slice writes the image directly; a heavier one writes per-slice
+// partial sums that k_gather_combine adds in slice order.  Every sum keeps a
+// fixed order (slice, then within a slice dy, position, entry ascending): the
+// output is deterministic.
+__device__ __forceinline__ int seg_entries(const int32_t* __restrict__ offs, int r, int c0, int H,
+                                           int W, int P) {
+  const int Hc = H - P + 1, Wc = W - P + 1;
+  const int tc0 = max(0, c0 - P + 1), tc1 = min(Wc - 1, c0 + GX - 1);
+  int e = 0;
+  for (int dy = 0; dy < P; ++dy) {
+    const int tr = r - dy;
+    if (tr >= 0 && tr < Hc && tc0 <= tc1) e += offs[tr * Wc + tc1 + 1] - offs[tr * Wc + tc0];
+  }
+  return e;
+}
+
+// slices per segment (at least one): nsub[id], id = r * nsw + segment
+__global__ void k_gather_count(const int32_t* __restrict__ offs, int H, int W, int P, int nsw,
+                               int32_t* __restrict__ nsub) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id > H * nsw) return;
+  if (id == H * nsw) {                       // the scan's last entry: the total
+    nsub[id] = 0;
+    return;
+  }
+  const int e = seg_entries(offs, id / nsw, (id % nsw) * GX, H, W, P);
+  nsub[id] = max(1, (e + EB - 1) / EB);
+}
+
+// owner[sub] = the segment of slice sub (first[]: exclusive scan of nsub)
+__global__ void k_gather_expand(const int32_t* __restrict__ first, int nseg,
+                                int32_t* __restrict__ owner) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nseg) return;
+  for (int k = first[id]; k < first[id + 1]; ++k) owner[k] = id;
+}
+
+// One block per (slice, channel group).  Estimates are stored per member
+// patch as xhat[e][dy][dx][c], so the dy-row of an entry is one contiguous
+// run of P*Cp floats.  The slice's entries are staged window by window in
+// LDS in chunks (all loads of a thread's batch issued before its stores) and
+// every (pixel, channel) of the segment sums its covering values in the
 // fixed order (dy, position, entry) ascending: the covering entries of a
 // pixel are one contiguous run of the staged list, whose column is kept per
 // entry.  Lanes run over the channels of a pixel, which all have the same
 // trip counts.  WG: entry e weighs gw[e / K] (its group's weight) and the
-// pixel is the weighted mean; otherwise every entry weighs 1.
+// pixel is the weighted mean; otherwise every entry weighs 1.  part: per
+// slice [CG][GX] sums (and weight sums), then [GX] counts, for segments of
+// more than one slice.
 template <bool WG>
 __global__ void __launch_bounds__(GT)
 k_gather(const float* __restrict__ xbar, const float* __restrict__ xhat,
          const int32_t* __restrict__ ent, const int32_t* __restrict__ offs, int Cp, int H, int W,
-         int P, int D, const float* __restrict__ gw, int K, float* __restrict__ out,
-         int32_t* __restrict__ cover) {
+         int P, int D, const float* __restrict__ gw, int K, const int32_t* __restrict__ first,
+         const int32_t* __restrict__ owner, int nsw, float* __restrict__ part,
+         float* __restrict__ out, int32_t* __restrict__ cover) {
   __shared__ __align__(16) float lds[LDS_FLOATS];
   __shared__ int spos[GX + 17];             // window bucket starts (P <= 16), + end
   __shared__ int sent[LDS_FLOATS / 4];      // entry ids of the staged chunk
   __shared__ int scol[LDS_FLOATS / 4];      // their top-left columns
   __shared__ float swt[WG ? LDS_FLOATS / 4 : 1];   // their weights
-  const int r = blockIdx.y;
-  const int c0 = blockIdx.x * GX;
-  const int cg0 = blockIdx.z * CG;
+  const int nseg = H * nsw;
+  const int sub = blockIdx.x;
+  if (sub >= first[nseg]) return;           // block-uniform: the grid is an upper bound
+  const int id = owner[sub];
+  const int k0 = sub - first[id], nsl = first[id + 1] - first[id];
+  const int r = id / nsw;
+  const int c0 = (id - r * nsw) * GX;
+  const int cg0 = blockIdx.y * CG;
   const int ncg = min(CG, Cp - cg0);
+  const int s0 = k0 * EB, s1 = s0 + EB;     // this slice of the segment's entry stream
   const int Hc = H - P + 1, Wc = W - P + 1;
   const int tid = threadIdx.x;
   const int npair = GX * ncg;
@@ -190,6 +242,7 @@ k_gather(const float* __restrict__ xbar, const float* __restrict__ xhat,
   const bool vec4 = ncg == Cp && (rowlen & 3) == 0 && (D & 3) == 0;
   const int tc0 = max(0, c0 - P + 1);
   const int tc1 = min(Wc - 1, c0 + GX - 1);
+  int pos0 = 0;                             // stream offset of this window
   for (int dy = 0; dy < P; ++dy) {
     const int tr = r - dy;
     if (tr < 0 || tr >= Hc || tc0 > tc1) continue;      // block-uniform
@@ -197,17 +250,10 @@ k_gather(const float* __restrict__ xbar, const float* __restrict__ xhat,
     __syncthreads();                                     // previous users of spos / lds
     for (int i = tid; i <= nwin; i += GT) spos[i] = offs[tr * Wc + tc0 + i];
     __syncthreads();
-    const int ea = spos[0], eb = spos[nwin];
-    // bucket counts (once per dy; independent of the chunking)
-#pragma unroll
-    for (int k = 0; k < NPT; ++k) {
-      const int p = tid + k * GT;
-      if (p < npair) {
-        const int c = c0 + p / ncg;
-        const int lo = max(tc0, c - P + 1), hi = min(tc1, c);
-        if (c < W && lo <= hi) cnt[k] += spos[hi - tc0 + 1] - spos[lo - tc0];
-      }
-    }
+    const int wa = spos[0], wb = spos[nwin];
+    // the part of this window inside the slice
+    const int ea = max(wa, wa + s0 - pos0), eb = min(wb, wa + s1 - pos0);
+    pos0 += wb - wa;
     for (int ia = ea; ia < eb; ia += cap) {
       const int ib = min(eb, ia + cap);
       const int nrow = ib - ia;
@@ -285,33 +331,101 @@ k_gather(const float* __restrict__ xbar, const float* __restrict__ xhat,
                 a += lds[(i - ia) * rowlen + (c - scol[i - ia]) * ncg + ch];
             }
             acc[k] = a;
+            cnt[k] += max(b1 - b0, 0);
           }
         }
       }
     }
   }
   const size_t HW = (size_t)H * W;
+  if (nsl == 1) {
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+      const int p = tid + k * GT;
+      if (p < npair) {
+        const int px = p / ncg, ch = p - px * ncg;
+        const int c = c0 + px;
+        if (c < W) {
+          const int n = cnt[k];
+          if (cover && cg0 == 0 && ch == 0) cover[(size_t)r * W + c] = n;
+          const size_t o = (size_t)(cg0 + ch) * HW + (size_t)r * W + c;
+          out[o] = n ? acc[k] / (WG ? wsum[k] : (float)n) : xbar[o];
+        }
+      }
+    }
+    return;
+  }
+  // partial sums of this slice: [ch][px] sums, [ch][px] weight sums, [px] counts
+  float* ps = part + ((size_t)sub * gridDim.y + blockIdx.y) * (size_t)GX * (2 * CG + 1);
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     const int p = tid + k * GT;
     if (p < npair) {
       const int px = p / ncg, ch = p - px * ncg;
-      const int c = c0 + px;
-      if (c < W) {
-        const int n = cnt[k];
-        if (cover && cg0 == 0 && ch == 0) cover[(size_t)r * W + c] = n;
-        const size_t o = (size_t)(cg0 + ch) * HW + (size_t)r * W + c;
-        out[o] = n ? acc[k] / (WG ? wsum[k] : (float)n) : xbar[o];
-      }
+      ps[ch * GX + px] = acc[k];
+      if (WG) ps[(CG + ch) * GX + px] = wsum[k];
+      if (ch == 0) ps[2 * CG * GX + px] = __int_as_float(cnt[k]);
     }
+  }
+}
+
+// Segments of more than one slice: the slices' partial sums added in slice
+// order, then the mean (or weighted mean).  One block per (segment, channel
+// group); single-slice segments exit.
+template <bool WG>
+__global__ void __launch_bounds__(GT)
+k_gather_combine(const float* __restrict__ xbar, const int32_t* __restrict__ first, int nsw,
+                 int Cp, int H, int W, const float* __restrict__ part, float* __restrict__ out,
+                 int32_t* __restrict__ cover) {
+  const int id = blockIdx.x;
+  const int f0 = first[id], nsl = first[id + 1] - f0;
+  if (nsl == 1) return;                     // block-uniform
+  const int r = id / nsw;
+  const int c0 = (id - r * nsw) * GX;
+  const int cg0 = blockIdx.y * CG;
+  const int ncg = min(CG, Cp - cg0);
+  const size_t HW = (size_t)H * W;
+  const size_t stride = (size_t)gridDim.y * GX * (2 * CG + 1);
+  for (int p = threadIdx.x; p < GX * ncg; p += GT) {
+    const int px = p / ncg, ch = p - px * ncg;
+    const int c = c0 + px;
+    if (c >= W) continue;
+    const float* ps = part + ((size_t)f0 * gridDim.y + blockIdx.y) * (size_t)GX * (2 * CG + 1);
+    float a = 0.f, ws = 0.f;
+    int n = 0;
+    for (int k = 0; k < nsl; ++k, ps += stride) {
+      a += ps[ch * GX + px];
+      if (WG) ws += ps[(CG + ch) * GX + px];
+      n += __float_as_int(ps[2 * CG * GX + px]);
+    }
+    if (cover && cg0 == 0 && ch == 0) cover[(size_t)r * W + c] = n;
+    const size_t o = (size_t)(cg0 + ch) * HW + (size_t)r * W + c;
+    out[o] = n ? a / (WG ? ws : (float)n) : xbar[o];
   }
 }
 
 }  // namespace
 
+static int gather_nsw(const glr_plan* pl) { return (pl->W + GX - 1) / GX; }
+static size_t gather_max_slices(const glr_plan* pl) {
+  // every entry lies in the streams of at most P rows x 2 segments (P < GX)
+  const size_t nseg = (size_t)pl->H * gather_nsw(pl);
+  return nseg + (2 * (size_t)pl->P * pl->M + EB - 1) / EB;
+}
+
+size_t agg_gather_ints(const glr_plan* pl) {
+  const size_t n = (size_t)pl->H * gather_nsw(pl) + 1;
+  // slice counts [n], their scan [n], scan block sums, slice owners
+  return 2 * ((n + 63) / 64 * 64) + (n + SE - 1) / SE + 64 + gather_max_slices(pl);
+}
+
+size_t agg_gather_part_floats(const glr_plan* pl) {
+  return gather_max_slices(pl) * (size_t)((pl->Cp + CG - 1) / CG) * GX * (2 * CG + 1);
+}
+
 void launch_aggregate(const glr_plan* pl, const float* xbar, const int32_t* idx,
                       const float* xhat, const float* gw, int32_t* sortbuf, int32_t* offs,
-                      float* out, int32_t* cover, hipStream_t s) {
+                      int32_t* gplan, float* gpart, float* out, int32_t* cover, hipStream_t s) {
   const int M = pl->M, n = pl->Ncand + 1;
   int32_t* ent = sortbuf;                       // [M]
   int32_t* cnt = sortbuf + pl->M2;              // [Ncand + 1], later the scatter cursor
@@ -327,11 +441,34 @@ void launch_aggregate(const glr_plan* pl, const float* xbar, const int32_t* idx,
   hipLaunchKernelGGL(k_bucket_sort, dim3((pl->Ncand + 255) / 256), dim3(256), 0, s, offs,
                      pl->Ncand, ent, big, nbig);
   hipLaunchKernelGGL(k_bucket_sort_large, dim3(256), dim3(1024), 0, s, offs, ent, big, nbig);
-  dim3 grid((pl->W + GX - 1) / GX, pl->H, (pl->Cp + CG - 1) / CG);
-  if (gw)
-    hipLaunchKernelGGL(k_gather<true>, grid, dim3(GT), 0, s, xbar, xhat, ent, offs, pl->Cp, pl->H,
-                       pl->W, pl->P, pl->D, gw, pl->K, out, cover);
-  else
-    hipLaunchKernelGGL(k_gather<false>, grid, dim3(GT), 0, s, xbar, xhat, ent, offs, pl->Cp, pl->H,
-                       pl->W, pl->P, pl->D, gw, pl->K, out, cover);
+  // slices: counts per segment, their exclusive scan, the owner of each slice
+  const int nsw = gather_nsw(pl), nseg = pl->H * nsw, ns1 = nseg + 1;
+  int32_t* gn = gplan;                                   // [ns1] slices per segment
+  int32_t* gfirst = gn + ((size_t)ns1 + 63) / 64 * 64;   // [ns1] first slice of each
+  int32_t* gbs = gfirst + ((size_t)ns1 + 63) / 64 * 64;  // scan block sums
+  const int nbs = (ns1 + SE - 1) / SE;
+  int32_t* gowner = gbs + nbs + 64;
+  hipLaunchKernelGGL(k_gather_count, dim3((ns1 + 255) / 256), dim3(256), 0, s, offs, pl->H,
+                     pl->W, pl->P, nsw, gn);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(nbs), dim3(SB), 0, s, gn, ns1, gfirst, gbs);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SB), 0, s, gbs, nbs);
+  hipLaunchKernelGGL(k_scan_add, dim3((ns1 + 255) / 256), dim3(256), 0, s, gfirst, ns1, gbs, gn);
+  hipLaunchKernelGGL(k_gather_expand, dim3((nseg + 255) / 256), dim3(256), 0, s, gfirst, nseg,
+                     gowner);
+  const int ncg = (pl->Cp + CG - 1) / CG;
+  const dim3 grid((unsigned)gather_max_slices(pl), ncg);
+  const dim3 cgrid((unsigned)nseg, ncg);
+  if (gw) {
+    hipLaunchKernelGGL(k_gather<true>, grid, dim3(GT), 0, s, xbar, xhat, ent, offs, pl->Cp,
+                       pl->H, pl->W, pl->P, pl->D, gw, pl->K, gfirst, gowner, nsw, gpart, out,
+                       cover);
+    hipLaunchKernelGGL(k_gather_combine<true>, cgrid, dim3(GT), 0, s, xbar, gfirst, nsw, pl->Cp,
+                       pl->H, pl->W, gpart, out, cover);
+  } else {
+    hipLaunchKernelGGL(k_gather<false>, grid, dim3(GT), 0, s, xbar, xhat, ent, offs, pl->Cp,
+                       pl->H, pl->W, pl->P, pl->D, gw, pl->K, gfirst, gowner, nsw, gpart, out,
+                       cover);
+    hipLaunchKernelGGL(k_gather_combine<false>, cgrid, dim3(GT), 0, s, xbar, gfirst, nsw, pl->Cp,
+                       pl->H, pl->W, gpart, out, cover);
+  }
 }

@@ -293,7 +293,8 @@ glr_status lowrank_stage(glr_plan* pl, const float* xp, const int32_t* idx, floa
   {
     StageTimer t(pl, s, T_AGG);
     launch_aggregate(pl, xp, idx, xhat, gw, (int32_t*)(ws + pl->ws.pairs),
-                     (int32_t*)(ws + pl->ws.offs), xo, cover, s);
+                     (int32_t*)(ws + pl->ws.offs), (int32_t*)(ws + pl->ws.gplan),
+                     (float*)(ws + pl->ws.gpart), xo, cover, s);
   }
   return check_hip("glr_lowrank_aggregate");
 }
@@ -719,6 +720,8 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
   L.isig = c.take(inner ? 4 : 0);
   L.pairs = c.take(agg_sort_ints(pl) * 4);
   L.offs = c.take(((size_t)Ncand + 1) * 4);
+  L.gplan = c.take(agg_gather_ints(pl) * 4);
+  L.gpart = c.take(agg_gather_part_floats(pl) * 4);
   L.cplx_a = c.take(pl->is_complex ? HW * 8 : 0);
   L.cplx_b = c.take(pl->is_complex ? HW * 8 : 0);
   L.red = c.take(1024);

@@ -46,6 +46,7 @@ struct WsLayout {
   size_t idx, dd;                // groups [N][K], distances [N][K]
   size_t xhat, sv;               // group estimates [N][D][K]; singular values
   size_t gw;                     // per-group aggregation weights [N] (GLR_AGG_RANK)
+  size_t gplan, gpart;           // aggregation: slice table, partial sums
   size_t yk, ipart, isig;        // inner WNNM iterations: y^(k), partial sums, sigma_k
   size_t pairs, offs;            // aggregation sort keys, CSR offsets
   size_t cplx_a, cplx_b;         // complex scratch (FFT / ADMM)
@@ -251,9 +252,13 @@ void launch_inner_update(const float* xbar, const float* x, const float* yprev, 
 // cover (nullable): per-pixel count of covering estimates [H][W]
 // The counters at agg_zero_range(pl, sortbuf) must be zero on entry.
 // gw: per-group weights [N] (weighted mean), or null (plain mean)
+// gplan (agg_gather_ints(pl) int32) and gpart (agg_gather_part_floats(pl)):
+// the load-balanced gather's slice table and partial sums
 void launch_aggregate(const glr_plan* pl, const float* xbar, const int32_t* idx,
                       const float* xhat, const float* gw, int32_t* sortbuf, int32_t* offs,
-                      float* out, int32_t* cover, hipStream_t s);
+                      int32_t* gplan, float* gpart, float* out, int32_t* cover, hipStream_t s);
+size_t agg_gather_ints(const glr_plan* pl);
+size_t agg_gather_part_floats(const glr_plan* pl);
 // counts, block sums and queue length of the aggregation sort: one contiguous
 // range of sortbuf (returns its start; *n its length)
 inline int32_t* agg_zero_range(const glr_plan* pl, int32_t* sortbuf, int* n) {
