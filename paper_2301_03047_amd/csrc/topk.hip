@@ -550,6 +550,7 @@ k_select_rescore(const float* __restrict__ xi, int H, int W, int P, int Cp, int 
   }
   const size_t o0 = (size_t)g * S * CAP;
   int m = 0;
+  float T;                                   // the key's K-th smallest U over its lists
   if (tot <= UW) {
     // every list entry into LDS in list order (entry e of the concatenation
     // is in the last list whose offset is <= e), up to four loads per lane in
@@ -587,11 +588,11 @@ k_select_rescore(const float* __restrict__ xi, int H, int W, int P, int Cp, int 
       }
     }
     wave_sync_lds();
-    const float T = wave_kth_smallest(u, tot, K, shist[wave]);
+    T = wave_kth_smallest(u, tot, K, shist[wave]);
     // margin set: ordered compaction of the entries with L <= T
     m = wave_compact(jj, u, lo, tot, T);
   } else {
-    const float T = wave_kth_lists(lu + o0, c, S, K, shist[wave]);
+    T = wave_kth_lists(lu + o0, c, S, K, shist[wave]);
     // margin set: ordered compaction of the entries with L <= T
     for (int sp = 0; sp < S; ++sp) {
       const int csp = __shfl(c, sp, 64);
@@ -608,7 +609,10 @@ k_select_rescore(const float* __restrict__ xi, int H, int W, int P, int Cp, int 
     }
   }
   if (m > MW || m < K) {                     // m < K cannot happen with valid lists
-    if (l == 0) oflag[g] = m > MW ? 1 : 2;
+    if (l == 0) {
+      oflag[g] = m > MW ? 1 : 2;
+      if (m > MW) tkey[g] = T;               // the block path reuses the key's T
+    }
     return;
   }
   if (l == 0) oflag[g] = 0;
@@ -742,7 +746,8 @@ __device__ float block_kth_by_bisection(const float* vals, int m, int K, int* ss
 }
 
 // Flagged keys, one block per key (unflagged keys exit at once):
-//  flag 1: the margin set exceeds the wave buffer.  It is gathered from the
+//  flag 1: the margin set exceeds the wave path's share.  With the key's T
+//          (the wave path leaves it in rb.tkey) it is gathered from the
 //          range lists into global scratch (up to mcap entries) and handed
 //          to rescore_select_set;
 //  flag 2: a range list overflowed, so the lists do not hold the margin set.
@@ -794,19 +799,8 @@ k_rescore_overflow(const float* __restrict__ xi, int H, int W, int P, int Cp, in
   __syncthreads();
   if (flag == 1) {
     const size_t o0 = (size_t)g * S * CAP;
-    // T: smallest U value (as ordered bits) with at least K list values <= it
-    uint32_t lo = 0u, hi = 0xffffffffu;
-    while (lo < hi) {
-      const uint32_t mid = lo + ((hi - lo) >> 1);
-      int c = 0;
-      for (int sp = 0; sp < S; ++sp) {
-        const int csp = scnt[sp];
-        for (int i = tid; i < csp; i += ST) c += (f2ord(lu[o0 + (size_t)sp * CAP + i]) <= mid) ? 1 : 0;
-      }
-      c = block_sum_i(c, ssh);
-      if (c >= K) hi = mid; else lo = mid + 1;
-    }
-    const float T = ord2f(lo);
+    // T (the K-th smallest U over the key's lists) as the wave path found it
+    const float T = rb.tkey[g];
     int m = 0;
     for (int sp = 0; sp < S; ++sp) {
       const int csp = scnt[sp];
