@@ -32,6 +32,22 @@ def wnnm_group(Y, sigma, c, eps):
     return X, s
 
 
+def wnnm_group_complex(Z, sigma, c, eps):
+    """Shrink one complex group ``Z`` (d x K complex, column j = member j) by
+    the same WNNM rule on the complex SVD Zc = U S V^H (variant for complex
+    data; the default stacks [Re; Im] into a real 2d x K group).  Reading:
+    the row mean mu is the complex mean, K is the member count and sigma the
+    noise level per real component, as in the real form.  LAPACK's complex
+    SVD, FP64.  Returns (X_hat d x K complex, singular values)."""
+    Z = np.asarray(Z, dtype=np.complex128)
+    d, K = Z.shape
+    mu = Z.mean(axis=1, keepdims=True)
+    U, s, Vh = np.linalg.svd(Z - mu, full_matrices=False)
+    s_new = wnnm_weights(s, K, sigma, c, eps)
+    X = Z - (U * (s - s_new)[None, :]) @ Vh
+    return X, s
+
+
 def gather_groups(x, patch, idx):
     """Group matrices ``[N][K][D]`` (member-major) from iterate ``x``."""
     from .matching import patch_matrix
@@ -39,12 +55,25 @@ def gather_groups(x, patch, idx):
     return pm[np.asarray(idx)]
 
 
-def shrink_groups(x, patch, idx, sigma, c, eps):
+def shrink_groups(x, patch, idx, sigma, c, eps, complex_groups=False):
     """WNNM of every group: returns X_hat ``[N][K][D]`` and singular values
-    ``[N][min(D,K)]`` (descending)."""
+    ``[N][min(D,K)]`` (descending).  With ``complex_groups`` the iterate is
+    planar complex ``[2][H][W]`` (Re, Im): each member's D = 2 P^2 entries
+    [Re; Im] form one complex P^2-vector, the group is shrunk by
+    ``wnnm_group_complex`` and written back as [Re; Im]; the singular values
+    are then ``[N][min(P^2, K)]``."""
     G = gather_groups(x, patch, idx)
     N, K, D = G.shape
     out = np.empty_like(G)
+    if complex_groups:
+        d = D // 2
+        sv = np.empty((N, min(d, K)))
+        for g in range(N):
+            X, s = wnnm_group_complex((G[g, :, :d] + 1j * G[g, :, d:]).T, sigma, c, eps)
+            out[g, :, :d] = X.T.real
+            out[g, :, d:] = X.T.imag
+            sv[g] = s
+        return out, sv
     sv = np.empty((N, min(D, K)))
     for g in range(N):
         X, s = wnnm_group(G[g].T, sigma, c, eps)

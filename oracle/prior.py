@@ -11,7 +11,7 @@ from .aggregate import aggregate
 
 def prior_step(x, patch, n_keys, K, sigma, c, eps, is_complex=False, keys=None,
                exemplars="corner", step=4, search="global", radius=20, score="l2",
-               agg_weights="uniform", inner=1, delta=0.1, lam=0.54):
+               agg_weights="uniform", inner=1, delta=0.1, lam=0.54, lowrank="stacked"):
     """Apply the prior to iterate ``x`` (planar real ``[C'][H][W]``; complex
     data as ``[2][H][W]`` = (Re, Im)).  ``keys`` may be supplied to bypass the
     detector.  ``exemplars`` ("corner", "uniform", "corner_uniform", with the
@@ -22,7 +22,9 @@ def prior_step(x, patch, n_keys, K, sigma, c, eps, is_complex=False, keys=None,
     ``agg_weights`` "rank" weighs each group's estimates by 1 / (its kept
     WNNM rank) in the aggregation (``weights`` then holds them).  ``inner``
     > 1 shrinks the same groups again with WNNM's iterative regularisation
-    (``inner_iterations``).
+    (``inner_iterations``).  ``lowrank`` "complex" (complex data only)
+    shrinks each group as one complex matrix (``wnnm_group_complex``) instead
+    of the real-stacked [Re; Im] group.
     Returns a dict with keys, idx, dist, Xhat, sv, weights, x_out, count."""
     x = np.asarray(x, dtype=np.float64)
     if keys is None:
@@ -38,9 +40,12 @@ def prior_step(x, patch, n_keys, K, sigma, c, eps, is_complex=False, keys=None,
         raise ValueError(search)
     if agg_weights not in ("uniform", "rank"):
         raise ValueError(agg_weights)
+    if lowrank not in ("stacked", "complex") or (lowrank == "complex" and not is_complex):
+        raise ValueError(lowrank)
+    cplx = lowrank == "complex"
 
     def shrink_and_aggregate(y, sig):
-        Xh, s = shrink_groups(y, patch, idx, sig, c, eps)
+        Xh, s = shrink_groups(y, patch, idx, sig, c, eps, complex_groups=cplx)
         w = group_weights(s, K, sig, c, eps) if agg_weights == "rank" else None
         xo, n = aggregate(y, patch, idx, Xh, weights=w)
         return Xh, s, w, xo, n

@@ -26,7 +26,8 @@ def _prior(xp, wl, sigma, is_complex):
                       agg_weights=getattr(wl, "agg_weights", "uniform"),
                       inner=getattr(wl, "wnnm_iters", 1),
                       delta=getattr(wl, "wnnm_delta", 0.1),
-                      lam=getattr(wl, "wnnm_lambda", 0.54))["x_out"]
+                      lam=getattr(wl, "wnnm_lambda", 0.54),
+                      lowrank=getattr(wl, "lowrank", "stacked"))["x_out"]
 
 
 def reconstruct(wl, y, mask, sigmas, iters=None, callback=None):

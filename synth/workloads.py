@@ -46,6 +46,9 @@ class Workload:
     wnnm_iters: int = 1
     wnnm_delta: float = 0.1
     wnnm_lambda: float = 0.54
+    # complex data: groups shrunk as real-stacked [Re; Im] ("stacked") or as
+    # complex matrices ("complex")
+    lowrank: str = "stacked"
 
     @property
     def real_channels(self):

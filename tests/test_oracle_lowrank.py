@@ -243,3 +243,110 @@ def test_inner_iterations_special_cases():
     again, _ = oag.aggregate(one["x_out"], P, one["idx"], Xh)
     np.testing.assert_allclose(two0["sigmas"][1], 0.05, rtol=1e-12)
     np.testing.assert_allclose(two0["x_out"], again, rtol=1e-12, atol=1e-14)
+
+
+# ---- complex-Hermitian form (complex data shrunk as complex matrices)
+
+def _cgroup(d, K, seed, zero_mean=False):
+    rng = np.random.default_rng(seed)
+    Z = rng.standard_normal((d, K)) + 1j * rng.standard_normal((d, K))
+    if zero_mean:
+        Z -= Z.mean(axis=1, keepdims=True)
+    return Z
+
+
+def test_complex_wnnm_real_group_is_the_real_form():
+    # a group with no imaginary part: the complex SVD is the real one, so the
+    # complex form equals the (separately pinned) real form
+    rng = np.random.default_rng(11)
+    Y = rng.uniform(size=(18, 12))
+    X, s = lr.wnnm_group_complex(Y.astype(np.complex128), 0.3, 2.8, 1e-16)
+    Xr, sr = lr.wnnm_group(Y, 0.3, 2.8, 1e-16)
+    np.testing.assert_allclose(X.real, Xr, atol=1e-12)
+    assert np.abs(X.imag).max() < 1e-12
+    np.testing.assert_allclose(s, sr, rtol=1e-12, atol=1e-12)
+
+
+def test_complex_wnnm_real_representation():
+    # a zero-mean complex group Z = A + iB and its real representation
+    # M = [[A, -B], [B, A]]: M's singular values are Z's, each twice, and
+    # shrinking M's SVD by the same rule (K = Z's member count) gives the real
+    # representation of the complex estimate.  A conjugate or transpose
+    # missing anywhere in the complex form breaks this.
+    d, K, sigma = 9, 14, 0.4
+    Z = _cgroup(d, K, 12, zero_mean=True)
+    X, s = lr.wnnm_group_complex(Z, sigma, 2.8, 1e-16)
+    A, B = Z.real, Z.imag
+    M = np.block([[A, -B], [B, A]])
+    U, sm, Vt = np.linalg.svd(M, full_matrices=False)
+    np.testing.assert_allclose(sm[0:2 * d:2], s, rtol=1e-12)
+    np.testing.assert_allclose(sm[1:2 * d:2], s, rtol=1e-12)
+    XM = M - (U * (sm - lr.wnnm_weights(sm, K, sigma, 2.8, 1e-16))[None, :]) @ Vt
+    np.testing.assert_allclose(XM, np.block([[X.real, -X.imag], [X.imag, X.real]]), atol=1e-12)
+
+
+def test_complex_wnnm_phase_equivariance():
+    # a global phase e^{i theta} rotates the complex estimate by the same
+    # phase and leaves the singular values
+    d, K, sigma, th = 16, 10, 0.5, 0.7
+    Z = _cgroup(d, K, 13)
+    X, s = lr.wnnm_group_complex(Z, sigma, 2.8, 1e-16)
+    Xp, sp = lr.wnnm_group_complex(Z * np.exp(1j * th), sigma, 2.8, 1e-16)
+    np.testing.assert_allclose(Xp, X * np.exp(1j * th), atol=1e-12)
+    np.testing.assert_allclose(sp, s, rtol=1e-12, atol=1e-12)
+
+
+def test_complex_wnnm_rank_one_closed_form():
+    # mu 1^T + s1 u v^H with unit u, v and v orthogonal to the ones vector:
+    # one singular value s1, and the estimate keeps mu and scales the rank-one
+    # term to the shrunk value
+    rng = np.random.default_rng(14)
+    d, K, s1, sigma = 8, 12, 5.0, 0.3
+    u = rng.standard_normal(d) + 1j * rng.standard_normal(d)
+    u /= np.linalg.norm(u)
+    v = rng.standard_normal(K) + 1j * rng.standard_normal(K)
+    v -= v.mean()
+    v /= np.linalg.norm(v)
+    mu = rng.uniform(size=d) + 1j * rng.uniform(size=d)
+    Z = mu[:, None] + s1 * np.outer(u, v.conj())
+    X, s = lr.wnnm_group_complex(Z, sigma, 2.8, 1e-16)
+    assert abs(s[0] - s1) < 1e-12 and np.all(s[1:] < 1e-12)
+    shat = np.sqrt(s1 * s1 - K * sigma * sigma)
+    s1n = s1 - 2.8 * np.sqrt(K) * sigma * sigma / (shat + 1e-16)
+    np.testing.assert_allclose(X, mu[:, None] + s1n * np.outer(u, v.conj()), atol=1e-12)
+    X0, _ = lr.wnnm_group_complex(Z, 0.0, 2.8, 1e-16)
+    np.testing.assert_array_equal(X0, Z)
+    # the real-stacked group [Re; Im] of the same data has rank two: the two
+    # forms differ
+    _, s2 = lr.wnnm_group(np.vstack([Z.real, Z.imag]), sigma, 2.8, 1e-16)
+    assert s2[1] > 1e-3 * s2[0]
+
+
+def test_shrink_groups_complex_packing():
+    # a planar complex image with a zero imaginary plane: the complex groups
+    # are the real groups of the real plane, written back as [Re; 0]; and on
+    # a general image the [Re; Im] halves are Re and Im of the complex group
+    # estimate of the gathered complex patches
+    rng = np.random.default_rng(15)
+    P, K = 3, 7
+    re = rng.uniform(size=(1, 14, 13))
+    x = np.concatenate([re, np.zeros_like(re)])
+    idx = rng.choice(12 * 11, size=(5, K), replace=False).reshape(5, K)
+    Xc, svc = lr.shrink_groups(x, P, idx, 0.2, 2.8, 1e-16, complex_groups=True)
+    Xr, svr = lr.shrink_groups(re, P, idx, 0.2, 2.8, 1e-16)
+    np.testing.assert_allclose(Xc[:, :, :P * P], Xr, atol=1e-12)
+    assert np.abs(Xc[:, :, P * P:]).max() < 1e-12
+    np.testing.assert_allclose(svc, svr[:, :min(P * P, K)], rtol=1e-10, atol=1e-12)
+    x = rng.uniform(size=(2, 14, 13))
+    Xc, svc = lr.shrink_groups(x, P, idx, 0.2, 2.8, 1e-16, complex_groups=True)
+    assert svc.shape == (5, min(P * P, K))
+    g = 3
+    Zg = np.array([[x[0, t // 13 + dy, t % 13 + dx] + 1j * x[1, t // 13 + dy, t % 13 + dx]
+                    for dy in range(P) for dx in range(P)] for t in
+                   [(i // 11) * 13 + i % 11 for i in idx[g]]]).T
+    Xg, sg = lr.wnnm_group_complex(Zg, 0.2, 2.8, 1e-16)
+    np.testing.assert_allclose(Xc[g, :, :P * P], Xg.T.real, atol=1e-12)
+    np.testing.assert_allclose(Xc[g, :, P * P:], Xg.T.imag, atol=1e-12)
+    np.testing.assert_allclose(svc[g], sg, rtol=1e-12)
+    with pytest.raises(ValueError):
+        pr.prior_step(x, P, 5, K, 0.2, 2.8, 1e-16, lowrank="complex")
