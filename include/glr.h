@@ -80,6 +80,13 @@ enum { GLR_SEARCH_GLOBAL = 0, GLR_SEARCH_WINDOW = 1 };
  * (larger = more similar). */
 enum { GLR_SCORE_L2 = 0, GLR_SCORE_EDGE = 1 };
 enum { GLR_AGG_UNIFORM = 0, GLR_AGG_RANK = 1 };
+/* Form of the low-rank step for complex data (MRI).  STACKED: each member's
+ * P^2 complex values enter the group as 2 P^2 real rows [Re; Im] and the real
+ * group is shrunk.  COMPLEX: the group is the P^2 x K complex matrix Z and
+ * WNNM runs on its complex SVD Z - mu 1^T = U S V^H (mu the complex row
+ * mean; the same weights and threshold, K the member count, sigma the noise
+ * level per real component).  Real modalities take STACKED only. */
+enum { GLR_LOWRANK_STACKED = 0, GLR_LOWRANK_COMPLEX = 1 };
 
 /* Sensing problem (eq. 2-5). */
 typedef struct glr_problem {
@@ -165,6 +172,7 @@ typedef struct glr_params {
   int32_t wnnm_iters;
   float wnnm_delta;
   float wnnm_lambda;
+  int32_t lowrank;       /* default GLR_LOWRANK_STACKED; COMPLEX for MRI only     */
 } glr_params;
 
 /* Counters of the last prior steps, read by glr_read_stats(). */
@@ -267,8 +275,11 @@ GLR_API glr_status glr_match_topk(glr_plan* plan, const void* x, const int32_t* 
  * the member estimates averaged back per pixel; pixels no member covers keep
  * x_in (weighted per group with params.agg_weights RANK).  One shrinkage:
  * params.wnnm_iters applies to glr_prior_step and glr_reconstruct only.
+ * With params.lowrank COMPLEX the group is the P^2 x K complex matrix and the
+ * SVD complex (Hermitian rotations).
  * sv: optional device float32 [N][K], singular values descending (NULL to
- * skip).  x_out must not alias x_in. */
+ * skip; the complex form has at most min(P^2, K) non-zero ones).  x_out must
+ * not alias x_in. */
 GLR_API glr_status glr_lowrank_aggregate(glr_plan* plan, const void* x_in, const int32_t* idx,
                                  float sigma, void* x_out, float* sv, void* ws,
                                  void* stream);

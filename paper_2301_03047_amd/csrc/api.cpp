@@ -489,6 +489,7 @@ void glr_params_default(glr_params* p) {
   p->wnnm_iters = 1;
   p->wnnm_delta = 0.1f;
   p->wnnm_lambda = 0.54f;
+  p->lowrank = GLR_LOWRANK_STACKED;
 }
 
 glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_params* pr,
@@ -527,6 +528,10 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
       !(pr->wnnm_delta >= 0.f && pr->wnnm_delta <= 1.f && pr->wnnm_lambda > 0.f &&
         std::isfinite(pr->wnnm_lambda)))
     return fail(GLR_ERR_INVALID_ARG, "wnnm_delta must lie in [0, 1] and wnnm_lambda be positive");
+  if (pr->lowrank != GLR_LOWRANK_STACKED && pr->lowrank != GLR_LOWRANK_COMPLEX)
+    return fail(GLR_ERR_INVALID_ARG, "unknown low-rank form %d", pr->lowrank);
+  if (pr->lowrank == GLR_LOWRANK_COMPLEX && pb->modality != GLR_MRI)
+    return fail(GLR_ERR_INVALID_ARG, "the complex low-rank form needs complex (MRI) data");
   if (pr->wnnm_iters > 1 && pr->surrogate)
     return fail(GLR_ERR_UNSUPPORTED, "inner WNNM iterations are not combined with the surrogate");
   const int Ce = pb->modality == GLR_MRI ? 1 : Cp;
@@ -614,6 +619,7 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
   pl->wnnm_iters = pr->wnnm_iters;
   pl->wnnm_delta = pr->wnnm_delta;
   pl->wnnm_lambda = pr->wnnm_lambda;
+  pl->lowrank_complex = pr->lowrank == GLR_LOWRANK_COMPLEX;
   pl->Ce = Ce;
   pl->K = pr->k;
   pl->T = pr->iters;

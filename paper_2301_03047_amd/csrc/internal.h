@@ -65,6 +65,7 @@ struct glr_plan {
   int agg_weights;                // GLR_AGG_UNIFORM | GLR_AGG_RANK
   int wnnm_iters;                 // inner WNNM iterations per prior step (1: one shrinkage)
   float wnnm_delta, wnnm_lambda;  // their regularisation step and noise re-estimate factor
+  bool lowrank_complex;           // complex data shrunk as complex groups
   int Ce;                         // edge-map channels per real channel group (score EDGE)
   float rho, wnnm_c, wnnm_eps;
   std::vector<float> sigma;

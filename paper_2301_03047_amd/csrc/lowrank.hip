@@ -546,6 +546,451 @@ k_wnnm(const float* __restrict__ xi, int H, int W, int P, int D, const int32_t* 
   }
 }
 
+// Complex-Hermitian form for complex data.  The interleaved image holds Re
+// and Im of a pixel as channels 0 and 1, so rows 2t and 2t+1 of the real
+// group are Re and Im of row t of the complex group Z (P^2 x K, t = dy P + dx,
+// D = 2 P^2).  The steps of k_wnnm in complex arithmetic:
+//  1. G = Zc^H Zc in FP64: Re G is the Gram matrix of the real rows (first
+//     pass over the rows), Im G[a][b] = sum_t (Re z_a Im z_b - Im z_a Re z_b)
+//     pairs each row with its partner row (second pass); the Cholesky factor
+//     R^H R = G is upper triangular with a real diagonal (rank-deficient G,
+//     K > P^2, leaves zero or rounding-sized rows);
+//  2. one-sided Jacobi on the columns of M = R^H (lane i holds the conjugate
+//     of row i of R): for a pair (a, b) with a^H b = |g| e^{i phi}, b turned
+//     by e^{-i phi} has a real inner product with a and the real rotation
+//     applies; the lower lane takes c (b + t e^{i phi} a), the upper
+//     c (a - t e^{-i phi} b).  The converged columns are sigma_i v_i with v_i
+//     the right singular vectors of R, hence of Zc;
+//  3. the WNNM factors of the real form (K the member count), and
+//     W = V diag(w) V^H (Hermitian);
+//  4. X = Z - Zc W in complex FP64.
+template <int KP>
+__global__ void __launch_bounds__(64)
+k_wnnm_cplx(const float* __restrict__ xi, int H, int W, int P, int D,
+            const int32_t* __restrict__ idx, int K, float sigma_h, const float* __restrict__ sigp,
+            float wc, float weps, int max_sweeps, float* __restrict__ xhat,
+            float* __restrict__ sv, DevStats* st, int32_t* __restrict__ zbuf, int zn, int bump,
+            float* __restrict__ gw) {
+  constexpr int XS = KP + 4;       // row stride of the streamed chunk and of V
+  constexpr int TS = 68;           // row stride of W and of the member-major chunk
+  constexpr int CH = 64 * XS;      // the chunk (64 rows), phase 1
+  constexpr int NG = 4 * KP * KP;  // Re G and Im G in FP64, phase 1
+  constexpr int NV = 2 * KP * XS;  // Re V and Im V, then the member-major chunk
+  constexpr int NW = 2 * KP * TS;  // Re W and Im W
+  constexpr int NR = 2 * KP * LS;  // Re R and Im R columns
+  constexpr int N1 = CH + NG > NV + NW ? CH + NG : NV + NW;
+  constexpr int NB = N1 > NR ? N1 : NR;
+  static_assert(KP * TS <= NV, "the member-major chunk fits the V buffer");
+  static_assert(KP % 8 == 0, "8 x 8 blocks");
+  __shared__ __align__(16) float RB[NB];
+  __shared__ __align__(16) double srr[64];      // a row of R; the column sums of W
+  __shared__ __align__(16) double sri[64];
+  __shared__ float smu[64];
+  __shared__ __align__(16) int spos[64];
+  __shared__ float sw[64];
+  __shared__ float ssig[64];
+  float* const Bl = RB;
+  double* const Gr = reinterpret_cast<double*>(RB + CH);
+  double* const Gi = Gr + KP * KP;
+  float* const Rr = RB;
+  float* const Ri = RB + KP * LS;
+  float* const Vr = RB;
+  float* const Vi = RB + KP * XS;
+  float* const Wr = RB + NV;
+  float* const Wi = RB + NV + KP * TS;
+
+  const int g = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int Wc = W - P + 1;
+  for (int i = g * 64 + lane; i < zn; i += gridDim.x * 64) zbuf[i] = 0;
+  if (bump && g == 0 && lane == 0) st->steps += 1;
+  {
+    const int t = idx[(size_t)g * K + min(lane, K - 1)];
+    const int r = t / Wc, c = t - r * Wc;
+    spos[lane] = r * W + c;
+  }
+  __syncthreads();
+
+  // ---- 1. G = Zc^H Zc (lane (bi, bj): the 8 x 8 block at 8 bi, 8 bj)
+  int fe = 0;
+  {
+    const int bi = lane >> 3, bj = lane & 7;
+    for (int pass = 0; pass < 2; ++pass) {
+      double acc[8][8];
+#pragma unroll
+      for (int p = 0; p < 8; ++p)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[p][q] = 0.0;
+      for (int d0 = 0; d0 < D; d0 += BR) {
+        const int nb = min(BR, D - d0);              // even: D is, and BR
+        load_rows(xi, spos, d0, nb, K, P, W, 2, Bl, smu, XS);
+        if (lane < nb) {
+          const float mu = smu[lane];
+          for (int u = 0; u < K; ++u) Bl[lane * XS + u] -= mu;
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int i = 0; i < nb; ++i) {
+          // Re G: row with itself; Im G: a Re row times its Im row, an Im row
+          // times minus its Re row
+          const int ib = pass ? (i ^ 1) : i;
+          const double sg = (pass && (i & 1)) ? -1.0 : 1.0;
+          float a[8], b[8];
+          load_vec(a, Bl + i * XS + 8 * bi);
+          load_vec(b, Bl + ib * XS + 8 * bj);
+          double ya[8], yb[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            ya[t] = 8 * bi + t < K ? (double)a[t] : 0.0;
+            yb[t] = 8 * bj + t < K ? sg * (double)b[t] : 0.0;
+          }
+#pragma unroll
+          for (int p = 0; p < 8; ++p)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc[p][q] = fma(ya[p], yb[q], acc[p][q]);
+        }
+        __syncthreads();
+      }
+      double* G = pass ? Gi : Gr;
+      if (8 * bi < KP && 8 * bj < KP) {
+#pragma unroll
+        for (int p = 0; p < 8; ++p)
+#pragma unroll
+          for (int q = 0; q < 8; ++q) G[(8 * bi + p) * KP + 8 * bj + q] = acc[p][q];
+      }
+    }
+  }
+  __syncthreads();
+  {
+    // lane j: column j of G, then of R (R[k][j] = conj(R[k][j]) of M's row)
+    double cr[KP], ci[KP];
+#pragma unroll
+    for (int i = 0; i < KP; ++i) {
+      cr[i] = lane < KP ? Gr[i * KP + lane] : 0.0;
+      ci[i] = lane < KP ? Gi[i * KP + lane] : 0.0;
+    }
+    __syncthreads();                             // RB is rewritten below
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const double dkk = bcast64(cr[k], k);      // the pivot is real
+      const double rkk = dkk > 0.0 ? sqrt(dkk) : 0.0;
+      const double inv = rkk > 0.0 ? 1.0 / rkk : 0.0;
+      cr[k] = lane == k ? rkk : cr[k] * inv;
+      ci[k] = lane == k ? 0.0 : ci[k] * inv;
+      srr[lane] = cr[k];
+      sri[lane] = ci[k];
+      wave_sync();
+      // G'[i][j] -= conj(R[k][i]) R[k][j]
+#pragma unroll
+      for (int i = k + 1; i < KP; ++i) {
+        const double ar = srr[i], ai = sri[i];
+        cr[i] = fma(-ar, cr[k], fma(-ai, ci[k], cr[i]));
+        ci[i] = fma(-ar, ci[k], fma(ai, cr[k], ci[i]));
+      }
+      wave_sync();
+    }
+    double mx = 0.0;
+#pragma unroll
+    for (int i = 0; i < KP; ++i) {
+      if (i > lane || lane >= K) {
+        cr[i] = 0.0;
+        ci[i] = 0.0;
+      }
+      mx = fmax(mx, fmax(fabs(cr[i]), fabs(ci[i])));
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+    if (mx > 0.0) {
+      int e;
+      frexp(mx, &e);
+      fe = max(min(1 - e, 126), -126);
+    }
+    if (lane < KP)
+      for (int i = 0; i < KP; ++i) {
+        Rr[lane * LS + i] = (float)ldexp(cr[i], fe);
+        Ri[lane * LS + i] = (float)ldexp(ci[i], fe);
+      }
+  }
+  __syncthreads();
+
+  // ---- 2. one-sided Jacobi on the columns of M = R^H
+  float mr[KP], mi[KP];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const bool in = lane < K && k < K;
+    mr[k] = in ? Rr[k * LS + lane] : 0.f;
+    mi[k] = in ? -Ri[k * LS + lane] : 0.f;
+  }
+  const int Kp = K + (K & 1);
+  const float tol = (float)K * 5.9604644775390625e-08f;
+  const float tol_last = 0.5f * sqrtf(tol);
+  const float tol2 = tol * tol, tol_last2 = tol_last * tol_last;
+  int sweeps = 0;
+  float sc = 1.f;
+  int cid = lane;
+  for (int swp = 0; swp < max_sweeps; ++swp) {
+    bool big = false;
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      mr[k] *= sc;
+      mi[k] *= sc;
+    }
+    sc = 1.f;
+    float al;
+    {
+      float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+#pragma unroll
+      for (int k = 0; k < KP; k += 2) {
+        a0 = fmaf(mr[k], mr[k], a0);
+        a1 = fmaf(mi[k], mi[k], a1);
+        a2 = fmaf(mr[k + 1], mr[k + 1], a2);
+        a3 = fmaf(mi[k + 1], mi[k + 1], a3);
+      }
+      al = (a0 + a1) + (a2 + a3);
+    }
+    auto round = [&](auto oddc) {
+      constexpr bool odd = decltype(oddc)::value;
+      const int q = odd ? ((lane & 1) ? lane + 1 : lane - 1) : (lane ^ 1);
+      const bool paired = lane < Kp && q >= 0 && q < Kp;
+      const bool up = (lane & 1) || lane >= Kp;
+      float orr[KP], oi[KP];
+      float be, osc;
+      int ocid;
+      if constexpr (odd) {
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+          orr[k] = lane_shift_pair(mr[k], up);
+          oi[k] = lane_shift_pair(mi[k], up);
+        }
+        be = lane_shift_pair(al, up);
+        osc = lane_shift_pair(sc, up);
+        ocid = __builtin_bit_cast(int, lane_shift_pair(__builtin_bit_cast(float, cid), up));
+      } else {
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+          orr[k] = lane_xor1(mr[k]);
+          oi[k] = lane_xor1(mi[k]);
+        }
+        be = lane_xor1(al);
+        osc = lane_xor1(sc);
+        ocid = __builtin_bit_cast(int, lane_xor1(__builtin_bit_cast(float, cid)));
+      }
+      // Re(m^H o) is symmetric in the pair; the two cross sums trade places
+      // between the lanes, so both lanes form Im(a^H b) (a the lower lane's
+      // column) from the same products in the same order
+      float gp[4] = {0.f, 0.f, 0.f, 0.f}, s1p[4] = {0.f, 0.f, 0.f, 0.f},
+            s2p[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int k = 0; k < KP; ++k) {
+        gp[k & 3] = fmaf(mr[k], orr[k], gp[k & 3]);
+        gp[k & 3] = fmaf(mi[k], oi[k], gp[k & 3]);
+        s1p[k & 3] = fmaf(mr[k], oi[k], s1p[k & 3]);
+        s2p[k & 3] = fmaf(mi[k], orr[k], s2p[k & 3]);
+      }
+      const bool first = lane < q;
+      const float scl = sc * osc;
+      const float gr = ((gp[0] + gp[1]) + (gp[2] + gp[3])) * scl;
+      const float s1 = (s1p[0] + s1p[1]) + (s1p[2] + s1p[3]);
+      const float s2 = (s2p[0] + s2p[1]) + (s2p[2] + s2p[3]);
+      const float gi = (first ? s1 - s2 : s2 - s1) * scl;
+      const float n1 = first ? al : be;
+      const float n2 = first ? be : al;
+      const float gg = fmaf(gr, gr, gi * gi), nn = n1 * n2;
+      const bool act = paired && gg > tol2 * nn && gg > 0.f;
+      float c = 1.f, fr = 0.f, fi = 0.f, tf = 0.f, ga = 0.f;
+      if (act) {
+        const double gd = sqrt((double)gr * gr + (double)gi * gi);
+        ga = (float)gd;
+        float sn;
+        tf = (float)jacobi_angle(n1, n2, ga, c, sn);
+        const float ig = (float)(1.0 / gd);
+        const float ratio = sc * __builtin_amdgcn_rcpf(osc);
+        fr = (first ? tf : -tf) * (gr * ig) * ratio;
+        fi = tf * (gi * ig) * ratio;
+      }
+      if (!paired) fr = 1.f;                    // o is 0 here: m stays
+#pragma unroll
+      for (int k = 0; k < KP; ++k) {
+        const float xr = mr[k], xm = mi[k];
+        mr[k] = fmaf(fr, xr, fmaf(-fi, xm, orr[k]));
+        mi[k] = fmaf(fr, xm, fmaf(fi, xr, oi[k]));
+      }
+      if (paired) {
+        al = fmaxf(first ? fmaf(tf, ga, n2) : fmaf(-tf, ga, n1), 0.f);
+        sc = c * osc;
+        cid = ocid;
+      }
+      big = big || (act && gg > tol_last2 * nn);
+    };
+    for (int r = 0; r < Kp; r += 2) {
+      round(std::false_type{});
+      round(std::true_type{});
+    }
+    sweeps = swp + 1;
+    if (__ballot(big) == 0) break;
+  }
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    mr[k] *= sc;
+    mi[k] *= sc;
+  }
+  __syncthreads();
+
+  // ---- 3. singular values, WNNM factors, V (V[k][i] = column i / sigma_i)
+  const float sigma = sigp ? sigp[0] : sigma_h;
+  float s2a = 0.f, s2b = 0.f;
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    s2a = fmaf(mr[k], mr[k], s2a);
+    s2b = fmaf(mi[k], mi[k], s2b);
+  }
+  const float ss = sqrtf(s2a + s2b);
+  const float s = ldexpf(ss, -fe);
+  bool kept = false;
+  if (lane < Kp) {
+    const float shat = sqrtf(fmaxf(s * s - (float)K * sigma * sigma, 0.f));
+    const float tau = wc * sqrtf((float)K) * sigma * sigma / (shat + weps);
+    const float sn = fmaxf(s - tau, 0.f);
+    ssig[lane] = cid < K ? ss : -1.f;
+    sw[lane] = s > 0.f ? (s - sn) / s : 0.f;
+    kept = cid < K && sn > 0.f;
+  }
+  const int rk = __popcll(__ballot(kept));
+  if (gw && lane == 0) gw[g] = 1.0f / (float)(rk > 0 ? rk : 1);
+  if (lane < KP) {
+    const float inv = (lane < Kp && ss > 0.f) ? 1.0f / ss : 0.f;
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const bool in = lane < Kp && k < K;
+      Vr[k * XS + lane] = in ? mr[k] * inv : 0.f;
+      Vi[k * XS + lane] = in ? mi[k] * inv : 0.f;
+    }
+  }
+  __syncthreads();
+  if (sv && lane < Kp && cid < K) {
+    int rank = 0;
+    for (int i = 0; i < Kp; ++i) rank += (ssig[i] > ss || (ssig[i] == ss && i < lane)) ? 1 : 0;
+    sv[(size_t)g * K + rank] = s;
+  }
+  if (lane == 0 && st) {
+    atomicMax(&st->sweeps_max, sweeps);
+    atomicAdd(&st->sweeps_sum, (unsigned long long)sweeps);
+  }
+  // W[a][b] = sum_i w_i V[a][i] conj(V[b][i]); lane b holds w_i conj(V[b][i])
+  {
+    const int b = min(lane, KP - 1);
+    float vbr[KP], vbi[KP];
+    load_vec(vbr, Vr + b * XS);
+    load_vec(vbi, Vi + b * XS);
+#pragma unroll
+    for (int i = 0; i < KP; ++i) {
+      const float w = (lane < K && i < Kp) ? sw[i] : 0.f;
+      vbr[i] *= w;
+      vbi[i] *= -w;
+    }
+    if (lane < K)
+      for (int a = 0; a < K; ++a) {
+        float var[KP], vai[KP];
+        load_vec(var, Vr + a * XS);
+        load_vec(vai, Vi + a * XS);
+        float r0 = 0.f, r1 = 0.f, i0 = 0.f, i1 = 0.f;
+#pragma unroll
+        for (int i = 0; i < KP; i += 2) {
+          r0 = fmaf(var[i], vbr[i], fmaf(-vai[i], vbi[i], r0));
+          r1 = fmaf(var[i + 1], vbr[i + 1], fmaf(-vai[i + 1], vbi[i + 1], r1));
+          i0 = fmaf(var[i], vbi[i], fmaf(vai[i], vbr[i], i0));
+          i1 = fmaf(var[i + 1], vbi[i + 1], fmaf(vai[i + 1], vbr[i + 1], i1));
+        }
+        Wr[a * TS + lane] = r0 + r1;
+        Wi[a * TS + lane] = i0 + i1;
+      }
+    for (int a = K; a < KP; ++a) {
+      Wr[a * TS + lane] = 0.f;
+      Wi[a * TS + lane] = 0.f;
+    }
+    if (lane >= K)
+      for (int a = 0; a < K; ++a) {
+        Wr[a * TS + lane] = 0.f;
+        Wi[a * TS + lane] = 0.f;
+      }
+  }
+  __syncthreads();
+  {
+    double a0 = 0.0, a1 = 0.0;
+    for (int a = 0; a < K; ++a) {
+      a0 += (double)Wr[a * TS + lane];
+      a1 += (double)Wi[a * TS + lane];
+    }
+    srr[lane] = a0;
+    sri[lane] = a1;
+  }
+  __syncthreads();
+
+  // ---- 4. X = Z - Zc W per streamed chunk, member-major (Bl[u*TS + i]):
+  // lane (bi, bj) computes real rows 8 bi .. (complex rows 4 bi ..) of
+  // members 8 bj .., with sum_a (z_a - mu) W_a = sum_a z_a W_a - mu sum_a W_a
+  {
+    const int bi = lane >> 3, bj = lane & 7;
+    double wsr[8], wsi[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      wsr[q] = srr[8 * bj + q];
+      wsi[q] = sri[8 * bj + q];
+    }
+    for (int d0 = 0; d0 < D; d0 += BR) {
+      const int nb = min(BR, D - d0);
+      load_rows(xi, spos, d0, nb, K, P, W, 2, Bl, smu, TS, KP, true);
+      double acc[8][8];
+#pragma unroll
+      for (int p = 0; p < 8; ++p)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[p][q] = 0.0;
+#pragma unroll 2
+      for (int a = 0; a < KP; ++a) {
+        float yv[8], wr[8], wi[8];
+        load_vec(yv, Bl + a * TS + 8 * bi);
+        load_vec(wr, Wr + a * TS + 8 * bj);
+        load_vec(wi, Wi + a * TS + 8 * bj);
+        double wrd[8], wid[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          wrd[q] = (double)wr[q];
+          wid[q] = (double)wi[q];
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const double yr = (double)yv[2 * t], yi = (double)yv[2 * t + 1];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            acc[2 * t][q] = fma(yr, wrd[q], fma(-yi, wid[q], acc[2 * t][q]));
+            acc[2 * t + 1][q] = fma(yr, wid[q], fma(yi, wrd[q], acc[2 * t + 1][q]));
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int j = 8 * bj + q;
+        if (j >= K) continue;
+        float* outp = xhat + ((size_t)g * K + j) * D + d0;
+        float yv[8];
+        load_vec(yv, Bl + j * TS + 8 * bi);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int i = 8 * bi + 2 * t;
+          const double mur = (double)smu[i], mui = (double)smu[i + 1];
+          const double rr = acc[2 * t][q] - (mur * wsr[q] - mui * wsi[q]);
+          const double ri = acc[2 * t + 1][q] - (mur * wsi[q] + mui * wsr[q]);
+          if (i < nb) {
+            outp[i] = (float)((double)yv[2 * t] - rr);
+            outp[i + 1] = (float)((double)yv[2 * t + 1] - ri);
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // Iterative regularisation between inner WNNM iterations:
 // y_new = x + delta (xbar - y_prev) elementwise (FP32), and per block the
 // FP64 sum of (xbar - y_new)^2 in a fixed order (grid-stride per thread,
@@ -610,6 +1055,13 @@ void launch_wnnm(const glr_plan* pl, const float* xi, const int32_t* idx, float 
                  float* xhat, float* sv, DevStats* st, int32_t* zbuf, int zn, int bump,
                  float* gw, const float* sigp, hipStream_t s) {
   const int K = pl->K;
+  if (pl->lowrank_complex) {
+    auto kern = K <= 32 ? k_wnnm_cplx<32> : K <= 48 ? k_wnnm_cplx<48> : k_wnnm_cplx<64>;
+    hipLaunchKernelGGL(kern, dim3(pl->N), dim3(64), 0, s, xi, pl->H, pl->W, pl->P, pl->D, idx, K,
+                       sigma, sigp, pl->wnnm_c, pl->wnnm_eps, 30, xhat, sv, st, zbuf, zn, bump,
+                       gw);
+    return;
+  }
   if (K <= 32)
     hipLaunchKernelGGL(k_wnnm<32>, dim3(pl->N), dim3(64), 0, s, xi, pl->H, pl->W, pl->P, pl->D,
                        idx, K, sigma, sigp, pl->wnnm_c, pl->wnnm_eps, 30, xhat, sv, st, zbuf, zn, bump,

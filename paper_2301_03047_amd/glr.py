@@ -22,6 +22,7 @@ EXEMPLARS = {"corner": 0, "uniform": 1, "corner_uniform": 2}
 SEARCH = {"global": 0, "window": 1}
 SCORE = {"l2": 0, "edge": 1}
 AGG_WEIGHTS = {"uniform": 0, "rank": 1}
+LOWRANK = {"stacked": 0, "complex": 1}
 STATIC_SCRATCH_BYTES = 64 << 20          # GLR_STATIC_SCRATCH_BYTES
 
 _c_i32 = ctypes.c_int32
@@ -44,7 +45,8 @@ class Params(ctypes.Structure):
                 ("cnn_packed", _vp), ("exemplars", _c_i32), ("uniform_step", _c_i32),
                 ("search", _c_i32), ("window", _c_i32), ("score", _c_i32),
                 ("agg_weights", _c_i32), ("wnnm_iters", _c_i32),
-                ("wnnm_delta", ctypes.c_float), ("wnnm_lambda", ctypes.c_float)]
+                ("wnnm_delta", ctypes.c_float), ("wnnm_lambda", ctypes.c_float),
+                ("lowrank", _c_i32)]
 
 
 class Stats(ctypes.Structure):
@@ -148,7 +150,8 @@ class Plan:
                  timing=False, device="cuda", allocate=True, cnn=None, surrogate_frac=0.6,
                  judge_stride=8, judge_delta_max=0.02, exemplars="corner", uniform_step=4,
                  search="global", window=20, gap_acc=False, score="l2",
-                 agg_weights="uniform", wnnm_iters=1, wnnm_delta=None, wnnm_lambda=None):
+                 agg_weights="uniform", wnnm_iters=1, wnnm_delta=None, wnnm_lambda=None,
+                 lowrank="stacked"):
         import torch
         L = lib()
         self.modality = _MODALITY[modality] if isinstance(modality, str) else int(modality)
@@ -183,6 +186,7 @@ class Plan:
             par.wnnm_delta = float(wnnm_delta)
         if wnnm_lambda is not None:
             par.wnnm_lambda = float(wnnm_lambda)
+        par.lowrank = LOWRANK[lowrank]
         self.cnn = cnn                      # keeps the packed weights alive
         if cnn is not None:
             par.surrogate = 1
@@ -219,7 +223,7 @@ class Plan:
                     uniform_step=wl.uniform_step, search=wl.search, window=wl.window,
                     gap_acc=wl.gap_acc, score=wl.score, agg_weights=wl.agg_weights,
                     wnnm_iters=wl.wnnm_iters, wnnm_delta=wl.wnnm_delta,
-                    wnnm_lambda=wl.wnnm_lambda)
+                    wnnm_lambda=wl.wnnm_lambda, lowrank=wl.lowrank)
         args.update(kw)
         return cls(wl.modality, wl.H, wl.W, wl.C, wl.patch, wl.n_keys, wl.k, **args)
 

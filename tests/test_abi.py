@@ -63,6 +63,8 @@ def test_valid_plans_report_workspace():
     assert ws_mri >= 1024 * 63040 * 4
     st, _, _ = _create(glr.MSFA, 32, 32, 16, 6, 20, 8, mask=0)
     assert st == 0
+    st, ws_c, _ = _create(glr.MRI, 256, 256, 1, 6, 1024, 45, lowrank=1)
+    assert st == 0 and ws_c == ws_mri
 
 
 @pytest.mark.parametrize("kw,code", [
@@ -73,6 +75,8 @@ def test_valid_plans_report_workspace():
     (dict(iters=3), 1), (dict(wnnm_eps=0.0), 1), (dict(agg_weights=2), 1),
     (dict(wnnm_iters=0), 1), (dict(wnnm_iters=17), 1), (dict(wnnm_iters=2, wnnm_delta=2.0), 1),
     (dict(wnnm_iters=2, wnnm_lambda=0.0), 1),
+    (dict(lowrank=1), 1), (dict(modality=glr.MRI, H=64, W=64, C=1, lowrank=2), 1),
+    (dict(modality=glr.MSFA, C=16, mask=0, lowrank=1), 1),
 ])
 def test_invalid_plans(kw, code):
     st, _, msg = _create(**kw)
