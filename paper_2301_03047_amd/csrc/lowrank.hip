@@ -137,13 +137,11 @@ __device__ __forceinline__ float lane_xor1(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, true));
 }
 
-// The value held by lane + 1 where up, else by lane - 1 (DPP shifts of the
-// whole wave by one lane); a read past either end of the wave gives 0.
-__device__ __forceinline__ float lane_shift_pair(float v, bool up) {
-  const int x = __builtin_bit_cast(int, v);
-  const int hi = __builtin_amdgcn_mov_dpp(x, 0x130, 0xF, 0xF, true);   // wave_shl:1, zero fill
-  const int lo = __builtin_amdgcn_mov_dpp(x, 0x138, 0xF, 0xF, true);   // wave_shr:1, zero fill
-  return __builtin_bit_cast(float, up ? hi : lo);
+// The value held by lane src4 / 4 (ds_bpermute: the LDS crossbar moves the
+// values, no LDS memory and no VALU work; one instruction where the odd-round
+// pattern lane +- 1 would take two DPP shifts and a select).
+__device__ __forceinline__ float lane_read(float v, int src4) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(src4, __builtin_bit_cast(int, v)));
 }
 
 // LDS ordering between lanes of the one wave that runs a group.
@@ -346,27 +344,26 @@ k_wnnm(const float* __restrict__ xi, int H, int W, int P, int D, const int32_t* 
     // odd-even transposition ordering: even rounds pair lanes (2i, 2i+1),
     // odd rounds (2i+1, 2i+2); after its rotation a pair's two columns trade
     // lanes, so in Kp rounds every column passes every other exactly once
-    // (the ordering is equivalent to the cyclic one).  The partner column
-    // arrives by a DPP lane shift (no LDS traffic); lanes at or past Kp hold
-    // zero columns that stay zero, and the out-of-range lanes of a shift read 0.
+    // (the ordering is equivalent to the cyclic one).  Even rounds take the
+    // partner column by a DPP quad permutation (lanes at or past Kp hold zero
+    // columns that stay zero); odd rounds by ds_bpermute, each unpaired lane
+    // reading its own column and keeping it (f = 0: m' = o = m).
     // (an even and an odd round per iteration, so the rotated columns stay
     // in the registers the exchange wrote, with no copy per round)
     auto round = [&](auto oddc) {
       constexpr bool odd = decltype(oddc)::value;
       const int q = odd ? ((lane & 1) ? lane + 1 : lane - 1) : (lane ^ 1);
       const bool paired = lane < Kp && q >= 0 && q < Kp;
-      // odd rounds: odd lanes (and the idle ones past Kp) read lane + 1,
-      // even lanes lane - 1
-      const bool up = (lane & 1) || lane >= Kp;
       float o[KP];
       float be, osc;
       int ocid;
       if constexpr (odd) {
+        const int src4 = (paired ? q : lane) << 2;
 #pragma unroll
-        for (int k = 0; k < KP; ++k) o[k] = lane_shift_pair(m[k], up);
-        be = lane_shift_pair(al, up);
-        osc = lane_shift_pair(sc, up);
-        ocid = __builtin_bit_cast(int, lane_shift_pair(__builtin_bit_cast(float, cid), up));
+        for (int k = 0; k < KP; ++k) o[k] = lane_read(m[k], src4);
+        be = lane_read(al, src4);
+        osc = lane_read(sc, src4);
+        ocid = __builtin_bit_cast(int, lane_read(__builtin_bit_cast(float, cid), src4));
       } else {
 #pragma unroll
         for (int k = 0; k < KP; ++k) o[k] = lane_xor1(m[k]);
@@ -393,7 +390,7 @@ k_wnnm(const float* __restrict__ xi, int H, int W, int P, int D, const int32_t* 
         tf = (float)jacobi_angle(n1, n2, ga, c, s);
         f = (first ? tf : -tf) * (sc * __builtin_amdgcn_rcpf(osc));   // rcp within 1 ulp
       }
-      if (!paired) f = 1.f;                      // o is 0 here: m stays
+      if (!odd && !paired) f = 1.f;              // o is 0 here: m stays
 #pragma unroll
       for (int k = 0; k < KP; ++k) m[k] = fmaf(f, m[k], o[k]);
       if (paired) {
@@ -752,19 +749,19 @@ k_wnnm_cplx(const float* __restrict__ xi, int H, int W, int P, int D,
       constexpr bool odd = decltype(oddc)::value;
       const int q = odd ? ((lane & 1) ? lane + 1 : lane - 1) : (lane ^ 1);
       const bool paired = lane < Kp && q >= 0 && q < Kp;
-      const bool up = (lane & 1) || lane >= Kp;
       float orr[KP], oi[KP];
       float be, osc;
       int ocid;
       if constexpr (odd) {
+        const int src4 = (paired ? q : lane) << 2;
 #pragma unroll
         for (int k = 0; k < KP; ++k) {
-          orr[k] = lane_shift_pair(mr[k], up);
-          oi[k] = lane_shift_pair(mi[k], up);
+          orr[k] = lane_read(mr[k], src4);
+          oi[k] = lane_read(mi[k], src4);
         }
-        be = lane_shift_pair(al, up);
-        osc = lane_shift_pair(sc, up);
-        ocid = __builtin_bit_cast(int, lane_shift_pair(__builtin_bit_cast(float, cid), up));
+        be = lane_read(al, src4);
+        osc = lane_read(sc, src4);
+        ocid = __builtin_bit_cast(int, lane_read(__builtin_bit_cast(float, cid), src4));
       } else {
 #pragma unroll
         for (int k = 0; k < KP; ++k) {
@@ -808,7 +805,7 @@ k_wnnm_cplx(const float* __restrict__ xi, int H, int W, int P, int D,
         fr = (first ? tf : -tf) * (gr * ig) * ratio;
         fi = tf * (gi * ig) * ratio;
       }
-      if (!paired) fr = 1.f;                    // o is 0 here: m stays
+      if (!odd && !paired) fr = 1.f;            // even rounds: o is 0 here, m stays
 #pragma unroll
       for (int k = 0; k < KP; ++k) {
         const float xr = mr[k], xm = mi[k];
