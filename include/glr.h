@@ -142,7 +142,7 @@ typedef struct glr_params {
    * count N is reported by glr_plan_keys() (at most 16384).  search: GLOBAL
    * (every candidate) or WINDOW (candidates within `window` rows and columns
    * of the key; (window + 1)^2 >= K required).  The groups are exact either
-   * way: the window's distances are all computed with compensated sums. */
+   * way: the window's distances are all computed exactly (FP64 sums). */
   int32_t exemplars;      /* default GLR_EXEMPLAR_CORNER                         */
   int32_t uniform_step;   /* default 4                                           */
   int32_t search;         /* default GLR_SEARCH_GLOBAL                           */
@@ -262,10 +262,10 @@ GLR_API glr_status glr_detect_keys(glr_plan* plan, const void* x, int32_t* keys,
  * squared L2 patch distance, ordered by (distance, position) ascending, and
  * dist[g][q] those distances (float32).  keys: device int32 [N] (any order,
  * each < N_cand).  The distance contraction runs on MFMA; candidates within a
- * certified error margin of the K-th distance are rescored with compensated
- * (double-float32) arithmetic so that the selection equals the exact one.
+ * certified error margin of the K-th distance are rescored in FP64 (exact
+ * differences, FP64 sums) so that the selection equals the exact one.
  * With params.search WINDOW the candidates are those of the key's window
- * (block matching), all scored with compensated arithmetic. */
+ * (block matching), all scored in FP64. */
 GLR_API glr_status glr_match_topk(glr_plan* plan, const void* x, const int32_t* keys,
                           int32_t* idx, float* dist, void* ws, void* stream);
 /* Low-rank step and aggregation (WNNM on each group, the low-rank objective

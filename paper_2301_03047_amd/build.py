@@ -18,8 +18,8 @@ BUILD = os.path.join(ROOT, "_build")
 ARCH = "gfx950"
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
-    # exact IEEE FP32 steps where the method fixes them (quantiser,
-    # compensated sums): no implicit contraction anywhere; FMA is explicit
+    # exact IEEE FP32 steps where the method fixes them (quantiser, the
+    # certified error bounds): no implicit contraction anywhere; FMA is explicit
     "-ffp-contract=off",
     # packed FP32 instructions are not generated
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

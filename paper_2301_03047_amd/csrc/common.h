@@ -71,38 +71,12 @@ __device__ __forceinline__ float ord2f(uint32_t u) {
   return __uint_as_float(b);
 }
 
-// ------------------------------------------------------------------ double-float32
-// Error-free transformations (Knuth TwoSum; FMA-based TwoProd) used for
-// compensated sums of squares.  Requires -ffp-contract=off.
+// ------------------------------------------------------------------ rescored distances
+// A rescored distance s (FP64) is carried as the FP32 pair (hi, lo) =
+// (fl32(s), fl32(s - hi)); pairs order lexicographically as s does.
 struct df32 {
   float hi, lo;
 };
-
-__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
-  s = a + b;
-  float bb = s - a;
-  e = (a - (s - bb)) + (b - bb);
-}
-
-// (hi, lo) += a + al, renormalised
-__device__ __forceinline__ void df_add(df32& x, float a, float al) {
-  float s, e;
-  two_sum(x.hi, a, s, e);
-  e += x.lo + al;
-  float hi = s + e;
-  x.lo = e - (hi - s);
-  x.hi = hi;
-}
-
-// exact difference k - p as hi + lo, then its square added to x
-__device__ __forceinline__ void df_add_sqdiff(df32& x, float k, float p) {
-  float dh, dl;
-  two_sum(k, -p, dh, dl);
-  float ph = dh * dh;
-  float pl = fmaf(dh, dh, -ph);
-  pl += fmaf(dl, dl, 2.0f * dh * dl);
-  df_add(x, ph, pl);
-}
 
 // lexicographic (hi, lo, j) order of rescored candidates
 __device__ __forceinline__ bool df_less(float ah, float al, int aj, float bh, float bl, int bj) {

@@ -24,9 +24,9 @@
 // range's margin set against an upper bound of T (the range's own K-th
 // smallest U, tightened by the best bound any range of the key has
 // published so far) in one streaming pass; stage 2 selects the key's T over
-// the range lists, recomputes the distance of each margin member with
-// compensated (double-float32) arithmetic and sorts by (distance, position),
-// lowest position winning ties.
+// the range lists, recomputes the distance of each margin member in FP64
+// (exact differences, FP64 sums) and sorts by (distance, position), lowest
+// position winning ties.
 #include <cmath>
 
 #include "common.h"
@@ -360,20 +360,19 @@ __device__ int block_sum_i(int v, int* sh) {
 }
 
 // ---------------------------------------------------------------- exact rescoring
-// The compensated (double-float32) distance of one candidate is computed by
-// L lanes together (L = 8..64, a power of two fixed by D): lane s of the
-// group owns the patch elements t = s + e L in the channel-interleaved order
-// t = (dy P + dx) Cp + c, holds the key's values and the elements' offsets
-// in registers, accumulates its squared differences with TwoSum/TwoProd, and
-// the group combines its partial sums with a butterfly of compensated
-// additions (every lane of the group ends with the same value).  Candidates
+// The FP64 distance of one candidate is computed by L lanes together
+// (L = 8..64, a power of two fixed by D): lane s of the group owns the patch
+// elements t = s + e L in the channel-interleaved order t = (dy P + dx) Cp +
+// c, holds the key's values and the elements' offsets in registers,
+// accumulates its squared differences in FP64, and the group combines its
+// partial sums with a butterfly of FP64 additions.  Candidates
 // are read from the channel-interleaved copy of the image, xi[(r W + c) Cp +
 // ch]: a patch row over all channels is one contiguous run of P Cp floats,
 // so consecutive lanes read consecutive addresses and a patch spans P runs
 // (P Cp / 32 cache lines each) instead of Cp P segments of P floats.
 template <int EM>
 struct KeySlice {
-  float kv[EM];
+  double kv[EM];     // the key's values (FP32 data held in FP64 for the sums)
   int off[EM];       // offset of element t in xi relative to the patch's top-left
 };
 
@@ -389,18 +388,26 @@ __device__ __forceinline__ void key_slice_load(KeySlice<EM>& ks, const float* __
     if (t < D) {
       const int pix = t / Cp, c = t - pix * Cp;
       const int dy = pix / P, dx = pix - dy * P;
-      ks.kv[e] = kvec[(c * P + dy) * P + dx];    // the key vector is in (c, dy, dx) order
+      ks.kv[e] = (double)kvec[(c * P + dy) * P + dx];   // the key vector is in (c, dy, dx) order
       ks.off[e] = (dy * W + dx) * Cp + c;
     } else {
-      ks.kv[e] = 0.f;
+      ks.kv[e] = 0.0;
       ks.off[e] = -1;
     }
   }
 }
 
-// Compensated distances of two candidates (xi offsets b0, b1 of their
-// top-left pixels; both valid positions) by the L-lane group; every lane of
-// the group returns the group's sums.
+// Exact-order distances of two candidates (xi offsets b0, b1 of their
+// top-left pixels; both valid positions) by the L-lane group, in FP64: the
+// difference of two FP32 values is exact in FP64 (their exponents are close
+// for patch values; otherwise rounded at 2^-53), so the only roundings are
+// those of the FP64 squares and sums, a relative error of about D 2^-53 —
+// the oracle's own.  FP64 VALU instructions issue at the FP32 rate on gfx950,
+// and the three per element here replace the ~25 of a double-float32 sum.
+// The result is returned as (hi, lo) = (fl32(s), fl32(s - hi)), whose
+// lexicographic order is the order of s up to 2^-48 relative.  Every lane of
+// the group returns the group's sums; the lanes are combined by a fixed
+// butterfly, and only the group's lane 0 result is stored by the callers.
 template <int EM>
 __device__ __forceinline__ void coop_dist2(const KeySlice<EM>& ks, const float* __restrict__ xi,
                                            size_t b0, size_t b1, int L, df32& r0, df32& r1) {
@@ -413,21 +420,23 @@ __device__ __forceinline__ void coop_dist2(const KeySlice<EM>& ks, const float* 
     p0[e] = x0[o];
     p1[e] = x1[o];
   }
-  df32 a0 = {0.f, 0.f}, a1 = {0.f, 0.f};
+  double a0 = 0.0, a1 = 0.0;
 #pragma unroll
   for (int e = 0; e < EM; ++e) {
-    const bool ok = ks.off[e] >= 0;
-    df_add_sqdiff(a0, ks.kv[e], ok ? p0[e] : ks.kv[e]);
-    df_add_sqdiff(a1, ks.kv[e], ok ? p1[e] : ks.kv[e]);
+    const bool ok = ks.off[e] >= 0;             // elements past D: zero difference
+    const double d0 = ok ? ks.kv[e] - (double)p0[e] : 0.0;
+    const double d1 = ok ? ks.kv[e] - (double)p1[e] : 0.0;
+    a0 = fma(d0, d0, a0);
+    a1 = fma(d1, d1, a1);
   }
   for (int o = L >> 1; o > 0; o >>= 1) {
-    const float h0 = __shfl_xor(a0.hi, o, 64), l0 = __shfl_xor(a0.lo, o, 64);
-    const float h1 = __shfl_xor(a1.hi, o, 64), l1 = __shfl_xor(a1.lo, o, 64);
-    df_add(a0, h0, l0);
-    df_add(a1, h1, l1);
+    a0 += __shfl_xor(a0, o, 64);
+    a1 += __shfl_xor(a1, o, 64);
   }
-  r0 = a0;
-  r1 = a1;
+  r0.hi = (float)a0;
+  r0.lo = (float)(a0 - (double)r0.hi);
+  r1.hi = (float)a1;
+  r1.lo = (float)(a1 - (double)r1.hi);
 }
 
 // Rescore entries i in [0, m) of a candidate list (pos(i) = image grid
@@ -509,7 +518,7 @@ constexpr int MW = 256;
 
 // One wave per key: the key's threshold T (K-th smallest U over all range
 // lists) by a radix selection streamed over the lists, the margin set
-// {L <= T} gathered in list order, rescored with compensated arithmetic,
+// {L <= T} gathered in list order, rescored in FP64,
 // sorted by (distance, position); the first K are kept.  Only the margin set
 // is held in LDS, so the lists' union may be far larger than UW.  Keys
 // whose margin set exceeds MW, or whose range lists overflowed, are flagged
@@ -617,7 +626,7 @@ k_select_rescore(const float* __restrict__ xi, int H, int W, int P, int Cp, int 
   }
   if (l == 0) oflag[g] = 0;
   wave_sync_lds();
-  // compensated rescoring, L lanes per candidate, two candidates per group
+  // FP64 rescoring, L lanes per candidate, two candidates per group
   {
     KeySlice<EM> ks;
     key_slice_load(ks, A + (size_t)gg * D, D, P, H, W, L, l & (L - 1));
@@ -645,7 +654,7 @@ k_select_rescore(const float* __restrict__ xi, int H, int W, int P, int Cp, int 
 
 // Rescore the margin set held in global scratch (positions gp[0..m)) and
 // write the key's K smallest by (hi, lo, position), sorted, to idx/dd row gg:
-// compensated distances into gh/gl, a radix selection of the K-th smallest
+// FP64 distances (as hi/lo pairs) into gh/gl, a radix selection of the K-th smallest
 // 96-bit key (ord(hi), ord(lo + 0), position), the K entries at or below it
 // gathered and sorted in LDS.  Every thread of the block calls it.
 template <int EM>
@@ -758,7 +767,7 @@ __device__ float block_kth_by_bisection(const float* vals, int m, int K, int* ss
 //          with (U, L); T is their K-th smallest U and the margin set
 //          {L_j <= T} is compacted in place and handed to rescore_select_set;
 //  either set above mcap: exact full-row path, every candidate rescored with
-//          compensated arithmetic and a running best list kept in LDS (flat
+//          FP64 arithmetic and a running best list kept in LDS (flat
 //          images, where most distances lie within the error bound of each
 //          other).
 // With defer != 0, flag-2 keys, and flag-1 keys whose set exceeds mcap, are
@@ -988,7 +997,7 @@ full_row:
 // Block matching in a local window (eq. 1 with KNN grouping, the vanilla
 // BM the paper compares global matching against): one block per key; the
 // candidates are the grid positions within `win` rows and columns of the
-// key (clipped to the grid), every one rescored with the compensated
+// key (clipped to the grid), every one rescored with the FP64
 // arithmetic of the margin sets, and a running best list kept in LDS gives
 // the first K by (distance, position).  No contraction form and no margin:
 // the window is small enough to score directly.
