@@ -698,7 +698,16 @@ __device__ void rescore_select_set(const KeySlice<EM>& ks, const float* __restri
     __syncthreads();
     pre[w] |= sdig[0];
     remaining -= (int)sdig[1];
+    // entries that match the key so far and fall in the chosen bin
+    const int inbin = hist[(sdig[0] >> shift) & 255u];
     __syncthreads();
+    // a word of the key complete and every entry that matches it needed (the
+    // common case: the K-th distance is not tied): the K entries are those
+    // with a key up to this word, whatever the remaining words hold
+    if ((p & 3) == 3 && w < 2 && inbin == remaining) {
+      for (int v = w + 1; v < 3; ++v) pre[v] = 0xffffffffu;
+      break;
+    }
   }
   // the K entries with key <= the K-th key, in list order, then sorted
   int n = 0;
