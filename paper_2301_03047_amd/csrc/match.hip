@@ -681,38 +681,72 @@ __global__ void k_key_meta(const float* __restrict__ A, int D, int P, int Cp, in
 // pbar = p - mu_p computed in FP32 exactly as the matcher forms its operand;
 // cm2[j] = (mu_p, ||pbar||) and cre[j] = ||pbar - bf16(pbar)|| (the residual
 // of the matcher's round-to-nearest-even BF16 operand) for the error bound
-// of the top-K pass.
-__global__ void k_cand_meta(const float* __restrict__ xp, int Cp, int H, int W, int P,
-                            float4* __restrict__ cmeta, float2* __restrict__ cm2,
-                            float* __restrict__ cre, int raw) {
-  const int Wc = W - P + 1, Hc = H - P + 1;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= Hc * Wc) return;
-  const int r = j / Wc, c = j - r * Wc;
+// of the top-K pass.  One block per 256 candidates of one grid row: each
+// channel's P image rows (256 + P - 1 columns) are staged in LDS and every
+// thread reads its window from there; the sums run in four partial sums per
+// quantity (over dx mod 4, combined in a fixed order), so the additions do
+// not form one dependency chain per thread.
+constexpr int CMB = 256;                     // candidates per block
+__global__ void __launch_bounds__(CMB)
+k_cand_meta(const float* __restrict__ xp, int Cp, int H, int W, int P,
+            float4* __restrict__ cmeta, float2* __restrict__ cm2, float* __restrict__ cre,
+            int raw) {
+  __shared__ float tile[16 * (CMB + 15)];    // P <= 16
+  const int Wc = W - P + 1;
+  const int r = blockIdx.y, c0 = blockIdx.x * CMB, t = threadIdx.x;
+  const int TW = CMB + P - 1;
   const int D = Cp * P * P;
-  float s = 0.f;
-  for (int ch = 0; ch < Cp; ++ch)
-    for (int dy = 0; dy < P; ++dy) {
-      const float* row = xp + ((size_t)ch * H + r + dy) * W + c;
-      for (int dx = 0; dx < P; ++dx) s += row[dx];
+  auto stage = [&](int ch) {
+    __syncthreads();                         // the previous channel's readers are done
+    for (int i = t; i < P * TW; i += CMB) {
+      const int dy = i / TW, x = i - dy * TW;
+      tile[i] = xp[((size_t)ch * H + r + dy) * W + min(c0 + x, W - 1)];
     }
-  const float mu = raw ? 0.f : s / (float)D;
-  float pn = 0.f, sp = 0.f, en = 0.f;
-  for (int ch = 0; ch < Cp; ++ch)
+    __syncthreads();
+  };
+  float s[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int ch = 0; ch < Cp; ++ch) {
+    stage(ch);
     for (int dy = 0; dy < P; ++dy) {
-      const float* row = xp + ((size_t)ch * H + r + dy) * W + c;
-      for (int dx = 0; dx < P; ++dx) {
-        const float v = row[dx] - mu;
-        const float e = v - bf16_val(v);    // exact
-        pn = fmaf(v, v, pn);
-        sp += v;
-        en = fmaf(e, e, en);
+      const float* row = tile + dy * TW + t;
+      for (int dx = 0; dx < P; dx += 4) {
+        s[0] += row[dx];
+        if (dx + 1 < P) s[1] += row[dx + 1];
+        if (dx + 2 < P) s[2] += row[dx + 2];
+        if (dx + 3 < P) s[3] += row[dx + 3];
       }
     }
-  const float pr = sqrtf(pn);
-  cmeta[j] = raw ? make_float4(0.f, 0.f, pr, 0.f) : make_float4(mu, pn, pr, sp);
+  }
+  const float mu = raw ? 0.f : ((s[0] + s[1]) + (s[2] + s[3])) / (float)D;
+  float pn[4] = {0.f, 0.f, 0.f, 0.f}, sp[4] = {0.f, 0.f, 0.f, 0.f}, en[4] = {0.f, 0.f, 0.f, 0.f};
+  auto acc = [&](int k, float x) {
+    const float v = x - mu;
+    const float e = v - bf16_val(v);         // exact
+    pn[k] = fmaf(v, v, pn[k]);
+    sp[k] += v;
+    en[k] = fmaf(e, e, en[k]);
+  };
+  for (int ch = 0; ch < Cp; ++ch) {
+    stage(ch);
+    for (int dy = 0; dy < P; ++dy) {
+      const float* row = tile + dy * TW + t;
+      for (int dx = 0; dx < P; dx += 4) {
+        acc(0, row[dx]);
+        if (dx + 1 < P) acc(1, row[dx + 1]);
+        if (dx + 2 < P) acc(2, row[dx + 2]);
+        if (dx + 3 < P) acc(3, row[dx + 3]);
+      }
+    }
+  }
+  if (c0 + t >= Wc) return;                  // no block barrier below
+  const size_t j = (size_t)r * Wc + c0 + t;
+  const float pnt = (pn[0] + pn[1]) + (pn[2] + pn[3]);
+  const float spt = (sp[0] + sp[1]) + (sp[2] + sp[3]);
+  const float ent = (en[0] + en[1]) + (en[2] + en[3]);
+  const float pr = sqrtf(pnt);
+  cmeta[j] = raw ? make_float4(0.f, 0.f, pr, 0.f) : make_float4(mu, pnt, pr, spt);
   cm2[j] = make_float2(mu, pr);
-  cre[j] = sqrtf(en);
+  cre[j] = sqrtf(ent);
 }
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -1187,9 +1221,9 @@ void launch_key_meta(const glr_plan* pl, const float* A, uint16_t* Ab, float* km
 
 void launch_cand_meta(const glr_plan* pl, const float* xp, float* cmeta, float* cm2, float* cre,
                       int raw, hipStream_t s) {
-  const int n = pl->Ncand;
-  hipLaunchKernelGGL(k_cand_meta, dim3((n + 255) / 256), dim3(256), 0, s, xp, pl->Cp, pl->H,
-                     pl->W, pl->P, (float4*)cmeta, (float2*)cm2, cre, raw);
+  const int Wc = pl->W - pl->P + 1, Hc = pl->H - pl->P + 1;
+  hipLaunchKernelGGL(k_cand_meta, dim3((Wc + CMB - 1) / CMB, Hc), dim3(CMB), 0, s, xp, pl->Cp,
+                     pl->H, pl->W, pl->P, (float4*)cmeta, (float2*)cm2, cre, raw);
 }
 
 void launch_key_meta_pc(const glr_plan* pl, const float* A, float* Ac, float* kn, float* kc,
