@@ -231,7 +231,10 @@ k_wnnm(const float* __restrict__ xi, int H, int W, int P, int D, const int32_t* 
       for (int q = 0; q < 8; ++q) acc[p][q] = 0.0;
     for (int d0 = 0; d0 < D; d0 += BR) {
       const int nb = min(BR, D - d0);
-      load_rows(xi, spos, d0, nb, K, P, W, Cp, Bl, smu, XS);
+      // members K..KP-1 of each row are zeros, so the products need no mask;
+      // blocks at or past KP (KP < 64) read other rows' values, and their
+      // entries of G are never read
+      load_rows(xi, spos, d0, nb, K, P, W, Cp, Bl, smu, XS, KP);
       // centre the chunk in place (lane i: row i), once for all lanes
       if (lane < nb) {
         const float mu = smu[lane];
@@ -246,8 +249,8 @@ k_wnnm(const float* __restrict__ xi, int H, int W, int P, int D, const int32_t* 
         double ya[8], yb[8];
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
-          ya[t] = 8 * bi + t < K ? (double)a[t] : 0.0;
-          yb[t] = 8 * bj + t < K ? (double)b[t] : 0.0;
+          ya[t] = (double)a[t];
+          yb[t] = (double)b[t];
         }
 #pragma unroll
         for (int p = 0; p < 8; ++p)
@@ -620,7 +623,9 @@ k_wnnm_cplx(const float* __restrict__ xi, int H, int W, int P, int D,
         for (int q = 0; q < 8; ++q) acc[p][q] = 0.0;
       for (int d0 = 0; d0 < D; d0 += BR) {
         const int nb = min(BR, D - d0);              // even: D is, and BR
-        load_rows(xi, spos, d0, nb, K, P, W, 2, Bl, smu, XS);
+        // members K..KP-1 are zeros (no masks below); blocks at or past KP
+        // read other rows' values, and their entries of G are not stored
+        load_rows(xi, spos, d0, nb, K, P, W, 2, Bl, smu, XS, KP);
         if (lane < nb) {
           const float mu = smu[lane];
           for (int u = 0; u < K; ++u) Bl[lane * XS + u] -= mu;
@@ -638,8 +643,8 @@ k_wnnm_cplx(const float* __restrict__ xi, int H, int W, int P, int D,
           double ya[8], yb[8];
 #pragma unroll
           for (int t = 0; t < 8; ++t) {
-            ya[t] = 8 * bi + t < K ? (double)a[t] : 0.0;
-            yb[t] = 8 * bj + t < K ? sg * (double)b[t] : 0.0;
+            ya[t] = (double)a[t];
+            yb[t] = sg * (double)b[t];
           }
 #pragma unroll
           for (int p = 0; p < 8; ++p)
