@@ -209,7 +209,7 @@ GLR_API const char* glr_status_string(glr_status s);
 /* Thread-local detail of the last failed call on this thread ("" if none). */
 GLR_API const char* glr_last_error_message(void);
 /* Fill *p with the defaults (c = 2*sqrt(2), eps = 1e-16, rho = 1, FP32,
- * 8192 MiB chunks, GAP, no timing); patch/n_keys/k/iters are set to 0. */
+ * 16384 MiB chunks, GAP, no timing); patch/n_keys/k/iters are set to 0. */
 GLR_API void glr_params_default(glr_params* p);
 
 /* Create a plan for one problem shape.  Validates everything that does not

@@ -473,7 +473,7 @@ void glr_params_default(glr_params* p) {
   p->wnnm_c = 2.0f * std::sqrt(2.0f);
   p->wnnm_eps = 1e-16f;
   p->precision = GLR_PREC_FP32;
-  p->dist_chunk_mb = 8192;
+  p->dist_chunk_mb = 16384;
   p->timing = 0;
   p->surrogate = 0;
   p->surrogate_frac = 0.6f;
@@ -642,7 +642,7 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
   pl->Ncand = (int)Ncand;
   pl->D = D;
   pl->ldd = (int)up((size_t)Ncand, 64);
-  size_t chunk_bytes = (size_t)(pr->dist_chunk_mb > 0 ? pr->dist_chunk_mb : 8192) << 20;
+  size_t chunk_bytes = (size_t)(pr->dist_chunk_mb > 0 ? pr->dist_chunk_mb : 16384) << 20;
   long long nch = (long long)(chunk_bytes / ((size_t)pl->ldd * 4));
   if (nch < 1) nch = 1;
   if (nch >= 128) nch = nch / 128 * 128;
@@ -651,7 +651,10 @@ glr_status glr_plan_create(glr_plan** out, const glr_problem* pb, const glr_para
   if (pl->search == GLR_SEARCH_WINDOW) pl->n_chunk = 1;
   // ranges per key: enough waves to fill the chip; more for the BF16 form,
   // whose larger margin sets need the combined capacity of more range lists
-  const int target = pr->precision == GLR_PREC_BF16_RESCORE ? 32768 : 8192;
+  // (on the 1024^2 x 24 workload, 16 GiB chunks of 4096 keys with 16 ranges
+  // each: no list overflow over the run, and half the launches, hence half
+  // the per-launch tails, of 8 GiB chunks)
+  const int target = pr->precision == GLR_PREC_BF16_RESCORE ? 65536 : 8192;
   int ns = (target + pl->n_chunk - 1) / pl->n_chunk;
   ns = std::min(ns, 64);
   ns = std::min<long long>(ns, (Ncand + 1023) / 1024);

@@ -146,7 +146,7 @@ class Plan:
     """One problem shape: modality, image size, patch size, keys, K, solver."""
 
     def __init__(self, modality, H, W, C, patch, n_keys, k, iters=0, sigma=None, mask=None,
-                 rho=1.0, wnnm_c=None, wnnm_eps=None, precision="fp32", dist_chunk_mb=8192,
+                 rho=1.0, wnnm_c=None, wnnm_eps=None, precision="fp32", dist_chunk_mb=16384,
                  timing=False, device="cuda", allocate=True, cnn=None, surrogate_frac=0.6,
                  judge_stride=8, judge_delta_max=0.02, exemplars="corner", uniform_step=4,
                  search="global", window=20, gap_acc=False, score="l2",
