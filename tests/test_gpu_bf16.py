@@ -1,6 +1,6 @@
 """BF16 form of the matcher (mean-centred key and candidate patches on BF16
 MFMA, FP32 accumulation, its own certified bound).  The margin set is
-rescored with the same compensated arithmetic as the FP32 form, so the bar
+rescored with the same FP64 arithmetic as the FP32 form, so the bar
 is unchanged: groups identical to the oracle's exact top-K, distances within
 1e-6 relative, and identical (bitwise) to the FP32 form's output."""
 import numpy as np

@@ -339,7 +339,7 @@ def test_msfa_512_full_size_prior_step_vs_oracle():
     # 507^2 candidates, FP32 matcher), first GAP iterate: keys bit-exact,
     # every group equal to the oracle's exact top-K except rows whose
     # differing members tie within 1e-9 of the row's distances (the GPU's
-    # compensated FP32 sums and the oracle's FP64 sums order such near-ties
+    # FP64 sums and the oracle's FP64 sums, in their own orders, order such near-ties
     # by their own roundings; check_groups verifies those rows' distance
     # profiles), the whole prior step within rel-L2 1e-5 of the oracle's
     require_gpu()
