@@ -15,7 +15,8 @@
  * - Array arguments are DEVICE pointers unless marked "host".  The caller
  *   owns all device memory (inputs, outputs, workspace); the library never
  *   allocates device memory.  A plan holds host metadata only.
- * - Every compute call is asynchronous on the given HIP stream; results are
+ * - Every compute call is asynchronous on the given HIP stream (except for
+ *   the one host read-back of the BF16 form, see precision); results are
  *   valid once the stream has completed.  Calls on one plan must not overlap
  *   (plans are not thread-safe); separate plans may run on separate streams.
  * - Arguments are validated on the host before anything is enqueued.  On an
@@ -117,7 +118,11 @@ typedef struct glr_params {
                             its own certified error bound; keys whose margin
                             set would not fit are re-matched in FP32).  The
                             groups are the same exact top-K with either; only
-                            the work spent on the margin sets differs        */
+                            the work spent on the margin sets differs.  The
+                            BF16 form reads the re-match count back to the
+                            host once per match (a synchronisation of the
+                            stream inside glr_match_topk, glr_prior_step and
+                            each iteration of glr_reconstruct)              */
   int32_t dist_chunk_mb; /* max size of one distance-matrix chunk (MiB)         */
   int32_t timing;        /* nonzero: record per-stage HIP event pairs on the
                             stream (no host sync); glr_read_stats() sums them */
