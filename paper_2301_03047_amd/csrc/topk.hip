@@ -157,8 +157,10 @@ __device__ __forceinline__ float margin_eps(float d, float p, float m, float ep,
     const float y = ((kr + p) + __builtin_amdgcn_sqrtf(fmaxf(d, 0x1p-126f))) + w;
     return fmaf(y, fmaf(coef2, y, w), w * w);
   }
-  const float R = (kr + p) + cz * fabsf(kmu - m);
-  return coef * (kr * ep + ek * (p + ep)) + coef2 * (R * R);
+  // (fused: nine instructions per candidate instead of twelve; every
+  // rounding is still covered by the coefficients' slack)
+  const float R = fmaf(cz, fabsf(kmu - m), kr + p);
+  return fmaf(coef2 * R, R, coef * fmaf(ek, p + ep, kr * ep));
 }
 
 // Error bound of d~ per candidate (key row kmap[g0+g] or g0+g):

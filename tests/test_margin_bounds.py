@@ -49,6 +49,14 @@ def bf16(x):
     return out.astype(f32)
 
 
+def fma(a, b, c):
+    """float32 fma: the product is exact in float64, then one rounding of the
+    sum in float64 and one to float32 (a double rounding that only moves a
+    tie, far below the bound's slack)."""
+    return (np.float64(1.0) * np.asarray(a, np.float64) * np.asarray(b, np.float64)
+            + np.asarray(c, np.float64)).astype(f32)
+
+
 def seq_sum(terms):
     """Sequential float32 sum over the first axis."""
     acc = np.zeros(terms.shape[1:], dtype=f32)
@@ -106,9 +114,11 @@ def bf16_form(k, P, key_residual=True):
     c1 = _up(2.0 * (1.0 + 2.0 ** -8))
     c2 = _up((3.0 * D + 26.0) * U)
     cz = _up(math.sqrt(D))
-    R = f32(f32(kr + pr) + f32(cz * np.abs(f32(mu_k - mu_p))))
-    res = f32(f32(kr * ep) + f32(ek * f32(pr + ep)))
-    eps = f32(f32(c1 * res) + f32(c2 * f32(R * R)))
+    # the kernel's order: R = fma(cz, |dmu|, kr + pr),
+    # eps = fma(c2 R, R, c1 fma(ek, pr + ep, kr ep))
+    R = fma(cz, np.abs(f32(mu_k - mu_p)), f32(kr + pr))
+    res = fma(ek, f32(pr + ep), f32(kr * ep))
+    eps = fma(f32(c2 * R), R, f32(c1 * res))
     return dt, eps
 
 
