@@ -1215,11 +1215,12 @@ void launch_topk_partial(const glr_plan* pl, const float* dist, const float* kmb
   // tsh[0..nk) holds +inf here: set by the key gather at the start of every
   // match call and restored by the rescoring kernel after every scan
   // the FP32 form's margin sets stay far below the BF16 form's: a smaller
-  // wave buffer (28 KB of LDS per block) and no residual norms to prefetch
-  // fit three waves per SIMD with 768-candidate steps; the BF16 form's
-  // 1024-entry buffers (53 KB) fit three blocks per CU, and its 512-candidate
-  // steps (16 bytes per candidate, always prefetched one step ahead) keep the
-  // registers within three waves per SIMD.  (768-candidate steps at two waves
+  // wave buffer (28 KB of LDS per block), no residual norms to prefetch and
+  // 512-candidate steps (110 VGPRs) fit four waves per SIMD (12 % faster
+  // than three with 768-candidate steps on the MRI 256^2 workload); the
+  // BF16 form's 1024-entry buffers (53 KB) fit three blocks per CU, and its
+  // 512-candidate steps (16 bytes per candidate, always prefetched one step
+  // ahead) keep the registers within three waves per SIMD.  (768-candidate steps at two waves
   // per SIMD: 8 % slower on the 1024^2 x 24 workload; 768-entry buffers for
   // four waves overflow the range lists of the hardest keys.)
   const dim3 grid((nk + 3) / 4 * pl->n_split);
@@ -1229,7 +1230,7 @@ void launch_topk_partial(const glr_plan* pl, const float* dist, const float* kmb
                        pl->split_len, pl->n_split, nk, pl->K, coef, coef2, cz, tsh, lj, lu, ll,
                        lcnt);
   else
-    hipLaunchKernelGGL((k_topk_partial<3, 512, 3, false, 1>), grid,
+    hipLaunchKernelGGL((k_topk_partial<2, 512, 4, false, 1>), grid,
                        dim3(256), 0, s, dist, (size_t)pl->ldd, (const float4*)kmb, kre, kmap, g0,
                        cm2, cre, pl->Ncand, pl->split_len, pl->n_split, nk, pl->K, coef, coef2,
                        cz, tsh, lj, lu, ll, lcnt);
