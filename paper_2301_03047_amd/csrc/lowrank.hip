@@ -6,8 +6,9 @@
 // column j and keeps it in registers:
 //  1. rows are streamed in chunks of up to 64 (each lane loads one row and
 //     its mean; Yc = Y - mu 1^T in FP32); the Gram matrix G = Yc^T Yc is
-//     accumulated in FP64 (lane (bi, bj) owns an 8 x 8 block) and factored by
-//     an FP64 Cholesky, R^T R = G: R is the QR factor of Yc up to row signs;
+//     accumulated on FP64 MFMA (16 x 16 tiles of its upper triangle) and
+//     factored by an FP64 Cholesky, R^T R = G: R is the QR factor of Yc up
+//     to row signs;
 //  2. one-sided Jacobi on the columns of R^T (odd-even transposition
 //     ordering, partner columns moved between lanes by DPP, rotation angles
 //     computed in FP64); the converged columns are sigma_i v_i with v_i the
@@ -210,9 +211,9 @@ k_wnnm(const float* __restrict__ xi, int H, int W, int P, int D, const int32_t* 
   for (int i = 0; i < 64; ++i) Rl[lane * LS + i] = 0.f;
   __syncthreads();
 
-  // ---- 1. Gram matrix G = Yc^T Yc in FP64 over the streamed rows (lane
-  // (bi, bj) accumulates the 8 x 8 block G[8 bi ..][8 bj ..]; the FP32
-  // centred values and their products are exact in FP64), then its Cholesky
+  // ---- 1. Gram matrix G = Yc^T Yc in FP64 over the streamed rows (FP64
+  // MFMA on the 16 x 16 tiles of its upper triangle; the FP32 centred values
+  // and their products are exact in FP64), then its Cholesky
   // factor R (R^T R = G, upper triangular, column j in lane j; a pivot <= 0,
   // which only a numerically dependent column gives, leaves a zero row).  R
   // equals the QR factor of Yc up to the signs of its rows, so it has the
@@ -223,47 +224,58 @@ k_wnnm(const float* __restrict__ xi, int H, int W, int P, int D, const int32_t* 
   // the raw rows).
   int fe = 0;
   {
-    const int bi = lane >> 3, bj = lane & 7;
-    double acc[8][8];
+    // FP64 MFMA (16 x 16 x 4): tile (I, J) of G, I <= J, sums four rows per
+    // step; lane (m, kq) = (lane % 16, lane / 16) holds row kq of the step
+    // for member 16 I + m, the A operand of tile row I and the B operand of
+    // tile column I alike, so one LDS read serves every tile of the step
+    constexpr int NTI = KP / 16;
+    constexpr int NTL = NTI * (NTI + 1) / 2;
+    using f64x4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
+    f64x4 gacc[NTL];
 #pragma unroll
-    for (int p = 0; p < 8; ++p)
-#pragma unroll
-      for (int q = 0; q < 8; ++q) acc[p][q] = 0.0;
+    for (int t = 0; t < NTL; ++t) gacc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+    const int gm = lane & 15, gk = lane >> 4;
     for (int d0 = 0; d0 < D; d0 += BR) {
       const int nb = min(BR, D - d0);
-      // members K..KP-1 of each row are zeros, so the products need no mask;
-      // blocks at or past KP (KP < 64) read other rows' values, and their
-      // entries of G are never read
+      const int nb4 = (nb + 3) & ~3;
+      // members K..KP-1 of each row are zeros, so the products need no mask
       load_rows(xi, spos, d0, nb, K, P, W, Cp, Bl, smu, XS, KP);
-      // centre the chunk in place (lane i: row i), once for all lanes
+      // centre the chunk in place (lane i: row i), once for all lanes; rows
+      // nb..nb4-1 (the last step's rows past the chunk) are zeros
       if (lane < nb) {
         const float mu = smu[lane];
         for (int u = 0; u < K; ++u) Bl[lane * XS + u] -= mu;
+      } else if (lane < nb4) {
+        for (int u = 0; u < KP; ++u) Bl[lane * XS + u] = 0.f;
       }
       __syncthreads();
-#pragma unroll 2
-      for (int i = 0; i < nb; ++i) {
-        float a[8], b[8];
-        load_vec(a, Bl + i * XS + 8 * bi);
-        load_vec(b, Bl + i * XS + 8 * bj);
-        double ya[8], yb[8];
+      for (int i0 = 0; i0 < nb4; i0 += 4) {
+        double v[NTI];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          ya[t] = (double)a[t];
-          yb[t] = (double)b[t];
-        }
+        for (int I = 0; I < NTI; ++I) v[I] = (double)Bl[(i0 + gk) * XS + 16 * I + gm];
+        int t = 0;
 #pragma unroll
-        for (int p = 0; p < 8; ++p)
+        for (int I = 0; I < NTI; ++I)
 #pragma unroll
-          for (int q = 0; q < 8; ++q) acc[p][q] = fma(ya[p], yb[q], acc[p][q]);
+          for (int J = I; J < NTI; ++J, ++t)
+            gacc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[I], v[J], gacc[t], 0, 0, 0);
       }
       __syncthreads();
     }
+    // lane (m, kq) holds G[16 I + kq + 4 i][16 J + m], i < 4; both triangles
+    // are stored (entries at or past KP are never read)
     double* G = reinterpret_cast<double*>(RB);
+    int t = 0;
 #pragma unroll
-    for (int p = 0; p < 8; ++p)
+    for (int I = 0; I < NTI; ++I)
 #pragma unroll
-      for (int q = 0; q < 8; ++q) G[(8 * bi + p) * 64 + 8 * bj + q] = acc[p][q];
+      for (int J = I; J < NTI; ++J, ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = 16 * I + gk + 4 * i, col = 16 * J + gm;
+          G[row * 64 + col] = gacc[t][i];
+          if (I != J) G[col * 64 + row] = gacc[t][i];
+        }
   }
   __syncthreads();
   {
