@@ -506,52 +506,55 @@ k_wnnm(const float* __restrict__ xi, int H, int W, int P, int D, const int32_t* 
   __syncthreads();
 
   // ---- 4. X = Y - Yc W (residual in FP64), per streamed chunk of rows held
-  // member-major (Bl[u*TS + i] = Y[i][u]): lane (bi, bj) computes the 8 x 8
-  // block of rows 8 bi .. and members 8 bj .., with
+  // member-major (Bl[u*TS + i] = Y[i][u]): the product Y W runs on FP64 MFMA
+  // (16 x 16 x 4) over 16-row by 16-member tiles, the A operand Y[16 R + m]
+  // [a0 + k] and the B operand W[a0 + k][16 C + n] of lane (m or n, k) =
+  // (lane % 16, lane / 16) read from LDS; then
   // sum_a (y_a - mu) w_a = sum_a y_a w_a - mu sum_a w_a (FP64; W and the
-  // chunk are zero past K), and writes each member's eight rows
+  // chunk are zero past K) and each lane writes its four rows of a member
+  // (rows past nb hold stale values, and only their own outputs, which are
+  // not stored)
   {
-    const int bi = lane >> 3, bj = lane & 7;
-    double wsj[8];
+    constexpr int NTI = KP / 16;
+    using f64x4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
+    const int gm = lane & 15, gk = lane >> 4;
+    double wsc[NTI];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) wsj[q] = srow[8 * bj + q];
+    for (int C = 0; C < NTI; ++C) wsc[C] = srow[16 * C + gm];
     for (int d0 = 0; d0 < D; d0 += BR) {
       const int nb = min(BR, D - d0);
       load_rows(xi, spos, d0, nb, K, P, W, Cp, Bl, smu, TS, KP, true);
-      double acc[8][8];
+      f64x4 o[4][NTI];
 #pragma unroll
-      for (int p = 0; p < 8; ++p)
+      for (int R = 0; R < 4; ++R)
 #pragma unroll
-        for (int q = 0; q < 8; ++q) acc[p][q] = 0.0;
-#pragma unroll 2
-      for (int a = 0; a < KP; ++a) {
-        float yv[8], wv[8];
-        load_vec(yv, Bl + a * TS + 8 * bi);
-        load_vec(wv, Rl + a * TS + 8 * bj);
-        double yd[8], wd[8];
+        for (int C = 0; C < NTI; ++C) o[R][C] = f64x4{0.0, 0.0, 0.0, 0.0};
+      for (int a0 = 0; a0 < KP; a0 += 4) {
+        double ya[4], wb[NTI];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          yd[t] = (double)yv[t];
-          wd[t] = (double)wv[t];
-        }
+        for (int R = 0; R < 4; ++R) ya[R] = (double)Bl[(a0 + gk) * TS + 16 * R + gm];
 #pragma unroll
-        for (int p = 0; p < 8; ++p)
+        for (int C = 0; C < NTI; ++C) wb[C] = (double)Rl[(a0 + gk) * TS + 16 * C + gm];
 #pragma unroll
-          for (int q = 0; q < 8; ++q) acc[p][q] = fma(yd[p], wd[q], acc[p][q]);
+        for (int R = 0; R < 4; ++R)
+#pragma unroll
+          for (int C = 0; C < NTI; ++C)
+            o[R][C] = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[R], wb[C], o[R][C], 0, 0, 0);
       }
+      // lane (n, k) holds rows 16 R + k + 4 i of member 16 C + n, i < 4
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int j = 8 * bj + q;
+      for (int C = 0; C < NTI; ++C) {
+        const int j = 16 * C + gm;
         if (j >= K) continue;
         float* outp = xhat + ((size_t)g * K + j) * D + d0;
-        float yv[8];
-        load_vec(yv, Bl + j * TS + 8 * bi);
 #pragma unroll
-        for (int p = 0; p < 8; ++p) {
-          const int i = 8 * bi + p;
-          const double r = acc[p][q] - (double)smu[i] * wsj[q];
-          if (i < nb) outp[i] = (float)((double)yv[p] - r);
-        }
+        for (int R = 0; R < 4; ++R)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int row = 16 * R + gk + 4 * i;
+            const double r = o[R][C][i] - (double)smu[row] * wsc[C];
+            if (row < nb) outp[row] = (float)((double)Bl[j * TS + row] - r);
+          }
       }
       __syncthreads();
     }
