@@ -163,12 +163,14 @@ def kernel_rooflines(wl, prec, st, n_iter):
         f64, f32 = wnnm_flop(wl.n_keys, wl.dim, wl.k, sweeps)
         flop = (f64 + f32) * n_iter
         ach = flop / (st["ms_lowrank"] * 1e-3) / 1e12
-        # the mix's peak: both parts at their own vector peaks
+        # the mix's peak: both parts at their own peaks (the FP64 Gram and
+        # residual products run on FP64 MFMA, whose dense peak on MI355X equals
+        # the FP64 vector peak; the FP32 Jacobi on the vector units)
         peak = (f64 + f32) / (f64 / PEAK_FP64_VALU_TFLOPS + f32 / PEAK_FP32_VALU_TFLOPS)
         out["k_wnnm"] = {"bound": "alu", "achieved": round(ach, 3),
                          "peak": round(peak, 2), "unit": "TFLOP/s",
                          "frac": round(ach / peak, 4),
-                         "peak_note": "FP64 (Gram, residual) at 78.6 and FP32 (Jacobi) at 157.3",
+                         "peak_note": "FP64 MFMA (Gram, residual) at 78.6 and FP32 VALU (Jacobi) at 157.3",
                          "launch_ms": round(st["ms_lowrank"] / n_iter, 4),
                          "sweeps_mean": round(sweeps, 3),
                          "traffic": measured_traffic("k_wnnm", wl.name)}
